@@ -1,0 +1,215 @@
+/*
+ * Oracle single-physics pieces.  TEST INFRASTRUCTURE ONLY.
+ *
+ * Constants are CODATA 2018 in SI; energies and temperatures in eV.  Each
+ * formula is written with the operand order that the specification of the
+ * method fixes, so that an independent implementation can reproduce it bit
+ * for bit.
+ */
+#include <math.h>
+#include <stdint.h>
+
+#include "orc.h"
+#include "orc_internal.h"
+
+void orc_occupancy(int32_t z, int32_t k, int32_t occ[ORC_NSUB])
+{
+    /* Lowest-energy configuration of charge state z with k K vacancies
+     * (Sec. III: only Z_i and the K-vacancy count are stored per ion). */
+    static const int cap[ORC_NSUB] = {2, 2, 6, 2, 6};
+    int nb = ORC_ZMAX - z;
+    int k1s = 2 - k;
+    if (k1s > nb) k1s = nb;
+    if (k1s < 0) k1s = 0;
+    occ[0] = k1s;
+    int rem = nb - k1s;
+    for (int s = 1; s < ORC_NSUB; ++s) {
+        int c = rem < cap[s] ? rem : cap[s];
+        occ[s] = c;
+        rem -= c;
+    }
+}
+
+/* Outermost occupied subshell, or -1 for a bare nucleus. */
+int orc_valence(int z, int k)
+{
+    int occ[ORC_NSUB];
+    orc_occupancy(z, k, occ);
+    for (int s = ORC_NSUB - 1; s >= 0; --s)
+        if (occ[s] > 0) return s;
+    return -1;
+}
+
+/*
+ * Ionization potential depression of charge state z (Sec. V).
+ *   Ecker-Kroll (Eq. 5): C = 1, applied when n = n_e + n_i exceeds the critical
+ *   density n_crit = (3/4pi)(4 pi eps0 kT / ((z+1)^2 e^2))^3; below it the
+ *   Debye-Hueckel shift (z+1) e^2 / (4 pi eps0 lambda_D) is used.
+ *   Stewart-Pyatt (Eq. 6) with K = (z+1) e^2 / (4 pi eps0 lambda_D kT),
+ *   lambda_D = sqrt(eps0 kT / (e^2 n_e (Zbar + 1))) taking T_i = T_e, and
+ *   z* = <Z^2>/<Z>.
+ */
+double orc_ipd(int32_t model, int32_t z, double t, double n_e, double n_i,
+               double zbar, double zstar)
+{
+    double lamd = INFINITY;
+    if (n_e > 0.0) lamd = sqrt((ORC_EPS0 * t) / (ORC_QE * (n_e * (zbar + 1.0))));
+    double zp1 = (double)(z + 1);
+    if (model == 1) {
+        double ntot = n_e + n_i;
+        double c = t / ((zp1 * zp1) * ORC_E2);
+        double ncrit = ORC_THREE_OVER_4PI * ((c * c) * c);
+        if (ntot > ncrit) {
+            double rek = orc_cbrt(ORC_THREE_OVER_4PI / ntot);
+            return (zp1 * ORC_E2) / rek;
+        }
+        return (zp1 * ORC_E2) / lamd;
+    }
+    double kk = (zp1 * ORC_E2) / (lamd * t);
+    double zs1 = zstar + 1.0;
+    double y = ((3.0 * zs1) * kk) + 1.0;
+    double c = orc_cbrt(y);
+    return (t / (2.0 * zs1)) * ((c * c) - 1.0);
+}
+
+/* Coulomb logarithm per cell: max(2, ln(1 + (lambda_De / b_min)^2) / 2). */
+double orc_coulomb_log(double t, double n_e, double zbar)
+{
+    if (!(n_e > 0.0)) return 2.0;
+    double lamde = sqrt((ORC_EPS0 * t) / (ORC_QE * n_e));
+    double bcl = (zbar * ORC_E2) / (3.0 * t);
+    double bq = ORC_HBAR / (2.0 * sqrt((3.0 * ORC_ME) * (t * ORC_QE)));
+    double bmin = bcl > bq ? bcl : bq;
+    double ratio = lamde / bmin;
+    double lnl = 0.5 * orc_log(1.0 + ratio * ratio);
+    return lnl < 2.0 ? 2.0 : lnl;
+}
+
+/*
+ * Lotz cross section (Eq. 4) of the average cell ion of charge zc in its
+ * ground configuration, with binding energies lowered by dE[zc] (clamped at
+ * 1 eV); m^2.  ln(E/P) is evaluated as ln E - ln P.
+ */
+double orc_lotz(const orc_tables *t, int32_t zc, const double dE[13], double e)
+{
+    if (zc >= ORC_ZMAX || !(e > 0.0)) return 0.0;
+    int occ[ORC_NSUB];
+    orc_occupancy(zc, 0, occ);
+    double lne = orc_log(e);
+    double sig = 0.0;
+    for (int s = 0; s < ORC_NSUB; ++s) {
+        if (occ[s] <= 0) continue;
+        double p = t->bind[zc][s] - dE[zc];
+        if (p < 1.0) p = 1.0;
+        if (!(e > p)) continue;
+        double lnp = orc_log(p);
+        double term = (((t->lotz_a[s] * 1.0e-4) * (double)occ[s]) * (lne - lnp)) / (e * p);
+        if (t->lotz_b[s] != 0.0)
+            term = term * (1.0 - t->lotz_b[s] * orc_exp(-(t->lotz_c[s] * (e / p - 1.0))));
+        sig = sig + term;
+    }
+    return sig;
+}
+
+/* Zbar_EOS(n_i, T): bilinear in (ln n_i, ln T) on the table grid, clamped. */
+double orc_eos(const orc_tables *t, double n_i, double tev)
+{
+    double u = (orc_log(n_i) - t->eos_lnn0) / t->eos_dlnn;
+    double v = (orc_log(tev) - t->eos_lnt0) / t->eos_dlnt;
+    int nn = t->eos_nn, nt = t->eos_nt;
+    double fu = floor(u), fv = floor(v);
+    int iu = (int)fu, iv = (int)fv;
+    double au = u - fu, av = v - fv;
+    if (u < 0.0) { iu = 0; au = 0.0; }
+    if (v < 0.0) { iv = 0; av = 0.0; }
+    if (iu > nn - 2) { iu = nn - 2; au = 1.0; }
+    if (iv > nt - 2) { iv = nt - 2; av = 1.0; }
+    const double *z = t->eos_zbar;
+    double z00 = z[iu * nt + iv], z01 = z[iu * nt + iv + 1];
+    double z10 = z[(iu + 1) * nt + iv], z11 = z[(iu + 1) * nt + iv + 1];
+    double a = (1.0 - av) * z00 + av * z01;
+    double b = (1.0 - av) * z10 + av * z11;
+    return (1.0 - au) * a + au * b;
+}
+
+/* Neutral-atom subshell photoionization cross section per electron, m^2
+ * (Sec. III, Fig. 2a): linear interpolation in ln sigma vs ln hv, clamped. */
+double orc_photo_sigma(const orc_tables *t, int32_t s, double hv)
+{
+    double u = (orc_log(hv) - t->photo_lnhv0) / t->photo_dlnhv;
+    double fu = floor(u);
+    int iu = (int)fu;
+    double a = u - fu;
+    if (u < 0.0) { iu = 0; a = 0.0; }
+    if (iu > t->photo_nh - 2) { iu = t->photo_nh - 2; a = 1.0; }
+    double l0 = t->photo_lnsig[s][iu], l1 = t->photo_lnsig[s][iu + 1];
+    double ls = l0 + a * (l1 - l0);
+    return orc_exp(ls) * 1.0e-4;
+}
+
+/*
+ * One binary Coulomb collision (Takizuka & Abe, J. Comput. Phys. 25, 205
+ * (1977)), non-relativistic, with weighted acceptance.
+ *   qq_coef = q_a^2 q_b^2 lnL dt / (8 pi eps0^2 m_ab^2)  (per unit density),
+ *   <delta^2> = qq_coef * max(w_a, w_b) * nunit / u^3,
+ *   delta = sqrt(<delta^2>) * sqrt(-2 ln r1) cos(2 pi r2), Phi = 2 pi r3,
+ *   sin(Theta) = 2 delta/(1+delta^2), 1 - cos(Theta) = 2 delta^2/(1+delta^2);
+ *   the heavier-weight side accepts with probability w_light / w_heavy (r4).
+ * draws = Philox words: [0..1] -> r1, [2] -> r2 angle, [3] -> Phi angle.
+ * Returns <delta^2>, or -1 when the relative velocity is zero (no collision).
+ */
+double orc_ta77(double va[3], double vb[3], double ma, double mb, uint32_t wa,
+              uint32_t wb, double qq_coef, double nunit, const uint32_t draws[4],
+              double r4, int32_t *acc_a, int32_t *acc_b)
+{
+    double ux = va[0] - vb[0], uy = va[1] - vb[1], uz = va[2] - vb[2];
+    double u2 = (ux * ux + uy * uy) + uz * uz;
+    *acc_a = 0;
+    *acc_b = 0;
+    if (u2 == 0.0) return -1.0;
+    uint32_t wmax = wa > wb ? wa : wb;
+    double u = sqrt(u2);
+    double d2 = ((qq_coef * (double)wmax) * nunit) / (u2 * u);
+    double r1 = orc_u52(draws[0], draws[1]);
+    double s2, c2;
+    orc_sincos2pi((uint64_t)draws[2] << 20, &s2, &c2);
+    double g = sqrt(-2.0 * orc_log(r1)) * c2;
+    double d = sqrt(d2) * g;
+    double dd = d * d;
+    double den = 1.0 + dd;
+    double st = (2.0 * d) / den;
+    double omc = (2.0 * dd) / den;
+    double sp, cp;
+    orc_sincos2pi((uint64_t)draws[3] << 20, &sp, &cp);
+    double a = st * cp;
+    double bb = st * sp;
+    double up = sqrt(ux * ux + uy * uy);
+    double dux, duy, duz;
+    if (up > 0.0) {
+        dux = ((ux / up) * uz) * a - ((uy / up) * u) * bb - ux * omc;
+        duy = ((uy / up) * uz) * a + ((ux / up) * u) * bb - uy * omc;
+        duz = -(up * a) - uz * omc;
+    } else {
+        double auz = fabs(uz);
+        dux = auz * a;
+        duy = auz * bb;
+        duz = -(uz * omc);
+    }
+    int ta = (wa <= wb) || (r4 < (double)wb / (double)wa);
+    int tb = (wb <= wa) || (r4 < (double)wa / (double)wb);
+    double fa = mb / (ma + mb);
+    double fb = ma / (ma + mb);
+    if (ta) {
+        va[0] = va[0] + fa * dux;
+        va[1] = va[1] + fa * duy;
+        va[2] = va[2] + fa * duz;
+    }
+    if (tb) {
+        vb[0] = vb[0] - fb * dux;
+        vb[1] = vb[1] - fb * duy;
+        vb[2] = vb[2] - fb * duz;
+    }
+    *acc_a = ta;
+    *acc_b = tb;
+    return d2;
+}

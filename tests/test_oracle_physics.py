@@ -1,0 +1,251 @@
+"""Pins of the oracle's single-physics functions.
+
+* Takizuka-Abe binary collision: exact momentum and energy conservation for
+  equal weights, |u'| = |u|, and the scattering angle Theta with
+  tan(Theta/2) = delta; the u_perp = 0 branch.
+* Continuum lowering (Sec. V, Eq. 5-6): Stewart-Pyatt reduces to Debye-Hueckel
+  for small K and to the ion-sphere result for large K; Ecker-Kroll switches to
+  Debye-Hueckel below its critical density and scales as (Z+1) n^(1/3) above it;
+  at 100 eV solid Al with Zbar = 7, EK exceeds SP at high charge (Fig. 4).
+* Lotz cross section (Eq. 4): its Maxwellian rate equals the closed form
+  a N vbar E1(P/T) / (P T) (scipy's exponential integral).
+* Table interpolation reproduces the tabulated nodes.
+"""
+
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+QE = 1.602176634e-19
+ME = 9.1093837015e-31
+EPS0 = 8.8541878128e-12
+E2 = QE / (4 * math.pi * EPS0)  # eV m
+
+
+def _words(rng):
+    return rng.integers(0, 1 << 32, 4, dtype=np.uint64).astype(np.uint32)
+
+
+def test_ta77_conservation_equal_weights(orc):
+    rng = np.random.default_rng(21)
+    mi = 26.98 * 1.66053906660e-27
+    worst_p = worst_e = worst_u = worst_th = 0.0
+    for trial in range(3000):
+        ma, mb = (ME, ME) if trial % 2 == 0 else (ME, mi)
+        va = rng.normal(0, 2e6, 3)
+        vb = rng.normal(0, 2e6 if mb == ME else 2e4, 3)
+        coef = 10 ** rng.uniform(-60, -52)
+        d = _words(rng)
+        va2, vb2, d2, aa, ab = orc.ta77(va, vb, ma, mb, 3, 3, coef, 1e28, d)
+        assert aa == 1 and ab == 1
+        p0 = ma * va + mb * vb
+        p1 = ma * va2 + mb * vb2
+        scale = ma * np.abs(va).max() + mb * np.abs(vb).max()
+        worst_p = max(worst_p, np.abs(p1 - p0).max() / scale)
+        e0 = ma * va @ va + mb * vb @ vb
+        e1 = ma * va2 @ va2 + mb * vb2 @ vb2
+        worst_e = max(worst_e, abs(e1 - e0) / e0)
+        u, u2 = va - vb, va2 - vb2
+        worst_u = max(worst_u, abs(np.linalg.norm(u2) - np.linalg.norm(u)) / np.linalg.norm(u))
+        # scattering angle: tan(Theta/2) = |delta|
+        r1 = orc.u52(d[0], d[1])
+        c2 = orc.sincos2pi(int(d[2]) << 20)[1]
+        delta = math.sqrt(d2) * math.sqrt(-2 * math.log(r1)) * c2
+        th = 2 * math.atan(abs(delta))
+        cos_th = float(u @ u2) / (np.linalg.norm(u) * np.linalg.norm(u2))
+        worst_th = max(worst_th, abs(math.acos(max(-1.0, min(1.0, cos_th))) - th))
+    assert worst_p < 1e-15
+    assert worst_e < 1e-14
+    assert worst_u < 1e-14
+    assert worst_th < 1e-6
+
+
+def test_ta77_uperp_zero_branch(orc):
+    rng = np.random.default_rng(22)
+    for _ in range(50):
+        va = np.array([0.0, 0.0, 3e6])
+        vb = np.array([0.0, 0.0, -1e6])
+        d = _words(rng)
+        va2, vb2, d2, aa, ab = orc.ta77(va, vb, ME, ME, 1, 1, 1e-55, 1e28, d)
+        assert d2 > 0
+        assert np.allclose(va + vb, va2 + vb2, rtol=0, atol=1e-9)
+        assert abs(va2 @ va2 + vb2 @ vb2 - (va @ va + vb @ vb)) < 1e-14 * (va @ va)
+        assert abs(np.linalg.norm(va2 - vb2) - 4e6) < 1e-8
+
+
+def test_ta77_zero_relative_velocity(orc):
+    v = np.array([1e5, -2e5, 3e5])
+    va2, vb2, d2, aa, ab = orc.ta77(v, v, ME, ME, 1, 1, 1e-55, 1e28,
+                                    np.array([1, 2, 3, 4], dtype=np.uint32))
+    assert d2 == -1.0
+    assert np.array_equal(va2, v) and np.array_equal(vb2, v)
+
+
+def test_ta77_weighted_acceptance_rates(orc):
+    # The heavier macro-particle accepts with probability w_light / w_heavy.
+    rng = np.random.default_rng(23)
+    acc_a = acc_b = 0
+    n = 20000
+    for _ in range(n):
+        r4 = rng.uniform()
+        _, _, _, aa, ab = orc.ta77(np.array([1e6, 0, 0]), np.array([0, 1e6, 0.0]), ME, ME,
+                                   3, 1, 1e-55, 1e28, _words(rng), r4)
+        acc_a += aa
+        acc_b += ab
+    assert acc_b == n
+    assert abs(acc_a / n - 1 / 3) < 5 * math.sqrt(2 / 9 / n)
+
+
+def _lam_d(t, ne, zbar):
+    return math.sqrt(EPS0 * t / (QE * ne * (zbar + 1)))
+
+
+def test_ipd_sp_debye_huckel_limit(orc):
+    # low density, high T: K << 1 -> Delta E = (z+1) e^2 / (4 pi eps0 lambda_D)
+    # (K between 1e-5 and 1e-3; the formula's own cancellation, ~1e-16/K,
+    # stays far below the second-order term)
+    t, ne, zbar = 2000.0, 1e26, 5.0
+    for z in range(13):
+        dh = (z + 1) * E2 / _lam_d(t, ne, zbar)
+        sp = orc.ipd(0, z, t, ne, ne / zbar, zbar, zbar)
+        k = (z + 1) * E2 / (_lam_d(t, ne, zbar) * t)
+        assert 1e-5 < k < 1e-3
+        # next order of [1 + 3(z*+1)K]^(2/3): relative -(z*+1) K / 2
+        assert sp == pytest.approx(dh * (1 - (zbar + 1) * k / 2), rel=20 * ((zbar + 1) * k) ** 2)
+
+
+def test_ipd_sp_ion_sphere_limit(orc):
+    # high density, low T: K >> 1 -> Delta E = (3/2) (z+1)^(2/3) e^2/(4 pi eps0)
+    # (4 pi n_e / 3)^(1/3) when z* = Zbar (ion-sphere / Zimmerman-More form)
+    t, ne, zbar = 0.1, 3e29, 5.0
+    for z in range(13):
+        k = (z + 1) * E2 / (_lam_d(t, ne, zbar) * t)
+        assert k > 1e3
+        ion_sphere = 1.5 * (z + 1) ** (2 / 3) * E2 * (4 * math.pi * ne / 3) ** (1 / 3)
+        sp = orc.ipd(0, z, t, ne, ne / zbar, zbar, zbar)
+        # next order: -kT/(2(z*+1)) and (1 + 1/(3(z*+1)K))^(2/3) corrections
+        assert sp == pytest.approx(ion_sphere, rel=3.0 / k ** (2 / 3) + 1e-9)
+
+
+def test_ipd_ek_branches(orc):
+    n_i, zbar, t = 6.0e28, 3.0, 10.0
+    ne = zbar * n_i
+    vals = [orc.ipd(1, z, t, ne, n_i, zbar, zbar) for z in range(13)]
+    # above the critical density: proportional to (z+1)
+    for z in range(13):
+        assert vals[z] / (z + 1) == pytest.approx(vals[0], rel=1e-13)
+    # scaling with total density n^(1/3)
+    v8 = orc.ipd(1, 3, t, 8 * ne, 8 * n_i, zbar, zbar)
+    assert v8 == pytest.approx(2 * vals[3], rel=1e-13)
+    # solid Al3+ at 10 eV: (z+1) e^2 / (4 pi eps0 r_EK), r_EK = (3 / 4 pi n)^(1/3)
+    r = (3 / (4 * math.pi * (ne + n_i))) ** (1 / 3)
+    assert vals[3] == pytest.approx(4 * E2 / r, rel=1e-13)
+    assert 57.5 < vals[3] < 57.9
+    # below the critical density the shift is Debye-Hueckel
+    t_hot, ne_lo = 50.0, 1.8e27
+    n_lo = ne_lo / 3
+    ncrit = 3 / (4 * math.pi) * (t_hot / (4 ** 2 * E2)) ** 3
+    assert ne_lo + n_lo < ncrit
+    dh = 4 * E2 / _lam_d(t_hot, ne_lo, 3.0)
+    assert orc.ipd(1, 3, t_hot, ne_lo, n_lo, 3.0, 3.0) == pytest.approx(dh, rel=1e-13)
+
+
+def test_ipd_ek_exceeds_sp_at_high_charge(orc):
+    # Fig. 4: 100 eV solid Al with Zbar = 7: |dE_EK| >> |dE_SP| at high charge
+    n_i = 6.0e28
+    ne = 7 * n_i
+    ek = [orc.ipd(1, z, 100.0, ne, n_i, 7.0, 7.0) for z in range(13)]
+    sp = [orc.ipd(0, z, 100.0, ne, n_i, 7.0, 7.0) for z in range(13)]
+    assert all(ek[z] > sp[z] for z in range(6, 13))
+    assert ek[12] > 1.3 * sp[12]
+    assert all(np.diff(sp) > 0)
+    # z = 0, 1 fall below their critical density at 100 eV (Debye-Hueckel
+    # branch); from z = 2 on the Ecker-Kroll form (z+1) e^2/(4 pi eps0 r_EK) holds
+    assert all(np.diff(ek[2:]) > 0)
+    assert ek[2] / 3 == pytest.approx(ek[12] / 13, rel=1e-13)
+
+
+def test_lotz_maxwell_rate_closed_form(orc, tables):
+    T = orc.Tables(tables)
+    dE = np.zeros(13)
+    dE[3] = 57.7
+    for tev in (10.0, 50.0, 200.0, 1000.0):
+        for zc in (3, 7, 11):
+            occ = orc.occupancy(zc)
+            m = ME
+            vbar = math.sqrt(8 * tev * QE / (math.pi * m))
+
+            def integrand(e):
+                f = 2 * math.sqrt(e / math.pi) * tev ** -1.5 * math.exp(-e / tev)
+                return T.lotz(zc, dE, e) * math.sqrt(2 * e * QE / m) * f
+
+            edges = sorted({max(tables.bind[zc, s] - dE[zc], 1.0) for s in range(5) if occ[s] > 0})
+            pts = [0.0] + edges + [edges[-1] + 60 * tev]
+            num = sum(integrate.quad(integrand, a, b, limit=200, epsrel=1e-11)[0]
+                      for a, b in zip(pts[:-1], pts[1:]))
+            ref = 0.0
+            for s in range(5):
+                if occ[s] == 0:
+                    continue
+                p = max(tables.bind[zc, s] - dE[zc], 1.0)
+                ref += tables.lotz_a[s] * 1e-4 * occ[s] * vbar / (p * tev) * special.exp1(p / tev)
+            assert num == pytest.approx(ref, rel=1e-7), (tev, zc)
+
+
+def test_lotz_threshold_and_shape(orc, tables):
+    T = orc.Tables(tables)
+    dE = np.zeros(13)
+    p2p = tables.bind[3, 2]
+    assert T.lotz(3, dE, p2p * 0.999) == 0.0 or T.lotz(3, dE, p2p * 0.999) < 1e-30
+    assert T.lotz(3, dE, p2p * 1.001) > 0.0
+    assert T.lotz(13, dE, 1e4) == 0.0
+    # lowering increases the cross section (Fig. 3a)
+    dE2 = dE.copy()
+    dE2[3] = 57.7
+    assert T.lotz(3, dE2, 500.0) > T.lotz(3, dE, 500.0)
+
+
+def test_occupancy_rules(orc):
+    for z in range(14):
+        for k in range(3):
+            occ = orc.occupancy(z, k)
+            nb = 13 - z
+            assert occ.sum() == nb
+            assert occ[0] <= 2 - k or nb < 2 - k
+            assert (occ <= np.array([2, 2, 6, 2, 6])).all()
+    assert list(orc.occupancy(3, 0)) == [2, 2, 6, 0, 0]
+    assert list(orc.occupancy(3, 1)) == [1, 2, 6, 1, 0]
+    assert list(orc.occupancy(11, 0)) == [2, 0, 0, 0, 0]
+    assert list(orc.occupancy(12, 1)) == [1, 0, 0, 0, 0]
+
+
+def test_eos_and_sigma_tables(orc, tables):
+    T = orc.Tables(tables)
+    nt = tables.eos_zbar.shape[1]
+    for j in range(0, nt, 7):
+        t = math.exp(tables.eos_lnt0 + j * tables.eos_dlnt)
+        for n in (1e26, 6e28, 1e30, 1e31, 1e20):
+            assert T.eos(n, t) == pytest.approx(tables.eos_zbar[0, j], rel=1e-12, abs=1e-12)
+    assert T.eos(6e28, 1e-5) == pytest.approx(tables.eos_zbar[0, 0])
+    assert T.eos(6e28, 1e6) == pytest.approx(tables.eos_zbar[0, -1])
+    # the synthetic EOS passes the paper's state point 100 eV <-> Zbar 7 (Sec. V)
+    assert T.eos(6e28, 100.0) == pytest.approx(7.0, abs=0.02)
+    nh = tables.photo_lnsig.shape[1]
+    for h in range(0, nh, 5):
+        hv = math.exp(tables.photo_lnhv0 + h * tables.photo_dlnhv)
+        for s in range(3):
+            assert T.photo_sigma(s, hv) == pytest.approx(
+                math.exp(tables.photo_lnsig[s, h]) * 1e-4, rel=1e-12)
+    # K shell an order of magnitude above L per electron above the K edge (Sec. III)
+    assert T.photo_sigma(0, 1850.0) > 10 * T.photo_sigma(2, 1850.0)
+
+
+def test_coulomb_log_limits(orc):
+    assert orc.coulomb_log(10.0, 0.0, 3.0) == 2.0
+    assert orc.coulomb_log(1.0, 1e31, 3.0) == 2.0
+    hot = orc.coulomb_log(5000.0, 1e25, 1.0)
+    # classical weakly coupled limit: ~ ln(lambda_D / b) >> 2
+    assert hot > 8
+    assert orc.coulomb_log(5000.0, 1e25, 1.0) > orc.coulomb_log(5000.0, 1e27, 1.0)

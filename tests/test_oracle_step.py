@@ -1,0 +1,294 @@
+"""Whole-step pins of the oracle: statistics against closed forms and exact
+conservation laws.
+
+* e-i temperature relaxation against the Spitzer rate (ODE integrated here).
+* collisional ionization: the cell-average probability equals n_e <sigma v> dt
+  of the Lotz cross section for a Maxwellian (E1 closed form), and the number
+  of fired ions is binomial with that probability (Sec. IV).
+* three-body recombination: the number of recombinations is the closed form
+  floor(SZ - W_i Zbar_EOS + 1/2), capped by the eligible ions, and the cell
+  charge lands within 1/(2 W_i) of Zbar_EOS (Sec. IV).
+* K-vacancy decay: frequency dt/tau_K, Auger branch 1 - omega_K, Auger energy
+  E_Kalpha - mean lowered L binding (Sec. III).
+* photoionization: frequency of Eq. 3 per subshell, photon-bin selection
+  proportional to n sigma, photoelectron energy hv - lowered binding (Sec. III).
+* conservation per step: charge neutrality (exact integers), energy ledger,
+  momentum; independence of the thread count.
+"""
+
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+from paper_1704_01202_amd import workloads as W
+from tests import cases
+
+QE, ME = cases.QE, cases.ME
+C_LIGHT = 299792458.0
+
+
+def _temps(st, mass_ion):
+    ke, ki = cases.kinetic(st, mass_ion)
+    return 2.0 * ke / (3.0 * st.ew.sum()), 2.0 * ki / (3.0 * st.iz.size)
+
+
+def _relax_ratio(orc, tab, mi, fac, nsteps, seed):
+    n_i, te0, ti0, lnl = 1.0e27, 200.0, 20.0, 10.0
+    e2 = QE * QE / (4 * math.pi * 8.8541878128e-12)
+
+    def nu(te, ti):
+        # Spitzer / NRL electron-ion energy-equilibration rate, SI form
+        return (8 * math.sqrt(2 * math.pi) / 3) * n_i * e2 ** 2 * lnl * math.sqrt(ME * mi) / (
+            (mi * te * QE + ME * ti * QE) ** 1.5)
+
+    dt = fac / nu(te0, ti0)
+    spec, parts = cases.one_run(32, 2000, 2000, te0, ti0, z0=1, e_weight=1, n_i=n_i, dt=dt,
+                                lnl=lnl, mass_ion=mi, seed=seed)
+    sim = orc.Sim(tab, spec)
+    sim.bin(parts)
+    te, ti = _temps(sim.state(), mi)
+    for s in range(nsteps):
+        sim.step(s, orc.EI)
+    te2, _ = _temps(sim.state(), mi)
+    return (te2 - te) / (-nu(te, ti) * (te - ti) * dt * nsteps)
+
+
+def test_spitzer_relaxation(orc, tables):
+    """Electron-ion energy exchange of the binary-collision step against the
+    Spitzer rate.  Takizuka-Abe pairing reproduces Spitzer as dt -> 0, with an
+    error that grows like (nu_ei dt)^(1/3) (slow pairs saturate the angle);
+    here nu_ei dt = 0.005 and 0.04."""
+    mi = 100.0 * ME
+    tab = cases.tables_with(tables, mass_ion=mi)
+    r_small = _relax_ratio(orc, tab, mi, 1.0e-4, 100, 31)
+    r_large = _relax_ratio(orc, tab, mi, 8.0e-4, 30, 31)
+    assert 0.84 < r_small < 1.04, r_small
+    assert r_large < r_small
+    growth = (1 - r_large) / (1 - r_small)
+    assert 1.4 < growth < 4.5, (r_small, r_large)
+
+
+def _lotz_rate(tables, zc, dE, tev):
+    occ = W.ground_occupancy(zc)
+    vbar = math.sqrt(8 * tev * QE / (math.pi * ME))
+    r = 0.0
+    for s in range(5):
+        if occ[s] == 0:
+            continue
+        p = max(tables.bind[zc, s] - dE, 1.0)
+        r += tables.lotz_a[s] * 1e-4 * occ[s] * vbar / (p * tev) * special.exp1(p / tev)
+    return r
+
+
+def test_ionization_probability_and_count(orc, tables):
+    spec, parts = cases.one_run(1, 30000, 10000, 60.0, 0.1, seed=32, dt=0.05e-15, e_weight=1)
+    sim = orc.Sim(tables, spec)
+    sim.bin(parts)
+    st0 = sim.state()
+    ke0, _ = cases.kinetic(st0, tables.mass_ion)
+    tsample = 2.0 * ke0 / (3.0 * st0.ew.sum())
+    sim.step(0, orc.ION)
+    m = sim.moments()[0]
+    cnt, led = sim.counters()
+    n_e = st0.ew.sum() * spec.w0 / spec.volume
+    p_cf = n_e * _lotz_rate(tables, 3, m[16 + 3], tsample) * spec.dt
+    p = m[12]
+    assert 0.01 < p < 0.5
+    assert p == pytest.approx(p_cf, rel=0.05)
+    c = dict(zip(orc.COUNTERS, cnt[0]))
+    n = 10000
+    assert abs(c["ION_FIRED"] - n * p) < 5 * math.sqrt(n * p * (1 - p))
+    assert c["ION_ACCEPTED"] == c["ION_FIRED"] and c["ION_STARVED"] == 0
+    st1 = sim.state()
+    assert int((st1.iz == 4).sum()) == c["ION_ACCEPTED"]
+    assert st1.ew.size == st0.ew.size + c["ION_ACCEPTED"]
+    # new electrons sit at their ion's position with zero velocity
+    assert np.all(st1.evx[st0.ew.size:] == 0.0)
+    # the debit equals the summed lowered potentials and the electrons paid it
+    ke1, _ = cases.kinetic(st1, tables.mass_ion)
+    ip = max(tables.bind[3, 2] - m[16 + 3], 1.0)
+    assert led[0, 2] == pytest.approx(c["ION_ACCEPTED"] * ip, rel=1e-12)
+    assert ke0 - ke1 == pytest.approx(led[0, 2], rel=1e-9)
+
+
+def test_recombination_capped_and_exact(orc, tables):
+    # all ions Al8+ at 10 eV: Zbar_EOS(10 eV) ~ 3.6, recombination capped by the
+    # eligible-ion count (each ion recombines at most once per step)
+    spec, parts = cases.one_run(1, 8000, 1000, 10.0, 0.1, z0=8, e_weight=1, seed=33)
+    sim = orc.Sim(tables, spec)
+    sim.bin(parts)
+    st0 = sim.state()
+    ke0, ki0 = cases.kinetic(st0, tables.mass_ion)
+    sim.step(0, orc.REC)
+    cnt, led = sim.counters()
+    c = dict(zip(orc.COUNTERS, cnt[0]))
+    st1 = sim.state()
+    assert c["REC"] == 1000 and c["E_REMOVED"] == 1000
+    assert np.all(st1.iz == 7)
+    assert int(st1.ew.sum()) - int(st1.iz.astype(np.int64).sum()) == \
+        int(st0.ew.sum()) - int(st0.iz.astype(np.int64).sum())
+    ke1, ki1 = cases.kinetic(st1, tables.mass_ion)
+    assert (ke1 + ki1) - (ke0 + ki0) == pytest.approx(led[0, 4], rel=1e-10)
+    # momentum conserved (electron unit momentum handed to the ion)
+    p0, sc = cases.momentum(st0, tables.mass_ion)
+    p1, _ = cases.momentum(st1, tables.mass_ion)
+    assert np.abs(p1 - p0).max() < 1e-12 * sc
+
+
+def test_recombination_closed_form_count(orc, tables):
+    rng = np.random.default_rng(34)
+    spec, parts = cases.one_run(1, 3300, 1000, 0.754, 0.01, z0=3, e_weight=1, seed=34)
+    parts.iz[:300] = 4
+    sim = orc.Sim(tables, spec)
+    sim.bin(parts)
+    st0 = sim.state()
+    ke0, _ = cases.kinetic(st0, tables.mass_ion)
+    t = 2.0 * ke0 / (3.0 * st0.ew.sum())
+    T = orc.Tables(tables)
+    n_i = 1000 * spec.w0 / spec.volume
+    zeos = T.eos(n_i, t)
+    d = 3300 - 1000 * zeos
+    nrec = int(math.floor(d + 0.5))
+    assert 0 < nrec < 300
+    sim.step(0, orc.REC)
+    cnt, _ = sim.counters()
+    c = dict(zip(orc.COUNTERS, cnt[0]))
+    assert c["REC"] == nrec
+    zbar = sim.state().iz.astype(np.int64).sum() / 1000.0
+    assert abs(zbar - zeos) <= 0.5 / 1000 + 1e-12
+
+
+def test_decay_and_auger_statistics(orc, tables):
+    n = 20000
+    spec, parts = cases.one_run(1, 3 * n, n, 10.0, 0.1, k0=1, seed=35, dt=0.1e-15)
+    sim = orc.Sim(tables, spec)
+    sim.bin(parts)
+    st0 = sim.state()
+    sim.step(0, orc.DECAY)
+    cnt, led = sim.counters()
+    c = dict(zip(orc.COUNTERS, cnt[0]))
+    ga, gx = tables.gamma_a[3, 1], tables.gamma_x[3, 1]
+    p = spec.dt_rad * (ga + gx)
+    assert abs(c["DECAY"] - n * p) < 5 * math.sqrt(n * p * (1 - p))
+    pa = ga / (ga + gx)
+    nd = c["DECAY"]
+    assert abs(c["AUGER"] - nd * pa) < 5 * math.sqrt(nd * pa * (1 - pa))
+    assert c["AUGER"] + c["KALPHA"] == nd
+    st1 = sim.state()
+    assert int((st1.ik == 0).sum()) == nd
+    assert int((st1.iz == 4).sum()) == c["AUGER"]
+    # Auger electrons: E = E_Kalpha - (n2s P'2s + n2p P'2p) / (n2s + n2p)
+    m = sim.moments()[0]
+    occ = W.ground_occupancy(3, 1)
+    p2s = max(tables.bind[3, 1] - m[16 + 3], 1.0)
+    p2p = max(tables.bind[3, 2] - m[16 + 3], 1.0)
+    ea = tables.e_kalpha[3] - (occ[1] * p2s + occ[2] * p2p) / (occ[1] + occ[2])
+    new = slice(st0.ew.size, st1.ew.size)
+    e_new = 0.5 * ME * (st1.evx[new] ** 2 + st1.evy[new] ** 2 + st1.evz[new] ** 2) / QE
+    assert e_new.size == c["AUGER"]
+    assert np.allclose(e_new, ea, rtol=1e-12)
+    assert 1.3e3 < ea < 1.5e3  # KLL Auger near 1.4 keV (Sec. VI.B)
+    # isotropic directions
+    mu = st1.evz[new] / np.sqrt(2 * ea * QE / ME)
+    assert abs(mu.mean()) < 5 / math.sqrt(3 * mu.size)
+
+
+def test_photoionization_statistics(orc, tables):
+    n = 20000
+    hv = (1700.0, 1850.0, 2500.0)
+    nhv = (1e29, 2e29, 1.5e29)
+    spec, parts = cases.one_run(1, 3 * n, n, 10.0, 0.1, seed=36, dt=0.1e-15,
+                                photon_hv=hv, photon_n=nhv)
+    sim = orc.Sim(tables, spec)
+    sim.bin(parts)
+    st0 = sim.state()
+    sim.step(0, orc.PHOTO)
+    cnt, led = sim.counters()
+    c = dict(zip(orc.COUNTERS, cnt[0]))
+    m = sim.moments()[0]
+    T = orc.Tables(tables)
+    occ = W.ground_occupancy(3, 0)
+    ps = []
+    for s, name in enumerate(("PHOTO_1S", "PHOTO_2S", "PHOTO_2P")):
+        pp = max(tables.bind[3, s] - m[16 + 3], 1.0)
+        tot = sum(nh * T.photo_sigma(s, h) for h, nh in zip(hv, nhv) if h >= pp)
+        p = C_LIGHT * spec.dt_rad * occ[s] * tot  # Eq. 3
+        ps.append(p)
+        assert abs(c[name] - n * p) < 5 * math.sqrt(n * p * (1 - p)) + 1, name
+    assert c["PHOTO_1S"] > 500
+    # bin selection of K-shell events follows n_i sigma_i (chi^2, 2 dof)
+    pp1 = max(tables.bind[3, 0] - m[16 + 3], 1.0)
+    st1 = sim.state()
+    new = slice(st0.ew.size, st1.ew.size)
+    e_new = 0.5 * ME * (st1.evx[new] ** 2 + st1.evy[new] ** 2 + st1.evz[new] ** 2) / QE
+    k_events = [int(np.isclose(e_new, h - pp1, rtol=1e-12).sum()) for h in hv]
+    assert sum(k_events) == c["PHOTO_1S"]
+    w = np.array([nh * T.photo_sigma(0, h) for h, nh in zip(hv, nhv)])
+    expct = c["PHOTO_1S"] * w / w.sum()
+    chi2 = (((np.array(k_events) - expct) ** 2) / expct).sum()
+    assert chi2 < 18
+    # every photoelectron energy is hv_i - P'_s for one of the bins and subshells
+    allowed = np.array([h - max(tables.bind[3, s] - m[16 + 3], 1.0) for h in hv for s in range(3)])
+    assert np.all(np.min(np.abs(e_new[:, None] / allowed[None, :] - 1), axis=1) < 1e-12)
+    # absorbed photon energy minus photoelectron energy = the lowered bindings paid
+    paid = sum(c[nm] * max(tables.bind[3, s] - m[16 + 3], 1.0)
+               for s, nm in enumerate(("PHOTO_1S", "PHOTO_2S", "PHOTO_2P")))
+    assert led[0, 6] - led[0, 0] == pytest.approx(paid, rel=1e-9)
+    assert int((st1.ik == 1).sum()) == c["PHOTO_1S"]
+
+
+def test_conservation_ledger_equal_weights(orc, tables):
+    # unit weights everywhere: every collision conserves energy and momentum
+    spec, parts = cases.one_run(4, 600, 200, 30.0, 0.5, e_weight=1, seed=37, dt=0.05e-15,
+                                photon_hv=(1850.0,), photon_n=(3e29,))
+    sim = orc.Sim(tables, spec)
+    sim.bin(parts)
+    st = sim.state()
+    mi = tables.mass_ion
+    q0 = int(st.ew.sum()) - int(st.iz.astype(np.int64).sum())
+    for s in range(8):
+        ke0, ki0 = cases.kinetic(st, mi)
+        p0, sc = cases.momentum(st, mi)
+        flags = orc.ALL if s % 2 == 0 else (orc.EE | orc.EI | orc.ION | orc.REC)
+        sim.step(s, flags)
+        cnt, led = sim.counters()
+        st = sim.state()
+        ke1, ki1 = cases.kinetic(st, mi)
+        tot = led.sum(0)
+        src = tot[0] + tot[1] - tot[2] + tot[4]
+        assert (ke1 + ki1) - (ke0 + ki0) == pytest.approx(src, abs=1e-11 * (ke0 + ki0))
+        assert int(st.ew.sum()) - int(st.iz.astype(np.int64).sum()) == q0
+        if not flags & (orc.PHOTO | orc.DECAY):
+            p1, _ = cases.momentum(st, mi)
+            assert np.abs(p1 - p0).max() < 1e-12 * sc
+        c = dict(zip(orc.COUNTERS, cnt.sum(0)))
+        assert c["E_NEW"] == c["ION_ACCEPTED"] + c["AUGER"] + c["PHOTO_1S"] + c["PHOTO_2S"] + \
+            c["PHOTO_2P"]
+
+
+def test_thread_count_invariance(orc, tables):
+    spec, parts = W.config_c1(ncells=16)
+    res = []
+    for nt in (1, 3, 8):
+        sim = orc.Sim(tables, spec)
+        sim.bin(parts)
+        for s in range(6):
+            sim.step(s, orc.ALL, nt)
+        st = sim.state()
+        res.append((st.evx.copy(), st.ivz.copy(), st.iz.copy(), st.e_start.copy()))
+    for r in res[1:]:
+        for a, b in zip(res[0], r):
+            assert np.array_equal(a, b)
+
+
+def test_binning_is_stable(orc, tables):
+    spec, parts = W.config_c1(ncells=8)
+    sim = orc.Sim(tables, spec)
+    sim.bin(parts)
+    st = sim.state()
+    cid = np.floor((parts.ex - spec.x0) / spec.dx).astype(np.int64)
+    order = np.argsort(cid, kind="stable")
+    assert np.array_equal(st.evx, parts.evx[order])
+    assert np.array_equal(st.e_start, np.concatenate([[0], np.cumsum(np.bincount(cid, minlength=8))]))
