@@ -1,0 +1,157 @@
+"""Throughput of the per-cell Monte-Carlo collision / ionization step on one MI355X.
+
+Workload: 2D uniform solid-Al target, 512 x 512 PIC cells x (64 electrons +
+64 Al3+ ions) = 33.5 M particles, FP64, Ecker-Kroll continuum lowering,
+dt = 0.05 fs, photoionization by a uniform 1.7e17 W/cm^2, 1.85 keV flux fused
+into every step (synthetic inputs, seeded).
+
+A step is one pass of the whole hot path over every cell: moments and
+continuum lowering, e-e and e-i binary collisions, collisional ionization,
+three-body recombination, K-vacancy decay and photoionization, with appends
+and removals, through `collide_ionize_step` (the slabs were filled by
+`bin_particles` before the timed region, outside the step).
+
+Prints one JSON line: binary collisions per second (whole job), the roofline
+of the step kernel (algorithmic HBM bytes / its average duration from HIP
+events on its stream), and the CPU oracle timed on a bounded sample.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+E_BYTES = 52      # electron per step: v read + write (48 B), weight read (4 B)
+I_BYTES = 52      # ion per step: v read + write (48 B), Z and k read + write (4 B)
+NEW_BYTES = 44    # appended electron: x, y, v (40 B) and weight (4 B) written
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(steps=4, nx=96, ny=96):
+    """The oracle on a bounded sample of the same workload (nx x ny cells)."""
+    from oracle import oracle as O
+    from paper_1704_01202_amd import workloads as W
+    tab = W.make_tables()
+    spec, parts = W.config_c2(nx=nx, ny=ny)
+    sim = O.Sim(tab, spec)
+    sim.bin(parts)
+    threads = os.cpu_count() or 1
+    coll = 0
+    t0 = time.perf_counter()
+    for s in range(steps):
+        sim.step(s, O.ALL, threads)
+        cnt, _ = sim.counters()
+        coll += int(cnt[:, 0].sum() + cnt[:, 1].sum() + cnt[:, 2].sum())
+    dt = time.perf_counter() - t0
+    return {"value": coll / dt, "unit": "collisions/s", "cores": threads, "kind": "oracle",
+            "sample": "%dx%d cells of the same workload, %d steps from the initial state, "
+                      "%.1f s" % (nx, ny, steps, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--nx", type=int, default=512)
+    ap.add_argument("--ny", type=int, default=512)
+    ap.add_argument("--schedule", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the step has no cross-GPU work here and only "
+              "--gpus 1 is supported (see DESIGN.md for how runs and cells would shard)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1704_01202_amd import binding as B
+    from paper_1704_01202_amd import runtime as RT
+    from paper_1704_01202_amd import workloads as W
+
+    t0 = time.perf_counter()
+    tab = W.make_tables()
+    spec, parts = W.config_c2(nx=args.nx, ny=args.ny)
+    log("workload generated (%.1f s): %d electrons, %d ions, %d cells"
+        % (time.perf_counter() - t0, parts.ne, parts.ni, spec.ncells))
+    ctx = RT.Context(tab)
+    bat = RT.Batch(ctx, [(spec, parts)], capacity=(7, 16))
+    torch.cuda.synchronize()
+    log("binned into slabs: e_slots %d, max cap %d (%.1f s)"
+        % (bat.e_slots, bat.e_cap_max, time.perf_counter() - t0))
+    stream = torch.cuda.current_stream()
+    for s in range(args.warmup):
+        bat.step(s, B.XP_ALL, schedule=args.schedule)
+    torch.cuda.synchronize()
+    bat.d_run_cnt.zero_()
+    ne_before = int(bat.d_e_cnt.sum().item())
+    ni = int(bat.d_i_cnt.sum().item())
+    log("warmup done, %d electrons resident" % ne_before)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    ne_steps = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        bat.step(args.warmup + k, B.XP_ALL, schedule=args.schedule)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    wall = t_end - t_start
+    kernel_ms = [a.elapsed_time(b) for a, b in ev]
+    cnt = bat.run_counters()[0]
+    status = bat.status()
+    ne_after = int(bat.d_e_cnt.sum().item())
+    coll = int(cnt[0] + cnt[1] + cnt[2])
+    new_e = int(cnt[21])
+    # algorithmic bytes of all timed launches: electrons present at each step
+    # start (interpolated between the measured ends) + ions + appended electrons
+    e_avg = 0.5 * (ne_before + ne_after)
+    bytes_total = args.steps * (E_BYTES * e_avg + I_BYTES * ni) + NEW_BYTES * new_e
+    avg_ms = sum(kernel_ms) / len(kernel_ms)
+    achieved = bytes_total / args.steps / (avg_ms * 1e-3) / 1e9
+    if status != 0:
+        log("WARNING: device status %d" % status)
+    out = {
+        "metric": "binary collisions/sec",
+        "value": coll / wall,
+        "unit": "collisions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "2D uniform solid Al, %dx%d cells x (64 e + 64 Al3+), EK IPD, "
+                               "dt 0.05 fs, 1.7e17 W/cm^2 1.85 keV photoionization fused"
+                               % (args.nx, args.ny),
+                   "cells": spec.ncells, "electrons_start": parts.ne, "ions": ni,
+                   "electrons_timed": [ne_before, ne_after], "status": status},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_step", "kernel_avg_ms": avg_ms,
+                     "bytes_per_launch": bytes_total / args.steps},
+        "collisions_total": coll,
+    }
+    if not args.no_cpu:
+        log("timing the CPU oracle on a sample ...")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

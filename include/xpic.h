@@ -1,0 +1,288 @@
+/*
+ * xpic: per-cell Monte-Carlo collision / ionization step of the collisional
+ * PIC method for XFEL-heated solid-density Al (Royle, Sentoku, Mancini,
+ * Paraschiv, Johzaki, "Kinetic modeling of x-ray laser-driven solid Al plasmas
+ * via particle-in-cell simulation"), on one AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Every pointer named d_* is device memory owned by the caller; every
+ * other pointer is host memory, read during the call only.  Streams are passed
+ * as `void *` holding a hipStream_t (NULL = the null stream).  All calls that
+ * take a stream only enqueue work on it and return without synchronizing,
+ * except where stated.  Every call returns an xp_status: XP_OK, or a negative
+ * code with a message available from xp_last_error() (thread-local).
+ *
+ * Conditions found on the device (a cell whose new electrons do not fit its
+ * slot capacity, a non-finite velocity) are reported through the batch's
+ * d_status word (bit mask XP_ST_*); a cell that cannot be completed is left
+ * exactly as it was before the step.
+ *
+ * Units: SI for positions, velocities, volumes and densities; energies and
+ * temperatures in eV; table cross sections in cm^2.
+ */
+#ifndef XPIC_H
+#define XPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define XP_ABI_VERSION 1u
+
+typedef int32_t xp_status;
+#define XP_OK                   0
+#define XP_ERR_INVALID_ARG     -1   /* null or inconsistent argument */
+#define XP_ERR_HIP             -2   /* a HIP runtime call failed */
+#define XP_ERR_TOO_SMALL       -3   /* a caller buffer is smaller than required */
+#define XP_ERR_NOT_INITIALIZED -4   /* init_species has not been called */
+#define XP_ERR_UNSUPPORTED     -5   /* size beyond what this build supports */
+
+/* Stage switches (xp_step_params.flags).  Order within a step is always
+ * moments -> e-e -> e-i -> ionization -> recombination -> decay/photo. */
+#define XP_EE      0x01u   /* electron-electron binary collisions (Sec. IV) */
+#define XP_EI      0x02u   /* electron-ion binary collisions (Sec. IV) */
+#define XP_ION     0x04u   /* collisional ionization, Lotz (Sec. IV, Eq. 4) */
+#define XP_REC     0x08u   /* three-body recombination to Zbar_EOS (Sec. IV) */
+#define XP_PHOTO   0x10u   /* subshell photoionization (Sec. III, Eq. 3) */
+#define XP_DECAY   0x20u   /* K-vacancy decay, KLL Auger or K-alpha (Sec. III) */
+#define XP_ALL     0x3Fu
+
+/* Device status bits (xp_batch.d_status, OR-ed by kernels). */
+#define XP_ST_CAPACITY  0x1u   /* a cell needed more electron slots than its capacity */
+#define XP_ST_NONFINITE 0x2u   /* a non-finite velocity was produced */
+#define XP_ST_BIN_SIZE  0x4u   /* bin_particles: output capacity too small, nothing written */
+
+/* Per-cell event counters (indices into counter records). */
+enum {
+    XP_C_EE = 0, XP_C_EI, XP_C_TRIPLET, XP_C_ACCEPT, XP_C_U0, XP_C_DELTA2_GT1,
+    XP_C_ION_FIRED, XP_C_ION_ACCEPTED, XP_C_ION_STARVED,
+    XP_C_REC, XP_C_REC_SKIPPED, XP_C_E_REMOVED,
+    XP_C_PHOTO_1S, XP_C_PHOTO_2S, XP_C_PHOTO_2P, XP_C_PHOTO_SKIPPED,
+    XP_C_DECAY, XP_C_AUGER, XP_C_KALPHA,
+    XP_C_P_CLAMPED, XP_C_IPD_CLAMPED, XP_C_E_NEW,
+    XP_NCOUNT = 24
+};
+
+/* Per-cell energy tallies (eV x weight units). */
+enum {
+    XP_L_PHOTO_E = 0,   /* kinetic energy given to photoelectrons */
+    XP_L_AUGER_E,       /* kinetic energy given to Auger electrons */
+    XP_L_ION_DEBIT,     /* lowered potentials paid by collisional ionization */
+    XP_L_REC_ADD,       /* energy returned to electrons by recombination */
+    XP_L_REC_BIND,      /* lowered binding released by recombination */
+    XP_L_KALPHA,        /* K-alpha photon energy emitted */
+    XP_L_PHOTON_ABS,    /* photon energy absorbed */
+    XP_NLEDGER = 8
+};
+
+#define XP_NMOM 32          /* per-cell moment record, see collide_ionize_step */
+#define XP_MAX_BINS 16      /* photon energy bins per run */
+
+typedef struct xp_ctx xp_ctx;
+
+/* ---- lifecycle ------------------------------------------------------- */
+
+uint32_t    xp_abi_version(void);
+const char *xp_last_error(void);
+/* Creates a context bound to HIP device device_id. */
+xp_status   xp_ctx_create(xp_ctx **out, int32_t device_id);
+void        xp_ctx_destroy(xp_ctx *ctx);
+
+/* ---- atomic data (Sec. III-V; Fig. 2, Fig. 3) ----------------------------
+ * Host arrays, copied into the caller's device buffer by init_species.
+ *   bind       [14][5]  eV   binding energy of subshell s (1s 2s 2p 3s 3p) of
+ *                            charge state Z (tables vs ion charge, Sec. III)
+ *   lotz_a,b,c [5]           Lotz constants of Eq. 4 (a in cm^2 eV^2)
+ *   gamma_a,x  [14][3]  1/s  Auger and radiative K-vacancy decay rates of
+ *                            charge state Z with k K vacancies (Sec. III)
+ *   e_kalpha   [14]     eV   K-alpha photon energy of charge state Z
+ *   photo_lnsig[5][photo_nh] ln(cm^2) per-electron subshell photoionization
+ *                            cross section on the uniform grid ln(hv/eV) =
+ *                            photo_lnhv0 + i photo_dlnhv (Fig. 2a)
+ *   eos_zbar   [eos_nn][eos_nt] Zbar_EOS on the uniform grid ln(n_i / m^-3) =
+ *                            eos_lnn0 + i eos_dlnn, ln(T/eV) = eos_lnt0 + j eos_dlnt
+ */
+typedef struct {
+    int32_t z_nuc;          /* must be 13 (Al) */
+    int32_t photo_nh;       /* 2 .. 512 */
+    int32_t eos_nn;         /* 2 .. 256 */
+    int32_t eos_nt;         /* 2 .. 1024 */
+    double mass_ion;        /* kg */
+    const double *bind;
+    const double *lotz_a;
+    const double *lotz_b;
+    const double *lotz_c;
+    const double *gamma_a;
+    const double *gamma_x;
+    const double *e_kalpha;
+    double photo_lnhv0, photo_dlnhv;
+    const double *photo_lnsig;
+    double eos_lnn0, eos_dlnn, eos_lnt0, eos_dlnt;
+    const double *eos_zbar;
+} xp_atomic_tables;
+
+/* Bytes of device memory init_species needs for these tables. */
+size_t    xp_table_bytes(const xp_atomic_tables *tab);
+/* Validates the tables (z_nuc == 13, grid sizes, positive spacings, finite
+ * values) and copies them into d_table_buf (caller-owned, >= xp_table_bytes,
+ * kept alive while the context is used).  Enqueued on stream; the host arrays
+ * may be freed on return.  Errors: XP_ERR_INVALID_ARG, XP_ERR_TOO_SMALL. */
+xp_status init_species(xp_ctx *ctx, const xp_atomic_tables *tab, void *d_table_buf,
+                       size_t table_buf_bytes, void *stream);
+
+/* ---- runs, batches and particles ----------------------------------------
+ * A batch holds n_runs independent runs; run r owns cells
+ * [cell_begin, cell_begin + ncells) of the batch.  Cell c of a run is grid
+ * cell (c % nx, c / nx).  Each cell owns a slab of electron slots
+ * [e_off[c], e_off[c] + e_cap[c]) of which the first e_cnt[c] are live, in
+ * canonical order, and likewise for ions (ion counts never grow).  Every
+ * macro-ion is one weight unit (w0 real ions); electrons carry integer units.
+ */
+typedef struct {
+    uint64_t seed;          /* Philox key of the run */
+    int32_t nx, ny;         /* grid; cell of (x, y) = floor((x-x0)/dx) + nx floor((y-y0)/dy) */
+    double dx, dy, x0, y0;  /* m */
+    double volume;          /* cell volume, m^3 */
+    double w0;              /* real particles per weight unit */
+    double dt;              /* PIC step, s */
+    double dt_rad;          /* step of the source terms (decay, photo), s */
+    double lnl_fixed;       /* > 0: fixed Coulomb logarithm; else computed per cell */
+    double e_bulk;          /* eV; electrons below it form the bulk for T_e (Sec. II) */
+    int32_t ipd_model;      /* 0 Stewart-Pyatt (Eq. 6), 1 Ecker-Kroll (Eq. 5) */
+    int32_t z_floor;        /* ions with Z > z_floor may recombine (Al3+ floor, Sec. V) */
+    int32_t cell_begin;     /* first batch cell of the run */
+    int32_t ncells;         /* nx * ny */
+    int32_t n_bins;         /* photon energy bins, 0 .. XP_MAX_BINS */
+    int32_t field_per_cell; /* 0: nhv below; 1: batch d_cell_nhv[cell][n_bins] */
+    double hv[XP_MAX_BINS];  /* eV */
+    double nhv[XP_MAX_BINS]; /* photons per m^3, prescribed (Sec. II: RT not modelled) */
+} xp_run;
+
+typedef struct {
+    int32_t n_runs;
+    int32_t n_cells;
+    const xp_run *d_runs;           /* [n_runs] */
+    const int32_t *d_cell_run;      /* [n_cells] run of each cell */
+    int64_t *d_e_off;               /* [n_cells] electron slab offsets */
+    int32_t *d_e_cap;               /* [n_cells] */
+    int32_t *d_e_cnt;               /* [n_cells] */
+    int64_t *d_i_off;               /* [n_cells] */
+    int32_t *d_i_cap;               /* [n_cells] */
+    int32_t *d_i_cnt;               /* [n_cells] */
+    int64_t e_slots, i_slots;       /* lengths of the particle arrays */
+    double *d_ex, *d_ey, *d_evx, *d_evy, *d_evz;   /* [e_slots] */
+    uint32_t *d_ew;                                /* [e_slots] weight units */
+    double *d_ix, *d_iy, *d_ivx, *d_ivy, *d_ivz;   /* [i_slots] */
+    uint8_t *d_iz, *d_ik;           /* charge state, K vacancies (0..2) */
+    const double *d_cell_nhv;       /* optional [n_cells][XP_MAX_BINS] */
+    uint64_t *d_run_counters;       /* [n_runs][XP_NCOUNT], accumulated */
+    double *d_run_ledger;           /* [n_runs][XP_NLEDGER], accumulated (order-free) */
+    int64_t *d_cell_counters;       /* optional [n_cells][XP_NCOUNT], last step */
+    double *d_cell_ledger;          /* optional [n_cells][XP_NLEDGER], last step */
+    double *d_cell_moments;         /* optional [n_cells][XP_NMOM], last step */
+    uint32_t *d_status;             /* one word, XP_ST_* bits */
+    void *d_work;                   /* workspace, >= xp_work_bytes */
+    size_t work_bytes;
+    int32_t e_cap_max;              /* host copy of max e_cap over cells (d_need[2]) */
+    int32_t i_cap_max;              /* host copy of max i_cap over cells (d_need[3]) */
+} xp_batch;
+
+/* Unsorted input particles of a batch for bin_particles.  Particle p belongs
+ * to run d_e_run[p] (NULL: run 0). */
+typedef struct {
+    int64_t ne, ni;
+    const int32_t *d_e_run, *d_i_run;
+    const double *d_ex, *d_ey, *d_evx, *d_evy, *d_evz;
+    const uint32_t *d_ew;
+    const double *d_ix, *d_iy, *d_ivx, *d_ivy, *d_ivz;
+    const uint8_t *d_iz, *d_ik;
+} xp_particles;
+
+/* Slab capacity rule used by bin_particles:
+ *   e_cap = round_up(cnt_e + e_per_ion * cnt_i + e_extra, 16), i_cap = round_up(cnt_i, 16). */
+typedef struct {
+    int32_t e_per_ion;
+    int32_t e_extra;
+} xp_capacity;
+
+/* Workspace bytes needed by every call on a batch with these sizes. */
+size_t xp_work_bytes(int64_t ne, int64_t ni, int32_t n_cells, int32_t n_runs);
+
+/* ---- the step ---------------------------------------------------------- */
+typedef struct {
+    uint32_t flags;            /* XP_* stage switches */
+    uint32_t step;             /* step index (Philox counter word 0) */
+    const uint32_t *d_step;    /* optional [n_runs] device step index per run; overrides step */
+    int32_t schedule;          /* 0 auto; 1 one wave per cell; 2 one block of 256 per cell */
+    int32_t reserved;
+} xp_step_params;
+
+/* Stable counting sort of the unsorted particles into the batch's cell slabs
+ * (Sec. VI: PIC cells).  The batch's run table, d_cell_run, slab arrays and
+ * workspace must be set; offsets, capacities and counts are written from the
+ * capacity rule.  Within a cell, particles keep their input order.  d_need is
+ * caller-owned device memory of four int64 receiving the required
+ * (e_slots, i_slots) and the largest (e_cap, i_cap) of any cell; the caller
+ * copies the last two into b->e_cap_max / i_cap_max before stepping.  If the
+ * particle arrays are too short, XP_ST_BIN_SIZE is set and no particle is
+ * written. */
+xp_status bin_particles(xp_ctx *ctx, const xp_particles *in, xp_batch *b,
+                        const xp_capacity *cap, int64_t *d_need, void *stream);
+
+/* One Monte-Carlo step of every cell of every run in the batch (Sec. II-V):
+ * moments and continuum lowering, e-e and e-i binary collisions, collisional
+ * ionization, three-body recombination, and -- when XP_PHOTO / XP_DECAY are in
+ * p->flags -- the XFEL source terms of photo_auger_step, fused in the same
+ * pass with dt_rad of the run table.  Cells stay in canonical slot order:
+ * survivors keep their order, new electrons are appended (ionization events
+ * in ion-slot order, then per ion Auger, photo 1s, 2s, 2p), electrons whose
+ * weight reaches 0 are removed.  Moments record (when d_cell_moments is set):
+ * [0] W_e [1] W_i [2] sum Z [3] sum Z^2 [4] K_e [5] T_e [6] n_e [7] n_i
+ * [8] Zbar [9] z* [10] lnL [11] Z_c [12] P_ion [13] K_th [14] debit [15] T_e
+ * before recombination [16..28] dE[Z] for Z = 0..12. */
+xp_status collide_ionize_step(xp_ctx *ctx, xp_batch *b, const xp_step_params *p,
+                              void *stream);
+
+/* Source terms alone (Sec. III): moments and continuum lowering of the current
+ * state, then K-vacancy decay with KLL Auger / K-alpha branching and subshell
+ * photoionization (Eq. 3) with the run's prescribed photon field, over
+ * dt_rad.  p->flags is masked to XP_PHOTO | XP_DECAY. */
+xp_status photo_auger_step(xp_ctx *ctx, xp_batch *b, const xp_step_params *p,
+                           void *stream);
+
+/* Run diagnostics (Sec. II, Sec. VI.B, Fig. 7-9): charge-state distribution,
+ * electron energy histogram (64 log bins from 0.1 eV to 1e5 eV, weight
+ * units), weights, Zbar, total kinetic energy and T_e = (2/3) K / W_e, and a
+ * copy of the accumulated counters and tallies.  With XP_DIAG_RESET the
+ * accumulated counters are zeroed afterwards.  d_out: [n_runs] records. */
+#define XP_DIAG_RESET 0x1u
+typedef struct {
+    int64_t csd[14];
+    int64_t fe_hist[64];
+    int64_t w_e, w_i, sum_z, n_e_macro;
+    double zbar, ke_ev, te_ev, reserved;
+    uint64_t counters[XP_NCOUNT];
+    double ledger[XP_NLEDGER];
+} xp_diag;
+
+xp_status diagnostics(xp_ctx *ctx, const xp_batch *b, xp_diag *d_out, uint32_t what,
+                      void *stream);
+
+/* ---- self-test ----------------------------------------------------------
+ * Evaluates one device building block of the step on n caller inputs, so that
+ * a test suite can compare it with an independent implementation:
+ *   which 0 log(d_x[i]), 1 exp(d_x[i]), 2 cbrt(d_x[i]), 5 sqrt(d_x[i]),
+ *         6 d_x[2i] / d_x[2i+1]                          -> d_out[i]
+ *   which 3 sin, cos of 2 pi (d_u[i] + 1/2) / 2^52       -> d_out[2i], d_out[2i+1]
+ *   which 4 Philox4x32-10 of counter/key words packed as six uint32 in
+ *         d_u[3i .. 3i+2] (c0 c1 c2 c3 k0 k1)             -> d_words[4i .. 4i+3]
+ * Device arrays are caller-owned; unused ones may be NULL. */
+xp_status xp_selftest(xp_ctx *ctx, int32_t which, int64_t n, const double *d_x,
+                      const uint64_t *d_u, double *d_out, uint32_t *d_words, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XPIC_H */

@@ -1,0 +1,304 @@
+// C-ABI entry points of the library: context, table upload, argument checks,
+// schedule choice and kernel launches.  No call synchronizes the stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "xp_kernels.h"
+
+struct xp_ctx {
+    int device;
+    const xpd::DevTables* d_tables;
+    bool tables_ready;
+    size_t max_lds;               // dynamic LDS limit per workgroup
+    std::vector<unsigned char> staging;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+xp_status fail(xp_status code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+xp_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(XP_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t table_layout(const xp_atomic_tables* t, size_t* off_lnsig, size_t* off_eos)
+{
+    size_t o = (sizeof(xpd::DevTables) + 255) & ~size_t(255);
+    *off_lnsig = o;
+    o += sizeof(double) * 5 * (size_t)t->photo_nh;
+    o = (o + 255) & ~size_t(255);
+    *off_eos = o;
+    o += sizeof(double) * (size_t)t->eos_nn * (size_t)t->eos_nt;
+    return (o + 255) & ~size_t(255);
+}
+
+bool finite_all(const double* p, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+xp_status check_batch(const xp_ctx* ctx, const xp_batch* b)
+{
+    if (!ctx) return fail(XP_ERR_INVALID_ARG, "null context");
+    if (!ctx->tables_ready) return fail(XP_ERR_NOT_INITIALIZED, "init_species has not been called");
+    if (!b) return fail(XP_ERR_INVALID_ARG, "null batch");
+    if (b->n_runs <= 0 || b->n_cells < 0) return fail(XP_ERR_INVALID_ARG, "batch needs n_runs > 0 and n_cells >= 0");
+    if (!b->d_runs || !b->d_cell_run || !b->d_status) return fail(XP_ERR_INVALID_ARG, "batch run table, cell map or status is null");
+    if (b->n_cells > 0 && (!b->d_e_off || !b->d_e_cap || !b->d_e_cnt || !b->d_i_off || !b->d_i_cap || !b->d_i_cnt))
+        return fail(XP_ERR_INVALID_ARG, "batch slab arrays are null");
+    if (b->e_slots > 0 && (!b->d_ex || !b->d_evx || !b->d_evy || !b->d_evz || !b->d_ew))
+        return fail(XP_ERR_INVALID_ARG, "batch electron arrays are null");
+    if (b->i_slots > 0 && (!b->d_ix || !b->d_ivx || !b->d_ivy || !b->d_ivz || !b->d_iz || !b->d_ik))
+        return fail(XP_ERR_INVALID_ARG, "batch ion arrays are null");
+    return XP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint32_t xp_abi_version(void) { return XP_ABI_VERSION; }
+
+const char* xp_last_error(void) { return g_err.c_str(); }
+
+xp_status xp_ctx_create(xp_ctx** out, int32_t device_id)
+{
+    if (!out) return fail(XP_ERR_INVALID_ARG, "null output pointer");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device_id < 0 || device_id >= n) return fail(XP_ERR_INVALID_ARG, "device id out of range");
+    if ((e = hipSetDevice(device_id)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    int lds = 0;
+    if ((e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device_id)) != hipSuccess)
+        return hip_fail(e, "hipDeviceGetAttribute");
+    xp_ctx* c = new xp_ctx();
+    c->device = device_id;
+    c->d_tables = nullptr;
+    c->tables_ready = false;
+    c->max_lds = (size_t)lds;
+    *out = c;
+    return XP_OK;
+}
+
+void xp_ctx_destroy(xp_ctx* ctx) { delete ctx; }
+
+size_t xp_table_bytes(const xp_atomic_tables* t)
+{
+    if (!t || t->photo_nh < 2 || t->eos_nn < 2 || t->eos_nt < 2) return 0;
+    size_t a, b;
+    return table_layout(t, &a, &b);
+}
+
+xp_status init_species(xp_ctx* ctx, const xp_atomic_tables* t, void* d_buf, size_t bytes, void* stream)
+{
+    if (!ctx || !t || !d_buf) return fail(XP_ERR_INVALID_ARG, "null context, tables or buffer");
+    if (t->z_nuc != 13) return fail(XP_ERR_INVALID_ARG, "only Al (Z = 13) tables are supported");
+    if (t->photo_nh < 2 || t->photo_nh > 512 || t->eos_nn < 2 || t->eos_nn > 256 || t->eos_nt < 2 || t->eos_nt > 1024)
+        return fail(XP_ERR_INVALID_ARG, "table grid sizes out of range");
+    if (!(t->photo_dlnhv > 0) || !(t->eos_dlnn > 0) || !(t->eos_dlnt > 0) || !(t->mass_ion > 0))
+        return fail(XP_ERR_INVALID_ARG, "table spacings and ion mass must be positive");
+    if (!t->bind || !t->lotz_a || !t->lotz_b || !t->lotz_c || !t->gamma_a || !t->gamma_x || !t->e_kalpha ||
+        !t->photo_lnsig || !t->eos_zbar)
+        return fail(XP_ERR_INVALID_ARG, "null table array");
+    if (!finite_all(t->bind, 70) || !finite_all(t->gamma_a, 42) || !finite_all(t->gamma_x, 42) ||
+        !finite_all(t->e_kalpha, 14) || !finite_all(t->photo_lnsig, 5 * (size_t)t->photo_nh) ||
+        !finite_all(t->eos_zbar, (size_t)t->eos_nn * t->eos_nt) || !finite_all(t->lotz_a, 5) ||
+        !finite_all(t->lotz_b, 5) || !finite_all(t->lotz_c, 5))
+        return fail(XP_ERR_INVALID_ARG, "non-finite table value");
+    size_t off_lnsig, off_eos;
+    const size_t need = table_layout(t, &off_lnsig, &off_eos);
+    if (bytes < need) return fail(XP_ERR_TOO_SMALL, "table buffer smaller than xp_table_bytes");
+    ctx->staging.assign(need, 0);
+    xpd::DevTables* h = (xpd::DevTables*)ctx->staging.data();
+    std::memcpy(h->bind, t->bind, sizeof(h->bind));
+    std::memcpy(h->lotz_a, t->lotz_a, sizeof(h->lotz_a));
+    std::memcpy(h->lotz_b, t->lotz_b, sizeof(h->lotz_b));
+    std::memcpy(h->lotz_c, t->lotz_c, sizeof(h->lotz_c));
+    std::memcpy(h->gamma_a, t->gamma_a, sizeof(h->gamma_a));
+    std::memcpy(h->gamma_x, t->gamma_x, sizeof(h->gamma_x));
+    std::memcpy(h->e_kalpha, t->e_kalpha, sizeof(h->e_kalpha));
+    h->mass_ion = t->mass_ion;
+    h->photo_lnhv0 = t->photo_lnhv0;
+    h->photo_dlnhv = t->photo_dlnhv;
+    h->eos_lnn0 = t->eos_lnn0;
+    h->eos_dlnn = t->eos_dlnn;
+    h->eos_lnt0 = t->eos_lnt0;
+    h->eos_dlnt = t->eos_dlnt;
+    h->photo_nh = t->photo_nh;
+    h->eos_nn = t->eos_nn;
+    h->eos_nt = t->eos_nt;
+    h->off_lnsig = (int64_t)off_lnsig;
+    h->off_eos = (int64_t)off_eos;
+    std::memcpy(ctx->staging.data() + off_lnsig, t->photo_lnsig, sizeof(double) * 5 * (size_t)t->photo_nh);
+    std::memcpy(ctx->staging.data() + off_eos, t->eos_zbar, sizeof(double) * (size_t)t->eos_nn * t->eos_nt);
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    e = hipMemcpyAsync(d_buf, ctx->staging.data(), need, hipMemcpyHostToDevice, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(tables)");
+    // the staging copy must outlive the transfer: keep it until the next call
+    e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(tables)");
+    ctx->d_tables = (const xpd::DevTables*)d_buf;
+    ctx->tables_ready = true;
+    return XP_OK;
+}
+
+size_t xp_work_bytes(int64_t ne, int64_t ni, int32_t n_cells, int32_t n_runs)
+{
+    (void)n_runs;
+    const xpd::BinPlan p = xpd::bin_plan(ne, ni, n_cells);
+    size_t diag = 8 * (size_t)(n_cells > 0 ? n_cells : 1) + 256;
+    return p.bytes > diag ? p.bytes : diag;
+}
+
+xp_status bin_particles(xp_ctx* ctx, const xp_particles* in, xp_batch* b, const xp_capacity* cap,
+                        int64_t* d_need, void* stream)
+{
+    xp_status st = check_batch(ctx, b);
+    if (st != XP_OK) return st;
+    if (!in || !cap || !d_need) return fail(XP_ERR_INVALID_ARG, "null particles, capacity rule or need buffer");
+    if (in->ne < 0 || in->ni < 0 || in->ne >= (1ll << 32) || in->ni >= (1ll << 32))
+        return fail(XP_ERR_UNSUPPORTED, "particle counts must be below 2^32 per species");
+    if ((in->ne > 0 && (!in->d_ex || !in->d_evx || !in->d_evy || !in->d_evz || !in->d_ew)) ||
+        (in->ni > 0 && (!in->d_ix || !in->d_ivx || !in->d_ivy || !in->d_ivz || !in->d_iz || !in->d_ik)))
+        return fail(XP_ERR_INVALID_ARG, "null input particle array");
+    if (b->n_runs > 1 && ((in->ne > 0 && !in->d_e_run) || (in->ni > 0 && !in->d_i_run)))
+        return fail(XP_ERR_INVALID_ARG, "particle run maps are required for more than one run");
+    if (cap->e_per_ion < 0 || cap->e_extra < 0) return fail(XP_ERR_INVALID_ARG, "negative capacity rule");
+    if (!b->d_work || b->work_bytes < xp_work_bytes(in->ne, in->ni, b->n_cells, b->n_runs))
+        return fail(XP_ERR_TOO_SMALL, "workspace smaller than xp_work_bytes");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    e = xpd::bin_launch(in, b, cap, d_need, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "bin_particles launch");
+    return XP_OK;
+}
+
+static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, uint32_t flags, void* stream)
+{
+    xp_status st = check_batch(ctx, b);
+    if (st != XP_OK) return st;
+    if (!p) return fail(XP_ERR_INVALID_ARG, "null step parameters");
+    if (b->n_cells == 0) return XP_OK;
+    if (b->e_cap_max <= 0 || b->i_cap_max < 0) return fail(XP_ERR_INVALID_ARG, "batch e_cap_max / i_cap_max not set");
+    xpd::StepArgs a{};
+    a.runs = b->d_runs;
+    a.cell_run = b->d_cell_run;
+    a.e_off = b->d_e_off;
+    a.e_cap = b->d_e_cap;
+    a.e_cnt = b->d_e_cnt;
+    a.i_off = b->d_i_off;
+    a.i_cnt = b->d_i_cnt;
+    a.ex = b->d_ex; a.ey = b->d_ey; a.evx = b->d_evx; a.evy = b->d_evy; a.evz = b->d_evz; a.ew = b->d_ew;
+    a.ix = b->d_ix; a.iy = b->d_iy; a.ivx = b->d_ivx; a.ivy = b->d_ivy; a.ivz = b->d_ivz;
+    a.iz = b->d_iz; a.ik = b->d_ik;
+    a.cell_nhv = b->d_cell_nhv;
+    a.run_cnt = b->d_run_counters;
+    a.run_led = b->d_run_ledger;
+    a.cell_cnt = b->d_cell_counters;
+    a.cell_led = b->d_cell_ledger;
+    a.cell_mom = b->d_cell_moments;
+    a.status = b->d_status;
+    a.tab = ctx->d_tables;
+    a.d_step = p->d_step;
+    a.step = p->step;
+    a.flags = flags;
+    a.cell_list = nullptr;
+    a.n_cells = b->n_cells;
+    a.lds_ce = b->e_cap_max;
+    a.lds_ci = b->i_cap_max > 0 ? b->i_cap_max : 1;
+    const size_t lds = xpd::step_lds_bytes(a.lds_ce, a.lds_ci);
+    if (lds > ctx->max_lds)
+        return fail(XP_ERR_UNSUPPORTED, "cell capacity exceeds the LDS of one workgroup");
+    int sched = p->schedule;
+    if (sched == 0) sched = (a.lds_ce > 1024 || a.lds_ci > 1024) ? 2 : 1;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if (sched == 1) {
+        if (lds > 65536) hipFuncSetAttribute((const void*)xpd::k_step<64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(xpd::k_step<64>, dim3(b->n_cells), dim3(64), lds, (hipStream_t)stream, a);
+    } else if (sched == 2) {
+        if (lds > 65536) hipFuncSetAttribute((const void*)xpd::k_step<256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(xpd::k_step<256>, dim3(b->n_cells), dim3(256), lds, (hipStream_t)stream, a);
+    } else {
+        return fail(XP_ERR_INVALID_ARG, "unknown schedule");
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "step launch");
+    return XP_OK;
+}
+
+xp_status collide_ionize_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, void* stream)
+{
+    if (!p) return fail(XP_ERR_INVALID_ARG, "null step parameters");
+    return launch_step(ctx, b, p, p->flags & XP_ALL, stream);
+}
+
+xp_status photo_auger_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, void* stream)
+{
+    if (!p) return fail(XP_ERR_INVALID_ARG, "null step parameters");
+    return launch_step(ctx, b, p, p->flags & (XP_PHOTO | XP_DECAY), stream);
+}
+
+xp_status diagnostics(xp_ctx* ctx, const xp_batch* b, xp_diag* d_out, uint32_t what, void* stream)
+{
+    xp_status st = check_batch(ctx, b);
+    if (st != XP_OK) return st;
+    if (!d_out) return fail(XP_ERR_INVALID_ARG, "null output");
+    if (!b->d_work || b->work_bytes < 8 * (size_t)(b->n_cells > 0 ? b->n_cells : 1))
+        return fail(XP_ERR_TOO_SMALL, "workspace too small for diagnostics");
+    xpd::DiagArgs a{};
+    a.runs = b->d_runs;
+    a.cell_run = b->d_cell_run;
+    a.e_off = b->d_e_off;
+    a.e_cnt = b->d_e_cnt;
+    a.i_off = b->d_i_off;
+    a.i_cnt = b->d_i_cnt;
+    a.evx = b->d_evx; a.evy = b->d_evy; a.evz = b->d_evz; a.ew = b->d_ew;
+    a.iz = b->d_iz;
+    a.run_cnt = b->d_run_counters;
+    a.run_led = b->d_run_ledger;
+    a.cell_k = (double*)b->d_work;
+    a.out = d_out;
+    a.n_runs = b->n_runs;
+    a.n_cells = b->n_cells;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    e = xpd::diag_launch(a, what, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "diagnostics launch");
+    return XP_OK;
+}
+
+xp_status xp_selftest(xp_ctx* ctx, int32_t which, int64_t n, const double* d_x, const uint64_t* d_u,
+                      double* d_out, uint32_t* d_words, void* stream)
+{
+    if (!ctx) return fail(XP_ERR_INVALID_ARG, "null context");
+    if (which < 0 || which > 6 || n < 0) return fail(XP_ERR_INVALID_ARG, "unknown self-test");
+    const bool need_x = which <= 2 || which >= 5;
+    if ((need_x && !d_x) || ((which == 3 || which == 4) && !d_u) || (which != 4 && !d_out) ||
+        (which == 4 && !d_words))
+        return fail(XP_ERR_INVALID_ARG, "null self-test array");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    e = xpd::selftest_launch(which, n, d_x, d_u, d_out, d_words, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "self-test launch");
+    return XP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,335 @@
+// Device-side building blocks of the collision / ionization step (gfx950).
+//
+// * Elementary functions defined by the method's arithmetic contract: log, exp,
+//   cbrt and sin/cos of 2 pi (k + 1/2) / 2^52, built from IEEE-754 correctly
+//   rounded +, -, *, / and sqrt only.  The library is compiled with
+//   -ffp-contract=off so that no product is fused into an FMA.  A bit-identical
+//   result on the CPU reference is what makes long runs comparable at all: the
+//   binary-collision map amplifies last-bit differences from step to step.
+// * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter-based random
+//   numbers keyed by the run seed, counter (step, cell, index, purpose<<24|sub).
+// * The canonical pairwise sum of a block (leaves in slot order padded with +0
+//   to a power of two, summed level by level).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace xpd {
+
+// CODATA 2018, SI
+constexpr double QE = 1.602176634e-19;
+constexpr double ME = 9.1093837015e-31;
+constexpr double EPS0 = 8.8541878128e-12;
+constexpr double HBAR = 1.054571817e-34;
+constexpr double CLIGHT = 299792458.0;
+constexpr double PI = 3.141592653589793;
+
+// Random-number purposes (word 3 of the Philox counter, << 24).
+enum : uint32_t {
+    RP_PERM_E = 1, RP_PERM_I = 2, RP_REC_I = 3, RP_REC_E = 4, RP_EE = 5,
+    RP_EE_TRI = 6, RP_EI = 7, RP_ION = 8, RP_S5 = 9, RP_DIR = 10
+};
+
+__device__ __forceinline__ double bits_to_f64(uint64_t b) { return __longlong_as_double((long long)b); }
+__device__ __forceinline__ uint64_t f64_to_bits(double d) { return (uint64_t)__double_as_longlong(d); }
+
+// 2^n, -1022 <= n <= 1023
+__device__ __forceinline__ double two_pow(int n) { return bits_to_f64((uint64_t)(n + 1023) << 52); }
+
+// Natural logarithm for x > 0 (finite): reduction to m in (sqrt(1/2), sqrt(2)],
+// log(1+f) = f - s (f - V), s = f / (2 + f), V = s^2 (2/3 + s^2 (2/5 + ...)).
+__device__ __noinline__ double xlog(double x)
+{
+    if (!(x > 0.0)) return x == 0.0 ? -__builtin_inf() : __builtin_nan("");
+    if (x == __builtin_inf()) return x;
+    uint64_t b = f64_to_bits(x);
+    int ebias = 0;
+    if ((b >> 52) == 0) {            // subnormal (sign is 0 here)
+        x = x * 0x1p54;
+        b = f64_to_bits(x);
+        ebias = -54;
+    }
+    int e = (int)(b >> 52) - 1023 + ebias;
+    double m = bits_to_f64((b & 0x000fffffffffffffull) | 0x3ff0000000000000ull);
+    if (m > 0x1.6a09e667f3bcdp+0) {
+        m = m * 0.5;
+        e += 1;
+    }
+    const double f = m - 1.0;
+    const double s = f / (2.0 + f);
+    const double z = s * s;
+    double v = 2.0 / 23.0;
+    v = 2.0 / 21.0 + z * v;
+    v = 2.0 / 19.0 + z * v;
+    v = 2.0 / 17.0 + z * v;
+    v = 2.0 / 15.0 + z * v;
+    v = 2.0 / 13.0 + z * v;
+    v = 2.0 / 11.0 + z * v;
+    v = 2.0 / 9.0 + z * v;
+    v = 2.0 / 7.0 + z * v;
+    v = 2.0 / 5.0 + z * v;
+    v = 2.0 / 3.0 + z * v;
+    v = z * v;
+    const double l1p = f - s * (f - v);
+    const double de = (double)e;
+    return de * 0x1.62e42p-1 + (l1p + de * 0x1.fdf473de6af28p-22);
+}
+
+// Exponential: k = floor(x / ln2 + 1/2), r = (x - k ln2_hi) - k ln2_lo, Taylor to r^13.
+__device__ __noinline__ double xexp(double x)
+{
+    if (x != x) return x;
+    if (x > 709.78) return __builtin_inf();
+    if (x < -745.14) return 0.0;
+    const double k = floor(x * 0x1.71547652b82fep+0 + 0.5);
+    const double r = (x - k * 0x1.62e42p-1) - k * 0x1.fdf473de6af28p-22;
+    double p = 1.0 / 6227020800.0;
+    p = 1.0 / 479001600.0 + r * p;
+    p = 1.0 / 39916800.0 + r * p;
+    p = 1.0 / 3628800.0 + r * p;
+    p = 1.0 / 362880.0 + r * p;
+    p = 1.0 / 40320.0 + r * p;
+    p = 1.0 / 5040.0 + r * p;
+    p = 1.0 / 720.0 + r * p;
+    p = 1.0 / 120.0 + r * p;
+    p = 1.0 / 24.0 + r * p;
+    p = 1.0 / 6.0 + r * p;
+    p = 0.5 + r * p;
+    p = 1.0 + r * p;
+    p = 1.0 + r * p;
+    const int n = (int)k;
+    if (n > 1023) return (p * 2.0) * two_pow(n - 1);
+    if (n < -1022) return (p * two_pow(n + 600)) * two_pow(-600);
+    return p * two_pow(n);
+}
+
+// Cube root for x >= 0: exponent split by 3, six Newton steps from 1 + (m'-1)/7.
+__device__ __noinline__ double xcbrt(double x)
+{
+    if (!(x > 0.0)) return x;
+    if (x == __builtin_inf()) return x;
+    double post = 1.0;
+    uint64_t b = f64_to_bits(x);
+    if ((b >> 52) == 0) {
+        x = x * 0x1p54;
+        post = 0x1p-18;
+        b = f64_to_bits(x);
+    }
+    const int e = (int)(b >> 52) - 1023;
+    const int r = ((e % 3) + 3) % 3;
+    const int e3 = (e - r) / 3;
+    double m = bits_to_f64((b & 0x000fffffffffffffull) | 0x3ff0000000000000ull);
+    if (r == 1) m = m * 2.0;
+    if (r == 2) m = m * 4.0;
+    double y = 1.0 + (m - 1.0) * (1.0 / 7.0);
+#pragma unroll
+    for (int it = 0; it < 6; ++it) {
+        const double t = m / (y * y);
+        y = y + (t - y) / 3.0;
+    }
+    return (y * two_pow(e3)) * post;
+}
+
+// sin and cos of 2 pi (k + 1/2) / 2^52 for a 52-bit integer k.
+__device__ __forceinline__ void xsincos2pi(uint64_t k, double& s_out, double& c_out)
+{
+    k &= 0x000fffffffffffffull;
+    const int64_t q = (int64_t)((k + (1ull << 49)) >> 50);
+    const int64_t rem = (int64_t)k - (q << 50);
+    const double th = (((double)rem + 0.5) * 0x1p-50) * 0x1.921fb54442d18p+0;
+    const double t2 = th * th;
+    double sp = 1.0 / 355687428096000.0;
+    sp = -1.0 / 1307674368000.0 + t2 * sp;
+    sp = 1.0 / 6227020800.0 + t2 * sp;
+    sp = -1.0 / 39916800.0 + t2 * sp;
+    sp = 1.0 / 362880.0 + t2 * sp;
+    sp = -1.0 / 5040.0 + t2 * sp;
+    sp = 1.0 / 120.0 + t2 * sp;
+    sp = -1.0 / 6.0 + t2 * sp;
+    const double sn = th + th * (t2 * sp);
+    double cp = 1.0 / 20922789888000.0;
+    cp = -1.0 / 87178291200.0 + t2 * cp;
+    cp = 1.0 / 479001600.0 + t2 * cp;
+    cp = -1.0 / 3628800.0 + t2 * cp;
+    cp = 1.0 / 40320.0 + t2 * cp;
+    cp = -1.0 / 720.0 + t2 * cp;
+    cp = 1.0 / 24.0 + t2 * cp;
+    cp = -0.5 + t2 * cp;
+    const double cs = 1.0 + t2 * cp;
+    const int qq = (int)(q & 3);
+    s_out = qq == 0 ? sn : (qq == 1 ? cs : (qq == 2 ? -sn : -cs));
+    c_out = qq == 0 ? cs : (qq == 1 ? -sn : (qq == 2 ? -cs : sn));
+}
+
+struct Words { uint32_t x0, x1, x2, x3; };
+
+__device__ __forceinline__ Words philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Words{c0, c1, c2, c3};
+}
+
+// Uniform on (0, 1) from the top 52 bits of the 64-bit word (hi, lo).
+__device__ __forceinline__ double u52(uint32_t hi, uint32_t lo)
+{
+    const uint64_t a = ((uint64_t)hi << 32) | lo;
+    return ((double)(a >> 12) + 0.5) * 0x1p-52;
+}
+
+__device__ __forceinline__ int ilog2_ceil(int n)
+{
+    int b = 0;
+    while ((1 << b) < n) ++b;
+    return b;
+}
+
+// Canonical pairwise sum of n leaves produced by leaf(j), over a block of B
+// threads (B a multiple of 64).  Thread t folds leaves [t m, t m + m) with a
+// carry stack (exact pairwise tree for a power-of-two run), then the block
+// reduces the thread partials pairwise (lanes by shuffles, waves through LDS).
+// The result (+0.0) is returned to every thread.  red must hold B/64 doubles.
+template <int B, class F>
+__device__ double block_tree_sum(int n, F leaf, double* red)
+{
+    const int tid = threadIdx.x;
+    int p = 1;
+    while (p < n) p <<= 1;
+    const int m = p > B ? p / B : 1;
+    double acc = 0.0;
+    {
+        double stk[12];
+        int cnt[12];
+        int top = 0;
+        const int base = tid * m;
+        for (int q = 0; q < m; ++q) {
+            const int j = base + q;
+            double v = j < n ? leaf(j) : 0.0;
+            int c = 1;
+            while (top > 0 && cnt[top - 1] == c) {
+                v = stk[top - 1] + v;
+                c <<= 1;
+                --top;
+            }
+            stk[top] = v;
+            cnt[top] = c;
+            ++top;
+        }
+        acc = stk[0];
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double o = __shfl_down(acc, off, 64);
+        acc = acc + o;
+    }
+    if (B == 64) {
+        acc = __shfl(acc, 0, 64);
+        return acc + 0.0;
+    }
+    __syncthreads();
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
+    __syncthreads();
+    double r = 0.0;
+    {
+        double lv[B / 64];
+#pragma unroll
+        for (int w = 0; w < B / 64; ++w) lv[w] = red[w];
+#pragma unroll
+        for (int len = B / 64; len > 1; len >>= 1)
+#pragma unroll
+            for (int i = 0; i < len / 2; ++i) lv[i] = lv[2 * i] + lv[2 * i + 1];
+        r = lv[0];
+    }
+    __syncthreads();
+    return r + 0.0;
+}
+
+// Block-wide integer sum (any order).
+template <int B>
+__device__ long long block_isum(long long v, long long* red)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (B == 64) return v;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    long long s = 0;
+#pragma unroll
+    for (int w = 0; w < B / 64; ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+
+// Stable in-order compaction helper: exclusive prefix count of pred over
+// indices j = 0..n-1 processed in chunks of B (slot order), writing the
+// position of every j with pred(j) through emit(j, pos).  Returns the total.
+template <int B, class P, class E>
+__device__ int block_ordered_select(int n, P pred, E emit, int* red)
+{
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wid = tid >> 6;
+    int base = 0;
+    for (int c0 = 0; c0 < n; c0 += B) {
+        const int j = c0 + tid;
+        const bool f = j < n && pred(j);
+        const uint64_t bal = __ballot(f);
+        const int before = __popcll(bal & ((1ull << lane) - 1ull));
+        const int wcount = __popcll(bal);
+        if (B > 64) {
+            __syncthreads();
+            if (lane == 0) red[wid] = wcount;
+            __syncthreads();
+        }
+        int woff = 0, tot = wcount;
+        if (B > 64) {
+            tot = 0;
+#pragma unroll
+            for (int w = 0; w < B / 64; ++w) {
+                if (w < wid) woff += red[w];
+                tot += red[w];
+            }
+        }
+        if (f) emit(j, base + woff + before);
+        base += tot;
+    }
+    if (B > 64) __syncthreads();
+    return base;
+}
+
+// Bitonic sort of p = 2^k 64-bit keys in LDS (ascending), B threads.
+template <int B>
+__device__ void bitonic_sort(uint64_t* a, int p)
+{
+    for (int k = 2; k <= p; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < p / 2; i += B) {
+                const int lo = ((i / j) * 2 * j) + (i % j);
+                const int hi = lo + j;
+                const bool up = (lo & k) == 0;
+                const uint64_t x = a[lo], y = a[hi];
+                const bool sw = up ? (x > y) : (x < y);
+                if (sw) {
+                    a[lo] = y;
+                    a[hi] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+}  // namespace xpd

@@ -1,0 +1,180 @@
+// Device physics of one cell: configurations, continuum lowering, Coulomb
+// logarithm, equation of state, photo cross sections and the binary collision.
+// Operand order of every expression follows the method's arithmetic contract.
+#pragma once
+
+#include "xp_device.h"
+#include "xp_tables.h"
+
+namespace xpd {
+
+constexpr double E2 = QE / ((4.0 * PI) * EPS0);          // e^2/(4 pi eps0), eV m
+constexpr double THREE_OVER_4PI = 3.0 / (4.0 * PI);
+constexpr double HALF_ME_OVER_QE = (0.5 * ME) / QE;
+constexpr double TWO_QE_OVER_ME = (2.0 * QE) / ME;
+
+// Lowest-energy configuration of charge state z with k K vacancies (Sec. III):
+// counts of 1s 2s 2p 3s 3p.
+struct Occ { int s[5]; };
+
+__device__ __forceinline__ Occ occupancy(int z, int k)
+{
+    Occ o;
+    const int nb = 13 - z;
+    int k1 = 2 - k;
+    k1 = k1 > nb ? nb : k1;
+    k1 = k1 < 0 ? 0 : k1;
+    o.s[0] = k1;
+    int rem = nb - k1;
+    const int cap[5] = {2, 2, 6, 2, 6};
+#pragma unroll
+    for (int q = 1; q < 5; ++q) {
+        const int c = rem < cap[q] ? rem : cap[q];
+        o.s[q] = c;
+        rem -= c;
+    }
+    return o;
+}
+
+__device__ __forceinline__ int valence(int z, int k)
+{
+    const Occ o = occupancy(z, k);
+    for (int q = 4; q >= 0; --q)
+        if (o.s[q] > 0) return q;
+    return -1;
+}
+
+// Continuum lowering of charge state z: Ecker-Kroll (Eq. 5; Debye-Hueckel
+// below n_crit) or Stewart-Pyatt (Eq. 6 with lambda_D including Zbar + 1).
+__device__ double ipd(int model, int z, double t, double n_e, double n_i, double zbar,
+                      double zstar)
+{
+    double lamd = __builtin_inf();
+    if (n_e > 0.0) lamd = sqrt((EPS0 * t) / (QE * (n_e * (zbar + 1.0))));
+    const double zp1 = (double)(z + 1);
+    if (model == 1) {
+        const double ntot = n_e + n_i;
+        const double c = t / ((zp1 * zp1) * E2);
+        const double ncrit = THREE_OVER_4PI * ((c * c) * c);
+        if (ntot > ncrit) return (zp1 * E2) / xcbrt(THREE_OVER_4PI / ntot);
+        return (zp1 * E2) / lamd;
+    }
+    const double kk = (zp1 * E2) / (lamd * t);
+    const double zs1 = zstar + 1.0;
+    const double c = xcbrt(((3.0 * zs1) * kk) + 1.0);
+    return (t / (2.0 * zs1)) * ((c * c) - 1.0);
+}
+
+__device__ double coulomb_log(double t, double n_e, double zbar)
+{
+    if (!(n_e > 0.0)) return 2.0;
+    const double lamde = sqrt((EPS0 * t) / (QE * n_e));
+    const double bcl = (zbar * E2) / (3.0 * t);
+    const double bq = HBAR / (2.0 * sqrt((3.0 * ME) * (t * QE)));
+    const double bmin = bcl > bq ? bcl : bq;
+    const double ratio = lamde / bmin;
+    const double lnl = 0.5 * xlog(1.0 + ratio * ratio);
+    return lnl < 2.0 ? 2.0 : lnl;
+}
+
+__device__ double eos_zbar(const DevTables* tb, double n_i, double tev)
+{
+    const double* zt = (const double*)((const char*)tb + tb->off_eos);
+    const double u = (xlog(n_i) - tb->eos_lnn0) / tb->eos_dlnn;
+    const double v = (xlog(tev) - tb->eos_lnt0) / tb->eos_dlnt;
+    const int nn = tb->eos_nn, nt = tb->eos_nt;
+    const double fu = floor(u), fv = floor(v);
+    double au = u - fu, av = v - fv;
+    int iu, iv;
+    if (u < 0.0) { iu = 0; au = 0.0; } else if (fu > (double)(nn - 2)) { iu = nn - 2; au = 1.0; } else { iu = (int)fu; }
+    if (v < 0.0) { iv = 0; av = 0.0; } else if (fv > (double)(nt - 2)) { iv = nt - 2; av = 1.0; } else { iv = (int)fv; }
+    const double z00 = zt[iu * nt + iv], z01 = zt[iu * nt + iv + 1];
+    const double z10 = zt[(iu + 1) * nt + iv], z11 = zt[(iu + 1) * nt + iv + 1];
+    const double a = (1.0 - av) * z00 + av * z01;
+    const double b = (1.0 - av) * z10 + av * z11;
+    return (1.0 - au) * a + au * b;
+}
+
+// Per-electron subshell photoionization cross section, m^2 (Fig. 2a table).
+__device__ double photo_sigma(const DevTables* tb, int s, double hv)
+{
+    const double* ls = (const double*)((const char*)tb + tb->off_lnsig) + s * tb->photo_nh;
+    const double u = (xlog(hv) - tb->photo_lnhv0) / tb->photo_dlnhv;
+    const double fu = floor(u);
+    double a = u - fu;
+    int iu;
+    if (u < 0.0) { iu = 0; a = 0.0; } else if (fu > (double)(tb->photo_nh - 2)) { iu = tb->photo_nh - 2; a = 1.0; } else { iu = (int)fu; }
+    const double l0 = ls[iu], l1 = ls[iu + 1];
+    return xexp(l0 + a * (l1 - l0)) * 1.0e-4;
+}
+
+// Lowered binding of subshell s of charge state z, clamped at 1 eV.
+__device__ __forceinline__ double lowered(const DevTables* tb, int z, int s, const double* dE)
+{
+    const double p = tb->bind[z][s] - dE[z];
+    return p < 1.0 ? 1.0 : p;
+}
+
+struct Coll {
+    double d2;        // <delta^2>, or -1 when the relative velocity is zero
+    int acc_a, acc_b;
+};
+
+// Takizuka-Abe binary collision with weighted acceptance (the heavier-weight
+// partner accepts with probability w_light / w_heavy, draw r4).
+__device__ __forceinline__ Coll ta77(double& ax, double& ay, double& az, double& bx, double& by,
+                                     double& bz, double ma, double mb, uint32_t wa, uint32_t wb,
+                                     double coef, double nunit, const Words& d, double r4)
+{
+    Coll out{-1.0, 0, 0};
+    const double ux = ax - bx, uy = ay - by, uz = az - bz;
+    const double u2 = (ux * ux + uy * uy) + uz * uz;
+    if (u2 == 0.0) return out;
+    const uint32_t wmax = wa > wb ? wa : wb;
+    const double u = sqrt(u2);
+    const double d2 = ((coef * (double)wmax) * nunit) / (u2 * u);
+    double s2, c2;
+    xsincos2pi((uint64_t)d.x2 << 20, s2, c2);
+    const double g = sqrt(-2.0 * xlog(u52(d.x0, d.x1))) * c2;
+    const double dl = sqrt(d2) * g;
+    const double dd = dl * dl;
+    const double den = 1.0 + dd;
+    const double st = (2.0 * dl) / den;
+    const double omc = (2.0 * dd) / den;
+    double sp, cp;
+    xsincos2pi((uint64_t)d.x3 << 20, sp, cp);
+    const double a = st * cp;
+    const double bb = st * sp;
+    const double up = sqrt(ux * ux + uy * uy);
+    double dux, duy, duz;
+    if (up > 0.0) {
+        dux = ((ux / up) * uz) * a - ((uy / up) * u) * bb - ux * omc;
+        duy = ((uy / up) * uz) * a + ((ux / up) * u) * bb - uy * omc;
+        duz = -(up * a) - uz * omc;
+    } else {
+        const double auz = fabs(uz);
+        dux = auz * a;
+        duy = auz * bb;
+        duz = -(uz * omc);
+    }
+    const bool ta = (wa <= wb) || (r4 < (double)wb / (double)wa);
+    const bool tb = (wb <= wa) || (r4 < (double)wa / (double)wb);
+    const double fa = mb / (ma + mb);
+    const double fb = ma / (ma + mb);
+    if (ta) {
+        ax = ax + fa * dux;
+        ay = ay + fa * duy;
+        az = az + fa * duz;
+    }
+    if (tb) {
+        bx = bx - fb * dux;
+        by = by - fb * duy;
+        bz = bz - fb * duz;
+    }
+    out.d2 = d2;
+    out.acc_a = ta;
+    out.acc_b = tb;
+    return out;
+}
+
+}  // namespace xpd

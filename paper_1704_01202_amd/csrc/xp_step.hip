@@ -1,0 +1,800 @@
+// The per-cell Monte-Carlo step (Sec. II-V): one workgroup per cell, the
+// cell's particles staged in LDS, every stage of the step in one pass.
+//
+// Work decomposition inside a cell:
+//   * moments, Lotz cross sections, per-ion draws and rescales: one thread per
+//     particle (strided loops over the block);
+//   * random permutations: 64-bit keys (Philox word << 32 | slot) sorted by a
+//     bitonic network in LDS;
+//   * e-e pairs: one thread per pair, the odd triplet on thread 0;
+//   * e-i pairs: one thread per pair within a round, rounds separated by
+//     barriers (a round touches every ion at most once);
+//   * accept-in-order decisions (ionization energy budget, recombination
+//     sequence) on thread 0 over the few selected events;
+//   * appends / removals: ordered compaction with wave ballots.
+// Global memory is touched twice per particle: one coalesced read of the
+// cell's slab at the start, one coalesced write at the end.
+#include <hip/hip_runtime.h>
+
+#include "xp_kernels.h"
+#include "xp_physics.h"
+
+namespace xpd {
+
+namespace {
+
+struct CellShared {
+    double red[16];
+    long long ired[16];
+    int sel[16];
+    int cnt[XP_NCOUNT];
+    double led[XP_NLEDGER];
+    double mom[XP_NMOM];
+    double sig[XP_MAX_BINS][3];
+    double ssum[13][3];
+    double dbl[8];
+    int ints[8];
+};
+
+struct Lds {
+    double *evx, *evy, *evz;
+    uint32_t* ew;
+    int32_t* eorg;     // position source: >= 0 old slot, < 0 new electron of ion (-1 - i)
+    int32_t* perm_e;
+    uint8_t* esel;
+    double *ivx, *ivy, *ivz;
+    uint8_t *iz, *ik;
+    int32_t* perm_i;
+    int32_t* list;
+    uint8_t *z0, *k0, *emask;
+    uint16_t* ebins;
+    uint64_t* sbuf;
+};
+
+__device__ __forceinline__ Lds carve(unsigned char* base, int ce, int ci, int ps)
+{
+    Lds L;
+    unsigned char* p = base;
+    auto take = [&](size_t bytes) {
+        unsigned char* r = p;
+        p += (bytes + 15) & ~size_t(15);
+        return r;
+    };
+    L.sbuf = (uint64_t*)take(sizeof(uint64_t) * ps);
+    L.evx = (double*)take(sizeof(double) * ce);
+    L.evy = (double*)take(sizeof(double) * ce);
+    L.evz = (double*)take(sizeof(double) * ce);
+    L.ivx = (double*)take(sizeof(double) * ci);
+    L.ivy = (double*)take(sizeof(double) * ci);
+    L.ivz = (double*)take(sizeof(double) * ci);
+    L.ew = (uint32_t*)take(sizeof(uint32_t) * ce);
+    L.eorg = (int32_t*)take(sizeof(int32_t) * ce);
+    L.perm_e = (int32_t*)take(sizeof(int32_t) * ce);
+    L.perm_i = (int32_t*)take(sizeof(int32_t) * ci);
+    L.list = (int32_t*)take(sizeof(int32_t) * ci);
+    L.ebins = (uint16_t*)take(sizeof(uint16_t) * ci);
+    L.esel = (uint8_t*)take(ce);
+    L.iz = (uint8_t*)take(ci);
+    L.ik = (uint8_t*)take(ci);
+    L.z0 = (uint8_t*)take(ci);
+    L.k0 = (uint8_t*)take(ci);
+    L.emask = (uint8_t*)take(ci);
+    return L;
+}
+
+__host__ __device__ inline int pow2_at_least(int n)
+{
+    int p = 1;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+size_t step_lds_bytes(int ce, int ci)
+{
+    const int ps = pow2_at_least(ce > ci ? ce : ci);
+    auto r = [](size_t b) { return (b + 15) & ~size_t(15); };
+    size_t n = r(8ull * ps) + 3 * r(8ull * ce) + 3 * r(8ull * ci) + 3 * r(4ull * ce) +
+               2 * r(4ull * ci) + r(2ull * ci) + r(ce) + 5 * r(ci);
+    return n;
+}
+
+template <int B>
+__global__ __launch_bounds__(B) void k_step(StepArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ CellShared S;
+    const int tid = threadIdx.x;
+    const int cell = a.cell_list ? a.cell_list[blockIdx.x] : (int)blockIdx.x;
+    if (cell < 0 || cell >= a.n_cells) return;
+    const int run = a.cell_run[cell];
+    const xp_run* R = a.runs + run;
+    const DevTables* tb = a.tab;
+    const uint32_t lcell = (uint32_t)(cell - R->cell_begin);
+    const uint32_t step = a.d_step ? a.d_step[run] : a.step;
+    const uint32_t key0 = (uint32_t)R->seed, key1 = (uint32_t)(R->seed >> 32);
+    const uint32_t flags = a.flags;
+    const double w0 = R->w0, vol = R->volume, dt = R->dt;
+    const double mi = tb->mass_ion;
+
+    int ne = a.e_cnt[cell];
+    const int ecap = a.e_cap[cell];
+    const int ni = a.i_cnt[cell];
+    const int64_t eo = a.e_off[cell], io = a.i_off[cell];
+    const int ce = a.lds_ce, ci = a.lds_ci;
+    const int ps = pow2_at_least(ce > ci ? ce : ci);
+    Lds L = carve(smem, ce, ci, ps);
+
+    // cells larger than this launch's LDS plan are left for another schedule
+    if (ne > ce || ni > ci || ecap > ce) {
+        if (tid == 0) atomicOr(a.status, XP_ST_CAPACITY);
+        return;
+    }
+
+    auto rng = [&](uint32_t idx, uint32_t purpose, uint32_t sub) {
+        return philox(step, lcell, idx, (purpose << 24) | sub, key0, key1);
+    };
+
+    for (int j = tid; j < ne; j += B) {
+        L.evx[j] = a.evx[eo + j];
+        L.evy[j] = a.evy[eo + j];
+        L.evz[j] = a.evz[eo + j];
+        L.ew[j] = a.ew[eo + j];
+        L.eorg[j] = j;
+    }
+    for (int j = tid; j < ni; j += B) {
+        L.ivx[j] = a.ivx[io + j];
+        L.ivy[j] = a.ivy[io + j];
+        L.ivz[j] = a.ivz[io + j];
+        L.iz[j] = a.iz[io + j];
+        L.ik[j] = a.ik[io + j];
+    }
+    for (int q = tid; q < XP_NCOUNT; q += B) S.cnt[q] = 0;
+    for (int q = tid; q < XP_NLEDGER; q += B) S.led[q] = 0.0;
+    for (int q = tid; q < XP_NMOM; q += B) S.mom[q] = 0.0;
+    if (tid < 8) S.ints[tid] = 0;
+    __syncthreads();
+
+    // ---------------- S0: moments and continuum lowering -----------------
+    const double ebulk = R->e_bulk;
+    auto kin = [&](int j) {
+        const double x = L.evx[j], y = L.evy[j], z = L.evz[j];
+        return HALF_ME_OVER_QE * ((x * x + y * y) + z * z);
+    };
+    auto moments_bulk = [&](int n, long long& we, long long& wb, double& ke) {
+        long long w_loc = 0, b_loc = 0;
+        for (int j = tid; j < n; j += B) {
+            const long long w = L.ew[j];
+            w_loc += w;
+            if (kin(j) < ebulk) b_loc += w;
+        }
+        we = block_isum<B>(w_loc, S.ired);
+        wb = block_isum<B>(b_loc, S.ired);
+        ke = block_tree_sum<B>(n, [&](int j) {
+            const double e = kin(j);
+            return e < ebulk ? (double)L.ew[j] * e : 0.0;
+        }, S.red);
+    };
+    auto ion_sums = [&](long long& sz, long long& sz2) {
+        long long s1 = 0, s2 = 0;
+        for (int j = tid; j < ni; j += B) {
+            const long long z = L.iz[j];
+            s1 += z;
+            s2 += z * z;
+        }
+        sz = block_isum<B>(s1, S.ired);
+        sz2 = block_isum<B>(s2, S.ired);
+    };
+
+    long long we, wb, sz, sz2;
+    double ke;
+    moments_bulk(ne, we, wb, ke);
+    ion_sums(sz, sz2);
+    const long long wi = ni;
+    double tmp = 0.01;
+    if (wb > 0) {
+        tmp = (2.0 * ke) / (3.0 * (double)wb);
+        if (tmp < 0.01) tmp = 0.01;
+    }
+    const double t_e = tmp;
+    const double n_e = ((double)we * w0) / vol;
+    const double n_i = ((double)wi * w0) / vol;
+    const double zbar = wi > 0 ? (double)sz / (double)wi : 0.0;
+    const double zstar = sz > 0 ? (double)sz2 / (double)sz : 0.0;
+    if (tid < 13) S.mom[16 + tid] = ipd(R->ipd_model, tid, t_e, n_e, n_i, zbar, zstar);
+    if (tid == 13)
+        S.mom[10] = R->lnl_fixed > 0.0 ? R->lnl_fixed : coulomb_log(t_e, n_e, zbar);
+    if (tid == 0) {
+        S.mom[0] = (double)we; S.mom[1] = (double)wi; S.mom[2] = (double)sz;
+        S.mom[3] = (double)sz2; S.mom[4] = ke; S.mom[5] = t_e; S.mom[6] = n_e;
+        S.mom[7] = n_i; S.mom[8] = zbar; S.mom[9] = zstar;
+    }
+    __syncthreads();
+    const double* dE = S.mom + 16;
+    const double lnl = S.mom[10];
+
+    // ------------- random permutations: sort (Philox key, slot) ---------------
+    auto make_perm = [&](uint32_t purpose, int n, int32_t* out) {
+        const int p = pow2_at_least(n);
+        for (int g = tid; 4 * g < n; g += B) {
+            const Words w = rng((uint32_t)g, purpose, 0);
+            const uint32_t k4[4] = {w.x0, w.x1, w.x2, w.x3};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = 4 * g + q;
+                if (i < n) L.sbuf[i] = ((uint64_t)k4[q] << 32) | (uint32_t)i;
+            }
+        }
+        for (int i = n + tid; i < p; i += B) L.sbuf[i] = ~0ull;
+        __syncthreads();
+        bitonic_sort<B>(L.sbuf, p);
+        for (int k = tid; k < n; k += B) out[k] = (int32_t)(uint32_t)L.sbuf[k];
+        __syncthreads();
+    };
+
+    auto collide = [&](int e, bool ion_b, int b, double coef, double nunit, uint32_t idx,
+                       uint32_t purpose) {
+        double ax = L.evx[e], ay = L.evy[e], az = L.evz[e];
+        double bx, by, bz, mb;
+        const uint32_t wa = L.ew[e];
+        uint32_t wbb;
+        if (ion_b) {
+            bx = L.ivx[b]; by = L.ivy[b]; bz = L.ivz[b];
+            wbb = 1;
+            mb = mi;
+        } else {
+            bx = L.evx[b]; by = L.evy[b]; bz = L.evz[b];
+            wbb = L.ew[b];
+            mb = ME;
+        }
+        const Words d = rng(idx, purpose, 0);
+        double r4 = 0.5;
+        if (wa != wbb) {
+            const Words d4 = rng(idx, purpose, 1);
+            r4 = u52(d4.x0, d4.x1);
+        }
+        const Coll c = ta77(ax, ay, az, bx, by, bz, ME, mb, wa, wbb, coef, nunit, d, r4);
+        if (c.d2 < 0.0) {
+            atomicAdd(&S.cnt[XP_C_U0], 1);
+            return;
+        }
+        if (c.d2 > 1.0) atomicAdd(&S.cnt[XP_C_DELTA2_GT1], 1);
+        atomicAdd(&S.cnt[XP_C_ACCEPT], c.acc_a + c.acc_b);
+        L.evx[e] = ax; L.evy[e] = ay; L.evz[e] = az;
+        if (ion_b) {
+            L.ivx[b] = bx; L.ivy[b] = by; L.ivz[b] = bz;
+        } else {
+            L.evx[b] = bx; L.evy[b] = by; L.evz[b] = bz;
+        }
+    };
+
+    const double qe4 = (QE * QE) * (QE * QE);
+
+    // ---------------- S1: electron-electron collisions ----------------
+    if ((flags & (XP_EE | XP_EI)) && ne >= 1 && (ne >= 2 || ni >= 1)) make_perm(RP_PERM_E, ne, L.perm_e);
+    if ((flags & XP_EE) && ne >= 2) {
+        const double mee = (ME * ME) / (ME + ME);
+        const double kee = qe4 / (((8.0 * PI) * (EPS0 * EPS0)) * (mee * mee));
+        const double afull = (kee * lnl) * dt;
+        const double ahalf = (kee * lnl) * (0.5 * dt);
+        const double nunit = (w0 * (double)ne) / vol;
+        const int start = (ne % 2 == 1 && ne >= 3) ? 3 : 0;
+        const int npairs = (ne - start) / 2;
+        if (tid == 0 && start == 3) {
+            const int32_t* p = L.perm_e;
+            collide(p[0], false, p[1], ahalf, nunit, 0, RP_EE_TRI);
+            collide(p[1], false, p[2], ahalf, nunit, 1, RP_EE_TRI);
+            collide(p[2], false, p[0], ahalf, nunit, 2, RP_EE_TRI);
+            S.cnt[XP_C_TRIPLET] += 3;
+        }
+        for (int j = tid; j < npairs; j += B)
+            collide(L.perm_e[start + 2 * j], false, L.perm_e[start + 2 * j + 1], afull, nunit,
+                    (uint32_t)j, RP_EE);
+        if (tid == 0) S.cnt[XP_C_EE] += npairs;
+        __syncthreads();
+    }
+
+    // ---------------- S2: electron-ion collisions ----------------
+    if ((flags & XP_EI) && ne >= 1 && ni >= 1) {
+        make_perm(RP_PERM_I, ni, L.perm_i);
+        const double mei = (ME * mi) / (ME + mi);
+        const double kei = qe4 / (((8.0 * PI) * (EPS0 * EPS0)) * (mei * mei));
+        const double a1 = (kei * lnl) * dt;
+        const int nmin = ne < ni ? ne : ni, nmax = ne < ni ? ni : ne;
+        const double nunit = (w0 * (double)nmin) / vol;
+        for (int r0 = 0; r0 < nmax; r0 += nmin) {
+            const int r1 = r0 + nmin < nmax ? r0 + nmin : nmax;
+            for (int k = r0 + tid; k < r1; k += B) {
+                int e, i;
+                if (ne >= ni) { e = L.perm_e[k]; i = L.perm_i[k % ni]; }
+                else          { i = L.perm_i[k]; e = L.perm_e[k % ne]; }
+                const int z = L.iz[i];
+                if (z == 0) continue;
+                collide(e, true, i, a1 * (double)(z * z), nunit, (uint32_t)k, RP_EI);
+            }
+            __syncthreads();
+        }
+        if (tid == 0) S.cnt[XP_C_EI] += nmax;
+    }
+
+    bool overflow = false;
+
+    // ---------------- S3: collisional ionization ----------------
+    if ((flags & XP_ION) && ne >= 1 && ni >= 1) {
+        long long szi, sz2i;
+        ion_sums(szi, sz2i);
+        const int zc = (int)((2 * szi + wi) / (2 * wi));
+        const int ne0 = ne;
+        if (tid == 0) S.mom[11] = (double)zc;
+        if (zc < 13) {
+            const Occ oc = occupancy(zc, 0);
+            double pp[5], lnp[5];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                const double raw = tb->bind[zc][q] - dE[zc];
+                pp[q] = raw < 1.0 ? 1.0 : raw;
+                lnp[q] = oc.s[q] > 0 ? xlog(pp[q]) : 0.0;
+                if (tid == 0 && oc.s[q] > 0 && raw < 1.0) S.cnt[XP_C_IPD_CLAMPED] += 1;
+            }
+            const double ssum = block_tree_sum<B>(ne0, [&](int j) {
+                const double x = L.evx[j], y = L.evy[j], z = L.evz[j];
+                const double v2 = (x * x + y * y) + z * z;
+                const double e = HALF_ME_OVER_QE * v2;
+                double sig = 0.0;
+                if (e > 0.0) {
+                    const double lne = xlog(e);
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) {
+                        if (oc.s[q] <= 0 || !(e > pp[q])) continue;
+                        double term = (((tb->lotz_a[q] * 1.0e-4) * (double)oc.s[q]) * (lne - lnp[q])) /
+                                      (e * pp[q]);
+                        if (tb->lotz_b[q] != 0.0)
+                            term = term * (1.0 - tb->lotz_b[q] *
+                                                     xexp(-(tb->lotz_c[q] * (e / pp[q] - 1.0))));
+                        sig = sig + term;
+                    }
+                }
+                return ((double)L.ew[j] * sig) * sqrt(v2);
+            }, S.red);
+            double p = ((ssum * w0) * dt) / vol;
+            if (p > 1.0) {
+                p = 1.0;
+                if (tid == 0) S.cnt[XP_C_P_CLAMPED] += 1;
+            }
+            if (tid == 0) S.mom[12] = p;
+            const int nfired = block_ordered_select<B>(
+                ni,
+                [&](int i) {
+                    if (L.iz[i] >= 13 || !(p > 0.0)) return false;
+                    const Words d = rng((uint32_t)i, RP_ION, 0);
+                    return u52(d.x0, d.x1) < p;
+                },
+                [&](int i, int pos) { L.list[pos] = i; }, S.sel);
+            if (tid == 0) S.cnt[XP_C_ION_FIRED] += nfired;
+            __syncthreads();
+            if (nfired > 0) {
+                long long ws_loc = 0;
+                for (int j = tid; j < ne0; j += B) ws_loc += L.ew[j];
+                const long long ws = block_isum<B>(ws_loc, S.ired);
+                const double ux = block_tree_sum<B>(ne0, [&](int j) { return (double)L.ew[j] * L.evx[j]; }, S.red) / (double)ws;
+                const double uy = block_tree_sum<B>(ne0, [&](int j) { return (double)L.ew[j] * L.evy[j]; }, S.red) / (double)ws;
+                const double uz = block_tree_sum<B>(ne0, [&](int j) { return (double)L.ew[j] * L.evz[j]; }, S.red) / (double)ws;
+                const double kth = block_tree_sum<B>(ne0, [&](int j) {
+                    const double dx = L.evx[j] - ux, dy = L.evy[j] - uy, dz = L.evz[j] - uz;
+                    return (double)L.ew[j] * (HALF_ME_OVER_QE * ((dx * dx + dy * dy) + dz * dz));
+                }, S.red);
+                if (tid == 0) {
+                    S.mom[13] = kth;
+                    double debit = 0.0;
+                    int acc = 0;
+                    for (int q = 0; q < nfired; ++q) {
+                        const int i = L.list[q];
+                        const int z = L.iz[i], kv = L.ik[i];
+                        const int sv = valence(z, kv);
+                        const double ip = lowered(tb, z, sv, dE);
+                        if (!(debit + ip <= kth)) break;
+                        const int slot = ne0 + acc;
+                        if (slot >= ecap) {
+                            S.ints[0] = 1;   // overflow
+                            break;
+                        }
+                        debit = debit + ip;
+                        L.iz[i] = (uint8_t)(z + 1);
+                        if (sv == 0) L.ik[i] = (uint8_t)(kv + 1);
+                        L.evx[slot] = 0.0; L.evy[slot] = 0.0; L.evz[slot] = 0.0;
+                        L.ew[slot] = 1;
+                        L.eorg[slot] = -1 - i;
+                        S.led[XP_L_ION_DEBIT] += ip;
+                        ++acc;
+                    }
+                    S.cnt[XP_C_ION_ACCEPTED] += acc;
+                    S.cnt[XP_C_ION_STARVED] += nfired - acc;
+                    S.cnt[XP_C_E_NEW] += acc;
+                    S.mom[14] = debit;
+                    S.dbl[0] = debit;
+                    S.ints[1] = acc;
+                }
+                __syncthreads();
+                if (S.ints[0]) overflow = true;
+                const double debit = S.dbl[0];
+                const int acc = S.ints[1];
+                if (debit > 0.0) {
+                    const double alpha = sqrt(1.0 - debit / kth);
+                    for (int j = tid; j < ne0; j += B) {
+                        L.evx[j] = ux + alpha * (L.evx[j] - ux);
+                        L.evy[j] = uy + alpha * (L.evy[j] - uy);
+                        L.evz[j] = uz + alpha * (L.evz[j] - uz);
+                    }
+                }
+                ne = ne0 + acc;
+                __syncthreads();
+            }
+        }
+    }
+
+    // ---------------- S4: three-body recombination ----------------
+    if (!overflow && (flags & XP_REC) && ne >= 1 && ni >= 1) {
+        long long szr, sz2r, wer, wbr;
+        double ker;
+        ion_sums(szr, sz2r);
+        moments_bulk(ne, wer, wbr, ker);
+        double tp = 0.01;
+        if (wbr > 0) {
+            tp = (2.0 * ker) / (3.0 * (double)wbr);
+            if (tp < 0.01) tp = 0.01;
+        }
+        if (tid == 0) S.mom[15] = tp;
+        const double zeos = eos_zbar(tb, n_i, tp);
+        const double dd = (double)szr - (double)ni * zeos;
+        if (dd > 0.0) {
+            long long nrec = (long long)floor(dd + 0.5);
+            long long el = 0;
+            for (int j = tid; j < ni; j += B) el += L.iz[j] > R->z_floor ? 1 : 0;
+            const long long nelig = block_isum<B>(el, S.ired);
+            if (nrec > nelig) nrec = nelig;
+            if (nrec > ne) nrec = ne;
+            if (nrec > 0) {
+                const int nr = (int)nrec;
+                make_perm(RP_REC_I, ni, L.perm_i);
+                make_perm(RP_REC_E, ne, L.perm_e);
+                const int zf = R->z_floor;
+                block_ordered_select<B>(
+                    ni, [&](int q) { return (int)L.iz[L.perm_i[q]] > zf; },
+                    [&](int q, int pos) {
+                        if (pos < nr) L.list[pos] = L.perm_i[q];
+                    },
+                    S.sel);
+                for (int j = tid; j < ne; j += B) L.esel[j] = 0;
+                __syncthreads();
+                for (int t = tid; t < nr; t += B) L.esel[L.perm_e[t]] = 1;
+                __syncthreads();
+                auto wp = [&](int j) { return (long long)L.ew[j] - (long long)L.esel[j]; };
+                long long wsl = 0;
+                for (int j = tid; j < ne; j += B) wsl += wp(j);
+                const long long ws = block_isum<B>(wsl, S.ired);
+                double ux = 0.0, uy = 0.0, uz = 0.0, kth = 0.0;
+                if (ws != 0) {
+                    ux = block_tree_sum<B>(ne, [&](int j) { return (double)wp(j) * L.evx[j]; }, S.red) / (double)ws;
+                    uy = block_tree_sum<B>(ne, [&](int j) { return (double)wp(j) * L.evy[j]; }, S.red) / (double)ws;
+                    uz = block_tree_sum<B>(ne, [&](int j) { return (double)wp(j) * L.evz[j]; }, S.red) / (double)ws;
+                    kth = block_tree_sum<B>(ne, [&](int j) {
+                        const double dx = L.evx[j] - ux, dy = L.evy[j] - uy, dz = L.evz[j] - uz;
+                        return (double)wp(j) * (HALF_ME_OVER_QE * ((dx * dx + dy * dy) + dz * dz));
+                    }, S.red);
+                }
+                if (ws == 0 || !(kth > 0.0)) {
+                    if (tid == 0) S.cnt[XP_C_REC_SKIPPED] += 1;
+                } else {
+                    if (tid == 0) {
+                        const double half_mi = (0.5 * mi) / QE;
+                        const double ratio = ME / mi;
+                        double eadd = 0.0;
+                        for (int t = 0; t < nr; ++t) {
+                            const int e = L.perm_e[t], i = L.list[t];
+                            const double keu = kin(e);
+                            const double v2b = (L.ivx[i] * L.ivx[i] + L.ivy[i] * L.ivy[i]) + L.ivz[i] * L.ivz[i];
+                            const double kib = half_mi * v2b;
+                            L.ivx[i] = L.ivx[i] + ratio * L.evx[e];
+                            L.ivy[i] = L.ivy[i] + ratio * L.evy[e];
+                            L.ivz[i] = L.ivz[i] + ratio * L.evz[e];
+                            const double v2a = (L.ivx[i] * L.ivx[i] + L.ivy[i] * L.ivy[i]) + L.ivz[i] * L.ivz[i];
+                            const double kia = half_mi * v2a;
+                            const int z = L.iz[i], kv = L.ik[i];
+                            const Occ o0 = occupancy(z, kv);
+                            const int kn = (kv >= 1 && o0.s[1] + o0.s[2] == 8) ? kv - 1 : kv;
+                            const Occ o1 = occupancy(z - 1, kn);
+                            int sl = 0;
+                            for (int q = 0; q < 5; ++q)
+                                if (o1.s[q] > o0.s[q]) { sl = q; break; }
+                            const double ipr = lowered(tb, z - 1, sl, dE);
+                            L.iz[i] = (uint8_t)(z - 1);
+                            L.ik[i] = (uint8_t)kn;
+                            eadd = eadd + ((keu + ipr) + (kib - kia));
+                            S.led[XP_L_REC_BIND] += ipr;
+                        }
+                        S.cnt[XP_C_REC] += nr;
+                        S.led[XP_L_REC_ADD] += eadd;
+                        S.dbl[1] = eadd;
+                    }
+                    __syncthreads();
+                    const double alpha = sqrt(1.0 + S.dbl[1] / kth);
+                    for (int j = tid; j < ne; j += B) {
+                        const long long w2 = wp(j);
+                        if (w2 > 0) {
+                            L.evx[j] = ux + alpha * (L.evx[j] - ux);
+                            L.evy[j] = uy + alpha * (L.evy[j] - uy);
+                            L.evz[j] = uz + alpha * (L.evz[j] - uz);
+                        }
+                        L.ew[j] = (uint32_t)(w2 > 0 ? w2 : 0);
+                    }
+                    __syncthreads();
+                    // stable compaction of the electrons whose weight reached 0,
+                    // chunk by chunk (positions only move down)
+                    int out = 0;
+                    for (int c0 = 0; c0 < ne; c0 += B) {
+                        const int j = c0 + tid;
+                        const bool alive = j < ne && L.ew[j] > 0;
+                        double vx = 0, vy = 0, vz = 0;
+                        uint32_t w = 0;
+                        int32_t org = 0;
+                        if (alive) {
+                            vx = L.evx[j]; vy = L.evy[j]; vz = L.evz[j];
+                            w = L.ew[j]; org = L.eorg[j];
+                        }
+                        int dst = 0;
+                        const int tot = block_ordered_select<B>(
+                            (c0 + B < ne ? B : ne - c0),
+                            [&](int q) { return L.ew[c0 + q] > 0; },
+                            [&](int q, int pos) { (void)q; dst = pos; }, S.sel);
+                        __syncthreads();
+                        if (alive) {
+                            const int d = out + dst;
+                            L.evx[d] = vx; L.evy[d] = vy; L.evz[d] = vz;
+                            L.ew[d] = w; L.eorg[d] = org;
+                        }
+                        out += tot;
+                        __syncthreads();
+                    }
+                    if (tid == 0) S.cnt[XP_C_E_REMOVED] += ne - out;
+                    ne = out;
+                }
+                __syncthreads();
+            }
+        }
+    }
+
+    // ---------------- S5: K-vacancy decay and photoionization ----------------
+    if (!overflow && (flags & (XP_PHOTO | XP_DECAY))) {
+        const int nb = R->n_bins;
+        const bool photo = (flags & XP_PHOTO) && nb > 0;
+        const double* nhv = (R->field_per_cell && a.cell_nhv) ? a.cell_nhv + (size_t)cell * XP_MAX_BINS : R->nhv;
+        const double dtr = R->dt_rad;
+        if (photo) {
+            for (int q = tid; q < 3 * nb; q += B) S.sig[q / 3][q % 3] = photo_sigma(tb, q % 3, R->hv[q / 3]);
+            __syncthreads();
+            for (int q = tid; q < 39; q += B) {
+                const int z = q / 3, s = q % 3;
+                const double pp = lowered(tb, z, s, dE);
+                double acc = 0.0;
+                for (int bq = 0; bq < nb; ++bq)
+                    if (R->hv[bq] >= pp) acc = acc + nhv[bq] * S.sig[bq][s];
+                S.ssum[z][s] = acc;
+            }
+            __syncthreads();
+        }
+        // pass 1: decisions per ion from its pre-S5 state
+        for (int i = tid; i < ni; i += B) {
+            const int z0 = L.iz[i], k0 = L.ik[i];
+            L.z0[i] = (uint8_t)z0;
+            L.k0[i] = (uint8_t)k0;
+            uint8_t mask = 0;
+            uint16_t bins = 0;
+            if (z0 < 13) {
+                const Occ o0 = occupancy(z0, k0);
+                const int nl0 = o0.s[1] + o0.s[2];
+                int z = z0, kv = k0;
+                if ((flags & XP_DECAY) && k0 >= 1 && nl0 >= 1) {
+                    const double ga = tb->gamma_a[z0][k0], gx = tb->gamma_x[z0][k0];
+                    const double rate = ga + gx;
+                    if (rate > 0.0) {
+                        const Words d = rng((uint32_t)i, RP_S5, 0);
+                        double pd = dtr * rate;
+                        if (pd > 1.0) {
+                            pd = 1.0;
+                            atomicAdd(&S.cnt[XP_C_P_CLAMPED], 1);
+                        }
+                        if (u52(d.x0, d.x1) < pd) {
+                            kv = k0 - 1;
+                            atomicAdd(&S.cnt[XP_C_DECAY], 1);
+                            if (nl0 >= 2 && u52(d.x2, d.x3) < ga / rate) {
+                                z = z0 + 1;
+                                mask |= 1;
+                                atomicAdd(&S.cnt[XP_C_AUGER], 1);
+                            } else {
+                                atomicAdd(&S.cnt[XP_C_KALPHA], 1);
+                                atomicAdd(&S.led[XP_L_KALPHA], tb->e_kalpha[z0]);
+                            }
+                        }
+                    }
+                }
+                if (photo) {
+                    for (int s = 0; s < 3; ++s) {
+                        if (o0.s[s] <= 0) continue;
+                        const double sum = S.ssum[z0][s];
+                        if (!(sum > 0.0)) continue;
+                        double p = ((CLIGHT * dtr) * (double)o0.s[s]) * sum;
+                        if (p > 1.0) {
+                            p = 1.0;
+                            atomicAdd(&S.cnt[XP_C_P_CLAMPED], 1);
+                        }
+                        const Words d = rng((uint32_t)i, RP_S5, (uint32_t)(1 + s));
+                        if (!(u52(d.x0, d.x1) < p)) continue;
+                        const Occ on = occupancy(z, kv);
+                        if (z >= 13 || on.s[s] <= 0) {
+                            atomicAdd(&S.cnt[XP_C_PHOTO_SKIPPED], 1);
+                            continue;
+                        }
+                        const double pp = lowered(tb, z0, s, dE);
+                        const double target = u52(d.x2, d.x3) * sum;
+                        double cum = 0.0;
+                        int sel = -1, lastpos = -1;
+                        for (int bq = 0; bq < nb; ++bq) {
+                            if (!(R->hv[bq] >= pp)) continue;
+                            const double term = nhv[bq] * S.sig[bq][s];
+                            cum = cum + term;
+                            if (term > 0.0) lastpos = bq;
+                            if (cum > target) {
+                                sel = bq;
+                                break;
+                            }
+                        }
+                        if (sel < 0) sel = lastpos;
+                        z = z + 1;
+                        if (s == 0) kv = kv + 1;
+                        mask |= (uint8_t)(2u << s);
+                        bins |= (uint16_t)(sel << (4 * s));
+                        atomicAdd(&S.cnt[XP_C_PHOTO_1S + s], 1);
+                    }
+                }
+                L.iz[i] = (uint8_t)z;
+                L.ik[i] = (uint8_t)kv;
+            }
+            L.emask[i] = mask;
+            L.ebins[i] = bins;
+        }
+        __syncthreads();
+        // pass 2: new electrons in ion-slot order (Auger, photo 1s, 2s, 2p)
+        int base_pos = ne;
+        for (int c0 = 0; c0 < ni; c0 += B) {
+            const int i = c0 + tid;
+            const int cnt = i < ni ? __popc((unsigned)L.emask[i]) : 0;
+            // exclusive prefix of cnt over the chunk (slot order)
+            int incl = cnt;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int o = __shfl_up(incl, off, 64);
+                if ((tid & 63) >= off) incl += o;
+            }
+            if (B > 64) {
+                __syncthreads();
+                if ((tid & 63) == 63) S.sel[tid >> 6] = incl;
+                __syncthreads();
+            }
+            int woff = 0, tot = __shfl(incl, 63, 64);
+            if (B > 64) {
+                tot = 0;
+                for (int w = 0; w < B / 64; ++w) {
+                    if (w < (tid >> 6)) woff += S.sel[w];
+                    tot += S.sel[w];
+                }
+            }
+            int pos = base_pos + woff + incl - cnt;
+            if (cnt > 0) {
+                const int z0 = L.z0[i], k0 = L.k0[i];
+                const Occ o0 = occupancy(z0, k0);
+                const uint8_t mask = L.emask[i];
+                for (int bit = 0; bit < 4; ++bit) {
+                    if (!(mask & (1u << bit))) continue;
+                    double en;
+                    if (bit == 0) {
+                        const int nl0 = o0.s[1] + o0.s[2];
+                        const double p2s = lowered(tb, z0, 1, dE);
+                        const double p2p = lowered(tb, z0, 2, dE);
+                        const double num = (double)o0.s[1] * p2s + (double)o0.s[2] * p2p;
+                        en = tb->e_kalpha[z0] - num / (double)nl0;
+                        if (en < 0.0) en = 0.0;
+                        atomicAdd(&S.led[XP_L_AUGER_E], en);
+                    } else {
+                        const int s = bit - 1;
+                        const int sel = (L.ebins[i] >> (4 * s)) & 15;
+                        en = R->hv[sel] - lowered(tb, z0, s, dE);
+                        atomicAdd(&S.led[XP_L_PHOTO_E], en);
+                        atomicAdd(&S.led[XP_L_PHOTON_ABS], R->hv[sel]);
+                    }
+                    if (pos < ecap) {
+                        const Words d = rng((uint32_t)i, RP_DIR, (uint32_t)bit);
+                        const double mu = 2.0 * u52(d.x0, d.x1) - 1.0;
+                        double sp, cp;
+                        xsincos2pi((((uint64_t)d.x2 << 32) | d.x3) >> 12, sp, cp);
+                        const double st = sqrt(1.0 - mu * mu);
+                        const double sv = sqrt(en * TWO_QE_OVER_ME);
+                        L.evx[pos] = sv * (st * cp);
+                        L.evy[pos] = sv * (st * sp);
+                        L.evz[pos] = sv * mu;
+                        L.ew[pos] = 1;
+                        L.eorg[pos] = -1 - i;
+                    }
+                    ++pos;
+                }
+            }
+            base_pos += tot;
+            if (B > 64) __syncthreads();
+        }
+        if (tid == 0) S.cnt[XP_C_E_NEW] += base_pos - ne;
+        if (base_pos > ecap) overflow = true;
+        ne = base_pos;
+        __syncthreads();
+    }
+
+    // ---------------- commit ----------------
+    if (overflow) {
+        if (tid == 0) atomicOr(a.status, XP_ST_CAPACITY);
+        return;
+    }
+    bool bad = false;
+    for (int j = tid; j < ne; j += B) {
+        const double x = L.evx[j], y = L.evy[j], z = L.evz[j];
+        bad |= !(__builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z));
+        a.evx[eo + j] = x;
+        a.evy[eo + j] = y;
+        a.evz[eo + j] = z;
+        a.ew[eo + j] = L.ew[j];
+    }
+    for (int j = tid; j < ni; j += B) {
+        a.ivx[io + j] = L.ivx[j];
+        a.ivy[io + j] = L.ivy[j];
+        a.ivz[io + j] = L.ivz[j];
+        a.iz[io + j] = L.iz[j];
+        a.ik[io + j] = L.ik[j];
+    }
+    if (bad) atomicOr(a.status, XP_ST_NONFINITE);
+    __syncthreads();
+    // positions of moved or new electrons: gather into LDS first, then write
+    for (int j = tid; j < ne; j += B) {
+        const int org = L.eorg[j];
+        if (org == j) continue;
+        if (org >= 0) {
+            L.evx[j] = a.ex[eo + org];
+            L.evy[j] = a.ey ? a.ey[eo + org] : 0.0;
+        } else {
+            const int i = -1 - org;
+            L.evx[j] = a.ix[io + i];
+            L.evy[j] = a.iy ? a.iy[io + i] : 0.0;
+        }
+    }
+    __syncthreads();
+    for (int j = tid; j < ne; j += B) {
+        if (L.eorg[j] == j) continue;
+        a.ex[eo + j] = L.evx[j];
+        if (a.ey) a.ey[eo + j] = L.evy[j];
+    }
+    if (tid == 0) a.e_cnt[cell] = ne;
+    if (a.cell_cnt)
+        for (int q = tid; q < XP_NCOUNT; q += B) a.cell_cnt[(size_t)cell * XP_NCOUNT + q] = S.cnt[q];
+    if (a.cell_led)
+        for (int q = tid; q < XP_NLEDGER; q += B) a.cell_led[(size_t)cell * XP_NLEDGER + q] = S.led[q];
+    if (a.cell_mom)
+        for (int q = tid; q < XP_NMOM; q += B) a.cell_mom[(size_t)cell * XP_NMOM + q] = S.mom[q];
+    if (a.run_cnt)
+        for (int q = tid; q < XP_NCOUNT; q += B)
+            if (S.cnt[q]) atomicAdd((unsigned long long*)&a.run_cnt[(size_t)run * XP_NCOUNT + q], (unsigned long long)S.cnt[q]);
+    if (a.run_led)
+        for (int q = tid; q < XP_NLEDGER; q += B)
+            if (S.led[q] != 0.0) atomicAdd(&a.run_led[(size_t)run * XP_NLEDGER + q], S.led[q]);
+}
+
+template __global__ void k_step<64>(StepArgs);
+template __global__ void k_step<256>(StepArgs);
+
+}  // namespace xpd

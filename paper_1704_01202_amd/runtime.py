@@ -1,0 +1,280 @@
+"""Device-resident runs driven through the C ABI.
+
+`Context` owns an xp_ctx and the device copy of the atomic tables.  `Batch`
+owns the device memory of one or more independent runs (run table, cell slabs,
+counters, workspace) as torch tensors and calls the library entry points on
+torch's current stream.  Nothing here computes any part of the method.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev(a, device, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to(device)
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+class Context:
+    """An xp_ctx bound to one device with the atomic tables uploaded."""
+
+    def __init__(self, tables, device="cuda:0"):
+        if not torch.cuda.is_available():
+            raise B.XpError("no HIP device is available")
+        self.device = torch.device(device)
+        B.load()
+        self.h = B.xp_ctx_create(self.device.index or 0)
+        s, keep = B.make_tables(tables)
+        nbytes = B.load().xp_table_bytes(C.byref(s))
+        self.table_buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        B.init_species(self.h, s, self.table_buf.data_ptr(), nbytes, _stream())
+        self._keep = keep
+        self.tables = tables
+
+    def close(self):
+        if getattr(self, "h", None):
+            B.xp_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class CompactState:
+    """Particle state gathered into the compact cell-major layout."""
+    e_start: np.ndarray
+    ex: np.ndarray
+    ey: np.ndarray
+    evx: np.ndarray
+    evy: np.ndarray
+    evz: np.ndarray
+    ew: np.ndarray
+    i_start: np.ndarray
+    ix: np.ndarray
+    iy: np.ndarray
+    ivx: np.ndarray
+    ivy: np.ndarray
+    ivz: np.ndarray
+    iz: np.ndarray
+    ik: np.ndarray
+
+    @property
+    def ne_cell(self):
+        return np.diff(self.e_start)
+
+    @property
+    def ni_cell(self):
+        return np.diff(self.i_start)
+
+
+class Batch:
+    """Independent runs resident in device memory.
+
+    runs: list of (workloads.RunSpec, workloads.Particles).  capacity =
+    (electron slots per ion, extra slots) of every cell's electron slab.
+    cell_records keeps per-cell counters, tallies and moments of the last step.
+    """
+
+    def __init__(self, ctx: Context, runs, capacity=(7, 16), cell_records=False,
+                 cell_nhv=None):
+        self.ctx = ctx
+        dev = ctx.device
+        self.device = dev
+        self.n_runs = len(runs)
+        self.specs = [r[0] for r in runs]
+        structs, begin = [], 0
+        self.cell_begin = []
+        for spec, _ in runs:
+            structs.append(B.make_run(spec, begin, field_per_cell=cell_nhv is not None))
+            self.cell_begin.append(begin)
+            begin += spec.nx * spec.ny
+        self.n_cells = begin
+        arr = (B.XpRun * self.n_runs)(*structs)
+        self.d_runs = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8).to(dev)
+        self.d_cell_run = _dev(np.repeat(np.arange(self.n_runs, dtype=np.int32),
+                                         [s.nx * s.ny for s in self.specs]), dev)
+        nc = max(self.n_cells, 1)
+        self.d_e_off = torch.zeros(nc, dtype=torch.int64, device=dev)
+        self.d_i_off = torch.zeros(nc, dtype=torch.int64, device=dev)
+        self.d_e_cap = torch.zeros(nc, dtype=torch.int32, device=dev)
+        self.d_i_cap = torch.zeros(nc, dtype=torch.int32, device=dev)
+        self.d_e_cnt = torch.zeros(nc, dtype=torch.int32, device=dev)
+        self.d_i_cnt = torch.zeros(nc, dtype=torch.int32, device=dev)
+        self.d_status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.d_need = torch.zeros(4, dtype=torch.int64, device=dev)
+        self.d_run_cnt = torch.zeros((self.n_runs, B.XP_NCOUNT), dtype=torch.int64, device=dev)
+        self.d_run_led = torch.zeros((self.n_runs, B.XP_NLEDGER), dtype=torch.float64, device=dev)
+        self.d_cell_nhv = None
+        if cell_nhv is not None:
+            f = np.zeros((self.n_cells, B.XP_MAX_BINS))
+            f[:, :np.asarray(cell_nhv).shape[1]] = cell_nhv
+            self.d_cell_nhv = _dev(f, dev)
+        self.cell_records = cell_records
+        if cell_records:
+            self.d_cell_cnt = torch.zeros((nc, B.XP_NCOUNT), dtype=torch.int64, device=dev)
+            self.d_cell_led = torch.zeros((nc, B.XP_NLEDGER), dtype=torch.float64, device=dev)
+            self.d_cell_mom = torch.zeros((nc, B.XP_NMOM), dtype=torch.float64, device=dev)
+        else:
+            self.d_cell_cnt = self.d_cell_led = self.d_cell_mom = None
+        self._inputs(runs)
+        self.capacity = B.XpCapacity(int(capacity[0]), int(capacity[1]))
+        self._bin()
+
+    # -- setup ----------------------------------------------------------------
+    def _inputs(self, runs):
+        dev = self.device
+        cat = lambda f: np.concatenate([getattr(p, f) for _, p in runs])
+        self.in_ne = int(sum(p.ne for _, p in runs))
+        self.in_ni = int(sum(p.ni for _, p in runs))
+        self.in_e = {f: _dev(cat(f), dev) for f in ("ex", "ey", "evx", "evy", "evz")}
+        self.in_e["ew"] = _dev(cat("ew").astype(np.uint32).view(np.int32), dev)
+        self.in_i = {f: _dev(cat(f), dev) for f in ("ix", "iy", "ivx", "ivy", "ivz")}
+        self.in_i["iz"] = _dev(cat("iz").astype(np.uint8), dev)
+        self.in_i["ik"] = _dev(cat("ik").astype(np.uint8), dev)
+        self.in_e_run = _dev(np.repeat(np.arange(self.n_runs, dtype=np.int32),
+                                       [p.ne for _, p in runs]), dev)
+        self.in_i_run = _dev(np.repeat(np.arange(self.n_runs, dtype=np.int32),
+                                       [p.ni for _, p in runs]), dev)
+        self.two_d = any(s.ny > 1 for s in self.specs)
+        self.work_bytes = int(B.load().xp_work_bytes(self.in_ne, self.in_ni, self.n_cells,
+                                                     self.n_runs))
+        self.d_work = torch.empty(self.work_bytes, dtype=torch.uint8, device=dev)
+
+    def _alloc_slabs(self, e_slots, i_slots):
+        dev = self.device
+        e, i = max(int(e_slots), 1), max(int(i_slots), 1)
+        self.e_slots, self.i_slots = int(e_slots), int(i_slots)
+        f64 = lambda n: torch.zeros(n, dtype=torch.float64, device=dev)
+        self.ex, self.ey = f64(e), f64(e)
+        self.evx, self.evy, self.evz = f64(e), f64(e), f64(e)
+        self.ew = torch.zeros(e, dtype=torch.int32, device=dev)
+        self.ix, self.iy = f64(i), f64(i)
+        self.ivx, self.ivy, self.ivz = f64(i), f64(i), f64(i)
+        self.iz = torch.zeros(i, dtype=torch.uint8, device=dev)
+        self.ik = torch.zeros(i, dtype=torch.uint8, device=dev)
+
+    def _particles(self):
+        p = B.XpParticles()
+        p.ne, p.ni = self.in_ne, self.in_ni
+        p.d_e_run, p.d_i_run = _ptr(self.in_e_run), _ptr(self.in_i_run)
+        p.d_ex, p.d_ey = _ptr(self.in_e["ex"]), _ptr(self.in_e["ey"]) if self.two_d else None
+        p.d_evx, p.d_evy, p.d_evz = (_ptr(self.in_e[k]) for k in ("evx", "evy", "evz"))
+        p.d_ew = _ptr(self.in_e["ew"])
+        p.d_ix, p.d_iy = _ptr(self.in_i["ix"]), _ptr(self.in_i["iy"]) if self.two_d else None
+        p.d_ivx, p.d_ivy, p.d_ivz = (_ptr(self.in_i[k]) for k in ("ivx", "ivy", "ivz"))
+        p.d_iz, p.d_ik = _ptr(self.in_i["iz"]), _ptr(self.in_i["ik"])
+        return p
+
+    def struct(self) -> B.XpBatch:
+        b = B.XpBatch()
+        b.n_runs, b.n_cells = self.n_runs, self.n_cells
+        b.d_runs, b.d_cell_run = _ptr(self.d_runs), _ptr(self.d_cell_run)
+        b.d_e_off, b.d_e_cap, b.d_e_cnt = _ptr(self.d_e_off), _ptr(self.d_e_cap), _ptr(self.d_e_cnt)
+        b.d_i_off, b.d_i_cap, b.d_i_cnt = _ptr(self.d_i_off), _ptr(self.d_i_cap), _ptr(self.d_i_cnt)
+        b.e_slots, b.i_slots = self.e_slots, self.i_slots
+        if self.e_slots > 0:
+            b.d_ex, b.d_ey = _ptr(self.ex), _ptr(self.ey) if self.two_d else None
+            b.d_evx, b.d_evy, b.d_evz = _ptr(self.evx), _ptr(self.evy), _ptr(self.evz)
+            b.d_ew = _ptr(self.ew)
+        if self.i_slots > 0:
+            b.d_ix, b.d_iy = _ptr(self.ix), _ptr(self.iy) if self.two_d else None
+            b.d_ivx, b.d_ivy, b.d_ivz = _ptr(self.ivx), _ptr(self.ivy), _ptr(self.ivz)
+            b.d_iz, b.d_ik = _ptr(self.iz), _ptr(self.ik)
+        b.d_cell_nhv = _ptr(self.d_cell_nhv)
+        b.d_run_counters, b.d_run_ledger = _ptr(self.d_run_cnt), _ptr(self.d_run_led)
+        b.d_cell_counters = _ptr(self.d_cell_cnt)
+        b.d_cell_ledger = _ptr(self.d_cell_led)
+        b.d_cell_moments = _ptr(self.d_cell_mom)
+        b.d_status = _ptr(self.d_status)
+        b.d_work, b.work_bytes = _ptr(self.d_work), self.work_bytes
+        b.e_cap_max = getattr(self, "e_cap_max", 0)
+        b.i_cap_max = getattr(self, "i_cap_max", 0)
+        return b
+
+    def _bin(self):
+        self._alloc_slabs(0, 0)
+        parts = self._particles()
+        b = self.struct()
+        B.bin_particles(self.ctx.h, parts, b, self.capacity, self.d_need.data_ptr(), _stream())
+        need = self.d_need.cpu().numpy()
+        self._alloc_slabs(need[0], need[1])
+        self.d_status.zero_()
+        b = self.struct()
+        B.bin_particles(self.ctx.h, parts, b, self.capacity, self.d_need.data_ptr(), _stream())
+        need = self.d_need.cpu().numpy()
+        self.e_cap_max, self.i_cap_max = int(need[2]), int(need[3])
+        st = int(self.d_status.item())
+        if st & B.XP_ST_BIN_SIZE:
+            raise B.XpError("bin_particles: slab arrays too small after sizing")
+
+    # -- the method ---------------------------------------------------------------
+    def step(self, step, flags=B.XP_ALL, schedule=0, d_step=None):
+        p = B.XpStepParams(int(flags), int(step), _ptr(d_step), int(schedule), 0)
+        B.collide_ionize_step(self.ctx.h, self.struct(), p, _stream())
+
+    def photo_auger(self, step, flags=B.XP_PHOTO | B.XP_DECAY, schedule=0, d_step=None):
+        p = B.XpStepParams(int(flags), int(step), _ptr(d_step), int(schedule), 0)
+        B.photo_auger_step(self.ctx.h, self.struct(), p, _stream())
+
+    def diagnostics(self, reset=False):
+        out = torch.zeros(self.n_runs * C.sizeof(B.XpDiag), dtype=torch.uint8, device=self.device)
+        B.diagnostics(self.ctx.h, self.struct(), out.data_ptr(),
+                      B.XP_DIAG_RESET if reset else 0, _stream())
+        raw = out.cpu().numpy().tobytes()
+        sz = C.sizeof(B.XpDiag)
+        return [B.XpDiag.from_buffer_copy(raw[r * sz:(r + 1) * sz]) for r in range(self.n_runs)]
+
+    def status(self):
+        return int(self.d_status.item())
+
+    # -- read-back for checks ---------------------------------------------------
+    def state(self, run=0) -> CompactState:
+        c0 = self.cell_begin[run]
+        nc = self.specs[run].nx * self.specs[run].ny
+        eo = self.d_e_off[c0:c0 + nc].cpu().numpy()
+        en = self.d_e_cnt[c0:c0 + nc].cpu().numpy().astype(np.int64)
+        io = self.d_i_off[c0:c0 + nc].cpu().numpy()
+        inn = self.d_i_cnt[c0:c0 + nc].cpu().numpy().astype(np.int64)
+        eidx = np.concatenate([np.arange(o, o + n) for o, n in zip(eo, en)]) if en.sum() else np.zeros(0, np.int64)
+        iidx = np.concatenate([np.arange(o, o + n) for o, n in zip(io, inn)]) if inn.sum() else np.zeros(0, np.int64)
+        g = lambda t, idx: t.cpu().numpy()[idx]
+        ey = g(self.ey, eidx) if self.two_d else np.zeros(eidx.size)
+        iy = g(self.iy, iidx) if self.two_d else np.zeros(iidx.size)
+        return CompactState(
+            e_start=np.concatenate([[0], np.cumsum(en)]), ex=g(self.ex, eidx), ey=ey,
+            evx=g(self.evx, eidx), evy=g(self.evy, eidx), evz=g(self.evz, eidx),
+            ew=g(self.ew, eidx).view(np.uint32),
+            i_start=np.concatenate([[0], np.cumsum(inn)]), ix=g(self.ix, iidx), iy=iy,
+            ivx=g(self.ivx, iidx), ivy=g(self.ivy, iidx), ivz=g(self.ivz, iidx),
+            iz=g(self.iz, iidx), ik=g(self.ik, iidx))
+
+    def cell_records_of(self, run=0):
+        c0 = self.cell_begin[run]
+        nc = self.specs[run].nx * self.specs[run].ny
+        return (self.d_cell_cnt[c0:c0 + nc].cpu().numpy(),
+                self.d_cell_led[c0:c0 + nc].cpu().numpy(),
+                self.d_cell_mom[c0:c0 + nc].cpu().numpy())
+
+    def run_counters(self):
+        return self.d_run_cnt.cpu().numpy().view(np.uint64)

@@ -1,0 +1,78 @@
+"""The C ABI without a GPU: libxpic.so loads, exports every function declared
+in include/xpic.h, and the ctypes mirrors of the structs have the C layout
+(sizes and field offsets printed by a probe compiled with gcc against the
+header)."""
+
+import ctypes as C
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+from paper_1704_01202_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "xpic.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:xp_status|uint32_t|const char \*|void|size_t)\s*\*?\s*(\w+)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_function():
+    if not os.path.exists(B.LIB_PATH):
+        pytest.skip("libxpic.so not built")
+    lib = C.CDLL(B.LIB_PATH)
+    names = _declared_functions()
+    assert {"init_species", "bin_particles", "collide_ionize_step", "photo_auger_step",
+            "diagnostics"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(B.EXPORTS)
+    assert lib.xp_abi_version() == 1
+
+
+STRUCTS = {
+    "xp_atomic_tables": B.XpAtomicTables, "xp_run": B.XpRun, "xp_batch": B.XpBatch,
+    "xp_particles": B.XpParticles, "xp_capacity": B.XpCapacity,
+    "xp_step_params": B.XpStepParams, "xp_diag": B.XpDiag,
+}
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="no C compiler")
+def test_ctypes_layout_matches_header(tmp_path):
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "xpic.h"', 'int main(void){']
+    for cname, cls in STRUCTS.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for fname, _ in cls._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, fname, cname, fname))
+    lines.append("return 0;}")
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c99", "-I" + os.path.join(ROOT, "include"), "-o", str(exe),
+                    str(src)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    got = {}
+    for line in out.splitlines():
+        a, b, c = line.split()
+        got[(a, b)] = int(c)
+    for cname, cls in STRUCTS.items():
+        assert got[(cname, "size")] == C.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_header_names_every_entry_point_with_citation():
+    text = open(HEADER).read()
+    for name in ("init_species", "bin_particles", "collide_ionize_step", "photo_auger_step",
+                 "diagnostics"):
+        i = text.index(name + "(")
+        block = text[max(0, i - 1500):i]
+        assert "Sec." in block or "Eq." in block, name
