@@ -187,6 +187,8 @@ typedef struct {
     size_t work_bytes;
     int32_t e_cap_max;              /* host copy of max e_cap over cells (d_need[2]) */
     int32_t i_cap_max;              /* host copy of max i_cap over cells (d_need[3]) */
+    int32_t *d_stats;               /* optional [4]: after a step, [0] the largest electron
+                                       count of any cell, [1] cells re-planned with more LDS */
 } xp_batch;
 
 /* Unsorted input particles of a batch for bin_particles.  Particle p belongs
@@ -216,7 +218,10 @@ typedef struct {
     uint32_t step;             /* step index (Philox counter word 0) */
     const uint32_t *d_step;    /* optional [n_runs] device step index per run; overrides step */
     int32_t schedule;          /* 0 auto; 1 one wave per cell; 2 one block of 256 per cell */
-    int32_t reserved;
+    int32_t e_hint;            /* expected largest electron count of a cell (e.g. d_stats[0]
+                                  of the previous step); 0: plan for e_cap_max.  Cells that
+                                  outgrow the plan are redone with a larger one in the same
+                                  call, so the hint changes speed, never results. */
 } xp_step_params;
 
 /* Stable counting sort of the unsorted particles into the batch's cell slabs

@@ -106,7 +106,8 @@ def lib():
         L.orc_photo_sigma.restype = d; L.orc_photo_sigma.argtypes = [vp, i32, d]
         L.orc_coulomb_log.restype = d; L.orc_coulomb_log.argtypes = [d, d, d]
         L.orc_ta77.restype = d
-        L.orc_ta77.argtypes = [vp, vp, d, d, u32, u32, d, d, vp, d, vp, vp]
+        L.orc_ta77.argtypes = [vp, vp, d, d, u32, u32, d, d, vp, vp, vp]
+        L.orc_u32.restype = d; L.orc_u32.argtypes = [u32]
         L.orc_create.restype = vp; L.orc_create.argtypes = [vp, vp]
         L.orc_destroy.restype = None; L.orc_destroy.argtypes = [vp]
         L.orc_bin.restype = i32
@@ -253,14 +254,17 @@ class Tables:
         return lib().orc_photo_sigma(C.byref(self.s), int(s), float(hv))
 
 
-def ta77(va, vb, ma, mb, wa, wb, coef, nunit, draws, r4=0.5):
+def u32(x):
+    return lib().orc_u32(int(x))
+
+
+def ta77(va, vb, ma, mb, wa, wb, coef, nunit, draws):
     va = np.array(va, dtype=np.float64)
     vb = np.array(vb, dtype=np.float64)
     d = np.ascontiguousarray(draws, dtype=np.uint32)
     aa, ab = C.c_int32(), C.c_int32()
     d2 = lib().orc_ta77(_p(va), _p(vb), float(ma), float(mb), int(wa), int(wb),
-                        float(coef), float(nunit), _p(d), float(r4), C.byref(aa),
-                        C.byref(ab))
+                        float(coef), float(nunit), _p(d), C.byref(aa), C.byref(ab))
     return va, vb, d2, aa.value, ab.value
 
 

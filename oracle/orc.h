@@ -103,6 +103,7 @@ void   orc_sincos2pi(uint64_t k52, double *s, double *c);
 void   orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 void   orc_philox_many(int64_t n, const uint32_t *ctr, const uint32_t *key, uint32_t *out);
 double orc_u52(uint32_t hi, uint32_t lo);
+double orc_u32(uint32_t x);
 void   orc_perm(int32_t n, const uint32_t *keys, int32_t *out);
 
 /* --- single-physics helpers, exported for the pins --- */
@@ -116,7 +117,7 @@ double orc_coulomb_log(double t_ev, double n_e, double zbar);
 /* One binary collision on explicit velocities (Takizuka-Abe 1977). */
 double orc_ta77(double va[3], double vb[3], double ma, double mb, uint32_t wa,
                 uint32_t wb, double qq_coef, double nunit, const uint32_t draws[4],
-                double r4, int32_t *accept_a, int32_t *accept_b);
+                int32_t *accept_a, int32_t *accept_b);
 
 /* --- simulation of one run --- */
 orc_sim *orc_create(const orc_tables *t, const orc_run *r);

@@ -191,6 +191,12 @@ void orc_philox_many(int64_t n, const uint32_t *ctr, const uint32_t *key, uint32
     for (int64_t i = 0; i < n; ++i) orc_philox(ctr + 4 * i, key + 2 * i, out + 4 * i);
 }
 
+/* Uniform on the open interval (0, 1) from a 32-bit word. */
+double orc_u32(uint32_t x)
+{
+    return ((double)x + 0.5) * 0x1p-32;
+}
+
 /* Uniform on the open interval (0, 1) from the top 52 bits of (hi, lo). */
 double orc_u52(uint32_t hi, uint32_t lo)
 {

@@ -155,12 +155,13 @@ double orc_photo_sigma(const orc_tables *t, int32_t s, double hv)
  *   delta = sqrt(<delta^2>) * sqrt(-2 ln r1) cos(2 pi r2), Phi = 2 pi r3,
  *   sin(Theta) = 2 delta/(1+delta^2), 1 - cos(Theta) = 2 delta^2/(1+delta^2);
  *   the heavier-weight side accepts with probability w_light / w_heavy (r4).
- * draws = Philox words: [0..1] -> r1, [2] -> r2 angle, [3] -> Phi angle.
+ * draws = the four Philox words of the pair: [0] -> r1, [1] -> the angle
+ * 2 pi r2, [2] -> Phi, [3] -> r4 (r1 and r4 as 32-bit uniforms).
  * Returns <delta^2>, or -1 when the relative velocity is zero (no collision).
  */
 double orc_ta77(double va[3], double vb[3], double ma, double mb, uint32_t wa,
               uint32_t wb, double qq_coef, double nunit, const uint32_t draws[4],
-              double r4, int32_t *acc_a, int32_t *acc_b)
+              int32_t *acc_a, int32_t *acc_b)
 {
     double ux = va[0] - vb[0], uy = va[1] - vb[1], uz = va[2] - vb[2];
     double u2 = (ux * ux + uy * uy) + uz * uz;
@@ -170,9 +171,9 @@ double orc_ta77(double va[3], double vb[3], double ma, double mb, uint32_t wa,
     uint32_t wmax = wa > wb ? wa : wb;
     double u = sqrt(u2);
     double d2 = ((qq_coef * (double)wmax) * nunit) / (u2 * u);
-    double r1 = orc_u52(draws[0], draws[1]);
+    double r1 = orc_u32(draws[0]);
     double s2, c2;
-    orc_sincos2pi((uint64_t)draws[2] << 20, &s2, &c2);
+    orc_sincos2pi((uint64_t)draws[1] << 20, &s2, &c2);
     double g = sqrt(-2.0 * orc_log(r1)) * c2;
     double d = sqrt(d2) * g;
     double dd = d * d;
@@ -180,7 +181,7 @@ double orc_ta77(double va[3], double vb[3], double ma, double mb, uint32_t wa,
     double st = (2.0 * d) / den;
     double omc = (2.0 * dd) / den;
     double sp, cp;
-    orc_sincos2pi((uint64_t)draws[3] << 20, &sp, &cp);
+    orc_sincos2pi((uint64_t)draws[2] << 20, &sp, &cp);
     double a = st * cp;
     double bb = st * sp;
     double up = sqrt(ux * ux + uy * uy);
@@ -195,6 +196,7 @@ double orc_ta77(double va[3], double vb[3], double ma, double mb, uint32_t wa,
         duy = auz * bb;
         duz = -(uz * omc);
     }
+    double r4 = orc_u32(draws[3]);
     int ta = (wa <= wb) || (r4 < (double)wb / (double)wa);
     int tb = (wb <= wa) || (r4 < (double)wa / (double)wb);
     double fa = mb / (ma + mb);

@@ -26,8 +26,10 @@
 #include "orc.h"
 #include "orc_internal.h"
 
+/* Random-number purposes.  P_ION is one call per ion and step whose four
+ * words decide collisional ionization and the photo events of 1s, 2s, 2p. */
 enum { P_PERM_E = 1, P_PERM_I = 2, P_REC_I = 3, P_REC_E = 4, P_EE = 5,
-       P_EE_TRI = 6, P_EI = 7, P_ION = 8, P_S5 = 9, P_DIR = 10 };
+       P_EE_TRI = 6, P_EI = 7, P_ION = 8, P_DECAY = 9, P_DIR = 10, P_BIN = 11 };
 
 #define NMOM 32
 
@@ -337,15 +339,10 @@ static void collide_pair(const cctx *x, ocell *c, int e_a, int is_ion_b, int b,
         wb = c->ew[b];
         mb = ORC_ME;
     }
-    uint32_t d[4], d4[4] = {0, 0, 0, 0};
+    uint32_t d[4];
     rng(x, idx, purpose, sub, d);
-    double r4 = 0.5;
-    if (wa != wb) {
-        rng(x, idx, purpose, sub + 1, d4);
-        r4 = orc_u52(d4[0], d4[1]);
-    }
     int32_t aa, ab;
-    double d2 = orc_ta77(va, vb, ORC_ME, mb, wa, wb, coef, nunit, d, r4, &aa, &ab);
+    double d2 = orc_ta77(va, vb, ORC_ME, mb, wa, wb, coef, nunit, d, &aa, &ab);
     if (d2 < 0.0) { x->cnt[OC_U0]++; return; }
     if (d2 > 1.0) x->cnt[OC_DELTA2_GT1]++;
     x->cnt[OC_ACCEPT] += aa + ab;
@@ -486,7 +483,7 @@ static void step_cell(cctx *x, ocell *c, uint32_t flags)
                 if (c->iz[i] >= ORC_ZMAX) continue;
                 uint32_t d[4];
                 rng(x, (uint32_t)i, P_ION, 0, d);
-                if (orc_u52(d[0], d[1]) < p) { x->perm_a[i] = 1; nfired++; }
+                if (orc_u32(d[0]) < p) { x->perm_a[i] = 1; nfired++; }
             }
             x->cnt[OC_ION_FIRED] += nfired;
             if (nfired > 0) {
@@ -650,7 +647,7 @@ static void step_cell(cctx *x, ocell *c, uint32_t flags)
                 double rate = ga + gx;
                 if (rate > 0.0) {
                     uint32_t d[4];
-                    rng(x, (uint32_t)i, P_S5, 0, d);
+                    rng(x, (uint32_t)i, P_DECAY, 0, d);
                     double pd = r->dt_rad * rate;
                     if (pd > 1.0) { pd = 1.0; x->cnt[OC_P_CLAMPED]++; }
                     if (orc_u52(d[0], d[1]) < pd) {
@@ -675,20 +672,22 @@ static void step_cell(cctx *x, ocell *c, uint32_t flags)
                 }
             }
             if (photo) {
+                uint32_t fire[4];
+                rng(x, (uint32_t)i, P_ION, 0, fire);
                 for (int q = 0; q < 3; ++q) {
                     if (occ0[q] <= 0) continue;
                     double sum = ssum[z0][q];
                     if (!(sum > 0.0)) continue;
                     double p = ((ORC_CLIGHT * r->dt_rad) * (double)occ0[q]) * sum;
                     if (p > 1.0) { p = 1.0; x->cnt[OC_P_CLAMPED]++; }
-                    uint32_t d[4];
-                    rng(x, (uint32_t)i, P_S5, (uint32_t)(1 + q), d);
-                    if (!(orc_u52(d[0], d[1]) < p)) continue;
+                    if (!(orc_u32(fire[1 + q]) < p)) continue;
                     int occn[ORC_NSUB];
                     orc_occupancy(z, kv, occn);
                     if (z >= ORC_ZMAX || occn[q] <= 0) { x->cnt[OC_PHOTO_SKIPPED]++; continue; }
                     double pp = lowered(x, z0, q, dE, 0);
-                    double target = orc_u52(d[2], d[3]) * sum;
+                    uint32_t d[4];
+                    rng(x, (uint32_t)i, P_BIN, (uint32_t)q, d);
+                    double target = orc_u52(d[0], d[1]) * sum;
                     double cum = 0.0;
                     int sel = -1, lastpos = -1;
                     for (int b = 0; b < nb; ++b) {

@@ -65,7 +65,7 @@ class XpBatch(C.Structure):
                 ("d_run_counters", _vp), ("d_run_ledger", _vp), ("d_cell_counters", _vp),
                 ("d_cell_ledger", _vp), ("d_cell_moments", _vp), ("d_status", _vp),
                 ("d_work", _vp), ("work_bytes", C.c_size_t),
-                ("e_cap_max", _i32), ("i_cap_max", _i32)]
+                ("e_cap_max", _i32), ("i_cap_max", _i32), ("d_stats", _vp)]
 
 
 class XpParticles(C.Structure):
@@ -81,7 +81,7 @@ class XpCapacity(C.Structure):
 
 class XpStepParams(C.Structure):
     _fields_ = [("flags", _u32), ("step", _u32), ("d_step", _vp), ("schedule", _i32),
-                ("reserved", _i32)]
+                ("e_hint", _i32)]
 
 
 class XpDiag(C.Structure):

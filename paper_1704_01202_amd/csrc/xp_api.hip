@@ -163,8 +163,9 @@ size_t xp_work_bytes(int64_t ne, int64_t ni, int32_t n_cells, int32_t n_runs)
 {
     (void)n_runs;
     const xpd::BinPlan p = xpd::bin_plan(ne, ni, n_cells);
-    size_t diag = 8 * (size_t)(n_cells > 0 ? n_cells : 1) + 256;
-    return p.bytes > diag ? p.bytes : diag;
+    const size_t cells = (size_t)(n_cells > 0 ? n_cells : 1);
+    size_t other = 8 * cells + 256;   // diagnostics: per-cell sums; step: two cell lists + counts
+    return p.bytes > other ? p.bytes : other;
 }
 
 xp_status bin_particles(xp_ctx* ctx, const xp_particles* in, xp_batch* b, const xp_capacity* cap,
@@ -190,6 +191,23 @@ xp_status bin_particles(xp_ctx* ctx, const xp_particles* in, xp_batch* b, const 
     return XP_OK;
 }
 
+// Work lists of the tiered launches inside the workspace.
+struct StepPlan {
+    int32_t* lists[2];
+    int32_t* counts;   // one per tier
+};
+
+static StepPlan step_plan(const xp_batch* b)
+{
+    StepPlan p;
+    char* w = (char*)b->d_work;
+    const size_t n = (size_t)(b->n_cells > 0 ? b->n_cells : 1);
+    p.lists[0] = (int32_t*)w;
+    p.lists[1] = (int32_t*)(w + 4 * n);
+    p.counts = (int32_t*)(w + 8 * n);
+    return p;
+}
+
 static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, uint32_t flags, void* stream)
 {
     xp_status st = check_batch(ctx, b);
@@ -197,6 +215,9 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
     if (!p) return fail(XP_ERR_INVALID_ARG, "null step parameters");
     if (b->n_cells == 0) return XP_OK;
     if (b->e_cap_max <= 0 || b->i_cap_max < 0) return fail(XP_ERR_INVALID_ARG, "batch e_cap_max / i_cap_max not set");
+    if (!b->d_work || b->work_bytes < 8 * (size_t)b->n_cells + 64)
+        return fail(XP_ERR_TOO_SMALL, "workspace smaller than xp_work_bytes");
+    if (p->schedule < 0 || p->schedule > 2) return fail(XP_ERR_INVALID_ARG, "unknown schedule");
     xpd::StepArgs a{};
     a.runs = b->d_runs;
     a.cell_run = b->d_cell_run;
@@ -219,28 +240,49 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
     a.d_step = p->d_step;
     a.step = p->step;
     a.flags = flags;
-    a.cell_list = nullptr;
+    a.stats = b->d_stats;
     a.n_cells = b->n_cells;
-    a.lds_ce = b->e_cap_max;
     a.lds_ci = b->i_cap_max > 0 ? b->i_cap_max : 1;
-    const size_t lds = xpd::step_lds_bytes(a.lds_ce, a.lds_ci);
-    if (lds > ctx->max_lds)
+    const int emax = b->e_cap_max;
+    if (xpd::step_lds_bytes(emax, a.lds_ci) > ctx->max_lds)
         return fail(XP_ERR_UNSUPPORTED, "cell capacity exceeds the LDS of one workgroup");
-    int sched = p->schedule;
-    if (sched == 0) sched = (a.lds_ce > 1024 || a.lds_ci > 1024) ? 2 : 1;
+    const StepPlan plan = step_plan(b);
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-    if (sched == 1) {
-        if (lds > 65536) hipFuncSetAttribute((const void*)xpd::k_step<64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(xpd::k_step<64>, dim3(b->n_cells), dim3(64), lds, (hipStream_t)stream, a);
-    } else if (sched == 2) {
-        if (lds > 65536) hipFuncSetAttribute((const void*)xpd::k_step<256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(xpd::k_step<256>, dim3(b->n_cells), dim3(256), lds, (hipStream_t)stream, a);
-    } else {
-        return fail(XP_ERR_INVALID_ARG, "unknown schedule");
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(xpd::k_step_prep, dim3(1), dim3(64), 0, s, plan.counts, b->d_stats);
+    // first plan: the hinted size plus headroom for this step's new electrons
+    int ce = emax;
+    if (p->e_hint > 0) {
+        const int head = p->e_hint / 4 > 32 ? p->e_hint / 4 : 32;
+        ce = p->e_hint + head;
+        ce = ((ce + 15) / 16) * 16;
+        if (ce > emax) ce = emax;
     }
-    e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "step launch");
+    for (int tier = 0;; ++tier) {
+        const bool last = ce >= emax;
+        a.lds_ce = ce;
+        a.cell_list = tier == 0 ? nullptr : plan.lists[(tier - 1) & 1];
+        a.cell_list_count = tier == 0 ? nullptr : plan.counts + (tier - 1);
+        a.defer_out = last ? nullptr : plan.lists[tier & 1];
+        a.defer_out_count = last ? nullptr : plan.counts + tier;
+        const size_t lds = xpd::step_lds_bytes(a.lds_ce, a.lds_ci);
+        int sched = p->schedule;
+        if (sched == 0) sched = (a.lds_ce > 512 || a.lds_ci > 512) ? 2 : 1;
+        const unsigned grid = tier == 0 ? (unsigned)b->n_cells
+                                        : (unsigned)(b->n_cells < 2048 ? b->n_cells : 2048);
+        if (sched == 1) {
+            if (lds > 65536) hipFuncSetAttribute((const void*)xpd::k_step<64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipLaunchKernelGGL(xpd::k_step<64>, dim3(grid), dim3(64), lds, s, a);
+        } else {
+            if (lds > 65536) hipFuncSetAttribute((const void*)xpd::k_step<256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipLaunchKernelGGL(xpd::k_step<256>, dim3(grid), dim3(256), lds, s, a);
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+        if (last || tier >= 14) break;
+        ce = ce * 2 < emax ? ce * 2 : emax;
+    }
     return XP_OK;
 }
 
@@ -261,6 +303,7 @@ xp_status diagnostics(xp_ctx* ctx, const xp_batch* b, xp_diag* d_out, uint32_t w
     xp_status st = check_batch(ctx, b);
     if (st != XP_OK) return st;
     if (!d_out) return fail(XP_ERR_INVALID_ARG, "null output");
+    if (b->e_cap_max > 8192) return fail(XP_ERR_UNSUPPORTED, "diagnostics support cells of up to 8192 electron slots");
     if (!b->d_work || b->work_bytes < 8 * (size_t)(b->n_cells > 0 ? b->n_cells : 1))
         return fail(XP_ERR_TOO_SMALL, "workspace too small for diagnostics");
     xpd::DiagArgs a{};

@@ -26,9 +26,11 @@ constexpr double CLIGHT = 299792458.0;
 constexpr double PI = 3.141592653589793;
 
 // Random-number purposes (word 3 of the Philox counter, << 24).
+// RP_ION is one call per ion and step: word 0 decides collisional
+// ionization, words 1..3 the photo events of 1s, 2s and 2p.
 enum : uint32_t {
     RP_PERM_E = 1, RP_PERM_I = 2, RP_REC_I = 3, RP_REC_E = 4, RP_EE = 5,
-    RP_EE_TRI = 6, RP_EI = 7, RP_ION = 8, RP_S5 = 9, RP_DIR = 10
+    RP_EE_TRI = 6, RP_EI = 7, RP_ION = 8, RP_DECAY = 9, RP_DIR = 10, RP_BIN = 11
 };
 
 __device__ __forceinline__ double bits_to_f64(uint64_t b) { return __longlong_as_double((long long)b); }
@@ -183,6 +185,9 @@ __device__ __forceinline__ Words philox(uint32_t c0, uint32_t c1, uint32_t c2, u
     return Words{c0, c1, c2, c3};
 }
 
+// Uniform on (0, 1) from a 32-bit word.
+__device__ __forceinline__ double u32(uint32_t x) { return ((double)x + 0.5) * 0x1p-32; }
+
 // Uniform on (0, 1) from the top 52 bits of the 64-bit word (hi, lo).
 __device__ __forceinline__ double u52(uint32_t hi, uint32_t lo)
 {
@@ -198,61 +203,54 @@ __device__ __forceinline__ int ilog2_ceil(int n)
 }
 
 // Canonical pairwise sum of n leaves produced by leaf(j), over a block of B
-// threads (B a multiple of 64).  Thread t folds leaves [t m, t m + m) with a
-// carry stack (exact pairwise tree for a power-of-two run), then the block
-// reduces the thread partials pairwise (lanes by shuffles, waves through LDS).
-// The result (+0.0) is returned to every thread.  red must hold B/64 doubles.
+// threads (B a multiple of 64).  Leaves are padded with +0 to P = 2^k.  Rows of
+// 64 consecutive leaves are owned by waves (lane = leaf mod 64): each row is
+// reduced by shuffles, which is levels 1..6 of the tree; the row sums (the
+// level-6 nodes) are then reduced pairwise in LDS, out of place, level by
+// level.  For P < 64 the row is padded with zeros, which adds only +0 above
+// the root.  red must hold 2 * max(1, P/64) doubles; the result (+0.0) is
+// returned to every thread.
 template <int B, class F>
 __device__ double block_tree_sum(int n, F leaf, double* red)
 {
-    const int tid = threadIdx.x;
-    int p = 1;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int p = 64;
     while (p < n) p <<= 1;
-    const int m = p > B ? p / B : 1;
-    double acc = 0.0;
-    {
-        double stk[12];
-        int cnt[12];
-        int top = 0;
-        const int base = tid * m;
-        for (int q = 0; q < m; ++q) {
-            const int j = base + q;
-            double v = j < n ? leaf(j) : 0.0;
-            int c = 1;
-            while (top > 0 && cnt[top - 1] == c) {
-                v = stk[top - 1] + v;
-                c <<= 1;
-                --top;
-            }
-            stk[top] = v;
-            cnt[top] = c;
-            ++top;
+    const int rows = p >> 6;
+    if (rows == 1) {
+        double acc = 0.0;
+        if (wid == 0) {
+            acc = lane < n ? leaf(lane) : 0.0;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) acc = acc + __shfl_down(acc, off, 64);
         }
-        acc = stk[0];
+        if (B == 64) return __shfl(acc, 0, 64) + 0.0;
+        __syncthreads();
+        if (threadIdx.x == 0) red[0] = acc;
+        __syncthreads();
+        const double r = red[0];
+        __syncthreads();
+        return r + 0.0;
     }
+    for (int r = wid; r < rows; r += B / 64) {
+        const int j = (r << 6) + lane;
+        double acc = j < n ? leaf(j) : 0.0;
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const double o = __shfl_down(acc, off, 64);
-        acc = acc + o;
-    }
-    if (B == 64) {
-        acc = __shfl(acc, 0, 64);
-        return acc + 0.0;
+        for (int off = 1; off < 64; off <<= 1) acc = acc + __shfl_down(acc, off, 64);
+        if (lane == 0) red[r] = acc;
     }
     __syncthreads();
-    if ((tid & 63) == 0) red[tid >> 6] = acc;
-    __syncthreads();
-    double r = 0.0;
-    {
-        double lv[B / 64];
-#pragma unroll
-        for (int w = 0; w < B / 64; ++w) lv[w] = red[w];
-#pragma unroll
-        for (int len = B / 64; len > 1; len >>= 1)
-#pragma unroll
-            for (int i = 0; i < len / 2; ++i) lv[i] = lv[2 * i] + lv[2 * i + 1];
-        r = lv[0];
+    double* src = red;
+    double* dst = red + rows;
+    for (int len = rows; len > 1; len >>= 1) {
+        const int half = len >> 1;
+        for (int i = threadIdx.x; i < half; i += B) dst[i] = src[2 * i] + src[2 * i + 1];
+        __syncthreads();
+        double* t = src;
+        src = dst;
+        dst = t;
     }
+    const double r = src[0];
     __syncthreads();
     return r + 0.0;
 }
@@ -311,23 +309,69 @@ __device__ int block_ordered_select(int n, P pred, E emit, int* red)
 }
 
 // Bitonic sort of p = 2^k 64-bit keys in LDS (ascending), B threads.
-template <int B>
-__device__ void bitonic_sort(uint64_t* a, int p)
+template <int B, class P>
+__device__ void bitonic_sort(P a, int p)
 {
     for (int k = 2; k <= p; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
             for (int i = threadIdx.x; i < p / 2; i += B) {
-                const int lo = ((i / j) * 2 * j) + (i % j);
+                const int lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));
                 const int hi = lo + j;
                 const bool up = (lo & k) == 0;
                 const uint64_t x = a[lo], y = a[hi];
-                const bool sw = up ? (x > y) : (x < y);
-                if (sw) {
+                if (up ? (x > y) : (x < y)) {
                     a[lo] = y;
                     a[hi] = x;
                 }
             }
             __syncthreads();
+        }
+    }
+}
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m)
+{
+    const uint32_t lo = __shfl_xor((uint32_t)v, m, 64);
+    const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), m, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Bitonic sort of P = 64 K keys held by one wave in registers: element
+// e = lane + 64 m is key[m].  Strides below 64 exchange across lanes with
+// shuffles, larger strides exchange between a lane's own registers.
+template <int K>
+__device__ __forceinline__ void wave_bitonic(uint64_t (&key)[K])
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 2; k <= 64 * K; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= 64) {
+                const int mj = j >> 6;
+#pragma unroll
+                for (int m = 0; m < K; ++m) {
+                    if (m & mj) continue;
+                    const int e = lane + 64 * m;
+                    const bool up = (e & k) == 0;
+                    const uint64_t x = key[m], y = key[m | mj];
+                    const bool sw = up ? (x > y) : (x < y);
+                    key[m] = sw ? y : x;
+                    key[m | mj] = sw ? x : y;
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < K; ++m) {
+                    const int e = lane + 64 * m;
+                    const uint64_t o = shfl_xor_u64(key[m], j);
+                    const bool up = (e & k) == 0;
+                    const bool lower = (lane & j) == 0;
+                    // the lower element of an ascending pair keeps the minimum
+                    const bool take_min = lower == up;
+                    const bool less = o < key[m];
+                    key[m] = (take_min == less) ? o : key[m];
+                }
+            }
         }
     }
 }

@@ -50,10 +50,11 @@ __global__ __launch_bounds__(64) void k_diag_cells(DiagArgs a)
         }
         atomicAdd((unsigned long long*)&o->fe_hist[bin], (unsigned long long)w);
     }
+    __shared__ double red[2 * 128];
     const double k = block_tree_sum<64>(ne, [&](int j) {
         const double x = a.evx[eo + j], y = a.evy[eo + j], z = a.evz[eo + j];
         return (double)a.ew[eo + j] * (HALF_ME_OVER_QE * ((x * x + y * y) + z * z));
-    }, nullptr);
+    }, red);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         we += __shfl_xor(we, off, 64);
@@ -71,7 +72,7 @@ __global__ __launch_bounds__(64) void k_diag_cells(DiagArgs a)
 
 __global__ __launch_bounds__(256) void k_diag_runs(DiagArgs a, uint32_t what)
 {
-    __shared__ double red[4];
+    extern __shared__ double red[];
     const int r = blockIdx.x;
     if (r >= a.n_runs) return;
     const xp_run* R = a.runs + r;
@@ -100,7 +101,11 @@ hipError_t diag_launch(const DiagArgs& a, uint32_t what, hipStream_t s)
 {
     hipLaunchKernelGGL(k_diag_zero, dim3(a.n_runs), dim3(64), 0, s, a.out, a.n_runs);
     if (a.n_cells > 0) hipLaunchKernelGGL(k_diag_cells, dim3(a.n_cells), dim3(64), 0, s, a);
-    hipLaunchKernelGGL(k_diag_runs, dim3(a.n_runs), dim3(256), 0, s, a, what);
+    int p = 64;
+    while (p < a.n_cells) p <<= 1;
+    const size_t smem = 2 * sizeof(double) * (size_t)(p / 64);
+    if (smem > 65536) hipFuncSetAttribute((const void*)k_diag_runs, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    hipLaunchKernelGGL(k_diag_runs, dim3(a.n_runs), dim3(256), smem, s, a, what);
     return hipGetLastError();
 }
 

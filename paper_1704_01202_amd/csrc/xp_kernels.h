@@ -34,10 +34,16 @@ struct StepArgs {
     const uint32_t* d_step;
     uint32_t step;
     uint32_t flags;
-    const int32_t* cell_list;   // optional: cells to process, one per block
+    const int32_t* cell_list;   // optional: cells to process (count in *cell_list_count)
+    const int32_t* cell_list_count;
+    int32_t* defer_out;         // cells that outgrow this launch's LDS plan
+    int32_t* defer_out_count;
+    int32_t* stats;             // [0] max electrons per cell after the step, [1] deferrals
     int32_t n_cells;
     int32_t lds_ce, lds_ci;     // LDS capacity per cell (electrons, ions)
 };
+
+__global__ void k_step_prep(int32_t* counts, int32_t* stats);
 
 size_t step_lds_bytes(int ce, int ci);
 

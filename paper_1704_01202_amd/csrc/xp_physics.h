@@ -3,6 +3,7 @@
 // Operand order of every expression follows the method's arithmetic contract.
 #pragma once
 
+#include "../../include/xpic.h"
 #include "xp_device.h"
 #include "xp_tables.h"
 
@@ -46,7 +47,7 @@ __device__ __forceinline__ int valence(int z, int k)
 
 // Continuum lowering of charge state z: Ecker-Kroll (Eq. 5; Debye-Hueckel
 // below n_crit) or Stewart-Pyatt (Eq. 6 with lambda_D including Zbar + 1).
-__device__ double ipd(int model, int z, double t, double n_e, double n_i, double zbar,
+__device__ __noinline__ double ipd(int model, int z, double t, double n_e, double n_i, double zbar,
                       double zstar)
 {
     double lamd = __builtin_inf();
@@ -65,7 +66,7 @@ __device__ double ipd(int model, int z, double t, double n_e, double n_i, double
     return (t / (2.0 * zs1)) * ((c * c) - 1.0);
 }
 
-__device__ double coulomb_log(double t, double n_e, double zbar)
+__device__ __noinline__ double coulomb_log(double t, double n_e, double zbar)
 {
     if (!(n_e > 0.0)) return 2.0;
     const double lamde = sqrt((EPS0 * t) / (QE * n_e));
@@ -77,7 +78,7 @@ __device__ double coulomb_log(double t, double n_e, double zbar)
     return lnl < 2.0 ? 2.0 : lnl;
 }
 
-__device__ double eos_zbar(const DevTables* tb, double n_i, double tev)
+__device__ __noinline__ double eos_zbar(const DevTables* tb, double n_i, double tev)
 {
     const double* zt = (const double*)((const char*)tb + tb->off_eos);
     const double u = (xlog(n_i) - tb->eos_lnn0) / tb->eos_dlnn;
@@ -96,7 +97,7 @@ __device__ double eos_zbar(const DevTables* tb, double n_i, double tev)
 }
 
 // Per-electron subshell photoionization cross section, m^2 (Fig. 2a table).
-__device__ double photo_sigma(const DevTables* tb, int s, double hv)
+__device__ __noinline__ double photo_sigma(const DevTables* tb, int s, double hv)
 {
     const double* ls = (const double*)((const char*)tb + tb->off_lnsig) + s * tb->photo_nh;
     const double u = (xlog(hv) - tb->photo_lnhv0) / tb->photo_dlnhv;
@@ -121,10 +122,12 @@ struct Coll {
 };
 
 // Takizuka-Abe binary collision with weighted acceptance (the heavier-weight
-// partner accepts with probability w_light / w_heavy, draw r4).
+// partner accepts with probability w_light / w_heavy).  The four Philox words
+// of the pair give r1 (word 0), the Box-Muller angle (word 1), Phi (word 2)
+// and the acceptance draw r4 (word 3).  fa = m_b/(m_a+m_b), fb = m_a/(m_a+m_b).
 __device__ __forceinline__ Coll ta77(double& ax, double& ay, double& az, double& bx, double& by,
-                                     double& bz, double ma, double mb, uint32_t wa, uint32_t wb,
-                                     double coef, double nunit, const Words& d, double r4)
+                                     double& bz, double fa, double fb, uint32_t wa, uint32_t wb,
+                                     double coef, double nunit, const Words& d)
 {
     Coll out{-1.0, 0, 0};
     const double ux = ax - bx, uy = ay - by, uz = az - bz;
@@ -134,15 +137,15 @@ __device__ __forceinline__ Coll ta77(double& ax, double& ay, double& az, double&
     const double u = sqrt(u2);
     const double d2 = ((coef * (double)wmax) * nunit) / (u2 * u);
     double s2, c2;
-    xsincos2pi((uint64_t)d.x2 << 20, s2, c2);
-    const double g = sqrt(-2.0 * xlog(u52(d.x0, d.x1))) * c2;
+    xsincos2pi((uint64_t)d.x1 << 20, s2, c2);
+    const double g = sqrt(-2.0 * xlog(u32(d.x0))) * c2;
     const double dl = sqrt(d2) * g;
     const double dd = dl * dl;
     const double den = 1.0 + dd;
     const double st = (2.0 * dl) / den;
     const double omc = (2.0 * dd) / den;
     double sp, cp;
-    xsincos2pi((uint64_t)d.x3 << 20, sp, cp);
+    xsincos2pi((uint64_t)d.x2 << 20, sp, cp);
     const double a = st * cp;
     const double bb = st * sp;
     const double up = sqrt(ux * ux + uy * uy);
@@ -157,10 +160,12 @@ __device__ __forceinline__ Coll ta77(double& ax, double& ay, double& az, double&
         duy = auz * bb;
         duz = -(uz * omc);
     }
-    const bool ta = (wa <= wb) || (r4 < (double)wb / (double)wa);
-    const bool tb = (wb <= wa) || (r4 < (double)wa / (double)wb);
-    const double fa = mb / (ma + mb);
-    const double fb = ma / (ma + mb);
+    bool ta = true, tb = true;
+    if (wa != wb) {
+        const double r4 = u32(d.x3);
+        ta = (wa < wb) || (r4 < (double)wb / (double)wa);
+        tb = (wb < wa) || (r4 < (double)wa / (double)wb);
+    }
     if (ta) {
         ax = ax + fa * dux;
         ay = ay + fa * duy;
@@ -175,6 +180,50 @@ __device__ __forceinline__ Coll ta77(double& ax, double& ay, double& az, double&
     out.acc_a = ta;
     out.acc_b = tb;
     return out;
+}
+
+// One binary collision between slot e of (avx, avy, avz, aw) and slot b of
+// (bvx, bvy, bvz) with weight wb, on LDS arrays; draws from Philox counter
+// (c0, c1, idx, c3).  Counts go to cnt (XP_C_* indices).
+__device__ __forceinline__ void collide_slots(double* avx, double* avy, double* avz, const uint32_t* aw,
+                                           double* bvx, double* bvy, double* bvz, int e, int b,
+                                           uint32_t wb, double fa, double fb, double coef,
+                                           double nunit, uint32_t c0, uint32_t c1, uint32_t idx,
+                                           uint32_t c3, uint32_t k0, uint32_t k1, int* cnt)
+{
+    double ax = avx[e], ay = avy[e], az = avz[e];
+    double bx = bvx[b], by = bvy[b], bz = bvz[b];
+    const Words d = philox(c0, c1, idx, c3, k0, k1);
+    const Coll c = ta77(ax, ay, az, bx, by, bz, fa, fb, aw[e], wb, coef, nunit, d);
+    if (c.d2 < 0.0) {
+        atomicAdd(&cnt[XP_C_U0], 1);
+        return;
+    }
+    if (c.d2 > 1.0) atomicAdd(&cnt[XP_C_DELTA2_GT1], 1);
+    atomicAdd(&cnt[XP_C_ACCEPT], c.acc_a + c.acc_b);
+    avx[e] = ax; avy[e] = ay; avz[e] = az;
+    bvx[b] = bx; bvy[b] = by; bvz[b] = bz;
+}
+
+// w sigma v of one electron for the average cell ion (Lotz, Eq. 4): occupied
+// subshells oc, lowered bindings pp and their logarithms lnp.
+__device__ __forceinline__ double lotz_leaf(double x, double y, double z, uint32_t w, const int* oc,
+                                         const double* pp, const double* lnp, const DevTables* tb)
+{
+    const double v2 = (x * x + y * y) + z * z;
+    const double e = HALF_ME_OVER_QE * v2;
+    double sig = 0.0;
+    if (e > 0.0) {
+        const double lne = xlog(e);
+        for (int q = 0; q < 5; ++q) {
+            if (oc[q] <= 0 || !(e > pp[q])) continue;
+            double term = (((tb->lotz_a[q] * 1.0e-4) * (double)oc[q]) * (lne - lnp[q])) / (e * pp[q]);
+            if (tb->lotz_b[q] != 0.0)
+                term = term * (1.0 - tb->lotz_b[q] * xexp(-(tb->lotz_c[q] * (e / pp[q] - 1.0))));
+            sig = sig + term;
+        }
+    }
+    return ((double)w * sig) * sqrt(v2);
 }
 
 }  // namespace xpd

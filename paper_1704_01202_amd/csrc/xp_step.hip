@@ -16,6 +16,8 @@
 // cell's slab at the start, one coalesced write at the end.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "xp_kernels.h"
 #include "xp_physics.h"
 
@@ -24,7 +26,7 @@ namespace xpd {
 namespace {
 
 struct CellShared {
-    double red[16];
+    double red[256];
     long long ired[16];
     int sel[16];
     int cnt[XP_NCOUNT];
@@ -46,8 +48,9 @@ struct Lds {
     uint8_t *iz, *ik;
     int32_t* perm_i;
     int32_t* list;
-    uint8_t *z0, *k0, *emask;
+    uint8_t *z0, *k0, *emask, *fwok;
     uint16_t* ebins;
+    uint32_t* fw;      // cached words 1..3 of each ion's RP_ION draw
     uint64_t* sbuf;
 };
 
@@ -73,12 +76,14 @@ __device__ __forceinline__ Lds carve(unsigned char* base, int ce, int ci, int ps
     L.perm_i = (int32_t*)take(sizeof(int32_t) * ci);
     L.list = (int32_t*)take(sizeof(int32_t) * ci);
     L.ebins = (uint16_t*)take(sizeof(uint16_t) * ci);
+    L.fw = (uint32_t*)take(sizeof(uint32_t) * 3 * ci);
     L.esel = (uint8_t*)take(ce);
     L.iz = (uint8_t*)take(ci);
     L.ik = (uint8_t*)take(ci);
     L.z0 = (uint8_t*)take(ci);
     L.k0 = (uint8_t*)take(ci);
     L.emask = (uint8_t*)take(ci);
+    L.fwok = (uint8_t*)take(ci);
     return L;
 }
 
@@ -96,17 +101,36 @@ size_t step_lds_bytes(int ce, int ci)
     const int ps = pow2_at_least(ce > ci ? ce : ci);
     auto r = [](size_t b) { return (b + 15) & ~size_t(15); };
     size_t n = r(8ull * ps) + 3 * r(8ull * ce) + 3 * r(8ull * ci) + 3 * r(4ull * ce) +
-               2 * r(4ull * ci) + r(2ull * ci) + r(ce) + 5 * r(ci);
+               2 * r(4ull * ci) + r(2ull * ci) + r(12ull * ci) + r(ce) + 6 * r(ci);
     return n;
 }
 
+template <int B>
+__device__ void step_cell(const StepArgs& a, int cell, CellShared& S, const Lds& L);
+
+// One workgroup per cell, looping over the cells of the launch: all cells
+// (cell_list == nullptr) or the cells listed by an earlier launch whose LDS
+// plan they outgrew.
 template <int B>
 __global__ __launch_bounds__(B) void k_step(StepArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ CellShared S;
+    const int ce = a.lds_ce, ci = a.lds_ci;
+    const int ps = pow2_at_least(ce > ci ? ce : ci);
+    const Lds L = carve(smem, ce, ci, ps);
+    const int nitems = a.cell_list ? *a.cell_list_count : a.n_cells;
+    for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const int cell = a.cell_list ? a.cell_list[item] : item;
+        step_cell<B>(a, cell, S, L);
+        __syncthreads();
+    }
+}
+
+template <int B>
+__device__ void step_cell(const StepArgs& a, int cell, CellShared& S, const Lds& L)
+{
     const int tid = threadIdx.x;
-    const int cell = a.cell_list ? a.cell_list[blockIdx.x] : (int)blockIdx.x;
     if (cell < 0 || cell >= a.n_cells) return;
     const int run = a.cell_run[cell];
     const xp_run* R = a.runs + run;
@@ -123,12 +147,31 @@ __global__ __launch_bounds__(B) void k_step(StepArgs a)
     const int ni = a.i_cnt[cell];
     const int64_t eo = a.e_off[cell], io = a.i_off[cell];
     const int ce = a.lds_ce, ci = a.lds_ci;
-    const int ps = pow2_at_least(ce > ci ? ce : ci);
-    Lds L = carve(smem, ce, ci, ps);
+    // the LDS plan of this launch bounds the cell; a cell beyond it is passed to
+    // the next (larger) plan, a cell beyond its slab capacity is an error
+    const int lim = ecap < ce ? ecap : ce;
 
-    // cells larger than this launch's LDS plan are left for another schedule
-    if (ne > ce || ni > ci || ecap > ce) {
+    auto defer = [&]() {
+        if (tid == 0) {
+            if (a.defer_out) {
+                const int k = atomicAdd(a.defer_out_count, 1);
+                a.defer_out[k] = cell;
+                if (a.stats) atomicAdd(&a.stats[1], 1);
+            } else {
+                atomicOr(a.status, XP_ST_CAPACITY);
+            }
+        }
+    };
+    if (ni > ci) {
         if (tid == 0) atomicOr(a.status, XP_ST_CAPACITY);
+        return;
+    }
+    if (ne > ce || ne > ecap) {
+        if (ne > ecap) {
+            if (tid == 0) atomicOr(a.status, XP_ST_CAPACITY);
+        } else {
+            defer();
+        }
         return;
     }
 
@@ -149,6 +192,7 @@ __global__ __launch_bounds__(B) void k_step(StepArgs a)
         L.ivz[j] = a.ivz[io + j];
         L.iz[j] = a.iz[io + j];
         L.ik[j] = a.ik[io + j];
+        L.fwok[j] = 0;
     }
     for (int q = tid; q < XP_NCOUNT; q += B) S.cnt[q] = 0;
     for (int q = tid; q < XP_NLEDGER; q += B) S.led[q] = 0.0;
@@ -215,7 +259,35 @@ __global__ __launch_bounds__(B) void k_step(StepArgs a)
     const double lnl = S.mom[10];
 
     // ------------- random permutations: sort (Philox key, slot) ---------------
-    auto make_perm = [&](uint32_t purpose, int n, int32_t* out) {
+    // out[k] = slot of rank k when slots are sorted by (Philox word, slot)
+    auto make_perm = [&](uint32_t purpose, int n, auto out) {
+        if (B == 64 && n <= 128) {
+            auto run_k = [&](auto kk) {
+                constexpr int K = decltype(kk)::value;
+                uint64_t key[K];
+#pragma unroll
+                for (int m = 0; m < K; ++m) {
+                    const int i = tid + 64 * m;
+                    key[m] = ~0ull;
+                    if (i < n) {
+                        const Words w = rng((uint32_t)(i >> 2), purpose, 0);
+                        const uint32_t q = i & 3;
+                        const uint32_t kw = q == 0 ? w.x0 : (q == 1 ? w.x1 : (q == 2 ? w.x2 : w.x3));
+                        key[m] = ((uint64_t)kw << 32) | (uint32_t)i;
+                    }
+                }
+                wave_bitonic<K>(key);
+#pragma unroll
+                for (int m = 0; m < K; ++m) {
+                    const int r = tid + 64 * m;
+                    if (r < n) out[r] = (int32_t)(uint32_t)key[m];
+                }
+            };
+            if (n <= 64) run_k(std::integral_constant<int, 1>{});
+            else run_k(std::integral_constant<int, 2>{});
+            __syncthreads();
+            return;
+        }
         const int p = pow2_at_least(n);
         for (int g = tid; 4 * g < n; g += B) {
             const Words w = rng((uint32_t)g, purpose, 0);
@@ -233,40 +305,18 @@ __global__ __launch_bounds__(B) void k_step(StepArgs a)
         __syncthreads();
     };
 
+    const double fe_ei = mi / (ME + mi);   // electron side of an e-i pair
+    const double fi_ei = ME / (ME + mi);   // ion side
+    const double f_ee = ME / (ME + ME);
     auto collide = [&](int e, bool ion_b, int b, double coef, double nunit, uint32_t idx,
                        uint32_t purpose) {
-        double ax = L.evx[e], ay = L.evy[e], az = L.evz[e];
-        double bx, by, bz, mb;
-        const uint32_t wa = L.ew[e];
-        uint32_t wbb;
-        if (ion_b) {
-            bx = L.ivx[b]; by = L.ivy[b]; bz = L.ivz[b];
-            wbb = 1;
-            mb = mi;
-        } else {
-            bx = L.evx[b]; by = L.evy[b]; bz = L.evz[b];
-            wbb = L.ew[b];
-            mb = ME;
-        }
-        const Words d = rng(idx, purpose, 0);
-        double r4 = 0.5;
-        if (wa != wbb) {
-            const Words d4 = rng(idx, purpose, 1);
-            r4 = u52(d4.x0, d4.x1);
-        }
-        const Coll c = ta77(ax, ay, az, bx, by, bz, ME, mb, wa, wbb, coef, nunit, d, r4);
-        if (c.d2 < 0.0) {
-            atomicAdd(&S.cnt[XP_C_U0], 1);
-            return;
-        }
-        if (c.d2 > 1.0) atomicAdd(&S.cnt[XP_C_DELTA2_GT1], 1);
-        atomicAdd(&S.cnt[XP_C_ACCEPT], c.acc_a + c.acc_b);
-        L.evx[e] = ax; L.evy[e] = ay; L.evz[e] = az;
-        if (ion_b) {
-            L.ivx[b] = bx; L.ivy[b] = by; L.ivz[b] = bz;
-        } else {
-            L.evx[b] = bx; L.evy[b] = by; L.evz[b] = bz;
-        }
+        const uint32_t c3 = (purpose << 24);
+        if (ion_b)
+            collide_slots(L.evx, L.evy, L.evz, L.ew, L.ivx, L.ivy, L.ivz, e, b, 1u, fe_ei, fi_ei,
+                          coef, nunit, step, lcell, idx, c3, key0, key1, S.cnt);
+        else
+            collide_slots(L.evx, L.evy, L.evz, L.ew, L.evx, L.evy, L.evz, e, b, L.ew[b], f_ee, f_ee,
+                          coef, nunit, step, lcell, idx, c3, key0, key1, S.cnt);
     };
 
     const double qe4 = (QE * QE) * (QE * QE);
@@ -318,13 +368,12 @@ __global__ __launch_bounds__(B) void k_step(StepArgs a)
         if (tid == 0) S.cnt[XP_C_EI] += nmax;
     }
 
-    bool overflow = false;
+    bool overflow = false, deferred = false;
 
     // ---------------- S3: collisional ionization ----------------
     if ((flags & XP_ION) && ne >= 1 && ni >= 1) {
-        long long szi, sz2i;
-        ion_sums(szi, sz2i);
-        const int zc = (int)((2 * szi + wi) / (2 * wi));
+        // charge states are unchanged since the moments: reuse their sum
+        const int zc = (int)((2 * sz + wi) / (2 * wi));
         const int ne0 = ne;
         if (tid == 0) S.mom[11] = (double)zc;
         if (zc < 13) {
@@ -338,24 +387,7 @@ __global__ __launch_bounds__(B) void k_step(StepArgs a)
                 if (tid == 0 && oc.s[q] > 0 && raw < 1.0) S.cnt[XP_C_IPD_CLAMPED] += 1;
             }
             const double ssum = block_tree_sum<B>(ne0, [&](int j) {
-                const double x = L.evx[j], y = L.evy[j], z = L.evz[j];
-                const double v2 = (x * x + y * y) + z * z;
-                const double e = HALF_ME_OVER_QE * v2;
-                double sig = 0.0;
-                if (e > 0.0) {
-                    const double lne = xlog(e);
-#pragma unroll
-                    for (int q = 0; q < 5; ++q) {
-                        if (oc.s[q] <= 0 || !(e > pp[q])) continue;
-                        double term = (((tb->lotz_a[q] * 1.0e-4) * (double)oc.s[q]) * (lne - lnp[q])) /
-                                      (e * pp[q]);
-                        if (tb->lotz_b[q] != 0.0)
-                            term = term * (1.0 - tb->lotz_b[q] *
-                                                     xexp(-(tb->lotz_c[q] * (e / pp[q] - 1.0))));
-                        sig = sig + term;
-                    }
-                }
-                return ((double)L.ew[j] * sig) * sqrt(v2);
+                return lotz_leaf(L.evx[j], L.evy[j], L.evz[j], L.ew[j], oc.s, pp, lnp, tb);
             }, S.red);
             double p = ((ssum * w0) * dt) / vol;
             if (p > 1.0) {
@@ -368,7 +400,11 @@ __global__ __launch_bounds__(B) void k_step(StepArgs a)
                 [&](int i) {
                     if (L.iz[i] >= 13 || !(p > 0.0)) return false;
                     const Words d = rng((uint32_t)i, RP_ION, 0);
-                    return u52(d.x0, d.x1) < p;
+                    L.fw[3 * i] = d.x1;
+                    L.fw[3 * i + 1] = d.x2;
+                    L.fw[3 * i + 2] = d.x3;
+                    L.fwok[i] = 1;
+                    return u32(d.x0) < p;
                 },
                 [&](int i, int pos) { L.list[pos] = i; }, S.sel);
             if (tid == 0) S.cnt[XP_C_ION_FIRED] += nfired;
@@ -395,8 +431,8 @@ __global__ __launch_bounds__(B) void k_step(StepArgs a)
                         const double ip = lowered(tb, z, sv, dE);
                         if (!(debit + ip <= kth)) break;
                         const int slot = ne0 + acc;
-                        if (slot >= ecap) {
-                            S.ints[0] = 1;   // overflow
+                        if (slot >= lim) {
+                            S.ints[0] = slot >= ecap ? 1 : 2;   // 1 over capacity, 2 over the LDS plan
                             break;
                         }
                         debit = debit + ip;
@@ -416,7 +452,8 @@ __global__ __launch_bounds__(B) void k_step(StepArgs a)
                     S.ints[1] = acc;
                 }
                 __syncthreads();
-                if (S.ints[0]) overflow = true;
+                if (S.ints[0] == 1) overflow = true;
+                if (S.ints[0] == 2) deferred = true;
                 const double debit = S.dbl[0];
                 const int acc = S.ints[1];
                 if (debit > 0.0) {
@@ -434,7 +471,7 @@ __global__ __launch_bounds__(B) void k_step(StepArgs a)
     }
 
     // ---------------- S4: three-body recombination ----------------
-    if (!overflow && (flags & XP_REC) && ne >= 1 && ni >= 1) {
+    if (!overflow && !deferred && (flags & XP_REC) && ne >= 1 && ni >= 1) {
         long long szr, sz2r, wer, wbr;
         double ker;
         ion_sums(szr, sz2r);
@@ -565,7 +602,7 @@ __global__ __launch_bounds__(B) void k_step(StepArgs a)
     }
 
     // ---------------- S5: K-vacancy decay and photoionization ----------------
-    if (!overflow && (flags & (XP_PHOTO | XP_DECAY))) {
+    if (!overflow && !deferred && (flags & (XP_PHOTO | XP_DECAY))) {
         const int nb = R->n_bins;
         const bool photo = (flags & XP_PHOTO) && nb > 0;
         const double* nhv = (R->field_per_cell && a.cell_nhv) ? a.cell_nhv + (size_t)cell * XP_MAX_BINS : R->nhv;
@@ -598,7 +635,7 @@ __global__ __launch_bounds__(B) void k_step(StepArgs a)
                     const double ga = tb->gamma_a[z0][k0], gx = tb->gamma_x[z0][k0];
                     const double rate = ga + gx;
                     if (rate > 0.0) {
-                        const Words d = rng((uint32_t)i, RP_S5, 0);
+                        const Words d = rng((uint32_t)i, RP_DECAY, 0);
                         double pd = dtr * rate;
                         if (pd > 1.0) {
                             pd = 1.0;
@@ -619,6 +656,17 @@ __global__ __launch_bounds__(B) void k_step(StepArgs a)
                     }
                 }
                 if (photo) {
+                    uint32_t fire[3];
+                    if (L.fwok[i]) {
+                        fire[0] = L.fw[3 * i];
+                        fire[1] = L.fw[3 * i + 1];
+                        fire[2] = L.fw[3 * i + 2];
+                    } else {
+                        const Words d = rng((uint32_t)i, RP_ION, 0);
+                        fire[0] = d.x1;
+                        fire[1] = d.x2;
+                        fire[2] = d.x3;
+                    }
                     for (int s = 0; s < 3; ++s) {
                         if (o0.s[s] <= 0) continue;
                         const double sum = S.ssum[z0][s];
@@ -628,15 +676,15 @@ __global__ __launch_bounds__(B) void k_step(StepArgs a)
                             p = 1.0;
                             atomicAdd(&S.cnt[XP_C_P_CLAMPED], 1);
                         }
-                        const Words d = rng((uint32_t)i, RP_S5, (uint32_t)(1 + s));
-                        if (!(u52(d.x0, d.x1) < p)) continue;
+                        if (!(u32(fire[s]) < p)) continue;
                         const Occ on = occupancy(z, kv);
                         if (z >= 13 || on.s[s] <= 0) {
                             atomicAdd(&S.cnt[XP_C_PHOTO_SKIPPED], 1);
                             continue;
                         }
                         const double pp = lowered(tb, z0, s, dE);
-                        const double target = u52(d.x2, d.x3) * sum;
+                        const Words d = rng((uint32_t)i, RP_BIN, (uint32_t)s);
+                        const double target = u52(d.x0, d.x1) * sum;
                         double cum = 0.0;
                         int sel = -1, lastpos = -1;
                         for (int bq = 0; bq < nb; ++bq) {
@@ -712,7 +760,7 @@ __global__ __launch_bounds__(B) void k_step(StepArgs a)
                         atomicAdd(&S.led[XP_L_PHOTO_E], en);
                         atomicAdd(&S.led[XP_L_PHOTON_ABS], R->hv[sel]);
                     }
-                    if (pos < ecap) {
+                    if (pos < lim) {
                         const Words d = rng((uint32_t)i, RP_DIR, (uint32_t)bit);
                         const double mu = 2.0 * u52(d.x0, d.x1) - 1.0;
                         double sp, cp;
@@ -733,6 +781,7 @@ __global__ __launch_bounds__(B) void k_step(StepArgs a)
         }
         if (tid == 0) S.cnt[XP_C_E_NEW] += base_pos - ne;
         if (base_pos > ecap) overflow = true;
+        else if (base_pos > lim) deferred = true;
         ne = base_pos;
         __syncthreads();
     }
@@ -740,6 +789,10 @@ __global__ __launch_bounds__(B) void k_step(StepArgs a)
     // ---------------- commit ----------------
     if (overflow) {
         if (tid == 0) atomicOr(a.status, XP_ST_CAPACITY);
+        return;
+    }
+    if (deferred) {
+        defer();
         return;
     }
     bool bad = false;
@@ -779,7 +832,10 @@ __global__ __launch_bounds__(B) void k_step(StepArgs a)
         a.ex[eo + j] = L.evx[j];
         if (a.ey) a.ey[eo + j] = L.evy[j];
     }
-    if (tid == 0) a.e_cnt[cell] = ne;
+    if (tid == 0) {
+        a.e_cnt[cell] = ne;
+        if (a.stats) atomicMax(&a.stats[0], ne);
+    }
     if (a.cell_cnt)
         for (int q = tid; q < XP_NCOUNT; q += B) a.cell_cnt[(size_t)cell * XP_NCOUNT + q] = S.cnt[q];
     if (a.cell_led)
@@ -796,5 +852,13 @@ __global__ __launch_bounds__(B) void k_step(StepArgs a)
 
 template __global__ void k_step<64>(StepArgs);
 template __global__ void k_step<256>(StepArgs);
+
+__global__ void k_step_prep(int32_t* counts, int32_t* stats)
+{
+    if (threadIdx.x < 4) {
+        if (counts) counts[threadIdx.x] = 0;
+        if (stats) stats[threadIdx.x] = 0;
+    }
+}
 
 }  // namespace xpd

@@ -123,6 +123,9 @@ class Batch:
         self.d_i_cnt = torch.zeros(nc, dtype=torch.int32, device=dev)
         self.d_status = torch.zeros(1, dtype=torch.int32, device=dev)
         self.d_need = torch.zeros(4, dtype=torch.int64, device=dev)
+        self.d_stats = torch.zeros(4, dtype=torch.int32, device=dev)
+        self.h_stats = torch.zeros(4, dtype=torch.int32, pin_memory=True)
+        self.e_hint = 0
         self.d_run_cnt = torch.zeros((self.n_runs, B.XP_NCOUNT), dtype=torch.int64, device=dev)
         self.d_run_led = torch.zeros((self.n_runs, B.XP_NLEDGER), dtype=torch.float64, device=dev)
         self.d_cell_nhv = None
@@ -210,6 +213,7 @@ class Batch:
         b.d_work, b.work_bytes = _ptr(self.d_work), self.work_bytes
         b.e_cap_max = getattr(self, "e_cap_max", 0)
         b.i_cap_max = getattr(self, "i_cap_max", 0)
+        b.d_stats = _ptr(self.d_stats)
         return b
 
     def _bin(self):
@@ -229,13 +233,28 @@ class Batch:
             raise B.XpError("bin_particles: slab arrays too small after sizing")
 
     # -- the method ---------------------------------------------------------------
-    def step(self, step, flags=B.XP_ALL, schedule=0, d_step=None):
-        p = B.XpStepParams(int(flags), int(step), _ptr(d_step), int(schedule), 0)
-        B.collide_ionize_step(self.ctx.h, self.struct(), p, _stream())
+    def _hint(self, use_hint):
+        if not use_hint:
+            return 0
+        # largest electron count of the step before last (copied without waiting)
+        seen = int(self.h_stats[0].item())
+        return seen if seen > 0 else 0
 
-    def photo_auger(self, step, flags=B.XP_PHOTO | B.XP_DECAY, schedule=0, d_step=None):
-        p = B.XpStepParams(int(flags), int(step), _ptr(d_step), int(schedule), 0)
+    def _after(self):
+        self.h_stats.copy_(self.d_stats, non_blocking=True)
+
+    def step(self, step, flags=B.XP_ALL, schedule=0, d_step=None, use_hint=True):
+        p = B.XpStepParams(int(flags), int(step), _ptr(d_step), int(schedule),
+                           self._hint(use_hint))
+        B.collide_ionize_step(self.ctx.h, self.struct(), p, _stream())
+        self._after()
+
+    def photo_auger(self, step, flags=B.XP_PHOTO | B.XP_DECAY, schedule=0, d_step=None,
+                    use_hint=True):
+        p = B.XpStepParams(int(flags), int(step), _ptr(d_step), int(schedule),
+                           self._hint(use_hint))
         B.photo_auger_step(self.ctx.h, self.struct(), p, _stream())
+        self._after()
 
     def diagnostics(self, reset=False):
         out = torch.zeros(self.n_runs * C.sizeof(B.XpDiag), dtype=torch.uint8, device=self.device)

@@ -36,6 +36,10 @@ def u52(hi, lo):
     return (((hi << 32) | lo) >> 12) / 2.0 ** 52 + 2.0 ** -53
 
 
+def u32(x):
+    return (x + 0.5) / 2.0 ** 32
+
+
 def occ(z, k):
     nb = 13 - z
     o = [max(0, min(2 - k, nb))]
@@ -123,13 +127,13 @@ class Brute:
             return
         wa = a[5]
         w = self.rng(step, cell, idx, purpose, 0)
-        r4 = u52(*self.rng(step, cell, idx, purpose, 1)[:2]) if wa != wb else 0.5
+        r4 = u32(w[3])
         u = math.sqrt(u2)
         d2 = coef * max(wa, wb) * nunit / u ** 3
-        g = math.sqrt(-2 * math.log(u52(w[0], w[1]))) * math.cos(2 * math.pi * ((w[2] << 20) + 0.5) / 2 ** 52)
+        g = math.sqrt(-2 * math.log(u32(w[0]))) * math.cos(2 * math.pi * ((w[1] << 20) + 0.5) / 2 ** 52)
         d = math.sqrt(d2) * g
         st, omc = 2 * d / (1 + d * d), 2 * d * d / (1 + d * d)
-        phi = 2 * math.pi * ((w[3] << 20) + 0.5) / 2 ** 52
+        phi = 2 * math.pi * ((w[2] << 20) + 0.5) / 2 ** 52
         up = math.hypot(ua[0], ua[1])
         ux, uy, uz = ua
         if up > 0:
@@ -228,7 +232,7 @@ class Brute:
                 p = min(tot * s.w0 * s.dt / s.volume, 1.0)
                 fired = []
                 for m, ion in enumerate(ions):
-                    if ion[5] < 13 and u52(*self.rng(step, cell_id, m, 8, 0)[:2]) < p:
+                    if ion[5] < 13 and u32(self.rng(step, cell_id, m, 8, 0)[0]) < p:
                         fired.append(m)
                 if fired:
                     u, kth = self.drift(es, [e[5] for e in es])
@@ -332,12 +336,13 @@ class Brute:
                         tot = sum(terms)
                         if tot <= 0:
                             continue
-                        w = self.rng(step, cell_id, m, 9, 1 + q)
-                        if not u52(w[0], w[1]) < min(CL * s.dt_rad * o0[q] * tot, 1.0):
+                        fire = self.rng(step, cell_id, m, 8, 0)
+                        if not u32(fire[1 + q]) < min(CL * s.dt_rad * o0[q] * tot, 1.0):
                             continue
                         if z >= 13 or occ(z, k)[q] == 0:
                             continue
-                        target, cum, sel = u52(w[2], w[3]) * tot, 0.0, None
+                        w = self.rng(step, cell_id, m, 11, q)
+                        target, cum, sel = u52(w[0], w[1]) * tot, 0.0, None
                         for b in range(nb):
                             cum += terms[b]
                             if terms[b] > 0 and cum > target:

@@ -50,8 +50,8 @@ def test_ta77_conservation_equal_weights(orc):
         u, u2 = va - vb, va2 - vb2
         worst_u = max(worst_u, abs(np.linalg.norm(u2) - np.linalg.norm(u)) / np.linalg.norm(u))
         # scattering angle: tan(Theta/2) = |delta|
-        r1 = orc.u52(d[0], d[1])
-        c2 = orc.sincos2pi(int(d[2]) << 20)[1]
+        r1 = orc.u32(d[0])
+        c2 = orc.sincos2pi(int(d[1]) << 20)[1]
         delta = math.sqrt(d2) * math.sqrt(-2 * math.log(r1)) * c2
         th = 2 * math.atan(abs(delta))
         cos_th = float(u @ u2) / (np.linalg.norm(u) * np.linalg.norm(u2))
@@ -89,9 +89,8 @@ def test_ta77_weighted_acceptance_rates(orc):
     acc_a = acc_b = 0
     n = 20000
     for _ in range(n):
-        r4 = rng.uniform()
         _, _, _, aa, ab = orc.ta77(np.array([1e6, 0, 0]), np.array([0, 1e6, 0.0]), ME, ME,
-                                   3, 1, 1e-55, 1e28, _words(rng), r4)
+                                   3, 1, 1e-55, 1e28, _words(rng))
         acc_a += aa
         acc_b += ab
     assert acc_b == n
