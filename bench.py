@@ -21,6 +21,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -37,25 +38,86 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(steps=4, nx=96, ny=96):
-    """The oracle on a bounded sample of the same workload (nx x ny cells)."""
+def cpu_threads():
+    """Threads the oracle may use: OMP_NUM_THREADS when set (the host's share),
+    else the visible cores."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    n = int(env) if env.isdigit() and int(env) > 0 else (os.cpu_count() or 1)
+    return max(1, min(n, os.cpu_count() or n))
+
+
+def cpu_baseline(spec, parts, budget_s=15.0, max_steps=40):
+    """The oracle on a bounded sample of the same workload: every cell of the
+    same initial state, stepped from step 0 until about budget_s of work."""
     from oracle import oracle as O
     from paper_1704_01202_amd import workloads as W
     tab = W.make_tables()
-    spec, parts = W.config_c2(nx=nx, ny=ny)
     sim = O.Sim(tab, spec)
     sim.bin(parts)
-    threads = os.cpu_count() or 1
+    threads = cpu_threads()
     coll = 0
+    steps = 0
     t0 = time.perf_counter()
-    for s in range(steps):
-        sim.step(s, O.ALL, threads)
+    while steps < max_steps:
+        sim.step(steps, O.ALL, threads)
         cnt, _ = sim.counters()
         coll += int(cnt[:, 0].sum() + cnt[:, 1].sum() + cnt[:, 2].sum())
+        steps += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
     dt = time.perf_counter() - t0
     return {"value": coll / dt, "unit": "collisions/s", "cores": threads, "kind": "oracle",
-            "sample": "%dx%d cells of the same workload, %d steps from the initial state, "
-                      "%.1f s" % (nx, ny, steps, dt)}
+            "sample": "all %d cells of the same workload, steps 0-%d (%d collisions) in %.1f s"
+                      % (spec.ncells, steps - 1, coll, dt)}
+
+
+def source_digest():
+    """sha256 over the device sources and build flags: counter figures taken
+    from a profile are only valid for the kernel they were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    pkg = os.path.join(ROOT, "paper_1704_01202_amd")
+    files = [os.path.join(ROOT, "include", "xpic.h"), os.path.join(pkg, "build.py")]
+    csrc = os.path.join(pkg, "csrc")
+    files += [os.path.join(csrc, f) for f in sorted(os.listdir(csrc))
+              if f.endswith((".hip", ".h"))]
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_step_c2_512x512_hbm_traffic.md")
+
+
+def measured_traffic():
+    """HBM bytes per k_step launch from the committed FETCH_SIZE / WRITE_SIZE
+    summary (already scaled by the copy-kernel calibration), or None when the
+    summary is missing or was taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    m = re.search(r"^source_digest:\s*(\w+)", text, re.M)
+    b = re.search(r"^traffic_bytes_per_launch:\s*([0-9.eE+]+)", text, re.M)
+    if not m or not b or m.group(1) != source_digest():
+        return None
+    return float(b.group(1))
+
+
+def copy_reference(mib):
+    """A plain device-to-device copy of known size (mib MiB read, mib MiB
+    written), three times: the reference the HBM counters are scaled by."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("copy reference: 3 x %d MiB device copies" % mib)
 
 
 def main():
@@ -67,6 +129,9 @@ def main():
     ap.add_argument("--ny", type=int, default=512)
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
+                    help="after the timed steps, run a plain device copy of MIB MiB "
+                         "(calibrates the HBM byte counters under a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the step has no cross-GPU work here and only "
@@ -142,14 +207,18 @@ def main():
                    "cells": spec.ncells, "electrons_start": parts.ne, "ions": ni,
                    "electrons_timed": [ne_before, ne_after], "status": status},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_step", "kernel_avg_ms": avg_ms,
                      "bytes_per_launch": bytes_total / args.steps},
         "collisions_total": coll,
     }
+    if args.copy_ref > 0:
+        copy_reference(args.copy_ref)
     if not args.no_cpu:
+        del bat
+        torch.cuda.empty_cache()
         log("timing the CPU oracle on a sample ...")
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(spec, parts)
     print(json.dumps(out), flush=True)
 
 
