@@ -13,8 +13,11 @@
  *
  * Conditions found on the device (a cell whose new electrons do not fit its
  * slot capacity, a non-finite velocity) are reported through the batch's
- * d_status word (bit mask XP_ST_*); a cell that cannot be completed is left
- * exactly as it was before the step.
+ * d_status word (bit mask XP_ST_*).  A cell stepped in LDS that cannot be
+ * completed is left exactly as it was before the step; a cell stepped on the
+ * global-memory path (see xp_step_params.schedule) keeps the collisions of that
+ * step and skips its later stages.  Either way the batch needs re-binning with
+ * more capacity before its results mean anything.
  *
  * Units: SI for positions, velocities, volumes and densities; energies and
  * temperatures in eV; table cross sections in cm^2.
@@ -188,7 +191,16 @@ typedef struct {
     int32_t e_cap_max;              /* host copy of max e_cap over cells (d_need[2]) */
     int32_t i_cap_max;              /* host copy of max i_cap over cells (d_need[3]) */
     int32_t *d_stats;               /* optional [4]: after a step, [0] the largest electron
-                                       count of any cell, [1] cells re-planned with more LDS */
+                                       count of a cell stepped in LDS, [1] cells re-planned
+                                       with more LDS, [2] cells stepped on the global-memory
+                                       path, [3] the largest electron count among those */
+    /* Bounds of the cells that may take the global-memory path (cells whose
+     * slab exceeds what one workgroup's LDS holds): their number and the sums
+     * of their e_cap and i_cap (d_need[4..6] of bin_particles).  All zero:
+     * the batch has no such cell and the path is never launched. */
+    int32_t big_cells_max;
+    int32_t reserved0;
+    int64_t big_e_slots, big_i_slots;
 } xp_batch;
 
 /* Unsorted input particles of a batch for bin_particles.  Particle p belongs
@@ -209,15 +221,25 @@ typedef struct {
     int32_t e_extra;
 } xp_capacity;
 
-/* Workspace bytes needed by every call on a batch with these sizes. */
+/* Workspace bytes bin_particles needs for these input sizes. */
 size_t xp_work_bytes(int64_t ne, int64_t ni, int32_t n_cells, int32_t n_runs);
+/* Workspace bytes the step, photo_auger_step and diagnostics need on batch b
+ * (reads n_cells and the big_* bounds only).  d_work must hold the larger of
+ * this and xp_work_bytes of the binning. */
+size_t xp_step_work_bytes(const xp_batch *b);
+/* Largest electron count a cell stepped in LDS may reach when it holds up to
+ * i_lds ions (*e_lds), and the ion limit itself (*i_lds); cells beyond either
+ * take the global-memory path.  Depends on the device's LDS size only. */
+xp_status xp_lds_limits(xp_ctx *ctx, int32_t *e_lds, int32_t *i_lds);
 
 /* ---- the step ---------------------------------------------------------- */
 typedef struct {
     uint32_t flags;            /* XP_* stage switches */
     uint32_t step;             /* step index (Philox counter word 0) */
     const uint32_t *d_step;    /* optional [n_runs] device step index per run; overrides step */
-    int32_t schedule;          /* 0 auto; 1 one wave per cell; 2 one block of 256 per cell */
+    int32_t schedule;          /* 0 auto; 1 one wave per cell; 2 one block of 256 per cell;
+                                  3 every cell on the global-memory path (needs big_* bounds
+                                  covering the whole batch).  Results never depend on it. */
     int32_t e_hint;            /* expected largest electron count of a cell (e.g. d_stats[0]
                                   of the previous step); 0: plan for e_cap_max.  Cells that
                                   outgrow the plan are redone with a larger one in the same
@@ -228,11 +250,12 @@ typedef struct {
  * (Sec. VI: PIC cells).  The batch's run table, d_cell_run, slab arrays and
  * workspace must be set; offsets, capacities and counts are written from the
  * capacity rule.  Within a cell, particles keep their input order.  d_need is
- * caller-owned device memory of four int64 receiving the required
- * (e_slots, i_slots) and the largest (e_cap, i_cap) of any cell; the caller
- * copies the last two into b->e_cap_max / i_cap_max before stepping.  If the
- * particle arrays are too short, XP_ST_BIN_SIZE is set and no particle is
- * written. */
+ * caller-owned device memory of eight int64 receiving the required
+ * (e_slots, i_slots), the largest (e_cap, i_cap) of any cell, and the number,
+ * summed e_cap and summed i_cap of the cells beyond xp_lds_limits; the caller
+ * copies [2], [3] into b->e_cap_max / i_cap_max and [4..6] into the big_*
+ * bounds before stepping.  If the particle arrays are too short,
+ * XP_ST_BIN_SIZE is set and no particle is written. */
 xp_status bin_particles(xp_ctx *ctx, const xp_particles *in, xp_batch *b,
                         const xp_capacity *cap, int64_t *d_need, void *stream);
 
@@ -246,7 +269,12 @@ xp_status bin_particles(xp_ctx *ctx, const xp_particles *in, xp_batch *b,
  * weight reaches 0 are removed.  Moments record (when d_cell_moments is set):
  * [0] W_e [1] W_i [2] sum Z [3] sum Z^2 [4] K_e [5] T_e [6] n_e [7] n_i
  * [8] Zbar [9] z* [10] lnL [11] Z_c [12] P_ion [13] K_th [14] debit [15] T_e
- * before recombination [16..28] dE[Z] for Z = 0..12. */
+ * before recombination [16..28] dE[Z] for Z = 0..12.
+ * Cells that fit one workgroup's LDS are stepped there, one workgroup per
+ * cell; larger cells (and every cell with schedule 3) go through a
+ * global-memory path that spreads each cell over many workgroups: chunked
+ * canonical sums, a segmented radix sort for the permutations and one thread
+ * per pair.  Both give the same bits. */
 xp_status collide_ionize_step(xp_ctx *ctx, xp_batch *b, const xp_step_params *p,
                               void *stream);
 

@@ -65,7 +65,9 @@ class XpBatch(C.Structure):
                 ("d_run_counters", _vp), ("d_run_ledger", _vp), ("d_cell_counters", _vp),
                 ("d_cell_ledger", _vp), ("d_cell_moments", _vp), ("d_status", _vp),
                 ("d_work", _vp), ("work_bytes", C.c_size_t),
-                ("e_cap_max", _i32), ("i_cap_max", _i32), ("d_stats", _vp)]
+                ("e_cap_max", _i32), ("i_cap_max", _i32), ("d_stats", _vp),
+                ("big_cells_max", _i32), ("reserved0", _i32), ("big_e_slots", _i64),
+                ("big_i_slots", _i64)]
 
 
 class XpParticles(C.Structure):
@@ -92,8 +94,9 @@ class XpDiag(C.Structure):
 
 
 EXPORTS = ["xp_abi_version", "xp_last_error", "xp_ctx_create", "xp_ctx_destroy",
-           "xp_table_bytes", "init_species", "xp_work_bytes", "bin_particles",
-           "collide_ionize_step", "photo_auger_step", "diagnostics", "xp_selftest"]
+           "xp_table_bytes", "init_species", "xp_work_bytes", "xp_step_work_bytes",
+           "xp_lds_limits", "bin_particles", "collide_ionize_step", "photo_auger_step",
+           "diagnostics", "xp_selftest"]
 
 _lib = None
 
@@ -125,6 +128,10 @@ def load(path=LIB_PATH):
     L.init_species.argtypes = [_vp, C.POINTER(XpAtomicTables), _vp, C.c_size_t, _vp]
     L.xp_work_bytes.restype = C.c_size_t
     L.xp_work_bytes.argtypes = [_i64, _i64, _i32, _i32]
+    L.xp_step_work_bytes.restype = C.c_size_t
+    L.xp_step_work_bytes.argtypes = [C.POINTER(XpBatch)]
+    L.xp_lds_limits.restype = _i32
+    L.xp_lds_limits.argtypes = [_vp, C.POINTER(_i32), C.POINTER(_i32)]
     L.bin_particles.restype = _i32
     L.bin_particles.argtypes = [_vp, C.POINTER(XpParticles), C.POINTER(XpBatch),
                                 C.POINTER(XpCapacity), _vp, _vp]
@@ -160,6 +167,20 @@ def xp_ctx_destroy(ctx):
 
 def init_species(ctx, tables, d_buf, nbytes, stream):
     check(load().init_species(ctx, C.byref(tables), _vp(d_buf), nbytes, _vp(stream)))
+
+
+def xp_work_bytes(ne, ni, n_cells, n_runs):
+    return int(load().xp_work_bytes(int(ne), int(ni), int(n_cells), int(n_runs)))
+
+
+def xp_step_work_bytes(batch):
+    return int(load().xp_step_work_bytes(C.byref(batch)))
+
+
+def xp_lds_limits(ctx):
+    e, i = _i32(), _i32()
+    check(load().xp_lds_limits(ctx, C.byref(e), C.byref(i)))
+    return int(e.value), int(i.value)
 
 
 def bin_particles(ctx, parts, batch, cap, d_need, stream):

@@ -164,8 +164,7 @@ size_t xp_work_bytes(int64_t ne, int64_t ni, int32_t n_cells, int32_t n_runs)
     (void)n_runs;
     const xpd::BinPlan p = xpd::bin_plan(ne, ni, n_cells);
     const size_t cells = (size_t)(n_cells > 0 ? n_cells : 1);
-    size_t other = 8 * cells + 256;   // diagnostics: per-cell sums; step: two cell lists + counts
-    return p.bytes > other ? p.bytes : other;
+    return p.bytes > 8 * cells + 256 ? p.bytes : 8 * cells + 256;
 }
 
 xp_status bin_particles(xp_ctx* ctx, const xp_particles* in, xp_batch* b, const xp_capacity* cap,
@@ -186,16 +185,27 @@ xp_status bin_particles(xp_ctx* ctx, const xp_particles* in, xp_batch* b, const 
         return fail(XP_ERR_TOO_SMALL, "workspace smaller than xp_work_bytes");
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-    e = xpd::bin_launch(in, b, cap, d_need, (hipStream_t)stream);
+    int e_lds, i_lds;
+    xpd::lds_limits(ctx->max_lds, &e_lds, &i_lds);
+    e = xpd::bin_launch(in, b, cap, d_need, e_lds, i_lds, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "bin_particles launch");
     return XP_OK;
 }
 
-// Work lists of the tiered launches inside the workspace.
+// Workspace of the step: two deferral lists, the per-tier counters, then the
+// global-memory path's buffers.
 struct StepPlan {
     int32_t* lists[2];
-    int32_t* counts;   // one per tier
+    int32_t* counts;   // STEP_COUNTS: one per tier, the last for the big list
+    char* big;         // BigPlan region (when the batch has big bounds)
+    size_t bytes;
 };
+
+static size_t step_fixed_bytes(int32_t n_cells)
+{
+    const size_t n = (size_t)(n_cells > 0 ? n_cells : 1);
+    return (8 * n + 4 * xpd::STEP_COUNTS + 255) & ~size_t(255);
+}
 
 static StepPlan step_plan(const xp_batch* b)
 {
@@ -205,7 +215,30 @@ static StepPlan step_plan(const xp_batch* b)
     p.lists[0] = (int32_t*)w;
     p.lists[1] = (int32_t*)(w + 4 * n);
     p.counts = (int32_t*)(w + 8 * n);
+    const size_t fixed = step_fixed_bytes(b->n_cells);
+    p.big = w + fixed;
+    p.bytes = fixed;
+    if (b->big_cells_max > 0)
+        p.bytes += xpd::big_plan(b->big_cells_max, b->big_e_slots, b->big_i_slots).bytes;
     return p;
+}
+
+size_t xp_step_work_bytes(const xp_batch* b)
+{
+    if (!b) return 0;
+    const size_t cells = 8 * (size_t)(b->n_cells > 0 ? b->n_cells : 1) + 256;
+    const StepPlan p = step_plan(b);
+    return p.bytes > cells ? p.bytes : cells;
+}
+
+xp_status xp_lds_limits(xp_ctx* ctx, int32_t* e_lds, int32_t* i_lds)
+{
+    if (!ctx || !e_lds || !i_lds) return fail(XP_ERR_INVALID_ARG, "null argument");
+    int e, i;
+    xpd::lds_limits(ctx->max_lds, &e, &i);
+    *e_lds = e;
+    *i_lds = i;
+    return XP_OK;
 }
 
 static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, uint32_t flags, void* stream)
@@ -215,9 +248,15 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
     if (!p) return fail(XP_ERR_INVALID_ARG, "null step parameters");
     if (b->n_cells == 0) return XP_OK;
     if (b->e_cap_max <= 0 || b->i_cap_max < 0) return fail(XP_ERR_INVALID_ARG, "batch e_cap_max / i_cap_max not set");
-    if (!b->d_work || b->work_bytes < 8 * (size_t)b->n_cells + 64)
-        return fail(XP_ERR_TOO_SMALL, "workspace smaller than xp_work_bytes");
-    if (p->schedule < 0 || p->schedule > 2) return fail(XP_ERR_INVALID_ARG, "unknown schedule");
+    if (p->schedule < 0 || p->schedule > 3) return fail(XP_ERR_INVALID_ARG, "unknown schedule");
+    if (b->big_cells_max < 0 || b->big_e_slots < 0 || b->big_i_slots < 0)
+        return fail(XP_ERR_INVALID_ARG, "negative big-cell bounds");
+    if (!b->d_work || b->work_bytes < xp_step_work_bytes(b))
+        return fail(XP_ERR_TOO_SMALL, "workspace smaller than xp_step_work_bytes");
+    const bool big_ok = b->big_cells_max > 0;
+    const bool all_big = p->schedule == 3;
+    if (all_big && (b->big_cells_max < b->n_cells || b->big_e_slots < b->e_slots || b->big_i_slots < b->i_slots))
+        return fail(XP_ERR_TOO_SMALL, "schedule 3 needs big-cell bounds covering the whole batch");
     xpd::StepArgs a{};
     a.runs = b->d_runs;
     a.cell_run = b->d_cell_run;
@@ -242,46 +281,95 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
     a.flags = flags;
     a.stats = b->d_stats;
     a.n_cells = b->n_cells;
-    a.lds_ci = b->i_cap_max > 0 ? b->i_cap_max : 1;
+    // LDS plans: ions up to min(i_cap_max, i_lds); electrons doubling from the
+    // hint up to what fits beside them
+    int e_lds, i_lds;
+    xpd::lds_limits(ctx->max_lds, &e_lds, &i_lds);
+    const int ci_plan = b->i_cap_max < 1 ? 1 : (b->i_cap_max < i_lds ? b->i_cap_max : i_lds);
+    const size_t budget = xpd::lds_budget(ctx->max_lds);
+    int ce_fit = 0;
+    while (xpd::step_lds_bytes(ce_fit + 16, ci_plan) <= budget) ce_fit += 16;
     const int emax = b->e_cap_max;
-    if (xpd::step_lds_bytes(emax, a.lds_ci) > ctx->max_lds)
-        return fail(XP_ERR_UNSUPPORTED, "cell capacity exceeds the LDS of one workgroup");
+    if (!big_ok && (emax > ce_fit || b->i_cap_max > i_lds))
+        return fail(XP_ERR_UNSUPPORTED, "cells beyond one workgroup's LDS need the batch's big-cell bounds");
+    const int ce_top = emax < ce_fit ? emax : ce_fit;
+    a.lds_ci = ci_plan;
     const StepPlan plan = step_plan(b);
+    xpd::BigArgs g{};
+    if (big_ok) {
+        const xpd::BigPlan bp = xpd::big_plan(b->big_cells_max, b->big_e_slots, b->big_i_slots);
+        char* w = plan.big;
+        g.list = (int32_t*)(w + bp.list);
+        g.count = plan.counts + xpd::BIG_COUNT_SLOT;
+        g.hdr = (xpd::BigHdr*)(w + bp.hdr);
+        g.rec = (xpd::BigRec*)(w + bp.rec);
+        g.e_chunk_cell = (int32_t*)(w + bp.e_chunk_cell);
+        g.i_chunk_cell = (int32_t*)(w + bp.i_chunk_cell);
+        const size_t part_stride = ((8 * (size_t)bp.e_chunks + 255) & ~size_t(255));
+        for (int q = 0; q < 4; ++q) g.part[q] = (double*)(w + bp.part + q * part_stride);
+        g.key_a = (uint32_t*)(w + bp.key_a);
+        g.val_a = (uint32_t*)(w + bp.val_a);
+        g.key_b = (uint32_t*)(w + bp.key_b);
+        g.val_b = (uint32_t*)(w + bp.val_b);
+        g.key_c = (uint32_t*)(w + bp.key_c);
+        g.val_c = (uint32_t*)(w + bp.val_c);
+        g.hist = (uint32_t*)(w + bp.hist);
+        g.iflag = (uint8_t*)(w + bp.iflag);
+        g.ccnt = (int32_t*)(w + bp.ccnt);
+        g.iaux = (uint32_t*)(w + bp.iaux);
+        g.wp = (uint32_t*)(w + bp.wp);
+        g.sel = (int32_t*)(w + bp.sel);
+        g.big_max = b->big_cells_max;
+        g.e_chunks_max = bp.e_chunks;
+        g.i_chunks_max = bp.i_chunks;
+        g.e_pop_max = b->big_e_slots;
+        g.i_pop_max = b->big_i_slots;
+        a.big_out = g.list;
+        a.big_out_count = g.count;
+        a.big_out_cap = b->big_cells_max;
+    }
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(xpd::k_step_prep, dim3(1), dim3(64), 0, s, plan.counts, b->d_stats);
-    // first plan: the hinted size plus headroom for this step's new electrons
-    int ce = emax;
-    if (p->e_hint > 0) {
-        const int head = p->e_hint / 4 > 32 ? p->e_hint / 4 : 32;
-        ce = p->e_hint + head;
-        ce = ((ce + 15) / 16) * 16;
-        if (ce > emax) ce = emax;
-    }
-    for (int tier = 0;; ++tier) {
-        const bool last = ce >= emax;
-        a.lds_ce = ce;
-        a.cell_list = tier == 0 ? nullptr : plan.lists[(tier - 1) & 1];
-        a.cell_list_count = tier == 0 ? nullptr : plan.counts + (tier - 1);
-        a.defer_out = last ? nullptr : plan.lists[tier & 1];
-        a.defer_out_count = last ? nullptr : plan.counts + tier;
-        const size_t lds = xpd::step_lds_bytes(a.lds_ce, a.lds_ci);
-        int sched = p->schedule;
-        if (sched == 0) sched = (a.lds_ce > 512 || a.lds_ci > 512) ? 2 : 1;
-        const unsigned grid = tier == 0 ? (unsigned)b->n_cells
-                                        : (unsigned)(b->n_cells < 2048 ? b->n_cells : 2048);
-        if (sched == 1) {
-            if (lds > 65536) hipFuncSetAttribute((const void*)xpd::k_step<64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipLaunchKernelGGL(xpd::k_step<64>, dim3(grid), dim3(64), lds, s, a);
-        } else {
-            if (lds > 65536) hipFuncSetAttribute((const void*)xpd::k_step<256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipLaunchKernelGGL(xpd::k_step<256>, dim3(grid), dim3(256), lds, s, a);
+    if (!all_big) {
+        // first plan: the hinted size plus headroom for this step's new electrons
+        int ce = ce_top;
+        if (p->e_hint > 0) {
+            const int head = p->e_hint / 4 > 32 ? p->e_hint / 4 : 32;
+            ce = p->e_hint + head;
+            ce = ((ce + 15) / 16) * 16;
+            if (ce > ce_top) ce = ce_top;
         }
-        e = hipGetLastError();
-        if (e != hipSuccess) return hip_fail(e, "step launch");
-        if (last || tier >= 14) break;
-        ce = ce * 2 < emax ? ce * 2 : emax;
+        for (int tier = 0;; ++tier) {
+            const bool last = ce >= ce_top || tier >= xpd::BIG_COUNT_SLOT - 1;
+            a.lds_ce = ce;
+            a.cell_list = tier == 0 ? nullptr : plan.lists[(tier - 1) & 1];
+            a.cell_list_count = tier == 0 ? nullptr : plan.counts + (tier - 1);
+            a.defer_out = last ? nullptr : plan.lists[tier & 1];
+            a.defer_out_count = last ? nullptr : plan.counts + tier;
+            const size_t lds = xpd::step_lds_bytes(a.lds_ce, a.lds_ci);
+            int sched = p->schedule;
+            if (sched == 0) sched = (a.lds_ce > 512 || a.lds_ci > 512) ? 2 : 1;
+            const unsigned grid = tier == 0 ? (unsigned)b->n_cells
+                                            : (unsigned)(b->n_cells < 2048 ? b->n_cells : 2048);
+            if (sched == 1) {
+                if (lds > 65536) hipFuncSetAttribute((const void*)xpd::k_step<64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                hipLaunchKernelGGL(xpd::k_step<64>, dim3(grid), dim3(64), lds, s, a);
+            } else {
+                if (lds > 65536) hipFuncSetAttribute((const void*)xpd::k_step<256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                hipLaunchKernelGGL(xpd::k_step<256>, dim3(grid), dim3(256), lds, s, a);
+            }
+            e = hipGetLastError();
+            if (e != hipSuccess) return hip_fail(e, "step launch");
+            if (last) break;
+            ce = ce * 2 < ce_top ? ce * 2 : ce_top;
+        }
+    }
+    if (big_ok) {
+        g.s = a;
+        e = xpd::big_launch(g, all_big, s);
+        if (e != hipSuccess) return hip_fail(e, "global-memory step launch");
     }
     return XP_OK;
 }
@@ -303,7 +391,8 @@ xp_status diagnostics(xp_ctx* ctx, const xp_batch* b, xp_diag* d_out, uint32_t w
     xp_status st = check_batch(ctx, b);
     if (st != XP_OK) return st;
     if (!d_out) return fail(XP_ERR_INVALID_ARG, "null output");
-    if (b->e_cap_max > 8192) return fail(XP_ERR_UNSUPPORTED, "diagnostics support cells of up to 8192 electron slots");
+    if ((int64_t)b->e_cap_max > (int64_t)xpd::DIAG_CHUNK * xpd::DIAG_MAX_CHUNKS)
+        return fail(XP_ERR_UNSUPPORTED, "diagnostics support cells of up to 2^25 electron slots");
     if (!b->d_work || b->work_bytes < 8 * (size_t)(b->n_cells > 0 ? b->n_cells : 1))
         return fail(XP_ERR_TOO_SMALL, "workspace too small for diagnostics");
     xpd::DiagArgs a{};
@@ -321,6 +410,7 @@ xp_status diagnostics(xp_ctx* ctx, const xp_batch* b, xp_diag* d_out, uint32_t w
     a.out = d_out;
     a.n_runs = b->n_runs;
     a.n_cells = b->n_cells;
+    a.e_cap_max = b->e_cap_max;
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     e = xpd::diag_launch(a, what, (hipStream_t)stream);

@@ -1,0 +1,1541 @@
+// Global-memory step for cells beyond one workgroup's LDS (and for every cell
+// when the caller asks for it): the same stages, draws and sums as the LDS
+// step, with each cell spread over many workgroups.
+//
+// * A cell's slots are cut into aligned chunks of BIG_CH.  The canonical
+//   pairwise sum over a cell equals the pairwise sum of its chunks' pairwise
+//   sums: the chunks are aligned power-of-two subtrees of the same tree, and
+//   the extra +0 padding changes at most the sign of a zero, which the final
+//   + 0.0 removes.  Every sum that feeds a decision therefore has the bits of
+//   the LDS path.
+// * The random permutations (slots sorted by Philox word, then slot) come
+//   from a segmented LSD radix sort: four stable 8-bit passes whose digit
+//   offsets are scanned per cell, so a chunk never mixes cells.
+// * e-e pairs are independent: one thread per pair.  In the e-i round robin
+//   each slot of the smaller population meets its partners in a fixed
+//   sequence (rank q, q + n_min, q + 2 n_min, ...), so one thread per slot of
+//   the smaller population runs all rounds without a grid-wide barrier.
+// * The ordered parts -- the ionization debit in ion-slot order and the
+//   recombination energy sum -- run on one wave per cell over compact lists.
+//
+// Stage order and every formula follow the LDS step (Sec. II-V of the paper).
+#include <hip/hip_runtime.h>
+
+#include "xp_kernels.h"
+#include "xp_physics.h"
+
+namespace xpd {
+
+namespace {
+
+constexpr int BT = 256;   // threads of the chunk and per-cell kernels
+
+__device__ __forceinline__ uint32_t step_of(const StepArgs& s, int run)
+{
+    return s.d_step ? s.d_step[run] : s.step;
+}
+
+__device__ __forceinline__ Words draw(const StepArgs& s, const BigRec& r, uint32_t idx,
+                                      uint32_t purpose, uint32_t sub)
+{
+    const xp_run& R = s.runs[r.run];
+    const uint32_t lcell = (uint32_t)(r.cell - R.cell_begin);
+    return philox(step_of(s, r.run), lcell, idx, (purpose << 24) | sub, (uint32_t)R.seed,
+                  (uint32_t)(R.seed >> 32));
+}
+
+__device__ __forceinline__ double kin_at(const StepArgs& s, int64_t p)
+{
+    const double x = s.evx[p], y = s.evy[p], z = s.evz[p];
+    return HALF_ME_OVER_QE * ((x * x + y * y) + z * z);
+}
+
+__device__ __forceinline__ void flush_counts(BigRec& r, const int* cnt, const double* led)
+{
+    for (int q = threadIdx.x; q < XP_NCOUNT; q += blockDim.x)
+        if (cnt[q]) atomicAdd(&r.cnt[q], cnt[q]);
+    if (led)
+        for (int q = threadIdx.x; q < XP_NLEDGER; q += blockDim.x)
+            if (led[q] != 0.0) atomicAdd(&r.led[q], led[q]);
+}
+
+// ---------------------------------------------------------------- set-up
+
+__global__ void k_big_all(BigArgs a, int n_cells)
+{
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n_cells; c += gridDim.x * blockDim.x)
+        a.list[c] = c;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.count = n_cells;
+}
+
+__global__ void k_big_init(BigArgs a)
+{
+    const int requested = *a.count;
+    const int nb = requested < a.big_max ? requested : a.big_max;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.hdr->count = nb;
+        a.hdr->n_e_chunks = 0;
+        a.hdr->n_i_chunks = 0;
+        if (requested > a.big_max) atomicOr(a.s.status, XP_ST_CAPACITY);
+        if (a.s.stats) a.s.stats[2] = nb;
+    }
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) {
+        BigRec& r = a.rec[b];
+        const int cell = a.list[b];
+        r.cell = cell;
+        r.run = a.s.cell_run[cell];
+        r.ne0 = r.ne = a.s.e_cnt[cell];
+        r.ni = a.s.i_cnt[cell];
+        r.ecap = a.s.e_cap[cell];
+        r.eo = a.s.e_off[cell];
+        r.io = a.s.i_off[cell];
+        r.ce0 = r.nce = r.ci0 = r.nci = 0;
+        r.ep0 = r.ip0 = 0;
+        r.state = 0;
+        r.need = 0;
+        r.zc = 0;
+        r.acc = 0;
+        r.nrec = 0;
+        r.epn = 0;
+        r.nnew5 = 0;
+        r.we = r.wb = r.sz = r.sz2 = r.ws = r.nelig = r.nfired = 0;
+        r.we4 = r.wb4 = r.sz4 = 0;
+        r.p = r.kth = r.debit = 0.0;
+        r.alpha = 1.0;
+        r.u[0] = r.u[1] = r.u[2] = 0.0;
+        for (int q = 0; q < XP_NMOM; ++q) r.mom[q] = 0.0;
+        for (int q = 0; q < XP_NCOUNT; ++q) r.cnt[q] = 0;
+        for (int q = 0; q < XP_NLEDGER; ++q) r.led[q] = 0.0;
+        const int64_t lim = (int64_t)BIG_MAX_CHUNKS * BIG_CH;
+        if ((int64_t)r.ecap > lim || (int64_t)r.ni > lim) {
+            r.state = 1;
+            atomicOr(a.s.status, XP_ST_CAPACITY);
+        }
+    }
+}
+
+// Chunk plan of one species: chunk ranges, population offsets and the chunk
+// -> cell map.  species 0 electrons (current count r.ne), 1 ions.
+__global__ __launch_bounds__(1024) void k_big_plan(BigArgs a, int species)
+{
+    __shared__ long long red[16];
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    const int nb = a.hdr->count;
+    if (tid == 0) bad = 0;
+    long long carry_c = 0, carry_p = 0;
+    for (int b0 = 0; b0 < nb; b0 += 1024) {
+        const int b = b0 + tid;
+        long long n = 0;
+        if (b < nb) {
+            const BigRec& r = a.rec[b];
+            n = r.state ? 0 : (species == 0 ? r.ne : r.ni);
+        }
+        const long long nch = (n + BIG_CH - 1) / BIG_CH;
+        long long tot_c, tot_p;
+        const long long ec = block_exclusive_sum<1024, long long>(nch, red, tot_c);
+        const long long ep = block_exclusive_sum<1024, long long>(n, red, tot_p);
+        if (b < nb) {
+            BigRec& r = a.rec[b];
+            if (species == 0) {
+                r.ce0 = (int32_t)(carry_c + ec);
+                r.nce = (int32_t)nch;
+                r.ep0 = carry_p + ep;
+                r.epn = (int32_t)n;
+            } else {
+                r.ci0 = (int32_t)(carry_c + ec);
+                r.nci = (int32_t)nch;
+                r.ip0 = carry_p + ep;
+            }
+        }
+        carry_c += tot_c;
+        carry_p += tot_p;
+    }
+    const long long cmax = species == 0 ? a.e_chunks_max : a.i_chunks_max;
+    const long long pmax = species == 0 ? a.e_pop_max : a.i_pop_max;
+    if (carry_c > cmax || carry_p > pmax) {
+        // beyond the caller's bounds: stop every cell of the path
+        for (int b = tid; b < nb; b += 1024) {
+            BigRec& r = a.rec[b];
+            r.state = 1;
+            if (species == 0) { r.nce = 0; r.epn = 0; } else { r.nci = 0; }
+        }
+        if (tid == 0) {
+            bad = 1;
+            atomicOr(a.s.status, XP_ST_CAPACITY);
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        if (species == 0) a.hdr->n_e_chunks = bad ? 0 : (int32_t)carry_c;
+        else a.hdr->n_i_chunks = bad ? 0 : (int32_t)carry_c;
+    }
+    if (bad) return;
+    int32_t* map = species == 0 ? a.e_chunk_cell : a.i_chunk_cell;
+    for (int b = tid; b < nb; b += 1024) {
+        const BigRec& r = a.rec[b];
+        const int c0 = species == 0 ? r.ce0 : r.ci0;
+        const int nc = species == 0 ? r.nce : r.nci;
+        for (int g = c0; g < c0 + nc; ++g) map[g] = b;
+    }
+}
+
+// ---------------------------------------------------------------- S0
+
+__global__ __launch_bounds__(BT) void k_big_s0(BigArgs a)
+{
+    __shared__ double red[2 * (BIG_CH / 64)];
+    __shared__ long long ired[BT / 64];
+    const int tid = threadIdx.x;
+    const StepArgs& s = a.s;
+    const int nce = a.hdr->n_e_chunks;
+    for (int g = blockIdx.x; g < nce; g += gridDim.x) {
+        BigRec& r = a.rec[a.e_chunk_cell[g]];
+        const double ebulk = s.runs[r.run].e_bulk;
+        const int base = (g - r.ce0) * BIG_CH;
+        const int n = r.epn - base < BIG_CH ? r.epn - base : BIG_CH;
+        const int64_t o = r.eo + base;
+        long long wl = 0, bl = 0;
+        bool bad = false;
+        for (int j = tid; j < n; j += BT) {
+            const double x = s.evx[o + j], y = s.evy[o + j], z = s.evz[o + j];
+            bad |= !(__builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z));
+            const long long w = s.ew[o + j];
+            wl += w;
+            if (HALF_ME_OVER_QE * ((x * x + y * y) + z * z) < ebulk) bl += w;
+        }
+        if (bad) atomicOr(s.status, XP_ST_NONFINITE);
+        const long long we = block_isum<BT>(wl, ired);
+        const long long wb = block_isum<BT>(bl, ired);
+        const double ke = block_tree_sum<BT>(BIG_CH, [&](int j) {
+            if (j >= n) return 0.0;
+            const double e = kin_at(s, o + j);
+            return e < ebulk ? (double)s.ew[o + j] * e : 0.0;
+        }, red);
+        if (tid == 0) {
+            a.part[0][g] = ke;
+            atomicAdd(&r.we, (unsigned long long)we);
+            atomicAdd(&r.wb, (unsigned long long)wb);
+        }
+    }
+    const int nci = a.hdr->n_i_chunks;
+    for (int g = blockIdx.x; g < nci; g += gridDim.x) {
+        BigRec& r = a.rec[a.i_chunk_cell[g]];
+        const int base = (g - r.ci0) * BIG_CH;
+        const int n = r.ni - base < BIG_CH ? r.ni - base : BIG_CH;
+        const int64_t o = r.io + base;
+        long long s1 = 0, s2 = 0;
+        for (int j = tid; j < n; j += BT) {
+            const long long z = s.iz[o + j];
+            s1 += z;
+            s2 += z * z;
+        }
+        s1 = block_isum<BT>(s1, ired);
+        s2 = block_isum<BT>(s2, ired);
+        if (tid == 0) {
+            atomicAdd(&r.sz, (unsigned long long)s1);
+            atomicAdd(&r.sz2, (unsigned long long)s2);
+        }
+    }
+}
+
+// Moments, continuum lowering and the per-cell constants of S3 and S5.
+__global__ __launch_bounds__(BT) void k_big_s0fin(BigArgs a)
+{
+    __shared__ double red[2 * (BIG_MAX_CHUNKS / 64)];
+    const int tid = threadIdx.x;
+    const StepArgs& s = a.s;
+    const DevTables* tb = s.tab;
+    const uint32_t flags = s.flags;
+    const int nb = a.hdr->count;
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+        BigRec& r = a.rec[b];
+        if (r.state) continue;
+        const xp_run& R = s.runs[r.run];
+        const double ke = block_tree_sum<BT>(r.nce, [&](int j) { return a.part[0][r.ce0 + j]; }, red);
+        const long long we = (long long)r.we, wb = (long long)r.wb;
+        const long long sz = (long long)r.sz, sz2 = (long long)r.sz2;
+        const int ne = r.ne, ni = r.ni;
+        const long long wi = ni;
+        const double w0 = R.w0, vol = R.volume;
+        double tmp = 0.01;
+        if (wb > 0) {
+            tmp = (2.0 * ke) / (3.0 * (double)wb);
+            if (tmp < 0.01) tmp = 0.01;
+        }
+        const double t_e = tmp;
+        const double n_e = ((double)we * w0) / vol;
+        const double n_i = ((double)wi * w0) / vol;
+        const double zbar = wi > 0 ? (double)sz / (double)wi : 0.0;
+        const double zstar = sz > 0 ? (double)sz2 / (double)sz : 0.0;
+        if (tid < 13) r.mom[16 + tid] = ipd(R.ipd_model, tid, t_e, n_e, n_i, zbar, zstar);
+        if (tid == 13) r.mom[10] = R.lnl_fixed > 0.0 ? R.lnl_fixed : coulomb_log(t_e, n_e, zbar);
+        if (tid == 0) {
+            r.mom[0] = (double)we; r.mom[1] = (double)wi; r.mom[2] = (double)sz;
+            r.mom[3] = (double)sz2; r.mom[4] = ke; r.mom[5] = t_e; r.mom[6] = n_e;
+            r.mom[7] = n_i; r.mom[8] = zbar; r.mom[9] = zstar;
+        }
+        __syncthreads();
+        const double* dE = r.mom + 16;
+        if (tid == 0) {
+            int need = 0;
+            if ((flags & (XP_EE | XP_EI)) && ne >= 1 && (ne >= 2 || ni >= 1)) need |= BN_PERM_E;
+            if ((flags & XP_EI) && ne >= 1 && ni >= 1) need |= BN_EI;
+            if ((flags & XP_ION) && ne >= 1 && ni >= 1) {
+                // charge states are unchanged until S3: the moments' sum serves
+                const int zc = (int)((2 * sz + wi) / (2 * wi));
+                r.zc = zc;
+                r.mom[11] = (double)zc;
+                if (zc < 13) {
+                    need |= BN_ION;
+                    const Occ oc = occupancy(zc, 0);
+                    int clamped = 0;
+                    for (int q = 0; q < 5; ++q) {
+                        const double raw = tb->bind[zc][q] - dE[zc];
+                        r.pp[q] = raw < 1.0 ? 1.0 : raw;
+                        r.lnp[q] = oc.s[q] > 0 ? xlog(r.pp[q]) : 0.0;
+                        r.occ[q] = oc.s[q];
+                        if (oc.s[q] > 0 && raw < 1.0) ++clamped;
+                    }
+                    r.cnt[XP_C_IPD_CLAMPED] += clamped;
+                }
+            }
+            r.need = need;
+        }
+        const int nbins = R.n_bins;
+        if ((flags & XP_PHOTO) && nbins > 0) {
+            for (int q = tid; q < 3 * nbins; q += BT) r.sig[q / 3][q % 3] = photo_sigma(tb, q % 3, R.hv[q / 3]);
+            __syncthreads();
+            const double* nhv = (R.field_per_cell && s.cell_nhv) ? s.cell_nhv + (size_t)r.cell * XP_MAX_BINS : R.nhv;
+            for (int q = tid; q < 39; q += BT) {
+                const int z = q / 3, sh = q % 3;
+                const double pp = lowered(tb, z, sh, dE);
+                double acc = 0.0;
+                for (int bq = 0; bq < nbins; ++bq)
+                    if (R.hv[bq] >= pp) acc = acc + nhv[bq] * r.sig[bq][sh];
+                r.ssum[z][sh] = acc;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- sorting
+
+__device__ __forceinline__ bool big_live(const BigRec& r, int needbit)
+{
+    return r.state == 0 && (r.need & needbit) != 0;
+}
+
+// Philox sort keys of one species in population order: slot j of a cell gets
+// word j % 4 of the call with index j / 4.
+__global__ __launch_bounds__(BT) void k_big_keys(BigArgs a, int species, int needbit, uint32_t purpose,
+                                                 uint32_t* key, uint32_t* val)
+{
+    const int tid = threadIdx.x;
+    const int nch = species == 0 ? a.hdr->n_e_chunks : a.hdr->n_i_chunks;
+    const int32_t* map = species == 0 ? a.e_chunk_cell : a.i_chunk_cell;
+    for (int g = blockIdx.x; g < nch; g += gridDim.x) {
+        const BigRec& r = a.rec[map[g]];
+        if (!big_live(r, needbit)) continue;
+        const int c0 = species == 0 ? r.ce0 : r.ci0;
+        const int cnt = species == 0 ? r.epn : r.ni;
+        const int64_t pop = species == 0 ? r.ep0 : r.ip0;
+        const int base = (g - c0) * BIG_CH;
+        const int end = cnt - base < BIG_CH ? cnt : base + BIG_CH;
+        for (int j0 = base + 4 * tid; j0 < end; j0 += 4 * BT) {
+            const Words w = draw(a.s, r, (uint32_t)(j0 >> 2), purpose, 0);
+            const uint32_t k4[4] = {w.x0, w.x1, w.x2, w.x3};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int j = j0 + q;
+                if (j < end) {
+                    key[pop + j] = k4[q];
+                    val[pop + j] = (uint32_t)j;
+                }
+            }
+        }
+    }
+}
+
+// One wave per chunk: digit counts -> hist[256 * c0 + digit * nc + chunk].
+__global__ __launch_bounds__(64) void k_big_rhist(BigArgs a, int species, int needbit, int shift,
+                                                  const uint32_t* key)
+{
+    __shared__ uint32_t h[256];
+    const int nch = species == 0 ? a.hdr->n_e_chunks : a.hdr->n_i_chunks;
+    const int32_t* map = species == 0 ? a.e_chunk_cell : a.i_chunk_cell;
+    for (int g = blockIdx.x; g < nch; g += gridDim.x) {
+        const BigRec& r = a.rec[map[g]];
+        if (!big_live(r, needbit)) continue;
+        const int c0 = species == 0 ? r.ce0 : r.ci0;
+        const int nc = species == 0 ? r.nce : r.nci;
+        const int cnt = species == 0 ? r.epn : r.ni;
+        const int64_t pop = species == 0 ? r.ep0 : r.ip0;
+        const int k = g - c0;
+        const int base = k * BIG_CH;
+        const int n = cnt - base < BIG_CH ? cnt - base : BIG_CH;
+        for (int q = threadIdx.x; q < 256; q += 64) h[q] = 0;
+        __syncthreads();
+        for (int q = threadIdx.x; q < n; q += 64) atomicAdd(&h[(key[pop + base + q] >> shift) & 255u], 1u);
+        __syncthreads();
+        uint32_t* hc = a.hist + (size_t)256 * c0;
+        for (int q = threadIdx.x; q < 256; q += 64) hc[(size_t)q * nc + k] = h[q];
+        __syncthreads();
+    }
+}
+
+// Exclusive scan of a cell's digit counts (digit-major, chunk-minor): thread
+// d owns digit d's run of nc entries.
+__global__ __launch_bounds__(256) void k_big_rscan(BigArgs a, int species, int needbit)
+{
+    __shared__ uint32_t red[4];
+    const int tid = threadIdx.x;
+    const int nb = a.hdr->count;
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+        const BigRec& r = a.rec[b];
+        if (!big_live(r, needbit)) continue;
+        const int c0 = species == 0 ? r.ce0 : r.ci0;
+        const int nc = species == 0 ? r.nce : r.nci;
+        if (nc == 0) continue;
+        uint32_t* h = a.hist + (size_t)256 * c0 + (size_t)tid * nc;
+        uint32_t sum = 0;
+        for (int k = 0; k < nc; ++k) sum += h[k];
+        uint32_t tot;
+        uint32_t run = block_exclusive_sum<256, uint32_t>(sum, red, tot);
+        for (int k = 0; k < nc; ++k) {
+            const uint32_t v = h[k];
+            h[k] = run;
+            run += v;
+        }
+        __syncthreads();
+    }
+}
+
+// One wave per chunk: stable scatter with ballot-ranked groups of 64.
+__global__ __launch_bounds__(64) void k_big_rscatter(BigArgs a, int species, int needbit, int shift,
+                                                     const uint32_t* key, const uint32_t* val,
+                                                     uint32_t* key_out, uint32_t* val_out)
+{
+    __shared__ uint32_t run[256];
+    const int lane = threadIdx.x;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const int nch = species == 0 ? a.hdr->n_e_chunks : a.hdr->n_i_chunks;
+    const int32_t* map = species == 0 ? a.e_chunk_cell : a.i_chunk_cell;
+    for (int g = blockIdx.x; g < nch; g += gridDim.x) {
+        const BigRec& r = a.rec[map[g]];
+        if (!big_live(r, needbit)) continue;
+        const int c0 = species == 0 ? r.ce0 : r.ci0;
+        const int nc = species == 0 ? r.nce : r.nci;
+        const int cnt = species == 0 ? r.epn : r.ni;
+        const int64_t pop = species == 0 ? r.ep0 : r.ip0;
+        const int k = g - c0;
+        const int base = k * BIG_CH;
+        const int n = cnt - base < BIG_CH ? cnt - base : BIG_CH;
+        const uint32_t* hc = a.hist + (size_t)256 * c0;
+        for (int q = lane; q < 256; q += 64) run[q] = hc[(size_t)q * nc + k];
+        __syncthreads();
+        for (int c = 0; c < n; c += 64) {
+            const int i = c + lane;
+            const bool valid = i < n;
+            const uint32_t kk = valid ? key[pop + base + i] : 0u;
+            const uint32_t vv = valid ? val[pop + base + i] : 0u;
+            const uint32_t d = (kk >> shift) & 255u;
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int bit = 0; bit < 8; ++bit) {
+                const uint64_t bal = __ballot((d >> bit) & 1u);
+                peers &= ((d >> bit) & 1u) ? bal : ~bal;
+            }
+            const uint32_t rank = (uint32_t)__popcll(peers & lt);
+            const uint32_t at = valid ? run[d] : 0u;
+            __syncthreads();
+            if (valid) {
+                key_out[pop + at + rank] = kk;
+                val_out[pop + at + rank] = vv;
+                if ((peers & lt) == 0) run[d] = at + (uint32_t)__popcll(peers);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------- S1, S2
+
+__global__ __launch_bounds__(BT) void k_big_ee(BigArgs a)
+{
+    __shared__ int cnt[XP_NCOUNT];
+    const int tid = threadIdx.x;
+    const StepArgs& s = a.s;
+    const double mi = s.tab->mass_ion;
+    (void)mi;
+    const int nce = a.hdr->n_e_chunks;
+    for (int g = blockIdx.x; g < nce; g += gridDim.x) {
+        BigRec& r = a.rec[a.e_chunk_cell[g]];
+        const int ne = r.epn;
+        if (r.state || !(r.need & BN_PERM_E) || ne < 2) continue;
+        const xp_run& R = s.runs[r.run];
+        for (int q = tid; q < XP_NCOUNT; q += BT) cnt[q] = 0;
+        __syncthreads();
+        const double qe4 = (QE * QE) * (QE * QE);
+        const double mee = (ME * ME) / (ME + ME);
+        const double kee = qe4 / (((8.0 * PI) * (EPS0 * EPS0)) * (mee * mee));
+        const double lnl = r.mom[10];
+        const double afull = (kee * lnl) * R.dt;
+        const double ahalf = (kee * lnl) * (0.5 * R.dt);
+        const double nunit = (R.w0 * (double)ne) / R.volume;
+        const double f_ee = ME / (ME + ME);
+        const int start = (ne % 2 == 1 && ne >= 3) ? 3 : 0;
+        const int npairs = (ne - start) / 2;
+        const int k = g - r.ce0;
+        const int base = k * BIG_CH;
+        const int jlo = base <= start ? 0 : (base - start + 1) / 2;
+        int jhi = (base + BIG_CH - start + 1) / 2;
+        if (jhi > npairs) jhi = npairs;
+        const uint32_t* perm = a.val_a + r.ep0;
+        double* vx = s.evx + r.eo;
+        double* vy = s.evy + r.eo;
+        double* vz = s.evz + r.eo;
+        const uint32_t* w = s.ew + r.eo;
+        const xp_run& RR = R;
+        const uint32_t st = step_of(s, r.run);
+        const uint32_t lcell = (uint32_t)(r.cell - RR.cell_begin);
+        const uint32_t k0 = (uint32_t)RR.seed, k1 = (uint32_t)(RR.seed >> 32);
+        if (k == 0 && start == 3 && tid == 0) {
+            const int p0 = perm[0], p1 = perm[1], p2 = perm[2];
+            collide_slots(vx, vy, vz, w, vx, vy, vz, p0, p1, w[p1], f_ee, f_ee, ahalf, nunit, st, lcell, 0u,
+                          RP_EE_TRI << 24, k0, k1, cnt);
+            collide_slots(vx, vy, vz, w, vx, vy, vz, p1, p2, w[p2], f_ee, f_ee, ahalf, nunit, st, lcell, 1u,
+                          RP_EE_TRI << 24, k0, k1, cnt);
+            collide_slots(vx, vy, vz, w, vx, vy, vz, p2, p0, w[p0], f_ee, f_ee, ahalf, nunit, st, lcell, 2u,
+                          RP_EE_TRI << 24, k0, k1, cnt);
+            cnt[XP_C_TRIPLET] += 3;
+        }
+        for (int j = jlo + tid; j < jhi; j += BT) {
+            const int e = perm[start + 2 * j], f = perm[start + 2 * j + 1];
+            collide_slots(vx, vy, vz, w, vx, vy, vz, e, f, w[f], f_ee, f_ee, afull, nunit, st, lcell,
+                          (uint32_t)j, RP_EE << 24, k0, k1, cnt);
+        }
+        __syncthreads();
+        if (tid == 0 && k == 0) cnt[XP_C_EE] += npairs;
+        __syncthreads();
+        flush_counts(r, cnt, nullptr);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(BT) void k_big_ei(BigArgs a)
+{
+    __shared__ int cnt[XP_NCOUNT];
+    const int tid = threadIdx.x;
+    const StepArgs& s = a.s;
+    const double mi = s.tab->mass_ion;
+    const double fe_ei = mi / (ME + mi);
+    const double fi_ei = ME / (ME + mi);
+    const double qe4 = (QE * QE) * (QE * QE);
+    const double mei = (ME * mi) / (ME + mi);
+    const double kei = qe4 / (((8.0 * PI) * (EPS0 * EPS0)) * (mei * mei));
+    // species 1: cells with n_e >= n_i, one thread per ion rank;
+    // species 0: cells with n_e < n_i, one thread per electron rank
+    for (int species = 1; species >= 0; --species) {
+        const int nch = species == 0 ? a.hdr->n_e_chunks : a.hdr->n_i_chunks;
+        const int32_t* map = species == 0 ? a.e_chunk_cell : a.i_chunk_cell;
+        for (int g = blockIdx.x; g < nch; g += gridDim.x) {
+            BigRec& r = a.rec[map[g]];
+            const int ne = r.epn, ni = r.ni;
+            if (r.state || !(r.need & BN_EI)) continue;
+            if ((species == 1) != (ne >= ni)) continue;
+            const xp_run& R = s.runs[r.run];
+            for (int q = tid; q < XP_NCOUNT; q += BT) cnt[q] = 0;
+            __syncthreads();
+            const double a1 = (kei * r.mom[10]) * R.dt;
+            const int nmin = ne < ni ? ne : ni, nmax = ne < ni ? ni : ne;
+            const double nunit = (R.w0 * (double)nmin) / R.volume;
+            const int c0 = species == 0 ? r.ce0 : r.ci0;
+            const int k = g - c0;
+            const int base = k * BIG_CH;
+            const int n = nmin - base < BIG_CH ? nmin - base : BIG_CH;
+            const uint32_t* pe = a.val_a + r.ep0;
+            const uint32_t* pi = a.val_c + r.ip0;
+            double* vx = s.evx + r.eo;
+            double* vy = s.evy + r.eo;
+            double* vz = s.evz + r.eo;
+            const uint32_t* w = s.ew + r.eo;
+            double* ix = s.ivx + r.io;
+            double* iy = s.ivy + r.io;
+            double* iz = s.ivz + r.io;
+            const uint8_t* zz = s.iz + r.io;
+            const uint32_t st = step_of(s, r.run);
+            const uint32_t lcell = (uint32_t)(r.cell - R.cell_begin);
+            const uint32_t k0 = (uint32_t)R.seed, k1 = (uint32_t)(R.seed >> 32);
+            for (int q = base + tid; q < base + n; q += BT) {
+                for (int kk = q; kk < nmax; kk += nmin) {
+                    int e, i;
+                    if (ne >= ni) { e = (int)pe[kk]; i = (int)pi[q]; }
+                    else          { i = (int)pi[kk]; e = (int)pe[q]; }
+                    const int z = zz[i];
+                    if (z == 0) continue;
+                    collide_slots(vx, vy, vz, w, ix, iy, iz, e, i, 1u, fe_ei, fi_ei, a1 * (double)(z * z),
+                                  nunit, st, lcell, (uint32_t)kk, RP_EI << 24, k0, k1, cnt);
+                }
+            }
+            __syncthreads();
+            if (tid == 0 && k == 0) cnt[XP_C_EI] += nmax;
+            __syncthreads();
+            flush_counts(r, cnt, nullptr);
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------- S3
+
+__global__ __launch_bounds__(BT) void k_big_lotz(BigArgs a)
+{
+    __shared__ double red[2 * (BIG_CH / 64)];
+    const int tid = threadIdx.x;
+    const StepArgs& s = a.s;
+    const DevTables* tb = s.tab;
+    const int nce = a.hdr->n_e_chunks;
+    for (int g = blockIdx.x; g < nce; g += gridDim.x) {
+        const BigRec& r = a.rec[a.e_chunk_cell[g]];
+        if (!big_live(r, BN_ION)) continue;
+        int oc[5];
+        double pp[5], lnp[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            oc[q] = r.occ[q];
+            pp[q] = r.pp[q];
+            lnp[q] = r.lnp[q];
+        }
+        const int base = (g - r.ce0) * BIG_CH;
+        const int n = r.epn - base < BIG_CH ? r.epn - base : BIG_CH;
+        const int64_t o = r.eo + base;
+        const double sum = block_tree_sum<BT>(BIG_CH, [&](int j) {
+            if (j >= n) return 0.0;
+            return lotz_leaf(s.evx[o + j], s.evy[o + j], s.evz[o + j], s.ew[o + j], oc, pp, lnp, tb);
+        }, red);
+        if (tid == 0) a.part[1][g] = sum;
+    }
+}
+
+__global__ __launch_bounds__(BT) void k_big_s3p(BigArgs a)
+{
+    __shared__ double red[2 * (BIG_MAX_CHUNKS / 64)];
+    const StepArgs& s = a.s;
+    const int nb = a.hdr->count;
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+        BigRec& r = a.rec[b];
+        if (!big_live(r, BN_ION)) continue;
+        const xp_run& R = s.runs[r.run];
+        const double ssum = block_tree_sum<BT>(r.nce, [&](int j) { return a.part[1][r.ce0 + j]; }, red);
+        if (threadIdx.x == 0) {
+            double p = ((ssum * R.w0) * R.dt) / R.volume;
+            if (p > 1.0) {
+                p = 1.0;
+                r.cnt[XP_C_P_CLAMPED] += 1;
+            }
+            r.p = p;
+            r.mom[12] = p;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(BT) void k_big_fire(BigArgs a)
+{
+    __shared__ long long ired[BT / 64];
+    const int tid = threadIdx.x;
+    const StepArgs& s = a.s;
+    const int nci = a.hdr->n_i_chunks;
+    for (int g = blockIdx.x; g < nci; g += gridDim.x) {
+        BigRec& r = a.rec[a.i_chunk_cell[g]];
+        if (!big_live(r, BN_ION)) continue;
+        const double p = r.p;
+        const int base = (g - r.ci0) * BIG_CH;
+        const int n = r.ni - base < BIG_CH ? r.ni - base : BIG_CH;
+        long long c = 0;
+        for (int q = tid; q < n; q += BT) {
+            const int i = base + q;
+            bool f = false;
+            if (s.iz[r.io + i] < 13 && p > 0.0) f = u32(draw(s, r, (uint32_t)i, RP_ION, 0).x0) < p;
+            a.iflag[r.ip0 + i] = f ? 1 : 0;
+            c += f ? 1 : 0;
+        }
+        c = block_isum<BT>(c, ired);
+        if (tid == 0) {
+            a.ccnt[g] = (int32_t)c;
+            if (c) atomicAdd(&r.nfired, (unsigned long long)c);
+        }
+    }
+}
+
+// Per-cell exclusive scan of the ion-chunk counts in ccnt.  mode 0: fired
+// ions of S3; 1: recombination-eligible ranks of S4; 2: electrons appended by
+// S5 (with the capacity check).
+__global__ __launch_bounds__(BT) void k_big_cscan(BigArgs a, int mode)
+{
+    __shared__ int red[BT / 64];
+    const int tid = threadIdx.x;
+    const int nb = a.hdr->count;
+    const int needbit = mode == 0 ? BN_ION : (mode == 1 ? BN_REC : 0);
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+        BigRec& r = a.rec[b];
+        if (r.state || (needbit && !(r.need & needbit))) continue;
+        int carry = 0;
+        for (int k0 = 0; k0 < r.nci; k0 += BT) {
+            const int k = k0 + tid;
+            const int v = k < r.nci ? a.ccnt[r.ci0 + k] : 0;
+            int tot;
+            const int ex = block_exclusive_sum<BT, int>(v, red, tot);
+            if (k < r.nci) a.ccnt[r.ci0 + k] = carry + ex;
+            carry += tot;
+        }
+        if (tid == 0) {
+            if (mode == 0) {
+                r.cnt[XP_C_ION_FIRED] += carry;
+                if (carry > 0) r.need |= BN_FIRED;
+            } else if (mode == 2) {
+                if ((long long)r.ne + carry > (long long)r.ecap) {
+                    r.state = 1;
+                    atomicOr(a.s.status, XP_ST_CAPACITY);
+                } else {
+                    r.nnew5 = carry;
+                    r.cnt[XP_C_E_NEW] += carry;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Drift-frame sums of electrons 0 .. epn-1: weights w (mode 0, S3) or the
+// reduced weights wp (mode 1, S4).
+__global__ __launch_bounds__(BT) void k_big_drift(BigArgs a, int mode)
+{
+    __shared__ double red[2 * (BIG_CH / 64)];
+    __shared__ long long ired[BT / 64];
+    const int tid = threadIdx.x;
+    const StepArgs& s = a.s;
+    const int needbit = mode == 0 ? BN_FIRED : BN_REC;
+    const int nce = a.hdr->n_e_chunks;
+    for (int g = blockIdx.x; g < nce; g += gridDim.x) {
+        BigRec& r = a.rec[a.e_chunk_cell[g]];
+        if (!big_live(r, needbit)) continue;
+        const int base = (g - r.ce0) * BIG_CH;
+        const int n = r.epn - base < BIG_CH ? r.epn - base : BIG_CH;
+        const int64_t o = r.eo + base;
+        const uint32_t* wsrc = mode == 0 ? s.ew + o : a.wp + r.ep0 + base;
+        long long wl = 0;
+        for (int j = tid; j < n; j += BT) wl += wsrc[j];
+        wl = block_isum<BT>(wl, ired);
+        const double* v3[3] = {s.evx + o, s.evy + o, s.evz + o};
+        for (int d = 0; d < 3; ++d) {
+            const double* v = v3[d];
+            const double t = block_tree_sum<BT>(BIG_CH, [&](int j) {
+                return j < n ? (double)wsrc[j] * v[j] : 0.0;
+            }, red);
+            if (tid == 0) a.part[1 + d][g] = t;
+        }
+        if (tid == 0 && wl) atomicAdd(&r.ws, (unsigned long long)wl);
+    }
+}
+
+__global__ __launch_bounds__(BT) void k_big_dfin(BigArgs a, int mode)
+{
+    __shared__ double red[2 * (BIG_MAX_CHUNKS / 64)];
+    const int needbit = mode == 0 ? BN_FIRED : BN_REC;
+    const int nb = a.hdr->count;
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+        BigRec& r = a.rec[b];
+        if (!big_live(r, needbit)) continue;
+        const long long ws = (long long)r.ws;
+        for (int d = 0; d < 3; ++d) {
+            const double t = block_tree_sum<BT>(r.nce, [&](int j) { return a.part[1 + d][r.ce0 + j]; }, red);
+            if (threadIdx.x == 0) r.u[d] = ws != 0 ? t / (double)ws : 0.0;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(BT) void k_big_kth(BigArgs a, int mode)
+{
+    __shared__ double red[2 * (BIG_CH / 64)];
+    const StepArgs& s = a.s;
+    const int needbit = mode == 0 ? BN_FIRED : BN_REC;
+    const int nce = a.hdr->n_e_chunks;
+    for (int g = blockIdx.x; g < nce; g += gridDim.x) {
+        const BigRec& r = a.rec[a.e_chunk_cell[g]];
+        if (!big_live(r, needbit)) continue;
+        if (mode == 1 && r.ws == 0) continue;
+        const int base = (g - r.ce0) * BIG_CH;
+        const int n = r.epn - base < BIG_CH ? r.epn - base : BIG_CH;
+        const int64_t o = r.eo + base;
+        const uint32_t* wsrc = mode == 0 ? s.ew + o : a.wp + r.ep0 + base;
+        const double ux = r.u[0], uy = r.u[1], uz = r.u[2];
+        const double t = block_tree_sum<BT>(BIG_CH, [&](int j) {
+            if (j >= n) return 0.0;
+            const double dx = s.evx[o + j] - ux, dy = s.evy[o + j] - uy, dz = s.evz[o + j] - uz;
+            return (double)wsrc[j] * (HALF_ME_OVER_QE * ((dx * dx + dy * dy) + dz * dz));
+        }, red);
+        if (threadIdx.x == 0) a.part[0][g] = t;
+    }
+}
+
+// One wave per cell: K_th, then fired ions accepted in slot order while the
+// running debit (a left-to-right sum) stays within K_th.
+__global__ __launch_bounds__(64) void k_big_accept(BigArgs a)
+{
+    __shared__ double red[2 * (BIG_MAX_CHUNKS / 64)];
+    const int lane = threadIdx.x;
+    const StepArgs& s = a.s;
+    const DevTables* tb = s.tab;
+    const int nb = a.hdr->count;
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+        BigRec& r = a.rec[b];
+        if (!big_live(r, BN_FIRED)) continue;
+        const double kth = block_tree_sum<64>(r.nce, [&](int j) { return a.part[0][r.ce0 + j]; }, red);
+        const double* dE = r.mom + 16;
+        const int ne0 = r.ne0, ni = r.ni;
+        const int nfired = (int)r.nfired;
+        double debit = 0.0, paid = 0.0;
+        int acc = 0;
+        bool stop = false, over = false;
+        for (int k = 0; k < r.nci && !stop; ++k) {
+            const int c_here = (k + 1 < r.nci ? a.ccnt[r.ci0 + k + 1] : nfired) - a.ccnt[r.ci0 + k];
+            if (c_here == 0) continue;
+            for (int c = 0; c < BIG_CH && !stop; c += 64) {
+                const int i = k * BIG_CH + c + lane;
+                const bool f = i < ni && a.iflag[r.ip0 + i] != 0;
+                double ip = 0.0;
+                if (f) {
+                    const int z = s.iz[r.io + i], kv = s.ik[r.io + i];
+                    ip = lowered(tb, z, valence(z, kv), dE);
+                }
+                uint64_t bal = __ballot(f);
+                while (bal) {
+                    const int bit = __ffsll((unsigned long long)bal) - 1;
+                    bal &= bal - 1;
+                    const double ipv = __shfl(ip, bit, 64);
+                    if (!(debit + ipv <= kth)) {
+                        stop = true;
+                        break;
+                    }
+                    if (ne0 + acc >= r.ecap) {
+                        over = true;
+                        stop = true;
+                        break;
+                    }
+                    debit = debit + ipv;
+                    paid = paid + ipv;
+                    ++acc;
+                }
+            }
+        }
+        if (lane == 0) {
+            r.kth = kth;
+            r.mom[13] = kth;
+            if (over) {
+                r.state = 1;
+                atomicOr(s.status, XP_ST_CAPACITY);
+            } else {
+                r.acc = acc;
+                r.debit = debit;
+                r.mom[14] = debit;
+                r.cnt[XP_C_ION_ACCEPTED] += acc;
+                r.cnt[XP_C_ION_STARVED] += nfired - acc;
+                r.cnt[XP_C_E_NEW] += acc;
+                r.led[XP_L_ION_DEBIT] += paid;
+                r.alpha = debit > 0.0 ? sqrt(1.0 - debit / kth) : 1.0;
+                r.ne = ne0 + acc;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Accepted ions (the first acc fired ones in slot order): Z + 1 (and a K
+// vacancy when the valence shell is 1s) and a new electron at rest at the ion.
+__global__ __launch_bounds__(BT) void k_big_apply3(BigArgs a)
+{
+    __shared__ int red[BT / 64];
+    const StepArgs& s = a.s;
+    const int nci = a.hdr->n_i_chunks;
+    for (int g = blockIdx.x; g < nci; g += gridDim.x) {
+        const BigRec& r = a.rec[a.i_chunk_cell[g]];
+        if (!big_live(r, BN_FIRED)) continue;
+        const int cb = a.ccnt[g];
+        if (cb >= r.acc) continue;
+        const int base = (g - r.ci0) * BIG_CH;
+        const int n = r.ni - base < BIG_CH ? r.ni - base : BIG_CH;
+        block_ordered_select<BT>(
+            n, [&](int q) { return a.iflag[r.ip0 + base + q] != 0; },
+            [&](int q, int pos) {
+                const int rank = cb + pos;
+                if (rank >= r.acc) return;
+                const int i = base + q;
+                const int64_t pi = r.io + i;
+                const int z = s.iz[pi], kv = s.ik[pi];
+                const int sv = valence(z, kv);
+                s.iz[pi] = (uint8_t)(z + 1);
+                if (sv == 0) s.ik[pi] = (uint8_t)(kv + 1);
+                const int64_t pe = r.eo + r.ne0 + rank;
+                s.ex[pe] = s.ix[pi];
+                if (s.ey) s.ey[pe] = s.iy ? s.iy[pi] : 0.0;
+                s.evx[pe] = 0.0;
+                s.evy[pe] = 0.0;
+                s.evz[pe] = 0.0;
+                s.ew[pe] = 1;
+            },
+            red);
+    }
+}
+
+// Drift-frame rescale: mode 0 (S3) electrons 0 .. ne0-1 by sqrt(1 - debit/K_th);
+// mode 1 (S4) every electron with reduced weight > 0 by sqrt(1 + E_add/K_th),
+// and the reduced weights become the weights.
+__global__ __launch_bounds__(BT) void k_big_rescale(BigArgs a, int mode)
+{
+    const StepArgs& s = a.s;
+    const int needbit = mode == 0 ? BN_FIRED : BN_REC_APPLY;
+    const int nce = a.hdr->n_e_chunks;
+    for (int g = blockIdx.x; g < nce; g += gridDim.x) {
+        const BigRec& r = a.rec[a.e_chunk_cell[g]];
+        if (!big_live(r, needbit)) continue;
+        if (mode == 0 && !(r.debit > 0.0)) continue;
+        const int base = (g - r.ce0) * BIG_CH;
+        const int n = r.epn - base < BIG_CH ? r.epn - base : BIG_CH;
+        const int64_t o = r.eo + base;
+        const double ux = r.u[0], uy = r.u[1], uz = r.u[2], al = r.alpha;
+        for (int j = threadIdx.x; j < n; j += BT) {
+            bool go = true;
+            if (mode == 1) {
+                const uint32_t w2 = a.wp[r.ep0 + base + j];
+                go = w2 > 0;
+                s.ew[o + j] = w2;
+            }
+            if (go) {
+                s.evx[o + j] = ux + al * (s.evx[o + j] - ux);
+                s.evy[o + j] = uy + al * (s.evy[o + j] - uy);
+                s.evz[o + j] = uz + al * (s.evz[o + j] - uz);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- S4
+
+__global__ __launch_bounds__(BT) void k_big_s4part(BigArgs a)
+{
+    __shared__ double red[2 * (BIG_CH / 64)];
+    __shared__ long long ired[BT / 64];
+    const int tid = threadIdx.x;
+    const StepArgs& s = a.s;
+    const int nce = a.hdr->n_e_chunks;
+    for (int g = blockIdx.x; g < nce; g += gridDim.x) {
+        BigRec& r = a.rec[a.e_chunk_cell[g]];
+        if (r.state) continue;
+        const double ebulk = s.runs[r.run].e_bulk;
+        const int base = (g - r.ce0) * BIG_CH;
+        const int n = r.epn - base < BIG_CH ? r.epn - base : BIG_CH;
+        const int64_t o = r.eo + base;
+        long long wl = 0, bl = 0;
+        for (int j = tid; j < n; j += BT) {
+            const long long w = s.ew[o + j];
+            wl += w;
+            if (kin_at(s, o + j) < ebulk) bl += w;
+        }
+        wl = block_isum<BT>(wl, ired);
+        bl = block_isum<BT>(bl, ired);
+        const double ke = block_tree_sum<BT>(BIG_CH, [&](int j) {
+            if (j >= n) return 0.0;
+            const double e = kin_at(s, o + j);
+            return e < ebulk ? (double)s.ew[o + j] * e : 0.0;
+        }, red);
+        if (tid == 0) {
+            a.part[0][g] = ke;
+            atomicAdd(&r.we4, (unsigned long long)wl);
+            atomicAdd(&r.wb4, (unsigned long long)bl);
+        }
+    }
+    const int nci = a.hdr->n_i_chunks;
+    for (int g = blockIdx.x; g < nci; g += gridDim.x) {
+        BigRec& r = a.rec[a.i_chunk_cell[g]];
+        if (r.state) continue;
+        const int zf = s.runs[r.run].z_floor;
+        const int base = (g - r.ci0) * BIG_CH;
+        const int n = r.ni - base < BIG_CH ? r.ni - base : BIG_CH;
+        const int64_t o = r.io + base;
+        long long s1 = 0, el = 0;
+        for (int j = tid; j < n; j += BT) {
+            const int z = s.iz[o + j];
+            s1 += z;
+            el += z > zf ? 1 : 0;
+        }
+        s1 = block_isum<BT>(s1, ired);
+        el = block_isum<BT>(el, ired);
+        if (tid == 0) {
+            atomicAdd(&r.sz4, (unsigned long long)s1);
+            atomicAdd(&r.nelig, (unsigned long long)el);
+        }
+    }
+}
+
+__global__ __launch_bounds__(BT) void k_big_s4fin(BigArgs a)
+{
+    __shared__ double red[2 * (BIG_MAX_CHUNKS / 64)];
+    const StepArgs& s = a.s;
+    const int nb = a.hdr->count;
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+        BigRec& r = a.rec[b];
+        if (r.state) continue;
+        const int ne = r.ne, ni = r.ni;
+        if (ne < 1 || ni < 1) continue;
+        const xp_run& R = s.runs[r.run];
+        const double ker = block_tree_sum<BT>(r.nce, [&](int j) { return a.part[0][r.ce0 + j]; }, red);
+        if (threadIdx.x == 0) {
+            const long long wbr = (long long)r.wb4;
+            double tp = 0.01;
+            if (wbr > 0) {
+                tp = (2.0 * ker) / (3.0 * (double)wbr);
+                if (tp < 0.01) tp = 0.01;
+            }
+            r.mom[15] = tp;
+            const double n_i = ((double)ni * R.w0) / R.volume;
+            const double zeos = eos_zbar(s.tab, n_i, tp);
+            const double dd = (double)(long long)r.sz4 - (double)ni * zeos;
+            if (dd > 0.0) {
+                long long nrec = (long long)floor(dd + 0.5);
+                if (nrec > (long long)r.nelig) nrec = (long long)r.nelig;
+                if (nrec > ne) nrec = ne;
+                if (nrec > 0) {
+                    r.nrec = (int32_t)nrec;
+                    r.need |= BN_REC;
+                    r.ws = 0;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Recombination-eligible ions along the REC_I order: count per chunk (pass 0)
+// or write the first nrec into sel (pass 1, after the per-cell scan).
+__global__ __launch_bounds__(BT) void k_big_recsel(BigArgs a, int pass)
+{
+    __shared__ int red[BT / 64];
+    __shared__ long long ired[BT / 64];
+    const int tid = threadIdx.x;
+    const StepArgs& s = a.s;
+    const int nci = a.hdr->n_i_chunks;
+    for (int g = blockIdx.x; g < nci; g += gridDim.x) {
+        const BigRec& r = a.rec[a.i_chunk_cell[g]];
+        if (!big_live(r, BN_REC)) continue;
+        const int zf = s.runs[r.run].z_floor;
+        const int base = (g - r.ci0) * BIG_CH;
+        const int n = r.ni - base < BIG_CH ? r.ni - base : BIG_CH;
+        const uint32_t* perm = a.val_c + r.ip0;
+        auto elig = [&](int q) { return (int)s.iz[r.io + perm[base + q]] > zf; };
+        if (pass == 0) {
+            long long c = 0;
+            for (int q = tid; q < n; q += BT) c += elig(q) ? 1 : 0;
+            c = block_isum<BT>(c, ired);
+            if (tid == 0) a.ccnt[g] = (int32_t)c;
+        } else {
+            const int cb = a.ccnt[g];
+            if (cb >= r.nrec) continue;
+            block_ordered_select<BT>(
+                n, elig,
+                [&](int q, int pos) {
+                    if (cb + pos < r.nrec) a.sel[r.ip0 + cb + pos] = (int32_t)perm[base + q];
+                },
+                red);
+        }
+    }
+}
+
+// Reduced weights: the electrons of the first nrec REC_E ranks lose one unit.
+__global__ __launch_bounds__(BT) void k_big_wp(BigArgs a)
+{
+    const StepArgs& s = a.s;
+    const int nce = a.hdr->n_e_chunks;
+    for (int g = blockIdx.x; g < nce; g += gridDim.x) {
+        const BigRec& r = a.rec[a.e_chunk_cell[g]];
+        if (!big_live(r, BN_REC)) continue;
+        const int base = (g - r.ce0) * BIG_CH;
+        const int n = r.epn - base < BIG_CH ? r.epn - base : BIG_CH;
+        const uint32_t* perm = a.val_a + r.ep0;
+        for (int t = base + threadIdx.x; t < base + n; t += BT) {
+            const uint32_t e = perm[t];
+            a.wp[r.ep0 + e] = s.ew[r.eo + e] - (t < r.nrec ? 1u : 0u);
+        }
+    }
+}
+
+// One wave per cell: K_th of the reduced population; recombinations paired
+// rank by rank (ion sel[t], electron REC_E rank t), their energies summed left
+// to right.
+__global__ __launch_bounds__(64) void k_big_recfin(BigArgs a)
+{
+    __shared__ double red[2 * (BIG_MAX_CHUNKS / 64)];
+    const int lane = threadIdx.x;
+    const StepArgs& s = a.s;
+    const DevTables* tb = s.tab;
+    const double mi = tb->mass_ion;
+    const int nb = a.hdr->count;
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+        BigRec& r = a.rec[b];
+        if (!big_live(r, BN_REC)) continue;
+        const long long ws = (long long)r.ws;
+        double kth = 0.0;
+        if (ws != 0) kth = block_tree_sum<64>(r.nce, [&](int j) { return a.part[0][r.ce0 + j]; }, red);
+        if (ws == 0 || !(kth > 0.0)) {
+            if (lane == 0) r.cnt[XP_C_REC_SKIPPED] += 1;
+            __syncthreads();
+            continue;
+        }
+        const double* dE = r.mom + 16;
+        const double half_mi = (0.5 * mi) / QE;
+        const double ratio = ME / mi;
+        const uint32_t* pe = a.val_a + r.ep0;
+        const int nr = r.nrec;
+        double eadd = 0.0, bind = 0.0;
+        for (int t0 = 0; t0 < nr; t0 += 64) {
+            const int t = t0 + lane;
+            double term = 0.0;
+            if (t < nr) {
+                const int64_t e = r.eo + pe[t];
+                const int64_t i = r.io + a.sel[r.ip0 + t];
+                const double keu = kin_at(s, e);
+                const double vx = s.ivx[i], vy = s.ivy[i], vz = s.ivz[i];
+                const double kib = half_mi * ((vx * vx + vy * vy) + vz * vz);
+                const double nx = vx + ratio * s.evx[e];
+                const double ny = vy + ratio * s.evy[e];
+                const double nz = vz + ratio * s.evz[e];
+                s.ivx[i] = nx;
+                s.ivy[i] = ny;
+                s.ivz[i] = nz;
+                const double kia = half_mi * ((nx * nx + ny * ny) + nz * nz);
+                const int z = s.iz[i], kv = s.ik[i];
+                const Occ o0 = occupancy(z, kv);
+                const int kn = (kv >= 1 && o0.s[1] + o0.s[2] == 8) ? kv - 1 : kv;
+                const Occ o1 = occupancy(z - 1, kn);
+                int sl = 0;
+                for (int q = 0; q < 5; ++q)
+                    if (o1.s[q] > o0.s[q]) { sl = q; break; }
+                const double ipr = lowered(tb, z - 1, sl, dE);
+                s.iz[i] = (uint8_t)(z - 1);
+                s.ik[i] = (uint8_t)kn;
+                term = (keu + ipr) + (kib - kia);
+                bind = bind + ipr;
+            }
+            const int m = nr - t0 < 64 ? nr - t0 : 64;
+            for (int l = 0; l < m; ++l) eadd = eadd + __shfl(term, l, 64);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) bind += __shfl_xor(bind, off, 64);
+        if (lane == 0) {
+            r.kth = kth;
+            r.cnt[XP_C_REC] += nr;
+            r.led[XP_L_REC_ADD] += eadd;
+            r.led[XP_L_REC_BIND] += bind;
+            r.alpha = sqrt(1.0 + eadd / kth);
+            r.need |= BN_REC_APPLY;
+        }
+        __syncthreads();
+    }
+}
+
+// Stable in-place removal of electrons whose weight reached zero; one block
+// per cell walks the slots in order (positions only move down).
+__global__ __launch_bounds__(BT) void k_big_compact(BigArgs a)
+{
+    __shared__ int red[BT / 64];
+    const int tid = threadIdx.x;
+    const StepArgs& s = a.s;
+    const int nb = a.hdr->count;
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+        BigRec& r = a.rec[b];
+        if (!big_live(r, BN_REC_APPLY)) continue;
+        const int ne = r.ne;
+        const int64_t o = r.eo;
+        int out = 0;
+        for (int c0 = 0; c0 < ne; c0 += BT) {
+            const int j = c0 + tid;
+            const bool alive = j < ne && s.ew[o + j] > 0;
+            double x = 0, y = 0, vx = 0, vy = 0, vz = 0;
+            uint32_t w = 0;
+            if (alive) {
+                x = s.ex[o + j];
+                y = s.ey ? s.ey[o + j] : 0.0;
+                vx = s.evx[o + j]; vy = s.evy[o + j]; vz = s.evz[o + j];
+                w = s.ew[o + j];
+            }
+            int tot;
+            const int ex = block_exclusive_sum<BT, int>(alive ? 1 : 0, red, tot);
+            if (alive) {
+                const int64_t d = o + out + ex;
+                s.ex[d] = x;
+                if (s.ey) s.ey[d] = y;
+                s.evx[d] = vx; s.evy[d] = vy; s.evz[d] = vz;
+                s.ew[d] = w;
+            }
+            out += tot;
+            __syncthreads();
+        }
+        if (tid == 0) {
+            r.cnt[XP_C_E_REMOVED] += ne - out;
+            r.ne = out;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- S5
+
+// Decisions per ion from its pre-S5 state (K-vacancy decay, then the photo
+// events of 1s, 2s, 2p): new Z and k in place, the emission record in iaux
+// (bit 0 Auger, bits 1..3 photo 1s 2s 2p, bins at 4 + 4 s, Z0 at 16, k0 at 24)
+// and the electrons per chunk in ccnt.
+__global__ __launch_bounds__(BT) void k_big_s5a(BigArgs a)
+{
+    __shared__ int cnt[XP_NCOUNT];
+    __shared__ double led[XP_NLEDGER];
+    __shared__ long long ired[BT / 64];
+    const int tid = threadIdx.x;
+    const StepArgs& s = a.s;
+    const DevTables* tb = s.tab;
+    const uint32_t flags = s.flags;
+    const int nci = a.hdr->n_i_chunks;
+    for (int g = blockIdx.x; g < nci; g += gridDim.x) {
+        BigRec& r = a.rec[a.i_chunk_cell[g]];
+        if (r.state) continue;
+        const xp_run& R = s.runs[r.run];
+        for (int q = tid; q < XP_NCOUNT; q += BT) cnt[q] = 0;
+        for (int q = tid; q < XP_NLEDGER; q += BT) led[q] = 0.0;
+        __syncthreads();
+        const int nbins = R.n_bins;
+        const bool photo = (flags & XP_PHOTO) && nbins > 0;
+        const double* nhv = (R.field_per_cell && s.cell_nhv) ? s.cell_nhv + (size_t)r.cell * XP_MAX_BINS : R.nhv;
+        const double dtr = R.dt_rad;
+        const double* dE = r.mom + 16;
+        const int base = (g - r.ci0) * BIG_CH;
+        const int n = r.ni - base < BIG_CH ? r.ni - base : BIG_CH;
+        long long newe = 0;
+        for (int q = tid; q < n; q += BT) {
+            const int i = base + q;
+            const int64_t pi = r.io + i;
+            const int z0 = s.iz[pi], k0 = s.ik[pi];
+            uint32_t mask = 0, bins = 0;
+            if (z0 < 13) {
+                const Occ o0 = occupancy(z0, k0);
+                const int nl0 = o0.s[1] + o0.s[2];
+                int z = z0, kv = k0;
+                if ((flags & XP_DECAY) && k0 >= 1 && nl0 >= 1) {
+                    const double ga = tb->gamma_a[z0][k0], gx = tb->gamma_x[z0][k0];
+                    const double rate = ga + gx;
+                    if (rate > 0.0) {
+                        const Words d = draw(s, r, (uint32_t)i, RP_DECAY, 0);
+                        double pd = dtr * rate;
+                        if (pd > 1.0) {
+                            pd = 1.0;
+                            atomicAdd(&cnt[XP_C_P_CLAMPED], 1);
+                        }
+                        if (u52(d.x0, d.x1) < pd) {
+                            kv = k0 - 1;
+                            atomicAdd(&cnt[XP_C_DECAY], 1);
+                            if (nl0 >= 2 && u52(d.x2, d.x3) < ga / rate) {
+                                z = z0 + 1;
+                                mask |= 1u;
+                                atomicAdd(&cnt[XP_C_AUGER], 1);
+                            } else {
+                                atomicAdd(&cnt[XP_C_KALPHA], 1);
+                                atomicAdd(&led[XP_L_KALPHA], tb->e_kalpha[z0]);
+                            }
+                        }
+                    }
+                }
+                if (photo) {
+                    const Words fw = draw(s, r, (uint32_t)i, RP_ION, 0);
+                    const uint32_t fire[3] = {fw.x1, fw.x2, fw.x3};
+                    for (int sh = 0; sh < 3; ++sh) {
+                        if (o0.s[sh] <= 0) continue;
+                        const double sum = r.ssum[z0][sh];
+                        if (!(sum > 0.0)) continue;
+                        double p = ((CLIGHT * dtr) * (double)o0.s[sh]) * sum;
+                        if (p > 1.0) {
+                            p = 1.0;
+                            atomicAdd(&cnt[XP_C_P_CLAMPED], 1);
+                        }
+                        if (!(u32(fire[sh]) < p)) continue;
+                        const Occ on = occupancy(z, kv);
+                        if (z >= 13 || on.s[sh] <= 0) {
+                            atomicAdd(&cnt[XP_C_PHOTO_SKIPPED], 1);
+                            continue;
+                        }
+                        const double pp = lowered(tb, z0, sh, dE);
+                        const Words d = draw(s, r, (uint32_t)i, RP_BIN, (uint32_t)sh);
+                        const double target = u52(d.x0, d.x1) * sum;
+                        double cum = 0.0;
+                        int sel = -1, lastpos = -1;
+                        for (int bq = 0; bq < nbins; ++bq) {
+                            if (!(R.hv[bq] >= pp)) continue;
+                            const double term = nhv[bq] * r.sig[bq][sh];
+                            cum = cum + term;
+                            if (term > 0.0) lastpos = bq;
+                            if (cum > target) {
+                                sel = bq;
+                                break;
+                            }
+                        }
+                        if (sel < 0) sel = lastpos;
+                        z = z + 1;
+                        if (sh == 0) kv = kv + 1;
+                        mask |= 2u << sh;
+                        bins |= (uint32_t)sel << (4 * sh);
+                        atomicAdd(&cnt[XP_C_PHOTO_1S + sh], 1);
+                    }
+                }
+                s.iz[pi] = (uint8_t)z;
+                s.ik[pi] = (uint8_t)kv;
+            }
+            a.iaux[r.ip0 + i] = mask | (bins << 4) | ((uint32_t)z0 << 16) | ((uint32_t)k0 << 24);
+            newe += __popc(mask);
+        }
+        newe = block_isum<BT>(newe, ired);
+        if (tid == 0) a.ccnt[g] = (int32_t)newe;
+        flush_counts(r, cnt, led);
+        __syncthreads();
+    }
+}
+
+// New electrons of S5 in ion-slot order (per ion: Auger, photo 1s, 2s, 2p),
+// isotropic with the energies of the decisions in iaux.
+__global__ __launch_bounds__(BT) void k_big_s5b(BigArgs a)
+{
+    __shared__ int red[BT / 64];
+    __shared__ double led[XP_NLEDGER];
+    const int tid = threadIdx.x;
+    const StepArgs& s = a.s;
+    const DevTables* tb = s.tab;
+    const int nci = a.hdr->n_i_chunks;
+    for (int g = blockIdx.x; g < nci; g += gridDim.x) {
+        BigRec& r = a.rec[a.i_chunk_cell[g]];
+        if (r.state || r.nnew5 == 0) continue;
+        const xp_run& R = s.runs[r.run];
+        for (int q = tid; q < XP_NLEDGER; q += BT) led[q] = 0.0;
+        __syncthreads();
+        const double* dE = r.mom + 16;
+        const int base = (g - r.ci0) * BIG_CH;
+        const int n = r.ni - base < BIG_CH ? r.ni - base : BIG_CH;
+        int run_pos = r.ne + a.ccnt[g];
+        for (int c0 = 0; c0 < n; c0 += BT) {
+            const int q = c0 + tid;
+            const uint32_t aux = q < n ? a.iaux[r.ip0 + base + q] : 0u;
+            const uint32_t mask = aux & 15u;
+            const int c = __popc(mask);
+            int tot;
+            const int ex = block_exclusive_sum<BT, int>(c, red, tot);
+            int pos = run_pos + ex;
+            if (c > 0) {
+                const int i = base + q;
+                const int64_t pi = r.io + i;
+                const int z0 = (aux >> 16) & 255u, k0 = (aux >> 24) & 255u;
+                const Occ o0 = occupancy(z0, k0);
+                for (int bit = 0; bit < 4; ++bit) {
+                    if (!(mask & (1u << bit))) continue;
+                    double en;
+                    if (bit == 0) {
+                        const int nl0 = o0.s[1] + o0.s[2];
+                        const double p2s = lowered(tb, z0, 1, dE);
+                        const double p2p = lowered(tb, z0, 2, dE);
+                        const double num = (double)o0.s[1] * p2s + (double)o0.s[2] * p2p;
+                        en = tb->e_kalpha[z0] - num / (double)nl0;
+                        if (en < 0.0) en = 0.0;
+                        atomicAdd(&led[XP_L_AUGER_E], en);
+                    } else {
+                        const int sh = bit - 1;
+                        const int sel = (aux >> (4 + 4 * sh)) & 15u;
+                        en = R.hv[sel] - lowered(tb, z0, sh, dE);
+                        atomicAdd(&led[XP_L_PHOTO_E], en);
+                        atomicAdd(&led[XP_L_PHOTON_ABS], R.hv[sel]);
+                    }
+                    const Words d = draw(s, r, (uint32_t)i, RP_DIR, (uint32_t)bit);
+                    const double mu = 2.0 * u52(d.x0, d.x1) - 1.0;
+                    double sp, cp;
+                    xsincos2pi((((uint64_t)d.x2 << 32) | d.x3) >> 12, sp, cp);
+                    const double st = sqrt(1.0 - mu * mu);
+                    const double sv = sqrt(en * TWO_QE_OVER_ME);
+                    const int64_t pe = r.eo + pos;
+                    s.evx[pe] = sv * (st * cp);
+                    s.evy[pe] = sv * (st * sp);
+                    s.evz[pe] = sv * mu;
+                    s.ew[pe] = 1;
+                    s.ex[pe] = s.ix[pi];
+                    if (s.ey) s.ey[pe] = s.iy ? s.iy[pi] : 0.0;
+                    ++pos;
+                }
+            }
+            run_pos += tot;
+        }
+        __syncthreads();
+        for (int q = tid; q < XP_NLEDGER; q += BT)
+            if (led[q] != 0.0) atomicAdd(&r.led[q], led[q]);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- commit
+
+__global__ __launch_bounds__(64) void k_big_commit(BigArgs a)
+{
+    const StepArgs& s = a.s;
+    const int nb = a.hdr->count;
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+        const BigRec& r = a.rec[b];
+        if (r.state) continue;
+        const int cell = r.cell;
+        const int ne = r.ne + r.nnew5;
+        if (threadIdx.x == 0) {
+            s.e_cnt[cell] = ne;
+            if (s.stats) atomicMax(&s.stats[3], ne);
+        }
+        if (s.cell_cnt)
+            for (int q = threadIdx.x; q < XP_NCOUNT; q += 64) s.cell_cnt[(size_t)cell * XP_NCOUNT + q] = r.cnt[q];
+        if (s.cell_led)
+            for (int q = threadIdx.x; q < XP_NLEDGER; q += 64) s.cell_led[(size_t)cell * XP_NLEDGER + q] = r.led[q];
+        if (s.cell_mom)
+            for (int q = threadIdx.x; q < XP_NMOM; q += 64) s.cell_mom[(size_t)cell * XP_NMOM + q] = r.mom[q];
+        if (s.run_cnt)
+            for (int q = threadIdx.x; q < XP_NCOUNT; q += 64)
+                if (r.cnt[q]) atomicAdd((unsigned long long*)&s.run_cnt[(size_t)r.run * XP_NCOUNT + q], (unsigned long long)r.cnt[q]);
+        if (s.run_led)
+            for (int q = threadIdx.x; q < XP_NLEDGER; q += 64)
+                if (r.led[q] != 0.0) atomicAdd(&s.run_led[(size_t)r.run * XP_NLEDGER + q], r.led[q]);
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+
+BigPlan big_plan(int32_t big_max, int64_t e_pop, int64_t i_pop)
+{
+    BigPlan p{};
+    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const int64_t bm = big_max > 0 ? big_max : 1;
+    const int64_t ep = e_pop > 0 ? e_pop : 1, ip = i_pop > 0 ? i_pop : 1;
+    p.e_chunks = (int32_t)(ep / BIG_CH + bm + 1);
+    p.i_chunks = (int32_t)(ip / BIG_CH + bm + 1);
+    const int64_t cmax = p.e_chunks > p.i_chunks ? p.e_chunks : p.i_chunks;
+    const int64_t pmax = ep > ip ? ep : ip;
+    size_t o = 0;
+    p.list = o; o += up(4 * (size_t)bm);
+    p.hdr = o; o += up(sizeof(BigHdr));
+    p.rec = o; o += up(sizeof(BigRec) * (size_t)bm);
+    p.e_chunk_cell = o; o += up(4 * (size_t)p.e_chunks);
+    p.i_chunk_cell = o; o += up(4 * (size_t)p.i_chunks);
+    p.part = o; o += 4 * up(8 * (size_t)p.e_chunks);
+    p.key_a = o; o += up(4 * (size_t)ep);
+    p.val_a = o; o += up(4 * (size_t)ep);
+    p.key_b = o; o += up(4 * (size_t)pmax);
+    p.val_b = o; o += up(4 * (size_t)pmax);
+    p.key_c = o; o += up(4 * (size_t)ip);
+    p.val_c = o; o += up(4 * (size_t)ip);
+    p.hist = o; o += up(4 * 256 * (size_t)cmax);
+    p.iflag = o; o += up((size_t)ip);
+    p.ccnt = o; o += up(4 * (size_t)p.i_chunks);
+    p.iaux = o; o += up(4 * (size_t)ip);
+    p.wp = o; o += up(4 * (size_t)ep);
+    p.sel = o; o += up(4 * (size_t)ip);
+    p.bytes = o;
+    return p;
+}
+
+namespace {
+
+hipError_t big_sort(BigArgs& a, int species, int needbit, uint32_t purpose, uint32_t* key,
+                    uint32_t* val, uint32_t* key2, uint32_t* val2, unsigned gch, unsigned gcell,
+                    hipStream_t s)
+{
+    hipLaunchKernelGGL(k_big_keys, dim3(gch), dim3(BT), 0, s, a, species, needbit, purpose, key, val);
+    for (int shift = 0; shift < 32; shift += 8) {
+        hipLaunchKernelGGL(k_big_rhist, dim3(gch), dim3(64), 0, s, a, species, needbit, shift, (const uint32_t*)key);
+        hipLaunchKernelGGL(k_big_rscan, dim3(gcell), dim3(256), 0, s, a, species, needbit);
+        hipLaunchKernelGGL(k_big_rscatter, dim3(gch), dim3(64), 0, s, a, species, needbit, shift,
+                           (const uint32_t*)key, (const uint32_t*)val, key2, val2);
+        uint32_t* t = key; key = key2; key2 = t;
+        t = val; val = val2; val2 = t;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t big_launch(BigArgs& a, bool all_cells, hipStream_t s)
+{
+    const int64_t cmax = a.e_chunks_max > a.i_chunks_max ? a.e_chunks_max : a.i_chunks_max;
+    const unsigned gch = (unsigned)(cmax < 4096 ? cmax : 4096);
+    const unsigned gcell = (unsigned)(a.big_max < 1024 ? a.big_max : 1024);
+    const uint32_t flags = a.s.flags;
+    if (all_cells)
+        hipLaunchKernelGGL(k_big_all, dim3((a.s.n_cells + 255) / 256 < 1024 ? (a.s.n_cells + 255) / 256 : 1024),
+                           dim3(256), 0, s, a, a.s.n_cells);
+    hipLaunchKernelGGL(k_big_init, dim3((gcell + 255) / 256), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_big_plan, dim3(1), dim3(1024), 0, s, a, 0);
+    hipLaunchKernelGGL(k_big_plan, dim3(1), dim3(1024), 0, s, a, 1);
+    hipLaunchKernelGGL(k_big_s0, dim3(gch), dim3(BT), 0, s, a);
+    hipLaunchKernelGGL(k_big_s0fin, dim3(gcell), dim3(BT), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (flags & (XP_EE | XP_EI)) {
+        if ((e = big_sort(a, 0, BN_PERM_E, RP_PERM_E, a.key_a, a.val_a, a.key_b, a.val_b, gch, gcell, s)) != hipSuccess)
+            return e;
+        if (flags & XP_EE) hipLaunchKernelGGL(k_big_ee, dim3(gch), dim3(BT), 0, s, a);
+        if (flags & XP_EI) {
+            if ((e = big_sort(a, 1, BN_EI, RP_PERM_I, a.key_c, a.val_c, a.key_b, a.val_b, gch, gcell, s)) != hipSuccess)
+                return e;
+            hipLaunchKernelGGL(k_big_ei, dim3(gch), dim3(BT), 0, s, a);
+        }
+    }
+    if (flags & XP_ION) {
+        hipLaunchKernelGGL(k_big_lotz, dim3(gch), dim3(BT), 0, s, a);
+        hipLaunchKernelGGL(k_big_s3p, dim3(gcell), dim3(BT), 0, s, a);
+        hipLaunchKernelGGL(k_big_fire, dim3(gch), dim3(BT), 0, s, a);
+        hipLaunchKernelGGL(k_big_cscan, dim3(gcell), dim3(BT), 0, s, a, 0);
+        hipLaunchKernelGGL(k_big_drift, dim3(gch), dim3(BT), 0, s, a, 0);
+        hipLaunchKernelGGL(k_big_dfin, dim3(gcell), dim3(BT), 0, s, a, 0);
+        hipLaunchKernelGGL(k_big_kth, dim3(gch), dim3(BT), 0, s, a, 0);
+        hipLaunchKernelGGL(k_big_accept, dim3(gcell), dim3(64), 0, s, a);
+        hipLaunchKernelGGL(k_big_apply3, dim3(gch), dim3(BT), 0, s, a);
+        hipLaunchKernelGGL(k_big_rescale, dim3(gch), dim3(BT), 0, s, a, 0);
+    }
+    if (flags & XP_REC) {
+        hipLaunchKernelGGL(k_big_plan, dim3(1), dim3(1024), 0, s, a, 0);
+        hipLaunchKernelGGL(k_big_s4part, dim3(gch), dim3(BT), 0, s, a);
+        hipLaunchKernelGGL(k_big_s4fin, dim3(gcell), dim3(BT), 0, s, a);
+        if ((e = big_sort(a, 1, BN_REC, RP_REC_I, a.key_c, a.val_c, a.key_b, a.val_b, gch, gcell, s)) != hipSuccess)
+            return e;
+        if ((e = big_sort(a, 0, BN_REC, RP_REC_E, a.key_a, a.val_a, a.key_b, a.val_b, gch, gcell, s)) != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_big_recsel, dim3(gch), dim3(BT), 0, s, a, 0);
+        hipLaunchKernelGGL(k_big_cscan, dim3(gcell), dim3(BT), 0, s, a, 1);
+        hipLaunchKernelGGL(k_big_recsel, dim3(gch), dim3(BT), 0, s, a, 1);
+        hipLaunchKernelGGL(k_big_wp, dim3(gch), dim3(BT), 0, s, a);
+        hipLaunchKernelGGL(k_big_drift, dim3(gch), dim3(BT), 0, s, a, 1);
+        hipLaunchKernelGGL(k_big_dfin, dim3(gcell), dim3(BT), 0, s, a, 1);
+        hipLaunchKernelGGL(k_big_kth, dim3(gch), dim3(BT), 0, s, a, 1);
+        hipLaunchKernelGGL(k_big_recfin, dim3(gcell), dim3(64), 0, s, a);
+        hipLaunchKernelGGL(k_big_rescale, dim3(gch), dim3(BT), 0, s, a, 1);
+        hipLaunchKernelGGL(k_big_compact, dim3(gcell), dim3(BT), 0, s, a);
+    }
+    if (flags & (XP_PHOTO | XP_DECAY)) {
+        hipLaunchKernelGGL(k_big_s5a, dim3(gch), dim3(BT), 0, s, a);
+        hipLaunchKernelGGL(k_big_cscan, dim3(gcell), dim3(BT), 0, s, a, 2);
+        hipLaunchKernelGGL(k_big_s5b, dim3(gch), dim3(BT), 0, s, a);
+    }
+    hipLaunchKernelGGL(k_big_commit, dim3(gcell), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace xpd

@@ -51,7 +51,7 @@ __global__ void k_cell_ids(int64_t n, const int32_t* prun, const double* x, cons
 __global__ void k_caps(int n_cells, const int32_t* ce, const int32_t* ci, int32_t e_per_ion,
                        int32_t e_extra, int32_t* e_cnt, int32_t* i_cnt, int32_t* e_cap,
                        int32_t* i_cap, int64_t* e_off, int64_t* i_off, int64_t* e_start,
-                       int64_t* i_start, int64_t* need)
+                       int64_t* i_start, int64_t* need, int32_t e_lds, int32_t i_lds)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_cells) return;
@@ -68,6 +68,12 @@ __global__ void k_caps(int n_cells, const int32_t* ce, const int32_t* ci, int32_
     i_start[c] = ni;
     atomicMax((unsigned long long*)&need[2], (unsigned long long)capE);
     atomicMax((unsigned long long*)&need[3], (unsigned long long)capI);
+    // cells that may outgrow every LDS plan: bounds of the global-memory path
+    if (capE > e_lds || ni > i_lds) {
+        atomicAdd((unsigned long long*)&need[4], 1ull);
+        atomicAdd((unsigned long long*)&need[5], (unsigned long long)capE);
+        atomicAdd((unsigned long long*)&need[6], (unsigned long long)capI);
+    }
 }
 
 // In-place exclusive scan of SCAN_B * SCAN_PER elements per block; block total
@@ -286,7 +292,7 @@ hipError_t radix_sort(int64_t n, int bits, uint32_t*& key, uint32_t*& val, uint3
 }  // namespace
 
 hipError_t bin_launch(const xp_particles* in, xp_batch* b, const xp_capacity* cap,
-                      int64_t* d_need, hipStream_t s)
+                      int64_t* d_need, int32_t e_lds, int32_t i_lds, hipStream_t s)
 {
     const BinPlan P = bin_plan(in->ne, in->ni, b->n_cells);
     char* w = (char*)b->d_work;
@@ -306,7 +312,7 @@ hipError_t bin_launch(const xp_particles* in, xp_batch* b, const xp_capacity* ca
     hipError_t e;
     if ((e = hipMemsetAsync(cnt_e, 0, 4 * (size_t)nc, s)) != hipSuccess) return e;
     if ((e = hipMemsetAsync(cnt_i, 0, 4 * (size_t)nc, s)) != hipSuccess) return e;
-    if ((e = hipMemsetAsync(d_need, 0, 4 * sizeof(int64_t), s)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(d_need, 0, 8 * sizeof(int64_t), s)) != hipSuccess) return e;
     int bits = 0;
     while ((1ll << bits) < (long long)nc) ++bits;
 
@@ -322,7 +328,7 @@ hipError_t bin_launch(const xp_particles* in, xp_batch* b, const xp_capacity* ca
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_caps, dim3((nc + 255) / 256), dim3(256), 0, s, nc, cnt_e, cnt_i,
                        cap->e_per_ion, cap->e_extra, b->d_e_cnt, b->d_i_cnt, b->d_e_cap,
-                       b->d_i_cap, b->d_e_off, b->d_i_off, st_e, st_i, d_need);
+                       b->d_i_cap, b->d_e_off, b->d_i_off, st_e, st_i, d_need, e_lds, i_lds);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = scan_exclusive<int64_t>(b->d_e_off, nc, aux64, s)) != hipSuccess) return e;
     if ((e = scan_exclusive<int64_t>(b->d_i_off, nc, aux64, s)) != hipSuccess) return e;

@@ -308,6 +308,36 @@ __device__ int block_ordered_select(int n, P pred, E emit, int* red)
     return base;
 }
 
+// Block-wide exclusive prefix sum of one value per thread, in thread order;
+// the block total through total.  red: >= B / 64 entries.
+template <int B, class T>
+__device__ T block_exclusive_sum(T v, T* red, T& total)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    T incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const T o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+    }
+    if (B == 64) {
+        total = __shfl(incl, 63, 64);
+        return incl - v;
+    }
+    __syncthreads();
+    if (lane == 63) red[wid] = incl;
+    __syncthreads();
+    T woff = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < B / 64; ++w) {
+        if (w < wid) woff += red[w];
+        tot += red[w];
+    }
+    __syncthreads();
+    total = tot;
+    return woff + incl - v;
+}
+
 // Bitonic sort of p = 2^k 64-bit keys in LDS (ascending), B threads.
 template <int B, class P>
 __device__ void bitonic_sort(P a, int p)

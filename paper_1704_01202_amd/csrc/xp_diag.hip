@@ -50,11 +50,27 @@ __global__ __launch_bounds__(64) void k_diag_cells(DiagArgs a)
         }
         atomicAdd((unsigned long long*)&o->fe_hist[bin], (unsigned long long)w);
     }
-    __shared__ double red[2 * 128];
-    const double k = block_tree_sum<64>(ne, [&](int j) {
+    __shared__ double red[2 * (DIAG_CHUNK / 64)];
+    extern __shared__ double part[];   // [ceil(e_cap_max / DIAG_CHUNK)]
+    auto leaf = [&](int64_t j) {
         const double x = a.evx[eo + j], y = a.evy[eo + j], z = a.evz[eo + j];
         return (double)a.ew[eo + j] * (HALF_ME_OVER_QE * ((x * x + y * y) + z * z));
-    }, red);
+    };
+    double k;
+    if (ne <= DIAG_CHUNK) {
+        k = block_tree_sum<64>(ne, [&](int j) { return leaf(j); }, red);
+    } else {
+        // aligned chunks are subtrees of the cell's pairwise sum
+        const int nch = (ne + DIAG_CHUNK - 1) / DIAG_CHUNK;
+        for (int c = 0; c < nch; ++c) {
+            const int64_t base = (int64_t)c * DIAG_CHUNK;
+            const int n = ne - base < DIAG_CHUNK ? (int)(ne - base) : DIAG_CHUNK;
+            const double t = block_tree_sum<64>(DIAG_CHUNK, [&](int j) { return j < n ? leaf(base + j) : 0.0; }, red);
+            if (threadIdx.x == 0) part[c] = t;
+        }
+        __syncthreads();
+        k = block_tree_sum<64>(nch, [&](int j) { return part[j]; }, red);
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         we += __shfl_xor(we, off, 64);
@@ -100,7 +116,9 @@ __global__ __launch_bounds__(256) void k_diag_runs(DiagArgs a, uint32_t what)
 hipError_t diag_launch(const DiagArgs& a, uint32_t what, hipStream_t s)
 {
     hipLaunchKernelGGL(k_diag_zero, dim3(a.n_runs), dim3(64), 0, s, a.out, a.n_runs);
-    if (a.n_cells > 0) hipLaunchKernelGGL(k_diag_cells, dim3(a.n_cells), dim3(64), 0, s, a);
+    const int nch_max = (a.e_cap_max + DIAG_CHUNK - 1) / DIAG_CHUNK;
+    const size_t cell_smem = sizeof(double) * (size_t)(nch_max > 1 ? nch_max : 1);
+    if (a.n_cells > 0) hipLaunchKernelGGL(k_diag_cells, dim3(a.n_cells), dim3(64), cell_smem, s, a);
     int p = 64;
     while (p < a.n_cells) p <<= 1;
     const size_t smem = 2 * sizeof(double) * (size_t)(p / 64);

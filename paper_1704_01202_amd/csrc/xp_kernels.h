@@ -38,14 +38,26 @@ struct StepArgs {
     const int32_t* cell_list_count;
     int32_t* defer_out;         // cells that outgrow this launch's LDS plan
     int32_t* defer_out_count;
+    int32_t* big_out;           // cells beyond every LDS plan (global-memory path)
+    int32_t* big_out_count;
+    int32_t big_out_cap;
     int32_t* stats;             // [0] max electrons per cell after the step, [1] deferrals
     int32_t n_cells;
     int32_t lds_ce, lds_ci;     // LDS capacity per cell (electrons, ions)
 };
 
+// Deferral counters of the tiered LDS launches: one per tier, the last one
+// counts the cells handed to the global-memory path.
+constexpr int STEP_COUNTS = 16;
+constexpr int BIG_COUNT_SLOT = STEP_COUNTS - 1;
+
 __global__ void k_step_prep(int32_t* counts, int32_t* stats);
 
 size_t step_lds_bytes(int ce, int ci);
+// Largest LDS plan: ions per cell (i_lds) and the electrons that fit beside
+// them (e_lds) within the dynamic LDS budget of one workgroup.
+void lds_limits(size_t max_lds, int* e_lds, int* i_lds);
+size_t lds_budget(size_t max_lds);
 
 template <int B>
 __global__ void k_step(StepArgs a);
@@ -62,7 +74,7 @@ struct BinPlan {
 
 BinPlan bin_plan(int64_t ne, int64_t ni, int32_t n_cells);
 hipError_t bin_launch(const xp_particles* in, xp_batch* b, const xp_capacity* cap,
-                      int64_t* d_need, hipStream_t s);
+                      int64_t* d_need, int32_t e_lds, int32_t i_lds, hipStream_t s);
 
 }  // namespace xpd
 
@@ -83,7 +95,13 @@ struct DiagArgs {
     double* cell_k;      // workspace [n_cells]
     xp_diag* out;
     int32_t n_runs, n_cells;
+    int32_t e_cap_max;
 };
+
+// Kinetic-energy sums of one cell are taken in aligned chunks of DIAG_CHUNK
+// electrons (canonical pairwise sums of the chunk sums).
+constexpr int DIAG_CHUNK = 8192;
+constexpr int DIAG_MAX_CHUNKS = 4096;
 
 hipError_t diag_launch(const DiagArgs& a, uint32_t what, hipStream_t s);
 
@@ -92,4 +110,84 @@ hipError_t diag_launch(const DiagArgs& a, uint32_t what, hipStream_t s);
 namespace xpd {
 hipError_t selftest_launch(int which, int64_t n, const double* x, const uint64_t* u, double* out,
                            uint32_t* words, hipStream_t s);
+}  // namespace xpd
+
+namespace xpd {
+
+// ---- global-memory path for cells beyond one workgroup's LDS -------------
+
+constexpr int BIG_CH = 1024;          // particle slots per chunk (a power of two)
+constexpr int BIG_MAX_CHUNKS = 32768; // chunks per cell and species (33.5 M slots)
+
+// Per-cell state of one step on the global-memory path.
+struct BigRec {
+    int32_t cell, run;
+    int32_t ne0, ne, ni, ecap;
+    int32_t ce0, nce, ci0, nci;        // chunk ranges of the current plan
+    int64_t eo, io;                    // slab offsets
+    int64_t ep0, ip0;                  // offsets in the population arrays
+    int32_t state;                     // 0 live, 1 stopped (capacity or size)
+    int32_t need;                      // BN_* bits
+    int32_t zc, acc, nrec, epn;        // epn: electrons covered by the current chunk plan
+    int32_t nnew5, pad0;               // electrons appended by the source terms
+    unsigned long long we, wb, sz, sz2, ws, nelig, nfired, we4, wb4, sz4;
+    double p, kth, debit, alpha;
+    double u[3];
+    double pp[5], lnp[5];
+    int32_t occ[5], pad;
+    double mom[XP_NMOM];
+    double sig[XP_MAX_BINS][3];
+    double ssum[13][3];
+    int32_t cnt[XP_NCOUNT];
+    double led[XP_NLEDGER];
+};
+
+enum : int32_t {
+    BN_PERM_E = 1,      // S1/S2 need the electron permutation
+    BN_EI = 2,          // S2 runs
+    BN_ION = 4,         // S3 evaluates Lotz and draws
+    BN_FIRED = 8,       // S3 has fired ions (drift frame, accept)
+    BN_REC = 16,        // S4 recombines
+    BN_REC_APPLY = 32,  // S4 drift frame is usable
+};
+
+struct BigHdr {
+    int32_t n_e_chunks, n_i_chunks;
+    int32_t count;      // cells on the path this step
+    int32_t pad;
+};
+
+struct BigArgs {
+    StepArgs s;
+    int32_t* list;              // cells on the path
+    int32_t* count;             // their number
+    BigRec* rec;
+    BigHdr* hdr;
+    int32_t* e_chunk_cell;      // chunk -> index into list
+    int32_t* i_chunk_cell;
+    double* part[4];            // per electron chunk partial sums
+    uint32_t *key_a, *val_a, *key_b, *val_b, *key_c, *val_c;
+    uint32_t* hist;             // [256 * chunks]
+    uint8_t* iflag;             // per ion (population)
+    int32_t* ccnt;              // per ion chunk counts / bases
+    uint32_t* iaux;             // per ion S5 decisions
+    uint32_t* wp;               // per electron reduced weights (S4)
+    int32_t* sel;               // per ion selected for recombination (S4)
+    int32_t big_max;
+    int32_t e_chunks_max, i_chunks_max;
+    int64_t e_pop_max, i_pop_max;
+};
+
+struct BigPlan {
+    size_t list, hdr, rec, e_chunk_cell, i_chunk_cell, part, key_a, val_a, key_b, val_b, key_c,
+        val_c, hist, iflag, ccnt, iaux, wp, sel;
+    size_t bytes;
+    int32_t e_chunks, i_chunks;
+};
+
+BigPlan big_plan(int32_t big_max, int64_t e_pop, int64_t i_pop);
+// Enqueues the global-memory step of the cells in a.list (all cells when
+// all_cells is set).
+hipError_t big_launch(BigArgs& a, bool all_cells, hipStream_t s);
+
 }  // namespace xpd

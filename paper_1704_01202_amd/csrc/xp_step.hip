@@ -151,19 +151,31 @@ __device__ void step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
     // the next (larger) plan, a cell beyond its slab capacity is an error
     const int lim = ecap < ce ? ecap : ce;
 
-    auto defer = [&]() {
+    // beyond every LDS plan: hand the cell to the global-memory path
+    auto to_big = [&]() {
         if (tid == 0) {
-            if (a.defer_out) {
-                const int k = atomicAdd(a.defer_out_count, 1);
-                a.defer_out[k] = cell;
-                if (a.stats) atomicAdd(&a.stats[1], 1);
+            if (a.big_out) {
+                const int k = atomicAdd(a.big_out_count, 1);
+                if (k < a.big_out_cap) a.big_out[k] = cell;
+                else atomicOr(a.status, XP_ST_CAPACITY);
             } else {
                 atomicOr(a.status, XP_ST_CAPACITY);
             }
         }
     };
+    auto defer = [&]() {
+        if (!a.defer_out) {
+            to_big();
+            return;
+        }
+        if (tid == 0) {
+            const int k = atomicAdd(a.defer_out_count, 1);
+            a.defer_out[k] = cell;
+            if (a.stats) atomicAdd(&a.stats[1], 1);
+        }
+    };
     if (ni > ci) {
-        if (tid == 0) atomicOr(a.status, XP_ST_CAPACITY);
+        to_big();
         return;
     }
     if (ne > ce || ne > ecap) {
@@ -855,10 +867,25 @@ template __global__ void k_step<256>(StepArgs);
 
 __global__ void k_step_prep(int32_t* counts, int32_t* stats)
 {
-    if (threadIdx.x < 4) {
-        if (counts) counts[threadIdx.x] = 0;
-        if (stats) stats[threadIdx.x] = 0;
-    }
+    if (threadIdx.x < STEP_COUNTS && counts) counts[threadIdx.x] = 0;
+    if (threadIdx.x < 4 && stats) stats[threadIdx.x] = 0;
+}
+
+size_t lds_budget(size_t max_lds)
+{
+    // static LDS of k_step (CellShared) plus a margin for the runtime's own
+    const size_t fixed = sizeof(CellShared) + 1024;
+    return max_lds > fixed ? max_lds - fixed : 0;
+}
+
+void lds_limits(size_t max_lds, int* e_lds, int* i_lds)
+{
+    const int ci = 1024;
+    const size_t budget = lds_budget(max_lds);
+    int ce = 0;
+    while (step_lds_bytes(ce + 16, ci) <= budget) ce += 16;
+    *e_lds = ce;
+    *i_lds = ci;
 }
 
 }  // namespace xpd

@@ -94,10 +94,17 @@ class Batch:
     runs: list of (workloads.RunSpec, workloads.Particles).  capacity =
     (electron slots per ion, extra slots) of every cell's electron slab.
     cell_records keeps per-cell counters, tallies and moments of the last step.
+    big: workspace of the global-memory path -- "auto" for the cells whose
+    slabs may outgrow one workgroup's LDS, "all" so that every cell can take it
+    (step(..., schedule=3)).
     """
 
     def __init__(self, ctx: Context, runs, capacity=(7, 16), cell_records=False,
-                 cell_nhv=None):
+                 cell_nhv=None, big="auto"):
+        if big not in ("auto", "all"):
+            raise ValueError("big must be 'auto' or 'all'")
+        self.big = big
+        self.big_cells_max, self.big_e_slots, self.big_i_slots = 0, 0, 0
         self.ctx = ctx
         dev = ctx.device
         self.device = dev
@@ -122,7 +129,7 @@ class Batch:
         self.d_e_cnt = torch.zeros(nc, dtype=torch.int32, device=dev)
         self.d_i_cnt = torch.zeros(nc, dtype=torch.int32, device=dev)
         self.d_status = torch.zeros(1, dtype=torch.int32, device=dev)
-        self.d_need = torch.zeros(4, dtype=torch.int64, device=dev)
+        self.d_need = torch.zeros(8, dtype=torch.int64, device=dev)
         self.d_stats = torch.zeros(4, dtype=torch.int32, device=dev)
         self.h_stats = torch.zeros(4, dtype=torch.int32, pin_memory=True)
         self.e_hint = 0
@@ -214,6 +221,8 @@ class Batch:
         b.e_cap_max = getattr(self, "e_cap_max", 0)
         b.i_cap_max = getattr(self, "i_cap_max", 0)
         b.d_stats = _ptr(self.d_stats)
+        b.big_cells_max = self.big_cells_max
+        b.big_e_slots, b.big_i_slots = self.big_e_slots, self.big_i_slots
         return b
 
     def _bin(self):
@@ -231,6 +240,16 @@ class Batch:
         st = int(self.d_status.item())
         if st & B.XP_ST_BIN_SIZE:
             raise B.XpError("bin_particles: slab arrays too small after sizing")
+        if self.big == "all":
+            self.big_cells_max, self.big_e_slots, self.big_i_slots = (
+                self.n_cells, self.e_slots, self.i_slots)
+        else:
+            self.big_cells_max, self.big_e_slots, self.big_i_slots = (
+                int(need[4]), int(need[5]), int(need[6]))
+        step_bytes = B.xp_step_work_bytes(self.struct())
+        if step_bytes > self.work_bytes:
+            self.work_bytes = step_bytes
+            self.d_work = torch.empty(self.work_bytes, dtype=torch.uint8, device=self.device)
 
     # -- the method ---------------------------------------------------------------
     def _hint(self, use_hint):
@@ -266,6 +285,11 @@ class Batch:
 
     def status(self):
         return int(self.d_status.item())
+
+    def stats(self):
+        """[largest electron count of an LDS cell, LDS re-plans, cells on the
+        global-memory path, largest electron count among those] of the last step."""
+        return self.d_stats.cpu().numpy().copy()
 
     # -- read-back for checks ---------------------------------------------------
     def state(self, run=0) -> CompactState:

@@ -65,11 +65,11 @@ def compare(gs, os_, label, vtol=1e-12):
 
 
 def run_pair(ctx, spec, parts, steps, flags=O.ALL, schedule=0, capacity=(7, 16),
-             check_every=1, label=""):
+             check_every=1, label="", big="auto"):
     tab = ctx.tables
     sim = O.Sim(tab, spec)
     sim.bin(parts)
-    bat = RT.Batch(ctx, [(spec, parts)], capacity=capacity, cell_records=True)
+    bat = RT.Batch(ctx, [(spec, parts)], capacity=capacity, cell_records=True, big=big)
     compare(bat.state(), sim.state(), label + " after binning")
     for s in range(steps):
         bat.step(s, flags, schedule=schedule)
