@@ -120,6 +120,97 @@ def copy_reference(mib):
     log("copy reference: 3 x %d MiB device copies" % mib)
 
 
+def bench_c4(args):
+    """Batched scan: independent 0D runs in one batch, graph-replayed steps,
+    knobs picked by the autotuner, against a sequential plain loop over the
+    same runs.  Prints one JSON line (runs/hour)."""
+    import torch
+    from paper_1704_01202_amd import runtime as RT
+    from paper_1704_01202_amd import scan as SC
+    from paper_1704_01202_amd import workloads as W
+
+    t0 = time.perf_counter()
+    tab = W.make_tables()
+    runs = W.config_c4_runs(nruns=args.runs, nsteps=args.run_steps)
+    n_part = sum(p.ne + p.ni for _, p in runs)
+    log("scan generated (%.1f s): %d runs, %d particles" % (time.perf_counter() - t0, len(runs), n_part))
+    ctx = RT.Context(tab)
+    # autotune on a throw-away copy: the knobs change speed, never results
+    tuner = SC.Scan(ctx, runs)
+    for _ in range(2):
+        tuner.eager_step()
+    best, best_ms = tuner.autotune(reps=1)
+    log("autotuned on steps 2-%d: %s (%.3f ms/step)" % (tuner.steps_done - 1, best, best_ms))
+    del tuner
+    torch.cuda.empty_cache()
+    # the timed scan: steps 0 .. steps-1 of every run, the first two eager
+    # (they give the LDS plan its size hint), the rest as graph replays
+    sc = SC.Scan(ctx, runs)
+    sc.config = dict(best)
+    torch.cuda.synchronize()
+    log("batched: %d cells, e_slots %d, global-path cells %d (%.1f s)"
+        % (sc.bat.n_cells, sc.bat.e_slots, sc.bat.big_cells_max, time.perf_counter() - t0))
+    k = 6
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    sc.eager_step()
+    sc.eager_step()
+    reps = max(1, (args.steps - 2) // k)
+    sc.capture(k)
+    for _ in range(reps):
+        sc.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    timed = 2 + reps * k
+    ms_step = e0.elapsed_time(e1) / timed
+    cnt = sc.bat.run_counters().sum(axis=0)
+    coll = int(cnt[0] + cnt[1] + cnt[2])
+    status = sc.status()
+    batched_rph = len(runs) * 3600.0 / (args.run_steps * wall / timed)
+    log("batched: %.3f ms/step over steps 0-%d (graph capture included), status %d"
+        % (ms_step, timed - 1, status))
+    # sequential plain loop: every run alone, eager, the same steps
+    seq_steps = timed
+    del sc
+    torch.cuda.empty_cache()
+    if args.no_seq:
+        stepping, total = float("nan"), float("nan")
+    else:
+        stepping, total, _ = SC.sequential(ctx, runs, seq_steps)
+    seq_rph = len(runs) * 3600.0 / (args.run_steps * stepping / seq_steps)
+    log("sequential: %.2f s stepping (%.2f s with set-up) for %d steps of every run"
+        % (stepping, total, seq_steps))
+    out = {
+        "metric": "runs/hour (batched scan)",
+        "value": batched_rph,
+        "unit": "runs/h",
+        "n_gpus": 1,
+        "steps": timed,
+        "warmup": 0,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "%d independent 0D runs, 1e4-2e6 particles log-uniform, 1e16-1e18 W/cm^2, "
+                               "1.55-1.9 keV, SP/EK alternating, dt 0.1 fs, %d steps per run"
+                               % (len(runs), args.run_steps),
+                   "particles": n_part, "autotuned": best, "graph_steps": k, "status": status},
+        "collisions_per_s": coll / wall,
+        "sequential_runs_per_hour": seq_rph,
+        "vs_sequential": batched_rph / seq_rph if seq_rph == seq_rph else None,
+        "sequential_steps": seq_steps,
+        "note": "both legs time steps 0..%d of every run from the same initial state; "
+                "runs/hour scales that to %d steps per run" % (timed - 1, args.run_steps),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,12 +223,21 @@ def main():
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run a plain device copy of MIB MiB "
                          "(calibrates the HBM byte counters under a profiler)")
+    ap.add_argument("--workload", choices=("c2", "c4"), default="c2",
+                    help="c2: the 512x512-cell step (default); c4: the batched scan")
+    ap.add_argument("--runs", type=int, default=256, help="c4: runs in the scan")
+    ap.add_argument("--run-steps", type=int, default=500, help="c4: steps of every run")
+    ap.add_argument("--no-seq", action="store_true", help="c4: skip the sequential leg (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the step has no cross-GPU work here and only "
               "--gpus 1 is supported (see DESIGN.md for how runs and cells would shard)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "c4":
+        bench_c4(args)
+        return
 
     import torch
     from paper_1704_01202_amd import binding as B

@@ -244,6 +244,9 @@ typedef struct {
                                   of the previous step); 0: plan for e_cap_max.  Cells that
                                   outgrow the plan are redone with a larger one in the same
                                   call, so the hint changes speed, never results. */
+    int32_t big_grid;          /* workgroups of the global-memory path's chunk kernels;
+                                  0: library default.  Speed only. */
+    int32_t reserved;
 } xp_step_params;
 
 /* Stable counting sort of the unsorted particles into the batch's cell slabs

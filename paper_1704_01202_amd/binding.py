@@ -83,7 +83,7 @@ class XpCapacity(C.Structure):
 
 class XpStepParams(C.Structure):
     _fields_ = [("flags", _u32), ("step", _u32), ("d_step", _vp), ("schedule", _i32),
-                ("e_hint", _i32)]
+                ("e_hint", _i32), ("big_grid", _i32), ("reserved", _i32)]
 
 
 class XpDiag(C.Structure):

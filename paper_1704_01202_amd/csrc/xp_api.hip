@@ -249,6 +249,7 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
     if (b->n_cells == 0) return XP_OK;
     if (b->e_cap_max <= 0 || b->i_cap_max < 0) return fail(XP_ERR_INVALID_ARG, "batch e_cap_max / i_cap_max not set");
     if (p->schedule < 0 || p->schedule > 3) return fail(XP_ERR_INVALID_ARG, "unknown schedule");
+    if (p->big_grid < 0 || p->big_grid > 65536) return fail(XP_ERR_INVALID_ARG, "big_grid out of range");
     if (b->big_cells_max < 0 || b->big_e_slots < 0 || b->big_i_slots < 0)
         return fail(XP_ERR_INVALID_ARG, "negative big-cell bounds");
     if (!b->d_work || b->work_bytes < xp_step_work_bytes(b))
@@ -320,6 +321,7 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
         g.wp = (uint32_t*)(w + bp.wp);
         g.sel = (int32_t*)(w + bp.sel);
         g.big_max = b->big_cells_max;
+        g.grid = p->big_grid;
         g.e_chunks_max = bp.e_chunks;
         g.i_chunks_max = bp.i_chunks;
         g.e_pop_max = b->big_e_slots;

@@ -1475,7 +1475,8 @@ hipError_t big_sort(BigArgs& a, int species, int needbit, uint32_t purpose, uint
 hipError_t big_launch(BigArgs& a, bool all_cells, hipStream_t s)
 {
     const int64_t cmax = a.e_chunks_max > a.i_chunks_max ? a.e_chunks_max : a.i_chunks_max;
-    const unsigned gch = (unsigned)(cmax < 4096 ? cmax : 4096);
+    const int64_t want = a.grid > 0 ? a.grid : 4096;
+    const unsigned gch = (unsigned)(cmax < want ? cmax : want);
     const unsigned gcell = (unsigned)(a.big_max < 1024 ? a.big_max : 1024);
     const uint32_t flags = a.s.flags;
     if (all_cells)

@@ -38,14 +38,32 @@ __global__ void k_cell_ids(int64_t n, const int32_t* prun, const double* x, cons
                            const xp_run* runs, uint32_t* key, uint32_t* val, int32_t* count)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const int r = prun ? prun[p] : 0;
-    const int c = cell_of(runs[r], x[p], y ? y[p] : 0.0);
-    if (key) {
-        key[p] = (uint32_t)c;
-        val[p] = (uint32_t)p;
+    const bool valid = p < n;
+    int c = 0;
+    if (valid) {
+        const int r = prun ? prun[p] : 0;
+        c = cell_of(runs[r], x[p], y ? y[p] : 0.0);
+        if (key) {
+            key[p] = (uint32_t)c;
+            val[p] = (uint32_t)p;
+        }
     }
-    if (count) atomicAdd(&count[c], 1);
+    if (!count) return;
+    // lanes of a wave that share a cell (inputs are often grouped by cell or
+    // run) add their count with one atomic; a few rounds, then one per lane
+    const int lane = threadIdx.x & 63;
+    bool todo = valid;
+    for (int it = 0; it < 4; ++it) {
+        const uint64_t act = __ballot(todo);
+        if (act == 0) break;
+        const int first = __ffsll((unsigned long long)act) - 1;
+        const int c0 = __shfl(c, first, 64);
+        const bool same = todo && c == c0;
+        const uint64_t grp = __ballot(same);
+        if (same && lane == first) atomicAdd(&count[c0], (int)__popcll(grp));
+        if (same) todo = false;
+    }
+    if (todo) atomicAdd(&count[c], 1);
 }
 
 __global__ void k_caps(int n_cells, const int32_t* ce, const int32_t* ci, int32_t e_per_ion,

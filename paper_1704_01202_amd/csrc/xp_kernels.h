@@ -174,6 +174,7 @@ struct BigArgs {
     uint32_t* wp;               // per electron reduced weights (S4)
     int32_t* sel;               // per ion selected for recombination (S4)
     int32_t big_max;
+    int32_t grid;               // chunk-kernel workgroups (0: default)
     int32_t e_chunks_max, i_chunks_max;
     int64_t e_pop_max, i_pop_max;
 };

@@ -262,18 +262,27 @@ class Batch:
     def _after(self):
         self.h_stats.copy_(self.d_stats, non_blocking=True)
 
-    def step(self, step, flags=B.XP_ALL, schedule=0, d_step=None, use_hint=True):
-        p = B.XpStepParams(int(flags), int(step), _ptr(d_step), int(schedule),
-                           self._hint(use_hint))
+    def _params(self, step, flags, schedule, d_step, use_hint, e_hint, big_grid):
+        hint = int(e_hint) if e_hint is not None else self._hint(use_hint)
+        return B.XpStepParams(int(flags), int(step), _ptr(d_step), int(schedule), hint,
+                              int(big_grid), 0)
+
+    def step(self, step, flags=B.XP_ALL, schedule=0, d_step=None, use_hint=True, e_hint=None,
+             big_grid=0, record_stats=True):
+        """One step of every run.  d_step: optional int32 [n_runs] device step
+        index per run (overrides step).  e_hint / big_grid / schedule change
+        speed only.  record_stats=False skips the stats read-back (graph capture)."""
+        p = self._params(step, flags, schedule, d_step, use_hint, e_hint, big_grid)
         B.collide_ionize_step(self.ctx.h, self.struct(), p, _stream())
-        self._after()
+        if record_stats:
+            self._after()
 
     def photo_auger(self, step, flags=B.XP_PHOTO | B.XP_DECAY, schedule=0, d_step=None,
-                    use_hint=True):
-        p = B.XpStepParams(int(flags), int(step), _ptr(d_step), int(schedule),
-                           self._hint(use_hint))
+                    use_hint=True, e_hint=None, big_grid=0, record_stats=True):
+        p = self._params(step, flags, schedule, d_step, use_hint, e_hint, big_grid)
         B.photo_auger_step(self.ctx.h, self.struct(), p, _stream())
-        self._after()
+        if record_stats:
+            self._after()
 
     def diagnostics(self, reset=False):
         out = torch.zeros(self.n_runs * C.sizeof(B.XpDiag), dtype=torch.uint8, device=self.device)
