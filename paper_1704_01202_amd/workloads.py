@@ -389,3 +389,50 @@ def config_c4_runs(seed=4, nruns=256, nsteps=500, size_lo=1e4, size_hi=2e6):
                                 0.1, prng)
         runs.append((spec, parts))
     return runs
+
+
+@dataclass
+class Request:
+    """One served run: arrival time (s from the start of the trace), the run and
+    its particles, and the steps it asks for."""
+    rid: int
+    arrival: float
+    spec: RunSpec
+    parts: Particles
+    nsteps: int
+
+
+def config_c5_trace(seed=5, n_requests=1000, rate=20.0, size_lo=1e4, size_hi=5e6,
+                    cells_lo=64, cells_hi=4096, steps_lo=100, steps_hi=2000):
+    """Served stream: Poisson arrivals at `rate` runs/s; half 0D runs (one
+    cell), half 1D runs of log-uniform-integer cells; particles log-uniform,
+    split evenly e/i (electrons carry 3 units, Al3+); steps uniform-integer;
+    intensity, photon energy and IPD model drawn as in the batched scan."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for q in range(n_requests):
+        t += rng.exponential(1.0 / rate)
+        size = math.exp(rng.uniform(math.log(size_lo), math.log(size_hi)))
+        one_d = rng.random() < 0.5
+        ncell = int(round(math.exp(rng.uniform(math.log(cells_lo), math.log(cells_hi))))) if one_d else 1
+        nsteps = int(rng.integers(steps_lo, steps_hi + 1))
+        inten = math.exp(rng.uniform(math.log(1e16), math.log(1e18)))
+        hv = float(rng.uniform(1550.0, 1900.0))
+        nion_total = max(2 * ncell, int(size) // 2)
+        per_cell = max(1, nion_total // ncell)
+        w0 = 100.0
+        vol = per_cell * w0 / SOLID_NI
+        dx = vol ** (1.0 / 3.0)
+        spec = RunSpec(seed=(seed << 32) + q, nx=ncell, ny=1, dx=dx, dy=dx, volume=vol, w0=w0,
+                       dt=0.1e-15, dt_rad=0.1e-15, ipd_model=IPD_SP if q % 2 == 0 else IPD_EK,
+                       photon_hv=(hv,), photon_n=(photon_density(inten, hv),), nsteps=nsteps)
+        prng = np.random.default_rng([seed, q])
+
+        def evel(rng, cid, slot):
+            return _maxwell(rng, cid.size, 10.0, _ME)
+
+        counts = np.full(ncell, per_cell, dtype=np.int64)
+        parts = build_particles(spec, counts, counts, evel, 0.1, prng)
+        out.append(Request(rid=q, arrival=t, spec=spec, parts=parts, nsteps=nsteps))
+    return out
