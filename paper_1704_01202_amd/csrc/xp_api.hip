@@ -15,6 +15,7 @@ struct xp_ctx {
     const xpd::DevTables* d_tables;
     bool tables_ready;
     size_t max_lds;               // dynamic LDS limit per workgroup
+    int n_cu;                     // compute units
     std::vector<unsigned char> staging;
 };
 
@@ -92,6 +93,12 @@ xp_status xp_ctx_create(xp_ctx** out, int32_t device_id)
     c->d_tables = nullptr;
     c->tables_ready = false;
     c->max_lds = (size_t)lds;
+    int ncu = 0;
+    if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device_id)) != hipSuccess) {
+        delete c;
+        return hip_fail(e, "hipDeviceGetAttribute");
+    }
+    c->n_cu = ncu > 0 ? ncu : 1;
     *out = c;
     return XP_OK;
 }
@@ -197,14 +204,21 @@ xp_status bin_particles(xp_ctx* ctx, const xp_particles* in, xp_batch* b, const 
 struct StepPlan {
     int32_t* lists[2];
     int32_t* counts;   // STEP_COUNTS: one per tier, the last for the big list
+    double* run_sig;   // [n_runs][XP_MAX_BINS][3]
     char* big;         // BigPlan region (when the batch has big bounds)
     size_t bytes;
 };
 
-static size_t step_fixed_bytes(int32_t n_cells)
+static size_t step_lists_bytes(int32_t n_cells)
 {
     const size_t n = (size_t)(n_cells > 0 ? n_cells : 1);
     return (8 * n + 4 * xpd::STEP_COUNTS + 255) & ~size_t(255);
+}
+
+static size_t step_fixed_bytes(int32_t n_cells, int32_t n_runs)
+{
+    const size_t r = (size_t)(n_runs > 0 ? n_runs : 1);
+    return step_lists_bytes(n_cells) + ((8 * XP_MAX_BINS * 3 * r + 255) & ~size_t(255));
 }
 
 static StepPlan step_plan(const xp_batch* b)
@@ -215,7 +229,8 @@ static StepPlan step_plan(const xp_batch* b)
     p.lists[0] = (int32_t*)w;
     p.lists[1] = (int32_t*)(w + 4 * n);
     p.counts = (int32_t*)(w + 8 * n);
-    const size_t fixed = step_fixed_bytes(b->n_cells);
+    p.run_sig = (double*)(w + step_lists_bytes(b->n_cells));
+    const size_t fixed = step_fixed_bytes(b->n_cells, b->n_runs);
     p.big = w + fixed;
     p.bytes = fixed;
     if (b->big_cells_max > 0)
@@ -334,6 +349,12 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(xpd::k_step_prep, dim3(1), dim3(64), 0, s, plan.counts, b->d_stats);
+    a.run_sig = plan.run_sig;
+    if (flags & XP_PHOTO) {
+        const int nt = b->n_runs * XP_MAX_BINS * 3;
+        hipLaunchKernelGGL(xpd::k_run_prep, dim3((nt + 255) / 256), dim3(256), 0, s, b->d_runs, b->n_runs,
+                           ctx->d_tables, plan.run_sig);
+    }
     if (!all_big) {
         // first plan: the hinted size plus headroom for this step's new electrons
         int ce = ce_top;
@@ -353,8 +374,19 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
             const size_t lds = xpd::step_lds_bytes(a.lds_ce, a.lds_ci);
             int sched = p->schedule;
             if (sched == 0) sched = (a.lds_ce > 512 || a.lds_ci > 512) ? 2 : 1;
-            const unsigned grid = tier == 0 ? (unsigned)b->n_cells
-                                            : (unsigned)(b->n_cells < 2048 ? b->n_cells : 2048);
+            // tier 0: a few resident rounds of workgroups, each looping over its
+            // cells (run records are summed per workgroup); later tiers: the
+            // deferred cells, read from the list
+            unsigned grid = (unsigned)(b->n_cells < 2048 ? b->n_cells : 2048);
+            if (tier == 0) {
+                int per_cu = 0;
+                const void* fn = sched == 1 ? (const void*)xpd::k_step<64> : (const void*)xpd::k_step<256>;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, sched == 1 ? 64 : 256, lds) != hipSuccess ||
+                    per_cu < 1)
+                    per_cu = 1;
+                const long long g0 = 4ll * per_cu * ctx->n_cu;
+                grid = (unsigned)(b->n_cells < g0 ? b->n_cells : g0);
+            }
             if (sched == 1) {
                 if (lds > 65536) hipFuncSetAttribute((const void*)xpd::k_step<64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
                 hipLaunchKernelGGL(xpd::k_step<64>, dim3(grid), dim3(64), lds, s, a);

@@ -304,7 +304,8 @@ __global__ __launch_bounds__(BT) void k_big_s0fin(BigArgs a)
         }
         const int nbins = R.n_bins;
         if ((flags & XP_PHOTO) && nbins > 0) {
-            for (int q = tid; q < 3 * nbins; q += BT) r.sig[q / 3][q % 3] = photo_sigma(tb, q % 3, R.hv[q / 3]);
+            const double* rs = s.run_sig + (size_t)r.run * (XP_MAX_BINS * 3);
+            for (int q = tid; q < 3 * nbins; q += BT) r.sig[q / 3][q % 3] = rs[q];
             __syncthreads();
             const double* nhv = (R.field_per_cell && s.cell_nhv) ? s.cell_nhv + (size_t)r.cell * XP_MAX_BINS : R.nhv;
             for (int q = tid; q < 39; q += BT) {

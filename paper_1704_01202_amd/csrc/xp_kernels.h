@@ -31,6 +31,7 @@ struct StepArgs {
     double* cell_mom;
     uint32_t* status;
     const DevTables* tab;
+    const double* run_sig;      // [n_runs][XP_MAX_BINS][3] photo cross sections (k_run_prep)
     const uint32_t* d_step;
     uint32_t step;
     uint32_t flags;
@@ -52,6 +53,7 @@ constexpr int STEP_COUNTS = 16;
 constexpr int BIG_COUNT_SLOT = STEP_COUNTS - 1;
 
 __global__ void k_step_prep(int32_t* counts, int32_t* stats);
+__global__ void k_run_prep(const xp_run* runs, int n_runs, const DevTables* tb, double* run_sig);
 
 size_t step_lds_bytes(int ce, int ci);
 // Largest LDS plan: ions per cell (i_lds) and the electrons that fit beside

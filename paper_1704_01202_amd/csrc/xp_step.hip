@@ -106,32 +106,131 @@ size_t step_lds_bytes(int ce, int ci)
 }
 
 template <int B>
-__device__ void step_cell(const StepArgs& a, int cell, CellShared& S, const Lds& L);
+__device__ bool step_cell(const StepArgs& a, int cell, CellShared& S, const Lds& L);
 
-// One workgroup per cell, looping over the cells of the launch: all cells
-// (cell_list == nullptr) or the cells listed by an earlier launch whose LDS
-// plan they outgrew.
+// One workgroup per cell at a time, looping over the cells of the launch:
+// all cells (cell_list == nullptr) or the cells listed by an earlier launch
+// whose LDS plan they outgrew.  The run counters and tallies of the committed
+// cells are summed in LDS and added to the run's records when the run
+// changes and at the end, so a launch issues a few atomics per workgroup
+// rather than per cell.  Three waves per SIMD: the step is bound by the
+// latency of its FP64 chains, and the register budget of three waves holds it
+// with almost no spilling.
 template <int B>
-__global__ __launch_bounds__(B) void k_step(StepArgs a)
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(3))) void k_step(StepArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ CellShared S;
+    __shared__ unsigned long long acc_cnt[XP_NCOUNT];
+    __shared__ double acc_led[XP_NLEDGER];
+    __shared__ int acc_run, acc_max;
+    const int tid = threadIdx.x;
     const int ce = a.lds_ce, ci = a.lds_ci;
     const int ps = pow2_at_least(ce > ci ? ce : ci);
     const Lds L = carve(smem, ce, ci, ps);
+    for (int q = tid; q < XP_NCOUNT; q += B) acc_cnt[q] = 0;
+    for (int q = tid; q < XP_NLEDGER; q += B) acc_led[q] = 0.0;
+    if (tid == 0) {
+        acc_run = -1;
+        acc_max = 0;
+    }
+    __syncthreads();
+    auto flush = [&]() {
+        const int r = acc_run;
+        if (r >= 0) {
+            if (a.run_cnt)
+                for (int q = tid; q < XP_NCOUNT; q += B)
+                    if (acc_cnt[q]) atomicAdd((unsigned long long*)&a.run_cnt[(size_t)r * XP_NCOUNT + q], acc_cnt[q]);
+            if (a.run_led)
+                for (int q = tid; q < XP_NLEDGER; q += B)
+                    if (acc_led[q] != 0.0) atomicAdd(&a.run_led[(size_t)r * XP_NLEDGER + q], acc_led[q]);
+        }
+        for (int q = tid; q < XP_NCOUNT; q += B) acc_cnt[q] = 0;
+        for (int q = tid; q < XP_NLEDGER; q += B) acc_led[q] = 0.0;
+    };
     const int nitems = a.cell_list ? *a.cell_list_count : a.n_cells;
     for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
         const int cell = a.cell_list ? a.cell_list[item] : item;
-        step_cell<B>(a, cell, S, L);
+        const bool done = step_cell<B>(a, cell, S, L);
+        __syncthreads();
+        if (done) {
+            const int run = a.cell_run[cell];
+            if (run != acc_run) {
+                flush();
+                __syncthreads();
+                if (tid == 0) acc_run = run;
+            }
+            for (int q = tid; q < XP_NCOUNT; q += B) acc_cnt[q] += (unsigned long long)S.cnt[q];
+            for (int q = tid; q < XP_NLEDGER; q += B) acc_led[q] = acc_led[q] + S.led[q];
+            if (tid == 0 && S.ints[6] > acc_max) acc_max = S.ints[6];
+        }
         __syncthreads();
     }
+    flush();
+    if (tid == 0 && a.stats && acc_max > 0) atomicMax(&a.stats[0], acc_max);
 }
 
+// Random permutation of slots 0..n-1: out[k] = slot of rank k when the slots
+// are sorted by (Philox word, slot); the word of slot i is word i % 4 of the
+// call (c0, c1, i / 4, c3).  One wave sorts up to 128 keys in registers;
+// larger cells use an LDS bitonic sort in sbuf (>= pow2(n) entries).  Out of
+// line: the step calls it four times.
 template <int B>
-__device__ void step_cell(const StepArgs& a, int cell, CellShared& S, const Lds& L)
+__device__ __noinline__ void make_perm_fn(int n, uint32_t c0, uint32_t c1, uint32_t c3, uint32_t k0,
+                                          uint32_t k1, int32_t* out, uint64_t* sbuf)
 {
     const int tid = threadIdx.x;
-    if (cell < 0 || cell >= a.n_cells) return;
+    if (B == 64 && n <= 128) {
+        auto run_k = [&](auto kk) {
+            constexpr int K = decltype(kk)::value;
+            uint64_t key[K];
+#pragma unroll
+            for (int m = 0; m < K; ++m) {
+                const int i = tid + 64 * m;
+                key[m] = ~0ull;
+                if (i < n) {
+                    const Words w = philox(c0, c1, (uint32_t)(i >> 2), c3, k0, k1);
+                    const uint32_t q = i & 3;
+                    const uint32_t kw = q == 0 ? w.x0 : (q == 1 ? w.x1 : (q == 2 ? w.x2 : w.x3));
+                    key[m] = ((uint64_t)kw << 32) | (uint32_t)i;
+                }
+            }
+            wave_bitonic<K>(key);
+#pragma unroll
+            for (int m = 0; m < K; ++m) {
+                const int r = tid + 64 * m;
+                if (r < n) out[r] = (int32_t)(uint32_t)key[m];
+            }
+        };
+        if (n <= 64) run_k(std::integral_constant<int, 1>{});
+        else run_k(std::integral_constant<int, 2>{});
+        __syncthreads();
+        return;
+    }
+    const int p = pow2_at_least(n);
+    for (int g = tid; 4 * g < n; g += B) {
+        const Words w = philox(c0, c1, (uint32_t)g, c3, k0, k1);
+        const uint32_t k4[4] = {w.x0, w.x1, w.x2, w.x3};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = 4 * g + q;
+            if (i < n) sbuf[i] = ((uint64_t)k4[q] << 32) | (uint32_t)i;
+        }
+    }
+    for (int i = n + tid; i < p; i += B) sbuf[i] = ~0ull;
+    __syncthreads();
+    bitonic_sort<B>(sbuf, p);
+    for (int k = tid; k < n; k += B) out[k] = (int32_t)(uint32_t)sbuf[k];
+    __syncthreads();
+}
+
+// Steps one cell; true when its new state was committed (the caller then adds
+// S.cnt / S.led to the run records and S.ints[6] holds its electron count).
+template <int B>
+__device__ bool step_cell(const StepArgs& a, int cell, CellShared& S, const Lds& L)
+{
+    const int tid = threadIdx.x;
+    if (cell < 0 || cell >= a.n_cells) return false;
     const int run = a.cell_run[cell];
     const xp_run* R = a.runs + run;
     const DevTables* tb = a.tab;
@@ -176,7 +275,7 @@ __device__ void step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
     };
     if (ni > ci) {
         to_big();
-        return;
+        return false;
     }
     if (ne > ce || ne > ecap) {
         if (ne > ecap) {
@@ -184,7 +283,7 @@ __device__ void step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
         } else {
             defer();
         }
-        return;
+        return false;
     }
 
     auto rng = [&](uint32_t idx, uint32_t purpose, uint32_t sub) {
@@ -218,14 +317,14 @@ __device__ void step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
         const double x = L.evx[j], y = L.evy[j], z = L.evz[j];
         return HALF_ME_OVER_QE * ((x * x + y * y) + z * z);
     };
-    auto moments_bulk = [&](int n, long long& we, long long& wb, double& ke) {
+    auto moments_bulk = [&](int n, long long* we, long long& wb, double& ke) {
         long long w_loc = 0, b_loc = 0;
         for (int j = tid; j < n; j += B) {
             const long long w = L.ew[j];
             w_loc += w;
             if (kin(j) < ebulk) b_loc += w;
         }
-        we = block_isum<B>(w_loc, S.ired);
+        if (we) *we = block_isum<B>(w_loc, S.ired);
         wb = block_isum<B>(b_loc, S.ired);
         ke = block_tree_sum<B>(n, [&](int j) {
             const double e = kin(j);
@@ -245,8 +344,9 @@ __device__ void step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
 
     long long we, wb, sz, sz2;
     double ke;
-    moments_bulk(ne, we, wb, ke);
+    moments_bulk(ne, &we, wb, ke);
     ion_sums(sz, sz2);
+    long long s3_accepted = 0;   // charge added by S3 (one per accepted ionization)
     const long long wi = ni;
     double tmp = 0.01;
     if (wb > 0) {
@@ -271,113 +371,96 @@ __device__ void step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
     const double lnl = S.mom[10];
 
     // ------------- random permutations: sort (Philox key, slot) ---------------
-    // out[k] = slot of rank k when slots are sorted by (Philox word, slot)
-    auto make_perm = [&](uint32_t purpose, int n, auto out) {
-        if (B == 64 && n <= 128) {
-            auto run_k = [&](auto kk) {
-                constexpr int K = decltype(kk)::value;
-                uint64_t key[K];
-#pragma unroll
-                for (int m = 0; m < K; ++m) {
-                    const int i = tid + 64 * m;
-                    key[m] = ~0ull;
-                    if (i < n) {
-                        const Words w = rng((uint32_t)(i >> 2), purpose, 0);
-                        const uint32_t q = i & 3;
-                        const uint32_t kw = q == 0 ? w.x0 : (q == 1 ? w.x1 : (q == 2 ? w.x2 : w.x3));
-                        key[m] = ((uint64_t)kw << 32) | (uint32_t)i;
-                    }
-                }
-                wave_bitonic<K>(key);
-#pragma unroll
-                for (int m = 0; m < K; ++m) {
-                    const int r = tid + 64 * m;
-                    if (r < n) out[r] = (int32_t)(uint32_t)key[m];
-                }
-            };
-            if (n <= 64) run_k(std::integral_constant<int, 1>{});
-            else run_k(std::integral_constant<int, 2>{});
-            __syncthreads();
-            return;
-        }
-        const int p = pow2_at_least(n);
-        for (int g = tid; 4 * g < n; g += B) {
-            const Words w = rng((uint32_t)g, purpose, 0);
-            const uint32_t k4[4] = {w.x0, w.x1, w.x2, w.x3};
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int i = 4 * g + q;
-                if (i < n) L.sbuf[i] = ((uint64_t)k4[q] << 32) | (uint32_t)i;
-            }
-        }
-        for (int i = n + tid; i < p; i += B) L.sbuf[i] = ~0ull;
-        __syncthreads();
-        bitonic_sort<B>(L.sbuf, p);
-        for (int k = tid; k < n; k += B) out[k] = (int32_t)(uint32_t)L.sbuf[k];
-        __syncthreads();
+    auto make_perm = [&](uint32_t purpose, int n, int32_t* out) {
+        make_perm_fn<B>(n, step, lcell, purpose << 24, key0, key1, out, L.sbuf);
     };
 
     const double fe_ei = mi / (ME + mi);   // electron side of an e-i pair
     const double fi_ei = ME / (ME + mi);   // ion side
     const double f_ee = ME / (ME + ME);
-    auto collide = [&](int e, bool ion_b, int b, double coef, double nunit, uint32_t idx,
-                       uint32_t purpose) {
-        const uint32_t c3 = (purpose << 24);
-        if (ion_b)
-            collide_slots(L.evx, L.evy, L.evz, L.ew, L.ivx, L.ivy, L.ivz, e, b, 1u, fe_ei, fi_ei,
-                          coef, nunit, step, lcell, idx, c3, key0, key1, S.cnt);
-        else
-            collide_slots(L.evx, L.evy, L.evz, L.ew, L.evx, L.evy, L.evz, e, b, L.ew[b], f_ee, f_ee,
-                          coef, nunit, step, lcell, idx, c3, key0, key1, S.cnt);
-    };
-
     const double qe4 = (QE * QE) * (QE * QE);
 
-    // ---------------- S1: electron-electron collisions ----------------
+    // ---------------- S1, S2: binary collisions ----------------
+    // Every collision of the step goes through one call site (the scattering
+    // is the largest code of the step).  Phase 0 is e-e: with an odd count
+    // >= 3, item 0 is the triplet (three collisions in sequence at dt/2), the
+    // other items are adjacent pairs of the permutation.  Phase 1 is e-i:
+    // round robin over the smaller population, round by round.
+    const bool do_ee = (flags & XP_EE) && ne >= 2;
+    const bool do_ei = (flags & XP_EI) && ne >= 1 && ni >= 1;
     if ((flags & (XP_EE | XP_EI)) && ne >= 1 && (ne >= 2 || ni >= 1)) make_perm(RP_PERM_E, ne, L.perm_e);
-    if ((flags & XP_EE) && ne >= 2) {
-        const double mee = (ME * ME) / (ME + ME);
-        const double kee = qe4 / (((8.0 * PI) * (EPS0 * EPS0)) * (mee * mee));
-        const double afull = (kee * lnl) * dt;
-        const double ahalf = (kee * lnl) * (0.5 * dt);
-        const double nunit = (w0 * (double)ne) / vol;
-        const int start = (ne % 2 == 1 && ne >= 3) ? 3 : 0;
-        const int npairs = (ne - start) / 2;
-        if (tid == 0 && start == 3) {
-            const int32_t* p = L.perm_e;
-            collide(p[0], false, p[1], ahalf, nunit, 0, RP_EE_TRI);
-            collide(p[1], false, p[2], ahalf, nunit, 1, RP_EE_TRI);
-            collide(p[2], false, p[0], ahalf, nunit, 2, RP_EE_TRI);
-            S.cnt[XP_C_TRIPLET] += 3;
-        }
-        for (int j = tid; j < npairs; j += B)
-            collide(L.perm_e[start + 2 * j], false, L.perm_e[start + 2 * j + 1], afull, nunit,
-                    (uint32_t)j, RP_EE);
-        if (tid == 0) S.cnt[XP_C_EE] += npairs;
-        __syncthreads();
-    }
-
-    // ---------------- S2: electron-ion collisions ----------------
-    if ((flags & XP_EI) && ne >= 1 && ni >= 1) {
-        make_perm(RP_PERM_I, ni, L.perm_i);
-        const double mei = (ME * mi) / (ME + mi);
-        const double kei = qe4 / (((8.0 * PI) * (EPS0 * EPS0)) * (mei * mei));
-        const double a1 = (kei * lnl) * dt;
-        const int nmin = ne < ni ? ne : ni, nmax = ne < ni ? ni : ne;
-        const double nunit = (w0 * (double)nmin) / vol;
-        for (int r0 = 0; r0 < nmax; r0 += nmin) {
-            const int r1 = r0 + nmin < nmax ? r0 + nmin : nmax;
+    const double mee = (ME * ME) / (ME + ME);
+    const double kee = qe4 / (((8.0 * PI) * (EPS0 * EPS0)) * (mee * mee));
+    const double afull = (kee * lnl) * dt;
+    const double ahalf = (kee * lnl) * (0.5 * dt);
+    const int start = (ne % 2 == 1 && ne >= 3) ? 3 : 0;
+    const int tri = start == 3 ? 1 : 0;
+    const int npairs = (ne - start) / 2;
+    const double mei = (ME * mi) / (ME + mi);
+    const double kei = qe4 / (((8.0 * PI) * (EPS0 * EPS0)) * (mei * mei));
+    const double a1 = (kei * lnl) * dt;
+    const int nmin = ne < ni ? ne : ni, nmax = ne < ni ? ni : ne;
+#pragma unroll 1
+    for (int phase = 0; phase < 2; ++phase) {
+        const bool ion = phase == 1;
+        if (ion ? !do_ei : !do_ee) continue;
+        if (ion) make_perm(RP_PERM_I, ni, L.perm_i);
+        double* bvx = ion ? L.ivx : L.evx;
+        double* bvy = ion ? L.ivy : L.evy;
+        double* bvz = ion ? L.ivz : L.evz;
+        const double fa = ion ? fe_ei : f_ee, fb = ion ? fi_ei : f_ee;
+        const double nunit = (w0 * (double)(ion ? nmin : ne)) / vol;
+        const int items = ion ? nmax : npairs + tri;
+        const int per_round = ion ? nmin : items;
+#pragma unroll 1
+        for (int r0 = 0; r0 < items; r0 += per_round) {
+            const int r1 = r0 + per_round < items ? r0 + per_round : items;
             for (int k = r0 + tid; k < r1; k += B) {
-                int e, i;
-                if (ne >= ni) { e = L.perm_e[k]; i = L.perm_i[k % ni]; }
-                else          { i = L.perm_i[k]; e = L.perm_e[k % ne]; }
-                const int z = L.iz[i];
-                if (z == 0) continue;
-                collide(e, true, i, a1 * (double)(z * z), nunit, (uint32_t)k, RP_EI);
+                const int nsub = (!ion && tri && k == 0) ? 3 : 1;
+#pragma unroll 1
+                for (int sub = 0; sub < nsub; ++sub) {
+                    int e, bb;
+                    uint32_t wb, idx, purpose;
+                    double coef;
+                    if (ion) {
+                        if (ne >= ni) { e = L.perm_e[k]; bb = L.perm_i[k % ni]; }
+                        else          { bb = L.perm_i[k]; e = L.perm_e[k % ne]; }
+                        const int z = L.iz[bb];
+                        if (z == 0) continue;
+                        coef = a1 * (double)(z * z);
+                        wb = 1u;
+                        idx = (uint32_t)k;
+                        purpose = RP_EI;
+                    } else if (nsub == 3) {
+                        e = L.perm_e[sub];
+                        bb = L.perm_e[sub == 2 ? 0 : sub + 1];
+                        coef = ahalf;
+                        wb = L.ew[bb];
+                        idx = (uint32_t)sub;
+                        purpose = RP_EE_TRI;
+                    } else {
+                        const int j = k - tri;
+                        e = L.perm_e[start + 2 * j];
+                        bb = L.perm_e[start + 2 * j + 1];
+                        coef = afull;
+                        wb = L.ew[bb];
+                        idx = (uint32_t)j;
+                        purpose = RP_EE;
+                    }
+                    collide_slots(L.evx, L.evy, L.evz, L.ew, bvx, bvy, bvz, e, bb, wb, fa, fb, coef, nunit,
+                                  step, lcell, idx, purpose << 24, key0, key1, S.cnt);
+                }
             }
             __syncthreads();
         }
-        if (tid == 0) S.cnt[XP_C_EI] += nmax;
+        if (tid == 0) {
+            if (ion) {
+                S.cnt[XP_C_EI] += nmax;
+            } else {
+                S.cnt[XP_C_EE] += npairs;
+                S.cnt[XP_C_TRIPLET] += 3 * tri;
+            }
+        }
     }
 
     bool overflow = false, deferred = false;
@@ -468,6 +551,7 @@ __device__ void step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
                 if (S.ints[0] == 2) deferred = true;
                 const double debit = S.dbl[0];
                 const int acc = S.ints[1];
+                s3_accepted = acc;
                 if (debit > 0.0) {
                     const double alpha = sqrt(1.0 - debit / kth);
                     for (int j = tid; j < ne0; j += B) {
@@ -484,10 +568,11 @@ __device__ void step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
 
     // ---------------- S4: three-body recombination ----------------
     if (!overflow && !deferred && (flags & XP_REC) && ne >= 1 && ni >= 1) {
-        long long szr, sz2r, wer, wbr;
+        // charge states changed only by S3 since the moments
+        const long long szr = sz + s3_accepted;
+        long long wbr;
         double ker;
-        ion_sums(szr, sz2r);
-        moments_bulk(ne, wer, wbr, ker);
+        moments_bulk(ne, nullptr, wbr, ker);
         double tp = 0.01;
         if (wbr > 0) {
             tp = (2.0 * ker) / (3.0 * (double)wbr);
@@ -620,7 +705,8 @@ __device__ void step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
         const double* nhv = (R->field_per_cell && a.cell_nhv) ? a.cell_nhv + (size_t)cell * XP_MAX_BINS : R->nhv;
         const double dtr = R->dt_rad;
         if (photo) {
-            for (int q = tid; q < 3 * nb; q += B) S.sig[q / 3][q % 3] = photo_sigma(tb, q % 3, R->hv[q / 3]);
+            const double* rs = a.run_sig + (size_t)run * (XP_MAX_BINS * 3);
+            for (int q = tid; q < 3 * nb; q += B) S.sig[q / 3][q % 3] = rs[q];
             __syncthreads();
             for (int q = tid; q < 39; q += B) {
                 const int z = q / 3, s = q % 3;
@@ -801,11 +887,11 @@ __device__ void step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
     // ---------------- commit ----------------
     if (overflow) {
         if (tid == 0) atomicOr(a.status, XP_ST_CAPACITY);
-        return;
+        return false;
     }
     if (deferred) {
         defer();
-        return;
+        return false;
     }
     bool bad = false;
     for (int j = tid; j < ne; j += B) {
@@ -846,7 +932,7 @@ __device__ void step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
     }
     if (tid == 0) {
         a.e_cnt[cell] = ne;
-        if (a.stats) atomicMax(&a.stats[0], ne);
+        S.ints[6] = ne;
     }
     if (a.cell_cnt)
         for (int q = tid; q < XP_NCOUNT; q += B) a.cell_cnt[(size_t)cell * XP_NCOUNT + q] = S.cnt[q];
@@ -854,12 +940,7 @@ __device__ void step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
         for (int q = tid; q < XP_NLEDGER; q += B) a.cell_led[(size_t)cell * XP_NLEDGER + q] = S.led[q];
     if (a.cell_mom)
         for (int q = tid; q < XP_NMOM; q += B) a.cell_mom[(size_t)cell * XP_NMOM + q] = S.mom[q];
-    if (a.run_cnt)
-        for (int q = tid; q < XP_NCOUNT; q += B)
-            if (S.cnt[q]) atomicAdd((unsigned long long*)&a.run_cnt[(size_t)run * XP_NCOUNT + q], (unsigned long long)S.cnt[q]);
-    if (a.run_led)
-        for (int q = tid; q < XP_NLEDGER; q += B)
-            if (S.led[q] != 0.0) atomicAdd(&a.run_led[(size_t)run * XP_NLEDGER + q], S.led[q]);
+    return true;
 }
 
 template __global__ void k_step<64>(StepArgs);
@@ -869,6 +950,18 @@ __global__ void k_step_prep(int32_t* counts, int32_t* stats)
 {
     if (threadIdx.x < STEP_COUNTS && counts) counts[threadIdx.x] = 0;
     if (threadIdx.x < 4 && stats) stats[threadIdx.x] = 0;
+}
+
+// Per-run photoionization cross sections of every bin and subshell (they
+// depend on the run's photon energies only): [run][bin][subshell].
+__global__ void k_run_prep(const xp_run* runs, int n_runs, const DevTables* tb, double* run_sig)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = t / (XP_MAX_BINS * 3), q = t % (XP_MAX_BINS * 3);
+    if (r >= n_runs) return;
+    const xp_run& R = runs[r];
+    const int b = q / 3, sh = q % 3;
+    run_sig[t] = b < R.n_bins ? photo_sigma(tb, sh, R.hv[b]) : 0.0;
 }
 
 size_t lds_budget(size_t max_lds)
