@@ -335,6 +335,15 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
         g.iaux = (uint32_t*)(w + bp.iaux);
         g.wp = (uint32_t*)(w + bp.wp);
         g.sel = (int32_t*)(w + bp.sel);
+        g.fip = (double*)(w + bp.fip);
+        const size_t ev_stride = ((8 * (size_t)(b->big_e_slots > 0 ? b->big_e_slots : 1) + 255) & ~size_t(255));
+        const size_t iv_stride = ((8 * (size_t)(b->big_i_slots > 0 ? b->big_i_slots : 1) + 255) & ~size_t(255));
+        for (int q = 0; q < 3; ++q) {
+            g.gev[q] = (double*)(w + bp.gev + q * ev_stride);
+            g.giv[q] = (double*)(w + bp.giv + q * iv_stride);
+        }
+        g.gew = (uint32_t*)(w + bp.gew);
+        g.giz = (uint8_t*)(w + bp.giz);
         g.big_max = b->big_cells_max;
         g.grid = p->big_grid;
         g.e_chunks_max = bp.e_chunks;

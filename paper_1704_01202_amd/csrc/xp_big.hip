@@ -380,14 +380,15 @@ __global__ __launch_bounds__(64) void k_big_rhist(BigArgs a, int species, int ne
         __syncthreads();
         for (int q = threadIdx.x; q < n; q += 64) atomicAdd(&h[(key[pop + base + q] >> shift) & 255u], 1u);
         __syncthreads();
-        uint32_t* hc = a.hist + (size_t)256 * c0;
-        for (int q = threadIdx.x; q < 256; q += 64) hc[(size_t)q * nc + k] = h[q];
+        uint32_t* hc = a.hist + (size_t)256 * g;
+        for (int q = threadIdx.x; q < 256; q += 64) hc[q] = h[q];
         __syncthreads();
     }
 }
 
-// Exclusive scan of a cell's digit counts (digit-major, chunk-minor): thread
-// d owns digit d's run of nc entries.
+// Exclusive scan of a cell's digit counts in (digit, chunk) order over the
+// chunk-major table hist[chunk][digit]: thread d runs down digit d's column
+// (coalesced across threads), then adds the offset of digit d.
 __global__ __launch_bounds__(256) void k_big_rscan(BigArgs a, int species, int needbit)
 {
     __shared__ uint32_t red[4];
@@ -399,16 +400,17 @@ __global__ __launch_bounds__(256) void k_big_rscan(BigArgs a, int species, int n
         const int c0 = species == 0 ? r.ce0 : r.ci0;
         const int nc = species == 0 ? r.nce : r.nci;
         if (nc == 0) continue;
-        uint32_t* h = a.hist + (size_t)256 * c0 + (size_t)tid * nc;
-        uint32_t sum = 0;
-        for (int k = 0; k < nc; ++k) sum += h[k];
-        uint32_t tot;
-        uint32_t run = block_exclusive_sum<256, uint32_t>(sum, red, tot);
+        uint32_t* h = a.hist + (size_t)256 * c0 + tid;
+        uint32_t run = 0;
         for (int k = 0; k < nc; ++k) {
-            const uint32_t v = h[k];
-            h[k] = run;
+            const uint32_t v = h[(size_t)256 * k];
+            h[(size_t)256 * k] = run;
             run += v;
         }
+        uint32_t tot;
+        const uint32_t base = block_exclusive_sum<256, uint32_t>(run, red, tot);
+        if (base)
+            for (int k = 0; k < nc; ++k) h[(size_t)256 * k] += base;
         __syncthreads();
     }
 }
@@ -433,8 +435,8 @@ __global__ __launch_bounds__(64) void k_big_rscatter(BigArgs a, int species, int
         const int k = g - c0;
         const int base = k * BIG_CH;
         const int n = cnt - base < BIG_CH ? cnt - base : BIG_CH;
-        const uint32_t* hc = a.hist + (size_t)256 * c0;
-        for (int q = lane; q < 256; q += 64) run[q] = hc[(size_t)q * nc + k];
+        const uint32_t* hc = a.hist + (size_t)256 * g;
+        for (int q = lane; q < 256; q += 64) run[q] = hc[q];
         __syncthreads();
         for (int c = 0; c < n; c += 64) {
             const int i = c + lane;
@@ -457,6 +459,58 @@ __global__ __launch_bounds__(64) void k_big_rscatter(BigArgs a, int species, int
                 if ((peers & lt) == 0) run[d] = at + (uint32_t)__popcll(peers);
             }
             __syncthreads();
+        }
+    }
+}
+
+// Velocities (and electron weights / ion charge states) copied into
+// permutation-rank order before the collisions (scatter = 0) and back to their
+// slots afterwards (scatter = 1), so that the collision kernels read and write
+// contiguous ranks.  species 0 electrons (PERM_E), 1 ions (PERM_I).
+__global__ __launch_bounds__(BT) void k_big_gather(BigArgs a, int species, int scatter)
+{
+    const StepArgs& s = a.s;
+    const int nch = species == 0 ? a.hdr->n_e_chunks : a.hdr->n_i_chunks;
+    const int32_t* map = species == 0 ? a.e_chunk_cell : a.i_chunk_cell;
+    const int needbit = species == 0 ? BN_PERM_E : BN_EI;
+    for (int g = blockIdx.x; g < nch; g += gridDim.x) {
+        const BigRec& r = a.rec[map[g]];
+        if (!big_live(r, needbit)) continue;
+        const int c0 = species == 0 ? r.ce0 : r.ci0;
+        const int cnt = species == 0 ? r.epn : r.ni;
+        const int64_t pop = species == 0 ? r.ep0 : r.ip0;
+        const int base = (g - c0) * BIG_CH;
+        const int n = cnt - base < BIG_CH ? cnt - base : BIG_CH;
+        if (species == 0) {
+            const uint32_t* perm = a.val_a + pop;
+            for (int q = threadIdx.x; q < n; q += BT) {
+                const int64_t gi = pop + base + q, sl = r.eo + perm[base + q];
+                if (!scatter) {
+                    a.gev[0][gi] = s.evx[sl];
+                    a.gev[1][gi] = s.evy[sl];
+                    a.gev[2][gi] = s.evz[sl];
+                    a.gew[gi] = s.ew[sl];
+                } else {
+                    s.evx[sl] = a.gev[0][gi];
+                    s.evy[sl] = a.gev[1][gi];
+                    s.evz[sl] = a.gev[2][gi];
+                }
+            }
+        } else {
+            const uint32_t* perm = a.val_c + pop;
+            for (int q = threadIdx.x; q < n; q += BT) {
+                const int64_t gi = pop + base + q, sl = r.io + perm[base + q];
+                if (!scatter) {
+                    a.giv[0][gi] = s.ivx[sl];
+                    a.giv[1][gi] = s.ivy[sl];
+                    a.giv[2][gi] = s.ivz[sl];
+                    a.giz[gi] = s.iz[sl];
+                } else {
+                    s.ivx[sl] = a.giv[0][gi];
+                    s.ivy[sl] = a.giv[1][gi];
+                    s.ivz[sl] = a.giv[2][gi];
+                }
+            }
         }
     }
 }
@@ -493,17 +547,17 @@ __global__ __launch_bounds__(BT) void k_big_ee(BigArgs a)
         const int jlo = base <= start ? 0 : (base - start + 1) / 2;
         int jhi = (base + BIG_CH - start + 1) / 2;
         if (jhi > npairs) jhi = npairs;
-        const uint32_t* perm = a.val_a + r.ep0;
-        double* vx = s.evx + r.eo;
-        double* vy = s.evy + r.eo;
-        double* vz = s.evz + r.eo;
-        const uint32_t* w = s.ew + r.eo;
+        // electrons in permutation-rank order
+        double* vx = a.gev[0] + r.ep0;
+        double* vy = a.gev[1] + r.ep0;
+        double* vz = a.gev[2] + r.ep0;
+        const uint32_t* w = a.gew + r.ep0;
         const xp_run& RR = R;
         const uint32_t st = step_of(s, r.run);
         const uint32_t lcell = (uint32_t)(r.cell - RR.cell_begin);
         const uint32_t k0 = (uint32_t)RR.seed, k1 = (uint32_t)(RR.seed >> 32);
         if (k == 0 && start == 3 && tid == 0) {
-            const int p0 = perm[0], p1 = perm[1], p2 = perm[2];
+            const int p0 = 0, p1 = 1, p2 = 2;
             collide_slots(vx, vy, vz, w, vx, vy, vz, p0, p1, w[p1], f_ee, f_ee, ahalf, nunit, st, lcell, 0u,
                           RP_EE_TRI << 24, k0, k1, cnt);
             collide_slots(vx, vy, vz, w, vx, vy, vz, p1, p2, w[p2], f_ee, f_ee, ahalf, nunit, st, lcell, 1u,
@@ -513,7 +567,7 @@ __global__ __launch_bounds__(BT) void k_big_ee(BigArgs a)
             cnt[XP_C_TRIPLET] += 3;
         }
         for (int j = jlo + tid; j < jhi; j += BT) {
-            const int e = perm[start + 2 * j], f = perm[start + 2 * j + 1];
+            const int e = start + 2 * j, f = start + 2 * j + 1;
             collide_slots(vx, vy, vz, w, vx, vy, vz, e, f, w[f], f_ee, f_ee, afull, nunit, st, lcell,
                           (uint32_t)j, RP_EE << 24, k0, k1, cnt);
         }
@@ -556,24 +610,23 @@ __global__ __launch_bounds__(BT) void k_big_ei(BigArgs a)
             const int k = g - c0;
             const int base = k * BIG_CH;
             const int n = nmin - base < BIG_CH ? nmin - base : BIG_CH;
-            const uint32_t* pe = a.val_a + r.ep0;
-            const uint32_t* pi = a.val_c + r.ip0;
-            double* vx = s.evx + r.eo;
-            double* vy = s.evy + r.eo;
-            double* vz = s.evz + r.eo;
-            const uint32_t* w = s.ew + r.eo;
-            double* ix = s.ivx + r.io;
-            double* iy = s.ivy + r.io;
-            double* iz = s.ivz + r.io;
-            const uint8_t* zz = s.iz + r.io;
+            // both species in permutation-rank order
+            double* vx = a.gev[0] + r.ep0;
+            double* vy = a.gev[1] + r.ep0;
+            double* vz = a.gev[2] + r.ep0;
+            const uint32_t* w = a.gew + r.ep0;
+            double* ix = a.giv[0] + r.ip0;
+            double* iy = a.giv[1] + r.ip0;
+            double* iz = a.giv[2] + r.ip0;
+            const uint8_t* zz = a.giz + r.ip0;
             const uint32_t st = step_of(s, r.run);
             const uint32_t lcell = (uint32_t)(r.cell - R.cell_begin);
             const uint32_t k0 = (uint32_t)R.seed, k1 = (uint32_t)(R.seed >> 32);
             for (int q = base + tid; q < base + n; q += BT) {
                 for (int kk = q; kk < nmax; kk += nmin) {
                     int e, i;
-                    if (ne >= ni) { e = (int)pe[kk]; i = (int)pi[q]; }
-                    else          { i = (int)pi[kk]; e = (int)pe[q]; }
+                    if (ne >= ni) { e = kk; i = q; }
+                    else          { i = kk; e = q; }
                     const int z = zz[i];
                     if (z == 0) continue;
                     collide_slots(vx, vy, vz, w, ix, iy, iz, e, i, 1u, fe_ei, fi_ei, a1 * (double)(z * z),
@@ -783,54 +836,75 @@ __global__ __launch_bounds__(BT) void k_big_kth(BigArgs a, int mode)
     }
 }
 
-// One wave per cell: K_th, then fired ions accepted in slot order while the
-// running debit (a left-to-right sum) stays within K_th.
+// Lowered potential of every fired ion, compacted in ion-slot order:
+// fip[ip0 + rank] (ranks from the per-cell scan of the chunk counts).
+__global__ __launch_bounds__(BT) void k_big_firelist(BigArgs a)
+{
+    __shared__ int red[BT / 64];
+    const StepArgs& s = a.s;
+    const DevTables* tb = s.tab;
+    const int nci = a.hdr->n_i_chunks;
+    for (int g = blockIdx.x; g < nci; g += gridDim.x) {
+        const BigRec& r = a.rec[a.i_chunk_cell[g]];
+        if (!big_live(r, BN_FIRED)) continue;
+        const int cb = a.ccnt[g];
+        const int base = (g - r.ci0) * BIG_CH;
+        const int n = r.ni - base < BIG_CH ? r.ni - base : BIG_CH;
+        const double* dE = r.mom + 16;
+        block_ordered_select<BT>(
+            n, [&](int q) { return a.iflag[r.ip0 + base + q] != 0; },
+            [&](int q, int pos) {
+                const int64_t pi = r.io + base + q;
+                const int z = s.iz[pi], kv = s.ik[pi];
+                a.fip[r.ip0 + cb + pos] = lowered(tb, z, valence(z, kv), dE);
+            },
+            red);
+    }
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// One wave per cell: K_th, then the fired ions accepted in slot order while
+// the running debit (a left-to-right sum) stays within K_th.  The wave loads
+// 64 potentials at a time and walks them with lane reads.
 __global__ __launch_bounds__(64) void k_big_accept(BigArgs a)
 {
     __shared__ double red[2 * (BIG_MAX_CHUNKS / 64)];
     const int lane = threadIdx.x;
     const StepArgs& s = a.s;
-    const DevTables* tb = s.tab;
     const int nb = a.hdr->count;
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
         BigRec& r = a.rec[b];
         if (!big_live(r, BN_FIRED)) continue;
         const double kth = block_tree_sum<64>(r.nce, [&](int j) { return a.part[0][r.ce0 + j]; }, red);
-        const double* dE = r.mom + 16;
-        const int ne0 = r.ne0, ni = r.ni;
+        const int ne0 = r.ne0;
         const int nfired = (int)r.nfired;
-        double debit = 0.0, paid = 0.0;
+        const int room = r.ecap - ne0;
+        double debit = 0.0;
         int acc = 0;
         bool stop = false, over = false;
-        for (int k = 0; k < r.nci && !stop; ++k) {
-            const int c_here = (k + 1 < r.nci ? a.ccnt[r.ci0 + k + 1] : nfired) - a.ccnt[r.ci0 + k];
-            if (c_here == 0) continue;
-            for (int c = 0; c < BIG_CH && !stop; c += 64) {
-                const int i = k * BIG_CH + c + lane;
-                const bool f = i < ni && a.iflag[r.ip0 + i] != 0;
-                double ip = 0.0;
-                if (f) {
-                    const int z = s.iz[r.io + i], kv = s.ik[r.io + i];
-                    ip = lowered(tb, z, valence(z, kv), dE);
+        for (int t0 = 0; t0 < nfired && !stop; t0 += 64) {
+            const int m = nfired - t0 < 64 ? nfired - t0 : 64;
+            const double ip = lane < m ? a.fip[r.ip0 + t0 + lane] : 0.0;
+            for (int l = 0; l < m; ++l) {
+                const double ipv = readlane_f64(ip, l);
+                if (!(debit + ipv <= kth)) {
+                    stop = true;
+                    break;
                 }
-                uint64_t bal = __ballot(f);
-                while (bal) {
-                    const int bit = __ffsll((unsigned long long)bal) - 1;
-                    bal &= bal - 1;
-                    const double ipv = __shfl(ip, bit, 64);
-                    if (!(debit + ipv <= kth)) {
-                        stop = true;
-                        break;
-                    }
-                    if (ne0 + acc >= r.ecap) {
-                        over = true;
-                        stop = true;
-                        break;
-                    }
-                    debit = debit + ipv;
-                    paid = paid + ipv;
-                    ++acc;
+                if (acc >= room) {
+                    over = true;
+                    stop = true;
+                    break;
                 }
+                debit = debit + ipv;
+                ++acc;
             }
         }
         if (lane == 0) {
@@ -846,7 +920,7 @@ __global__ __launch_bounds__(64) void k_big_accept(BigArgs a)
                 r.cnt[XP_C_ION_ACCEPTED] += acc;
                 r.cnt[XP_C_ION_STARVED] += nfired - acc;
                 r.cnt[XP_C_E_NEW] += acc;
-                r.led[XP_L_ION_DEBIT] += paid;
+                r.led[XP_L_ION_DEBIT] += debit;
                 r.alpha = debit > 0.0 ? sqrt(1.0 - debit / kth) : 1.0;
                 r.ne = ne0 + acc;
             }
@@ -1449,6 +1523,11 @@ BigPlan big_plan(int32_t big_max, int64_t e_pop, int64_t i_pop)
     p.iaux = o; o += up(4 * (size_t)ip);
     p.wp = o; o += up(4 * (size_t)ep);
     p.sel = o; o += up(4 * (size_t)ip);
+    p.fip = o; o += up(8 * (size_t)ip);
+    p.gev = o; o += 3 * up(8 * (size_t)ep);
+    p.gew = o; o += up(4 * (size_t)ep);
+    p.giv = o; o += 3 * up(8 * (size_t)ip);
+    p.giz = o; o += up((size_t)ip);
     p.bytes = o;
     return p;
 }
@@ -1493,18 +1572,23 @@ hipError_t big_launch(BigArgs& a, bool all_cells, hipStream_t s)
     if (flags & (XP_EE | XP_EI)) {
         if ((e = big_sort(a, 0, BN_PERM_E, RP_PERM_E, a.key_a, a.val_a, a.key_b, a.val_b, gch, gcell, s)) != hipSuccess)
             return e;
+        hipLaunchKernelGGL(k_big_gather, dim3(gch), dim3(BT), 0, s, a, 0, 0);
         if (flags & XP_EE) hipLaunchKernelGGL(k_big_ee, dim3(gch), dim3(BT), 0, s, a);
         if (flags & XP_EI) {
             if ((e = big_sort(a, 1, BN_EI, RP_PERM_I, a.key_c, a.val_c, a.key_b, a.val_b, gch, gcell, s)) != hipSuccess)
                 return e;
+            hipLaunchKernelGGL(k_big_gather, dim3(gch), dim3(BT), 0, s, a, 1, 0);
             hipLaunchKernelGGL(k_big_ei, dim3(gch), dim3(BT), 0, s, a);
+            hipLaunchKernelGGL(k_big_gather, dim3(gch), dim3(BT), 0, s, a, 1, 1);
         }
+        hipLaunchKernelGGL(k_big_gather, dim3(gch), dim3(BT), 0, s, a, 0, 1);
     }
     if (flags & XP_ION) {
         hipLaunchKernelGGL(k_big_lotz, dim3(gch), dim3(BT), 0, s, a);
         hipLaunchKernelGGL(k_big_s3p, dim3(gcell), dim3(BT), 0, s, a);
         hipLaunchKernelGGL(k_big_fire, dim3(gch), dim3(BT), 0, s, a);
         hipLaunchKernelGGL(k_big_cscan, dim3(gcell), dim3(BT), 0, s, a, 0);
+        hipLaunchKernelGGL(k_big_firelist, dim3(gch), dim3(BT), 0, s, a);
         hipLaunchKernelGGL(k_big_drift, dim3(gch), dim3(BT), 0, s, a, 0);
         hipLaunchKernelGGL(k_big_dfin, dim3(gcell), dim3(BT), 0, s, a, 0);
         hipLaunchKernelGGL(k_big_kth, dim3(gch), dim3(BT), 0, s, a, 0);

@@ -175,6 +175,11 @@ struct BigArgs {
     uint32_t* iaux;             // per ion S5 decisions
     uint32_t* wp;               // per electron reduced weights (S4)
     int32_t* sel;               // per ion selected for recombination (S4)
+    double* fip;                // per fired ion (rank order) lowered potential (S3)
+    double* gev[3];             // electron velocities in permutation-rank order (S1, S2)
+    uint32_t* gew;              // electron weights in rank order
+    double* giv[3];             // ion velocities in rank order (S2)
+    uint8_t* giz;               // ion charge states in rank order
     int32_t big_max;
     int32_t grid;               // chunk-kernel workgroups (0: default)
     int32_t e_chunks_max, i_chunks_max;
@@ -183,7 +188,7 @@ struct BigArgs {
 
 struct BigPlan {
     size_t list, hdr, rec, e_chunk_cell, i_chunk_cell, part, key_a, val_a, key_b, val_b, key_c,
-        val_c, hist, iflag, ccnt, iaux, wp, sel;
+        val_c, hist, iflag, ccnt, iaux, wp, sel, fip, gev, gew, giv, giz;
     size_t bytes;
     int32_t e_chunks, i_chunks;
 };
