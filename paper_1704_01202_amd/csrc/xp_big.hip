@@ -387,12 +387,15 @@ __global__ __launch_bounds__(64) void k_big_rhist(BigArgs a, int species, int ne
 }
 
 // Exclusive scan of a cell's digit counts in (digit, chunk) order over the
-// chunk-major table hist[chunk][digit]: thread d runs down digit d's column
-// (coalesced across threads), then adds the offset of digit d.
-__global__ __launch_bounds__(256) void k_big_rscan(BigArgs a, int species, int needbit)
+// chunk-major table hist[chunk][digit].  1024 threads: thread (q, d) runs down
+// quarter q of digit d's column (coalesced across d), the quarter totals are
+// scanned per digit, the digit totals across digits, and each thread adds
+// its offset to its quarter.
+__global__ __launch_bounds__(1024) void k_big_rscan(BigArgs a, int species, int needbit)
 {
-    __shared__ uint32_t red[4];
-    const int tid = threadIdx.x;
+    __shared__ uint32_t qsum[4][256];
+    __shared__ uint32_t red[16];
+    const int tid = threadIdx.x, d = tid & 255, qt = tid >> 8;
     const int nb = a.hdr->count;
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
         const BigRec& r = a.rec[b];
@@ -400,28 +403,55 @@ __global__ __launch_bounds__(256) void k_big_rscan(BigArgs a, int species, int n
         const int c0 = species == 0 ? r.ce0 : r.ci0;
         const int nc = species == 0 ? r.nce : r.nci;
         if (nc == 0) continue;
-        uint32_t* h = a.hist + (size_t)256 * c0 + tid;
+        const int per = (nc + 3) / 4;
+        const int k0 = qt * per, k1 = k0 + per < nc ? k0 + per : nc;
+        uint32_t* h = a.hist + (size_t)256 * c0 + d;
         uint32_t run = 0;
-        for (int k = 0; k < nc; ++k) {
+        for (int k = k0; k < k1; ++k) {
             const uint32_t v = h[(size_t)256 * k];
             h[(size_t)256 * k] = run;
             run += v;
         }
+        qsum[qt][d] = run;
+        __syncthreads();
+        // digit totals (threads of quarter 0), exclusive over digits: every
+        // thread takes part in the block scan, the other quarters add 0
+        uint32_t t = 0;
+        if (qt == 0) {
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t v = qsum[q][d];
+                qsum[q][d] = t;
+                t += v;
+            }
+        }
         uint32_t tot;
-        const uint32_t base = block_exclusive_sum<256, uint32_t>(run, red, tot);
-        if (base)
-            for (int k = 0; k < nc; ++k) h[(size_t)256 * k] += base;
+        const uint32_t dbase = block_exclusive_sum<1024, uint32_t>(t, red, tot);
+        if (qt == 0)
+            for (int q = 0; q < 4; ++q) qsum[q][d] += dbase;
+        __syncthreads();
+        const uint32_t off = qsum[qt][d];
+        if (off)
+            for (int k = k0; k < k1; ++k) h[(size_t)256 * k] += off;
         __syncthreads();
     }
 }
 
-// One wave per chunk: stable scatter with ballot-ranked groups of 64.
-__global__ __launch_bounds__(64) void k_big_rscatter(BigArgs a, int species, int needbit, int shift,
-                                                     const uint32_t* key, const uint32_t* val,
-                                                     uint32_t* key_out, uint32_t* val_out)
+// One block per chunk: the chunk's keys are ranked stably by digit in LDS
+// (first a digit histogram and its scan give each digit's local run, then
+// groups of 256 keys are ranked with wave ballots and per-wave digit counts),
+// then written out in staged order so that each digit's run lands
+// contiguously at the chunk's global offset for that digit.
+__global__ __launch_bounds__(256) void k_big_rscatter(BigArgs a, int species, int needbit, int shift,
+                                                      const uint32_t* key, const uint32_t* val,
+                                                      uint32_t* key_out, uint32_t* val_out)
 {
-    __shared__ uint32_t run[256];
-    const int lane = threadIdx.x;
+    __shared__ uint32_t lstart[256];     // local start of each digit's run in the chunk
+    __shared__ uint32_t gbase[256];      // global offset of each digit for this chunk
+    __shared__ uint32_t seen[256];       // keys of each digit placed so far
+    __shared__ uint32_t wcnt[4][256];    // per-wave digit counts of the current group
+    __shared__ uint32_t skey[BIG_CH], sval[BIG_CH];
+    __shared__ uint32_t red[4];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const uint64_t lt = (1ull << lane) - 1ull;
     const int nch = species == 0 ? a.hdr->n_e_chunks : a.hdr->n_i_chunks;
     const int32_t* map = species == 0 ? a.e_chunk_cell : a.i_chunk_cell;
@@ -429,37 +459,62 @@ __global__ __launch_bounds__(64) void k_big_rscatter(BigArgs a, int species, int
         const BigRec& r = a.rec[map[g]];
         if (!big_live(r, needbit)) continue;
         const int c0 = species == 0 ? r.ce0 : r.ci0;
-        const int nc = species == 0 ? r.nce : r.nci;
         const int cnt = species == 0 ? r.epn : r.ni;
         const int64_t pop = species == 0 ? r.ep0 : r.ip0;
-        const int k = g - c0;
-        const int base = k * BIG_CH;
+        const int base = (g - c0) * BIG_CH;
         const int n = cnt - base < BIG_CH ? cnt - base : BIG_CH;
-        const uint32_t* hc = a.hist + (size_t)256 * g;
-        for (int q = lane; q < 256; q += 64) run[q] = hc[q];
+        const uint32_t* kin = key + pop + base;
+        const uint32_t* vin = val + pop + base;
+        // local digit histogram and its exclusive scan
+        seen[tid] = 0;
+        gbase[tid] = a.hist[(size_t)256 * g + tid];
         __syncthreads();
-        for (int c = 0; c < n; c += 64) {
-            const int i = c + lane;
+        for (int q = tid; q < n; q += 256) atomicAdd(&seen[(kin[q] >> shift) & 255u], 1u);
+        __syncthreads();
+        uint32_t tot;
+        lstart[tid] = block_exclusive_sum<256, uint32_t>(seen[tid], red, tot);
+        __syncthreads();
+        seen[tid] = 0;
+        __syncthreads();
+        // stable ranking, 256 keys at a time
+        for (int c = 0; c < n; c += 256) {
+            const int i = c + tid;
             const bool valid = i < n;
-            const uint32_t kk = valid ? key[pop + base + i] : 0u;
-            const uint32_t vv = valid ? val[pop + base + i] : 0u;
-            const uint32_t d = (kk >> shift) & 255u;
+            const uint32_t k = valid ? kin[i] : 0u;
+            const uint32_t v = valid ? vin[i] : 0u;
+            const uint32_t d = (k >> shift) & 255u;
             uint64_t peers = __ballot(valid);
 #pragma unroll
             for (int bit = 0; bit < 8; ++bit) {
                 const uint64_t bal = __ballot((d >> bit) & 1u);
                 peers &= ((d >> bit) & 1u) ? bal : ~bal;
             }
-            const uint32_t rank = (uint32_t)__popcll(peers & lt);
-            const uint32_t at = valid ? run[d] : 0u;
+            const uint32_t below = (uint32_t)__popcll(peers & lt);
+            for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
             __syncthreads();
+            if (valid && below == 0) wcnt[wid][d] = (uint32_t)__popcll(peers);
+            __syncthreads();
+            uint32_t before = 0;
+            if (valid)
+                for (int w = 0; w < wid; ++w) before += wcnt[w][d];
             if (valid) {
-                key_out[pop + at + rank] = kk;
-                val_out[pop + at + rank] = vv;
-                if ((peers & lt) == 0) run[d] = at + (uint32_t)__popcll(peers);
+                const uint32_t pos = lstart[d] + seen[d] + before + below;
+                skey[pos] = k;
+                sval[pos] = v;
             }
             __syncthreads();
+            seen[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
+            __syncthreads();
         }
+        // each digit's run to its global place (consecutive t, consecutive addresses)
+        for (int t = tid; t < n; t += 256) {
+            const uint32_t k = skey[t];
+            const uint32_t d = (k >> shift) & 255u;
+            const int64_t dst = pop + gbase[d] + (t - lstart[d]);
+            key_out[dst] = k;
+            val_out[dst] = sval[t];
+        }
+        __syncthreads();
     }
 }
 
@@ -1541,8 +1596,8 @@ hipError_t big_sort(BigArgs& a, int species, int needbit, uint32_t purpose, uint
     hipLaunchKernelGGL(k_big_keys, dim3(gch), dim3(BT), 0, s, a, species, needbit, purpose, key, val);
     for (int shift = 0; shift < 32; shift += 8) {
         hipLaunchKernelGGL(k_big_rhist, dim3(gch), dim3(64), 0, s, a, species, needbit, shift, (const uint32_t*)key);
-        hipLaunchKernelGGL(k_big_rscan, dim3(gcell), dim3(256), 0, s, a, species, needbit);
-        hipLaunchKernelGGL(k_big_rscatter, dim3(gch), dim3(64), 0, s, a, species, needbit, shift,
+        hipLaunchKernelGGL(k_big_rscan, dim3(gcell), dim3(1024), 0, s, a, species, needbit);
+        hipLaunchKernelGGL(k_big_rscatter, dim3(gch), dim3(256), 0, s, a, species, needbit, shift,
                            (const uint32_t*)key, (const uint32_t*)val, key2, val2);
         uint32_t* t = key; key = key2; key2 = t;
         t = val; val = val2; val2 = t;
