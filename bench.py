@@ -213,6 +213,69 @@ def bench_c4(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_c3(args):
+    """Uneven occupancy: 1024 x 256 cells on a density ramp (4 to ~1024
+    particles per cell).  The autotuner picks among one wave per cell, one
+    block per cell and the automatic choice (and the quantile of cell sizes the
+    first LDS plan covers); the tuned
+    configuration is then timed over graph-replayed steps.  One JSON line."""
+    import torch
+    from paper_1704_01202_amd import runtime as RT
+    from paper_1704_01202_amd import scan as SC
+    from paper_1704_01202_amd import workloads as W
+
+    t0 = time.perf_counter()
+    tab = W.make_tables()
+    spec, parts = W.config_c3()
+    log("C3 generated (%.1f s): %d electrons, %d ions" % (time.perf_counter() - t0, parts.ne, parts.ni))
+    ctx = RT.Context(tab)
+    sc = SC.Scan(ctx, [(spec, parts)], capacity=(7, 16))
+    for _ in range(2):
+        sc.eager_step()
+    cands = [{"schedule": s_, "quantile": q, "big_grid": 0} for s_ in (0, 1, 2) for q in (0.9, 0.99, 1.0)]
+    best, best_ms = sc.autotune(cands, reps=2)
+    log("autotune: " + ", ".join("%s/%.2f: %.3f ms" % (c["schedule"], c["quantile"], ms) for c, ms in sc.tuning))
+    k = 5
+    sc.capture(k)
+    sc.bat.d_run_cnt.zero_()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    reps = max(1, args.steps // k)
+    for _ in range(reps):
+        sc.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    timed = reps * k
+    cnt = sc.bat.run_counters()[0]
+    coll = int(cnt[0] + cnt[1] + cnt[2])
+    st = sc.bat.stats()
+    out = {
+        "metric": "binary collisions/sec",
+        "value": coll / wall,
+        "unit": "collisions/s",
+        "n_gpus": 1,
+        "steps": timed,
+        "warmup": sc.steps_done - timed,
+        "ms_per_step": e0.elapsed_time(e1) / timed,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "2D 1024x256 cells, density ramp 0.01-1x solid (20-cell scale), "
+                               "Poisson 4-1024 particles per cell, T_e 5-50 eV per column, EK, dt 0.05 fs",
+                   "cells": spec.ncells, "electrons_start": parts.ne, "ions": parts.ni,
+                   "autotuned": best, "status": sc.status(),
+                   "global_path_cells_last_step": int(st[2])},
+        "autotune_ms": [[c["schedule"], c["quantile"], ms] for c, ms in sc.tuning],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_c5(args):
     """Served stream: Poisson arrivals of 0D and 1D runs served with continuous
     batching from a resident pool, against a sequential plain loop over the
@@ -291,9 +354,9 @@ def main():
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run a plain device copy of MIB MiB "
                          "(calibrates the HBM byte counters under a profiler)")
-    ap.add_argument("--workload", choices=("c2", "c4", "c5"), default="c2",
-                    help="c2: the 512x512-cell step (default); c4: the batched scan; "
-                         "c5: the served stream")
+    ap.add_argument("--workload", choices=("c2", "c3", "c4", "c5"), default="c2",
+                    help="c2: the 512x512-cell step (default); c3: uneven occupancy with the "
+                         "autotuned schedule; c4: the batched scan; c5: the served stream")
     ap.add_argument("--requests", type=int, default=48, help="c5: requests in the trace")
     ap.add_argument("--rate", type=float, default=20.0, help="c5: arrivals per second")
     ap.add_argument("--size-hi", type=float, default=2e6, help="c5: largest run, particles")
@@ -311,6 +374,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "c3":
+        bench_c3(args)
+        return
     if args.workload == "c4":
         bench_c4(args)
         return

@@ -81,6 +81,7 @@ enum {
 };
 
 #define XP_NMOM 32          /* per-cell moment record, see collide_ionize_step */
+#define XP_NSTATS 68        /* entries of xp_batch.d_stats */
 #define XP_MAX_BINS 16      /* photon energy bins per run */
 
 typedef struct xp_ctx xp_ctx;
@@ -190,10 +191,12 @@ typedef struct {
     size_t work_bytes;
     int32_t e_cap_max;              /* host copy of max e_cap over cells (d_need[2]) */
     int32_t i_cap_max;              /* host copy of max i_cap over cells (d_need[3]) */
-    int32_t *d_stats;               /* optional [4]: after a step, [0] the largest electron
-                                       count of a cell stepped in LDS, [1] cells re-planned
-                                       with more LDS, [2] cells stepped on the global-memory
-                                       path, [3] the largest electron count among those */
+    int32_t *d_stats;               /* optional [XP_NSTATS]: after a step, [0] the largest
+                                       electron count of a cell stepped in LDS, [1] cells
+                                       re-planned with more LDS, [2] cells stepped on the
+                                       global-memory path, [3] the largest electron count
+                                       among those, [4 + b] LDS cells ending the step with
+                                       16(b-1) < n_e <= 16 b electrons (b = 63: more) */
     /* Bounds of the cells that may take the global-memory path (cells whose
      * slab exceeds what one workgroup's LDS holds): their number and the sums
      * of their e_cap and i_cap (d_need[4..6] of bin_particles).  All zero:

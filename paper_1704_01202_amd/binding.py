@@ -20,6 +20,7 @@ XP_EE, XP_EI, XP_ION, XP_REC, XP_PHOTO, XP_DECAY = 0x01, 0x02, 0x04, 0x08, 0x10,
 XP_ALL = 0x3F
 XP_ST_CAPACITY, XP_ST_NONFINITE, XP_ST_BIN_SIZE = 0x1, 0x2, 0x4
 XP_NCOUNT, XP_NLEDGER, XP_NMOM, XP_MAX_BINS = 24, 8, 32, 16
+XP_NSTATS = 68
 XP_DIAG_RESET = 0x1
 
 COUNTERS = ["EE", "EI", "TRIPLET", "ACCEPT", "U0", "DELTA2_GT1",

@@ -124,12 +124,14 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(3))) void k_s
     __shared__ unsigned long long acc_cnt[XP_NCOUNT];
     __shared__ double acc_led[XP_NLEDGER];
     __shared__ int acc_run, acc_max;
+    __shared__ int acc_hist[64];      // committed cells by electron count (16 per bucket)
     const int tid = threadIdx.x;
     const int ce = a.lds_ce, ci = a.lds_ci;
     const int ps = pow2_at_least(ce > ci ? ce : ci);
     const Lds L = carve(smem, ce, ci, ps);
     for (int q = tid; q < XP_NCOUNT; q += B) acc_cnt[q] = 0;
     for (int q = tid; q < XP_NLEDGER; q += B) acc_led[q] = 0.0;
+    for (int q = tid; q < 64; q += B) acc_hist[q] = 0;
     if (tid == 0) {
         acc_run = -1;
         acc_max = 0;
@@ -162,12 +164,21 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(3))) void k_s
             }
             for (int q = tid; q < XP_NCOUNT; q += B) acc_cnt[q] += (unsigned long long)S.cnt[q];
             for (int q = tid; q < XP_NLEDGER; q += B) acc_led[q] = acc_led[q] + S.led[q];
-            if (tid == 0 && S.ints[6] > acc_max) acc_max = S.ints[6];
+            if (tid == 0) {
+                const int n = S.ints[6];
+                if (n > acc_max) acc_max = n;
+                const int bk = (n + 15) / 16;
+                acc_hist[bk < 63 ? bk : 63] += 1;
+            }
         }
         __syncthreads();
     }
     flush();
-    if (tid == 0 && a.stats && acc_max > 0) atomicMax(&a.stats[0], acc_max);
+    if (a.stats) {
+        if (tid == 0 && acc_max > 0) atomicMax(&a.stats[0], acc_max);
+        for (int q = tid; q < 64; q += B)
+            if (acc_hist[q]) atomicAdd(&a.stats[4 + q], acc_hist[q]);
+    }
 }
 
 // Random permutation of slots 0..n-1: out[k] = slot of rank k when the slots
@@ -949,7 +960,8 @@ template __global__ void k_step<256>(StepArgs);
 __global__ void k_step_prep(int32_t* counts, int32_t* stats)
 {
     if (threadIdx.x < STEP_COUNTS && counts) counts[threadIdx.x] = 0;
-    if (threadIdx.x < 4 && stats) stats[threadIdx.x] = 0;
+    if (stats)
+        for (int q = threadIdx.x; q < XP_NSTATS; q += blockDim.x) stats[q] = 0;
 }
 
 // Per-run photoionization cross sections of every bin and subshell (they

@@ -17,6 +17,27 @@ import torch
 from . import binding as B
 
 
+def plan_hint(stats, quantile=0.9):
+    """LDS plan size for the next step from a step's stats: the electron
+    count that covers `quantile` of the cells stepped in LDS (16-electron
+    buckets); cells above it are re-planned with more LDS in the same call.
+    quantile >= 1: the largest cell."""
+    stats = np.asarray(stats)
+    if quantile >= 1.0:
+        m = int(stats[0])
+        return m if m > 0 else 0
+    hist = stats[4:4 + 64].astype(np.int64)
+    tot = int(hist.sum())
+    if tot == 0:
+        return 0
+    need = quantile * tot
+    cum = np.cumsum(hist)
+    b = int(np.searchsorted(cum, need))
+    if b >= 63:
+        return int(stats[0])
+    return max(16, 16 * b)
+
+
 def _stream():
     return torch.cuda.current_stream().cuda_stream
 
@@ -130,8 +151,8 @@ class Batch:
         self.d_i_cnt = torch.zeros(nc, dtype=torch.int32, device=dev)
         self.d_status = torch.zeros(1, dtype=torch.int32, device=dev)
         self.d_need = torch.zeros(8, dtype=torch.int64, device=dev)
-        self.d_stats = torch.zeros(4, dtype=torch.int32, device=dev)
-        self.h_stats = torch.zeros(4, dtype=torch.int32, pin_memory=True)
+        self.d_stats = torch.zeros(B.XP_NSTATS, dtype=torch.int32, device=dev)
+        self.h_stats = torch.zeros(B.XP_NSTATS, dtype=torch.int32, pin_memory=True)
         self.e_hint = 0
         self.d_run_cnt = torch.zeros((self.n_runs, B.XP_NCOUNT), dtype=torch.int64, device=dev)
         self.d_run_led = torch.zeros((self.n_runs, B.XP_NLEDGER), dtype=torch.float64, device=dev)
@@ -252,12 +273,11 @@ class Batch:
             self.d_work = torch.empty(self.work_bytes, dtype=torch.uint8, device=self.device)
 
     # -- the method ---------------------------------------------------------------
-    def _hint(self, use_hint):
+    def _hint(self, use_hint, quantile=0.9):
         if not use_hint:
             return 0
-        # largest electron count of the step before last (copied without waiting)
-        seen = int(self.h_stats[0].item())
-        return seen if seen > 0 else 0
+        # from the step before last (copied without waiting)
+        return plan_hint(self.h_stats.numpy(), quantile)
 
     def _after(self):
         self.h_stats.copy_(self.d_stats, non_blocking=True)
@@ -296,8 +316,9 @@ class Batch:
         return int(self.d_status.item())
 
     def stats(self):
-        """[largest electron count of an LDS cell, LDS re-plans, cells on the
-        global-memory path, largest electron count among those] of the last step."""
+        """Of the last step: [0] largest electron count of an LDS cell, [1] LDS
+        re-plans, [2] cells on the global-memory path, [3] largest electron
+        count among those, [4 + b] LDS cells with 16(b-1) < n_e <= 16 b."""
         return self.d_stats.cpu().numpy().copy()
 
     # -- read-back for checks ---------------------------------------------------

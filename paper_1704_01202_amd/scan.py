@@ -8,8 +8,8 @@ workgroups.  Together these split the work by per-cell size.  Each run keeps
 its own step index in device memory (d_step), so a HIP graph captured over k
 steps advances every run by k on each replay.
 
-Knobs that change speed but never results (schedule, LDS plan headroom,
-global-path grid) are picked by timing real steps: the physics of the step
+Knobs that change speed but never results (schedule, the quantile of cell
+sizes the first LDS plan covers, global-path grid) are picked by timing real steps: the physics of the step
 does not depend on them, so a tuning step is an ordinary step of the scan.
 
 The sequential baseline steps every run alone, one after the other, with
@@ -34,17 +34,14 @@ class Scan:
         self.n_runs = len(runs)
         self.d_step = torch.zeros(self.n_runs, dtype=torch.int32, device=ctx.device)
         self.steps_done = 0
-        self.config = {"schedule": 0, "headroom": 1.25, "big_grid": 0}
+        self.config = {"schedule": 0, "quantile": 0.9, "big_grid": 0}
         self.graph = None
         self.graph_k = 0
         self.tuning = []
 
     # -- stepping ---------------------------------------------------------
     def _hint(self):
-        seen = int(self.bat.h_stats[0].item())
-        if seen <= 0:
-            return 0
-        return int(seen * self.config["headroom"]) + 16
+        return RT.plan_hint(self.bat.h_stats.numpy(), self.config["quantile"])
 
     def eager_step(self):
         c = self.config
@@ -56,8 +53,8 @@ class Scan:
     def autotune(self, candidates=None, reps=2):
         """Time `reps` real steps per candidate; keep the fastest."""
         if candidates is None:
-            candidates = [{"schedule": s, "headroom": h, "big_grid": g}
-                          for s in (0, 1, 2) for h in (1.25, 2.0) for g in (0, 1024, 8192)]
+            candidates = [{"schedule": s, "quantile": q, "big_grid": g}
+                          for s in (0, 1, 2) for q in (0.9, 0.99, 1.0) for g in (0, 1024, 8192)]
         stream = torch.cuda.current_stream()
         best, best_ms = None, float("inf")
         self.tuning = []

@@ -124,8 +124,8 @@ class Pool:
         self.run_cnt = torch.zeros((self.max_runs, B.XP_NCOUNT), dtype=torch.int64, device=dev)
         self.run_led = torch.zeros((self.max_runs, B.XP_NLEDGER), dtype=torch.float64, device=dev)
         self.d_status = torch.zeros(1, dtype=torch.int32, device=dev)
-        self.d_stats = torch.zeros(4, dtype=torch.int32, device=dev)
-        self.h_stats = torch.zeros(4, dtype=torch.int32, pin_memory=True)
+        self.d_stats = torch.zeros(B.XP_NSTATS, dtype=torch.int32, device=dev)
+        self.h_stats = torch.zeros(B.XP_NSTATS, dtype=torch.int32, pin_memory=True)
         self.ealloc, self.ialloc = RangeAlloc(self.E), RangeAlloc(self.I)
         self.active: list[Resident] = []
         self.cells_used = 0
@@ -265,8 +265,7 @@ class Pool:
         if not self.active:
             return
         b = self._struct(self.cells_used, len(self.active), self._big_bounds())
-        seen = int(self.h_stats[0].item())
-        hint = int(seen * 1.25) + 16 if seen > 0 else 0
+        hint = RT.plan_hint(self.h_stats.numpy(), 0.9)
         nr = len(self.active)
         for _ in range(k):
             prm = B.XpStepParams(B.XP_ALL, 0, RT._ptr(self.d_step), int(schedule), hint, 0, 0)

@@ -69,9 +69,9 @@ def test_scan_graph_replays_match_eager_alone_and_oracle(ctx):
 def test_autotune_changes_speed_not_results(ctx):
     runs = small_scan(4)
     sc = SC.Scan(ctx, runs)
-    cands = [{"schedule": 1, "headroom": 1.25, "big_grid": 0},
-             {"schedule": 2, "headroom": 2.0, "big_grid": 1024},
-             {"schedule": 0, "headroom": 1.25, "big_grid": 8192}]
+    cands = [{"schedule": 1, "quantile": 0.9, "big_grid": 0},
+             {"schedule": 2, "quantile": 1.0, "big_grid": 1024},
+             {"schedule": 0, "quantile": 0.99, "big_grid": 8192}]
     best, ms = sc.autotune(cands, reps=2)
     assert best in cands and ms > 0
     n = sc.steps_done
