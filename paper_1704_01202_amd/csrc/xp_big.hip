@@ -711,18 +711,20 @@ __global__ __launch_bounds__(BT) void k_big_lotz(BigArgs a)
         if (!big_live(r, BN_ION)) continue;
         int oc[5];
         double pp[5], lnp[5];
+        double pmin = __builtin_inf();
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
             oc[q] = r.occ[q];
             pp[q] = r.pp[q];
             lnp[q] = r.lnp[q];
+            if (oc[q] > 0 && pp[q] < pmin) pmin = pp[q];
         }
         const int base = (g - r.ce0) * BIG_CH;
         const int n = r.epn - base < BIG_CH ? r.epn - base : BIG_CH;
         const int64_t o = r.eo + base;
         const double sum = block_tree_sum<BT>(BIG_CH, [&](int j) {
             if (j >= n) return 0.0;
-            return lotz_leaf(s.evx[o + j], s.evy[o + j], s.evz[o + j], s.ew[o + j], oc, pp, lnp, tb);
+            return lotz_leaf(s.evx[o + j], s.evy[o + j], s.evz[o + j], s.ew[o + j], oc, pp, lnp, pmin, tb);
         }, red);
         if (tid == 0) a.part[1][g] = sum;
     }

@@ -206,14 +206,17 @@ __device__ __forceinline__ void collide_slots(double* avx, double* avy, double* 
 }
 
 // w sigma v of one electron for the average cell ion (Lotz, Eq. 4): occupied
-// subshells oc, lowered bindings pp and their logarithms lnp.
+// subshells oc, lowered bindings pp and their logarithms lnp; pmin is the
+// smallest pp of an occupied subshell.  An electron at or below pmin meets no
+// subshell term, so its cross section stays 0.0 without the logarithm.
 __device__ __forceinline__ double lotz_leaf(double x, double y, double z, uint32_t w, const int* oc,
-                                         const double* pp, const double* lnp, const DevTables* tb)
+                                         const double* pp, const double* lnp, double pmin,
+                                         const DevTables* tb)
 {
     const double v2 = (x * x + y * y) + z * z;
     const double e = HALF_ME_OVER_QE * v2;
     double sig = 0.0;
-    if (e > 0.0) {
+    if (e > 0.0 && e > pmin) {
         const double lne = xlog(e);
         for (int q = 0; q < 5; ++q) {
             if (oc[q] <= 0 || !(e > pp[q])) continue;
@@ -227,3 +230,4 @@ __device__ __forceinline__ double lotz_leaf(double x, double y, double z, uint32
 }
 
 }  // namespace xpd
+

@@ -492,8 +492,12 @@ __device__ bool step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
                 lnp[q] = oc.s[q] > 0 ? xlog(pp[q]) : 0.0;
                 if (tid == 0 && oc.s[q] > 0 && raw < 1.0) S.cnt[XP_C_IPD_CLAMPED] += 1;
             }
+            double pmin = __builtin_inf();
+#pragma unroll
+            for (int q = 0; q < 5; ++q)
+                if (oc.s[q] > 0 && pp[q] < pmin) pmin = pp[q];
             const double ssum = block_tree_sum<B>(ne0, [&](int j) {
-                return lotz_leaf(L.evx[j], L.evy[j], L.evz[j], L.ew[j], oc.s, pp, lnp, tb);
+                return lotz_leaf(L.evx[j], L.evy[j], L.evz[j], L.ew[j], oc.s, pp, lnp, pmin, tb);
             }, S.red);
             double p = ((ssum * w0) * dt) / vol;
             if (p > 1.0) {
