@@ -240,13 +240,19 @@ typedef struct {
     uint32_t flags;            /* XP_* stage switches */
     uint32_t step;             /* step index (Philox counter word 0) */
     const uint32_t *d_step;    /* optional [n_runs] device step index per run; overrides step */
-    int32_t schedule;          /* 0 auto; 1 one wave per cell; 2 one block of 256 per cell;
-                                  3 every cell on the global-memory path (needs big_* bounds
-                                  covering the whole batch).  Results never depend on it. */
+    int32_t schedule;          /* 0 auto, per LDS plan: four cells per wave for plans of at
+                                  most 64 slots per species, a wave per cell up to 128, a
+                                  block of 256 per cell above; 1 one wave per cell; 2 one
+                                  block of 256 per cell; 3 every cell on the global-memory
+                                  path (needs big_* bounds covering the whole batch); 4, 5, 6
+                                  two, four, eight cells per wave (groups of 32, 16, 8 lanes)
+                                  for plans of at most 128, 64, 32 slots per species, as auto
+                                  above.  Results never depend on it. */
     int32_t e_hint;            /* expected largest electron count of a cell (e.g. d_stats[0]
-                                  of the previous step); 0: plan for e_cap_max.  Cells that
-                                  outgrow the plan are redone with a larger one in the same
-                                  call, so the hint changes speed, never results. */
+                                  of the previous step); 0: plan for e_cap_max.  Plans
+                                  before the last hold no more ion than electron slots.
+                                  Cells that outgrow a plan are redone with a larger one in
+                                  the same call, so the hint changes speed, never results. */
     int32_t big_grid;          /* workgroups of the global-memory path's chunk kernels;
                                   0: library default.  Speed only. */
     int32_t reserved;

@@ -263,7 +263,7 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
     if (!p) return fail(XP_ERR_INVALID_ARG, "null step parameters");
     if (b->n_cells == 0) return XP_OK;
     if (b->e_cap_max <= 0 || b->i_cap_max < 0) return fail(XP_ERR_INVALID_ARG, "batch e_cap_max / i_cap_max not set");
-    if (p->schedule < 0 || p->schedule > 3) return fail(XP_ERR_INVALID_ARG, "unknown schedule");
+    if (p->schedule < 0 || p->schedule > 6) return fail(XP_ERR_INVALID_ARG, "unknown schedule");
     if (p->big_grid < 0 || p->big_grid > 65536) return fail(XP_ERR_INVALID_ARG, "big_grid out of range");
     if (b->big_cells_max < 0 || b->big_e_slots < 0 || b->big_i_slots < 0)
         return fail(XP_ERR_INVALID_ARG, "negative big-cell bounds");
@@ -368,7 +368,7 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
         // first plan: the hinted size plus headroom for this step's new electrons
         int ce = ce_top;
         if (p->e_hint > 0) {
-            const int head = p->e_hint / 4 > 32 ? p->e_hint / 4 : 32;
+            const int head = p->e_hint / 4 > 16 ? p->e_hint / 4 : 16;
             ce = p->e_hint + head;
             ce = ((ce + 15) / 16) * 16;
             if (ce > ce_top) ce = ce_top;
@@ -376,33 +376,55 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
         for (int tier = 0;; ++tier) {
             const bool last = ce >= ce_top || tier >= xpd::BIG_COUNT_SLOT - 1;
             a.lds_ce = ce;
+            // ions: the whole batch's bound on the last plan, no more than the
+            // electron plan before it (ion-heavy cells move on with the
+            // electron-heavy ones)
+            a.lds_ci = last || ce >= ci_plan ? ci_plan : ce;
             a.cell_list = tier == 0 ? nullptr : plan.lists[(tier - 1) & 1];
             a.cell_list_count = tier == 0 ? nullptr : plan.counts + (tier - 1);
             a.defer_out = last ? nullptr : plan.lists[tier & 1];
             a.defer_out_count = last ? nullptr : plan.counts + tier;
-            const size_t lds = xpd::step_lds_bytes(a.lds_ce, a.lds_ci);
+            const size_t lds1 = xpd::step_lds_bytes(a.lds_ce, a.lds_ci);
+            const int m = a.lds_ce > a.lds_ci ? a.lds_ce : a.lds_ci;
             int sched = p->schedule;
-            if (sched == 0) sched = (a.lds_ce > 512 || a.lds_ci > 512) ? 2 : 1;
+            if (sched == 0) {
+                // small plans: four cells per wave; mid-sized plans: a wave per
+                // cell; large plans (whose LDS leaves few workgroups per CU): a
+                // block of four waves per cell
+                if (m <= 4 * 16) sched = 5;
+                else sched = m > 128 ? 2 : 1;
+            }
+            if (sched >= 4) {
+                const int w = sched == 4 ? 32 : (sched == 5 ? 16 : 8);
+                if (m > 4 * w) sched = m > 128 ? 2 : 1;   // plan too large for the group
+            }
+            const void* fn;
+            int threads = 64, per_cell_groups = 1;
+            switch (sched) {
+            case 1: fn = (const void*)xpd::k_step<64>; break;
+            case 2: fn = (const void*)xpd::k_step<256>; threads = 256; break;
+            case 4: fn = (const void*)xpd::k_step_g<32>; per_cell_groups = 2; break;
+            case 5: fn = (const void*)xpd::k_step_g<16>; per_cell_groups = 4; break;
+            default: fn = (const void*)xpd::k_step_g<8>; per_cell_groups = 8; break;
+            }
+            const size_t lds = sched >= 4 ? (size_t)per_cell_groups * ((lds1 + 15) & ~size_t(15)) : lds1;
+            if (lds > ctx->max_lds) return fail(XP_ERR_UNSUPPORTED, "LDS plan too large");
+            if (lds > 65536) hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             // tier 0: a few resident rounds of workgroups, each looping over its
             // cells (run records are summed per workgroup); later tiers: the
             // deferred cells, read from the list
-            unsigned grid = (unsigned)(b->n_cells < 2048 ? b->n_cells : 2048);
+            const long long items = ((long long)b->n_cells + per_cell_groups - 1) / per_cell_groups;
+            unsigned grid = (unsigned)(items < 2048 ? items : 2048);
             if (tier == 0) {
                 int per_cu = 0;
-                const void* fn = sched == 1 ? (const void*)xpd::k_step<64> : (const void*)xpd::k_step<256>;
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, sched == 1 ? 64 : 256, lds) != hipSuccess ||
-                    per_cu < 1)
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess || per_cu < 1)
                     per_cu = 1;
                 const long long g0 = 4ll * per_cu * ctx->n_cu;
-                grid = (unsigned)(b->n_cells < g0 ? b->n_cells : g0);
+                grid = (unsigned)(items < g0 ? items : g0);
             }
-            if (sched == 1) {
-                if (lds > 65536) hipFuncSetAttribute((const void*)xpd::k_step<64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-                hipLaunchKernelGGL(xpd::k_step<64>, dim3(grid), dim3(64), lds, s, a);
-            } else {
-                if (lds > 65536) hipFuncSetAttribute((const void*)xpd::k_step<256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-                hipLaunchKernelGGL(xpd::k_step<256>, dim3(grid), dim3(256), lds, s, a);
-            }
+            void* kargs[] = {(void*)&a};
+            e = hipLaunchKernel(fn, dim3(grid), dim3(threads), kargs, lds, s);
+            if (e != hipSuccess) return hip_fail(e, "step launch");
             e = hipGetLastError();
             if (e != hipSuccess) return hip_fail(e, "step launch");
             if (last) break;

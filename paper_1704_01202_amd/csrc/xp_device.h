@@ -406,4 +406,81 @@ __device__ __forceinline__ void wave_bitonic(uint64_t (&key)[K])
     }
 }
 
+
+__device__ __forceinline__ uint64_t shfl_xor_u64w(uint64_t v, int m, int width)
+{
+    const uint32_t lo = __shfl_xor((uint32_t)v, m, width);
+    const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), m, width);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Bitonic sort of P = W K keys held by a group of W lanes (W a power of two
+// <= 64, groups aligned in the wave): element e = t + W m is key[m] of group
+// lane t.  Strides below W exchange across the group's lanes, larger strides
+// between a lane's own registers.  Same network as the one-wave sort.
+template <int W, int K>
+__device__ __forceinline__ void group_bitonic(uint64_t (&key)[K])
+{
+    const int t = threadIdx.x & (W - 1);
+#pragma unroll
+    for (int k = 2; k <= W * K; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= W) {
+                const int mj = j / W;
+#pragma unroll
+                for (int m = 0; m < K; ++m) {
+                    if (m & mj) continue;
+                    const int e = t + W * m;
+                    const bool up = (e & k) == 0;
+                    const uint64_t x = key[m], y = key[m | mj];
+                    const bool sw = up ? (x > y) : (x < y);
+                    key[m] = sw ? y : x;
+                    key[m | mj] = sw ? x : y;
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < K; ++m) {
+                    const int e = t + W * m;
+                    const uint64_t o = shfl_xor_u64w(key[m], j, W);
+                    const bool up = (e & k) == 0;
+                    const bool lower = (t & j) == 0;
+                    const bool take_min = lower == up;
+                    const bool less = o < key[m];
+                    key[m] = (take_min == less) ? o : key[m];
+                }
+            }
+        }
+    }
+}
+
+// Canonical pairwise sum over n <= 4 W leaves by a group of W lanes: leaves
+// padded with +0 to p = pow2 >= n; lane t holds the aligned block of R = p / W
+// leaves (R <= 4) and sums it pairwise, then the groups' lanes are summed
+// pairwise by shuffles.  Equals the level-by-level sum of the p leaves.
+template <int W, class F>
+__device__ double group_tree_sum(int n, F leaf)
+{
+    const int t = threadIdx.x & (W - 1);
+    int p = 1;
+    while (p < n) p <<= 1;
+    const int R = p <= W ? 1 : p / W;   // leaves per lane: 1, 2 or 4
+    // one evaluation site for the leaf: the in-lane block is read in a loop
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll 1
+    for (int r = 0; r < R; ++r) {
+        const int j = t * R + r;
+        const double v = j < n ? leaf(j) : 0.0;
+        if (r == 0) a0 = v;
+        else if (r == 1) a1 = v;
+        else if (r == 2) a2 = v;
+        else a3 = v;
+    }
+    const double acc0 = R == 1 ? a0 : (R == 2 ? a0 + a1 : (a0 + a1) + (a2 + a3));
+    double acc = acc0;
+#pragma unroll
+    for (int off = 1; off < W; off <<= 1) acc = acc + __shfl_down(acc, off, W);
+    return __shfl(acc, 0, W) + 0.0;
+}
+
 }  // namespace xpd

@@ -63,6 +63,10 @@ size_t lds_budget(size_t max_lds);
 
 template <int B>
 __global__ void k_step(StepArgs a);
+// 64 / W cells per wave, W lanes per cell (W = 32, 16, 8); plans with at most
+// 4 W electrons and 4 W ions.
+template <int W>
+__global__ void k_step_g(StepArgs a);
 
 }  // namespace xpd
 

@@ -25,8 +25,9 @@ namespace xpd {
 
 namespace {
 
-struct CellShared {
-    double red[256];
+template <int RED>
+struct CellSharedT {
+    double red[RED];
     long long ired[16];
     int sel[16];
     int cnt[XP_NCOUNT];
@@ -36,6 +37,78 @@ struct CellShared {
     double ssum[13][3];
     double dbl[8];
     int ints[8];
+};
+using CellShared = CellSharedT<256>;
+
+// A team steps one cell: a whole workgroup of B threads (one or four waves),
+// or an aligned group of W lanes of a wave that steps 64 / W cells at once.
+// The step is written once against this interface.
+template <int B>
+struct BlockTeam {
+    static constexpr int N = B;
+    using Shared = CellShared;
+    __device__ static int rank() { return threadIdx.x; }
+    __device__ static void sync() { __syncthreads(); }
+    __device__ static long long isum(long long v, Shared& S) { return block_isum<B>(v, S.ired); }
+    template <class F>
+    __device__ static double tree(int n, F f, Shared& S) { return block_tree_sum<B>(n, f, S.red); }
+    template <class P, class E>
+    __device__ static int select(int n, P pred, E emit, Shared& S)
+    {
+        return block_ordered_select<B>(n, pred, emit, S.sel);
+    }
+    __device__ static int prefix(int v, int& tot, Shared& S) { return block_exclusive_sum<B, int>(v, S.sel, tot); }
+};
+
+template <int W>
+struct GroupTeam {
+    static constexpr int N = W;
+    using Shared = CellSharedT<1>;
+    __device__ static int rank() { return threadIdx.x & (W - 1); }
+    // the groups of a workgroup share one wave: LDS accesses of a wave are
+    // ordered, so a wave barrier with workgroup fences orders the group
+    __device__ static void sync()
+    {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+    __device__ static long long isum(long long v, Shared&)
+    {
+#pragma unroll
+        for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
+        return v;
+    }
+    template <class F>
+    __device__ static double tree(int n, F f, Shared&) { return group_tree_sum<W>(n, f); }
+    template <class P, class E>
+    __device__ static int select(int n, P pred, E emit, Shared&)
+    {
+        const int t = rank();
+        const int sh = threadIdx.x & 63 & ~(W - 1);
+        const uint64_t gmask = W == 64 ? ~0ull : ((1ull << W) - 1ull);
+        int base = 0;
+        for (int c0 = 0; c0 < n; c0 += W) {
+            const int j = c0 + t;
+            const bool f = j < n && pred(j);
+            const uint64_t gm = (__ballot(f) >> sh) & gmask;
+            if (f) emit(j, base + __popcll(gm & ((1ull << t) - 1ull)));
+            base += __popcll(gm);
+        }
+        return base;
+    }
+    __device__ static int prefix(int v, int& tot, Shared&)
+    {
+        const int t = rank();
+        int incl = v;
+#pragma unroll
+        for (int off = 1; off < W; off <<= 1) {
+            const int o = __shfl_up(incl, off, W);
+            if (t >= off) incl += o;
+        }
+        tot = __shfl(incl, W - 1, W);
+        return incl - v;
+    }
 };
 
 struct Lds {
@@ -96,7 +169,7 @@ __host__ __device__ inline int pow2_at_least(int n)
 
 }  // namespace
 
-size_t step_lds_bytes(int ce, int ci)
+__host__ __device__ size_t step_lds_bytes_dev(int ce, int ci)
 {
     const int ps = pow2_at_least(ce > ci ? ce : ci);
     auto r = [](size_t b) { return (b + 15) & ~size_t(15); };
@@ -105,8 +178,10 @@ size_t step_lds_bytes(int ce, int ci)
     return n;
 }
 
-template <int B>
-__device__ bool step_cell(const StepArgs& a, int cell, CellShared& S, const Lds& L);
+template <class T>
+__device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, const Lds& L);
+
+size_t step_lds_bytes(int ce, int ci) { return step_lds_bytes_dev(ce, ci); }
 
 // One workgroup per cell at a time, looping over the cells of the launch:
 // all cells (cell_list == nullptr) or the cells listed by an earlier launch
@@ -153,7 +228,7 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(3))) void k_s
     const int nitems = a.cell_list ? *a.cell_list_count : a.n_cells;
     for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
         const int cell = a.cell_list ? a.cell_list[item] : item;
-        const bool done = step_cell<B>(a, cell, S, L);
+        const bool done = step_cell<BlockTeam<B>>(a, cell, S, L);
         __syncthreads();
         if (done) {
             const int run = a.cell_run[cell];
@@ -181,23 +256,101 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(3))) void k_s
     }
 }
 
+// Several small cells per wave: the wave is cut into 64 / W aligned groups of
+// W lanes and every group steps its own cell with its own LDS plan (the same
+// step, written against the group team).  Cells are taken G at a time; run
+// records are summed per group and flushed like those of k_step.  Per-cell
+// values differ between the groups of a wave, so they live in vector
+// registers: two waves per SIMD, each carrying G cells.
+template <int W>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_step_g(StepArgs a)
+{
+    constexpr int G = 64 / W;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ CellSharedT<1> S[G];
+    __shared__ unsigned long long acc_cnt[G][XP_NCOUNT];
+    __shared__ double acc_led[G][XP_NLEDGER];
+    __shared__ int acc_run[G], acc_max[G];
+    __shared__ int acc_hist[64];
+    using T = GroupTeam<W>;
+    const int g = threadIdx.x / W, t = threadIdx.x & (W - 1);
+    const int ce = a.lds_ce, ci = a.lds_ci;
+    const int ps = pow2_at_least(ce > ci ? ce : ci);
+    const size_t cb = (step_lds_bytes_dev(ce, ci) + 15) & ~size_t(15);
+    const Lds L = carve(smem + g * cb, ce, ci, ps);
+    for (int q = threadIdx.x; q < 64; q += 64) acc_hist[q] = 0;
+    for (int q = t; q < XP_NCOUNT; q += W) acc_cnt[g][q] = 0;
+    for (int q = t; q < XP_NLEDGER; q += W) acc_led[g][q] = 0.0;
+    if (t == 0) {
+        acc_run[g] = -1;
+        acc_max[g] = 0;
+    }
+    __syncthreads();
+    auto flush = [&]() {
+        const int r = acc_run[g];
+        if (r >= 0) {
+            if (a.run_cnt)
+                for (int q = t; q < XP_NCOUNT; q += W)
+                    if (acc_cnt[g][q]) atomicAdd((unsigned long long*)&a.run_cnt[(size_t)r * XP_NCOUNT + q], acc_cnt[g][q]);
+            if (a.run_led)
+                for (int q = t; q < XP_NLEDGER; q += W)
+                    if (acc_led[g][q] != 0.0) atomicAdd(&a.run_led[(size_t)r * XP_NLEDGER + q], acc_led[g][q]);
+        }
+        for (int q = t; q < XP_NCOUNT; q += W) acc_cnt[g][q] = 0;
+        for (int q = t; q < XP_NLEDGER; q += W) acc_led[g][q] = 0.0;
+    };
+    const int nitems = a.cell_list ? *a.cell_list_count : a.n_cells;
+    for (int it = blockIdx.x; it * G < nitems; it += gridDim.x) {
+        const int item = it * G + g;
+        const int cell = item < nitems ? (a.cell_list ? a.cell_list[item] : item) : -1;
+        const bool done = step_cell<T>(a, cell, S[g], L);
+        T::sync();
+        if (done) {
+            const int run = a.cell_run[cell];
+            if (run != acc_run[g]) {
+                flush();
+                T::sync();
+                if (t == 0) acc_run[g] = run;
+            }
+            for (int q = t; q < XP_NCOUNT; q += W) acc_cnt[g][q] += (unsigned long long)S[g].cnt[q];
+            for (int q = t; q < XP_NLEDGER; q += W) acc_led[g][q] = acc_led[g][q] + S[g].led[q];
+            if (t == 0) {
+                const int n = S[g].ints[6];
+                if (n > acc_max[g]) acc_max[g] = n;
+                const int bk = (n + 15) / 16;
+                atomicAdd(&acc_hist[bk < 63 ? bk : 63], 1);
+            }
+        }
+        T::sync();
+    }
+    flush();
+    __syncthreads();
+    if (a.stats) {
+        if (t == 0 && acc_max[g] > 0) atomicMax(&a.stats[0], acc_max[g]);
+        if (threadIdx.x < 64 && acc_hist[threadIdx.x]) atomicAdd(&a.stats[4 + threadIdx.x], acc_hist[threadIdx.x]);
+    }
+}
+
 // Random permutation of slots 0..n-1: out[k] = slot of rank k when the slots
 // are sorted by (Philox word, slot); the word of slot i is word i % 4 of the
-// call (c0, c1, i / 4, c3).  One wave sorts up to 128 keys in registers;
-// larger cells use an LDS bitonic sort in sbuf (>= pow2(n) entries).  Out of
-// line: the step calls it four times.
-template <int B>
+// call (c0, c1, i / 4, c3).  A team of up to 64 lanes sorts in registers
+// (up to 2 keys per lane for a whole wave, 4 for a group); larger cells use an
+// LDS bitonic sort in sbuf (>= pow2(n) entries).  Out of line: the step calls
+// it four times.
+template <class T>
 __device__ __noinline__ void make_perm_fn(int n, uint32_t c0, uint32_t c1, uint32_t c3, uint32_t k0,
                                           uint32_t k1, int32_t* out, uint64_t* sbuf)
 {
-    const int tid = threadIdx.x;
-    if (B == 64 && n <= 128) {
+    constexpr int W = T::N;
+    const int tid = T::rank();
+    constexpr int KMAX = W == 64 ? 2 : 4;
+    if (W <= 64 && n <= KMAX * W) {
         auto run_k = [&](auto kk) {
             constexpr int K = decltype(kk)::value;
             uint64_t key[K];
 #pragma unroll
             for (int m = 0; m < K; ++m) {
-                const int i = tid + 64 * m;
+                const int i = tid + W * m;
                 key[m] = ~0ull;
                 if (i < n) {
                     const Words w = philox(c0, c1, (uint32_t)(i >> 2), c3, k0, k1);
@@ -206,20 +359,21 @@ __device__ __noinline__ void make_perm_fn(int n, uint32_t c0, uint32_t c1, uint3
                     key[m] = ((uint64_t)kw << 32) | (uint32_t)i;
                 }
             }
-            wave_bitonic<K>(key);
+            group_bitonic<W, K>(key);
 #pragma unroll
             for (int m = 0; m < K; ++m) {
-                const int r = tid + 64 * m;
+                const int r = tid + W * m;
                 if (r < n) out[r] = (int32_t)(uint32_t)key[m];
             }
         };
-        if (n <= 64) run_k(std::integral_constant<int, 1>{});
-        else run_k(std::integral_constant<int, 2>{});
-        __syncthreads();
+        if (n <= W) run_k(std::integral_constant<int, 1>{});
+        else if (KMAX == 2 || n <= 2 * W) run_k(std::integral_constant<int, 2>{});
+        else run_k(std::integral_constant<int, KMAX>{});
+        T::sync();
         return;
     }
     const int p = pow2_at_least(n);
-    for (int g = tid; 4 * g < n; g += B) {
+    for (int g = tid; 4 * g < n; g += W) {
         const Words w = philox(c0, c1, (uint32_t)g, c3, k0, k1);
         const uint32_t k4[4] = {w.x0, w.x1, w.x2, w.x3};
 #pragma unroll
@@ -228,19 +382,20 @@ __device__ __noinline__ void make_perm_fn(int n, uint32_t c0, uint32_t c1, uint3
             if (i < n) sbuf[i] = ((uint64_t)k4[q] << 32) | (uint32_t)i;
         }
     }
-    for (int i = n + tid; i < p; i += B) sbuf[i] = ~0ull;
-    __syncthreads();
-    bitonic_sort<B>(sbuf, p);
-    for (int k = tid; k < n; k += B) out[k] = (int32_t)(uint32_t)sbuf[k];
-    __syncthreads();
+    for (int i = n + tid; i < p; i += W) sbuf[i] = ~0ull;
+    T::sync();
+    bitonic_sort<W>(sbuf, p);
+    for (int k = tid; k < n; k += W) out[k] = (int32_t)(uint32_t)sbuf[k];
+    T::sync();
 }
 
 // Steps one cell; true when its new state was committed (the caller then adds
 // S.cnt / S.led to the run records and S.ints[6] holds its electron count).
-template <int B>
-__device__ bool step_cell(const StepArgs& a, int cell, CellShared& S, const Lds& L)
+template <class T>
+__device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, const Lds& L)
 {
-    const int tid = threadIdx.x;
+    constexpr int B = T::N;
+    const int tid = T::rank();
     if (cell < 0 || cell >= a.n_cells) return false;
     const int run = a.cell_run[cell];
     const xp_run* R = a.runs + run;
@@ -285,7 +440,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
         }
     };
     if (ni > ci) {
-        to_big();
+        defer();
         return false;
     }
     if (ne > ce || ne > ecap) {
@@ -319,8 +474,8 @@ __device__ bool step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
     for (int q = tid; q < XP_NCOUNT; q += B) S.cnt[q] = 0;
     for (int q = tid; q < XP_NLEDGER; q += B) S.led[q] = 0.0;
     for (int q = tid; q < XP_NMOM; q += B) S.mom[q] = 0.0;
-    if (tid < 8) S.ints[tid] = 0;
-    __syncthreads();
+    for (int q = tid; q < 8; q += B) S.ints[q] = 0;
+    T::sync();
 
     // ---------------- S0: moments and continuum lowering -----------------
     const double ebulk = R->e_bulk;
@@ -335,12 +490,12 @@ __device__ bool step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
             w_loc += w;
             if (kin(j) < ebulk) b_loc += w;
         }
-        if (we) *we = block_isum<B>(w_loc, S.ired);
-        wb = block_isum<B>(b_loc, S.ired);
-        ke = block_tree_sum<B>(n, [&](int j) {
+        if (we) *we = T::isum(w_loc, S);
+        wb = T::isum(b_loc, S);
+        ke = T::tree(n, [&](int j) {
             const double e = kin(j);
             return e < ebulk ? (double)L.ew[j] * e : 0.0;
-        }, S.red);
+        }, S);
     };
     auto ion_sums = [&](long long& sz, long long& sz2) {
         long long s1 = 0, s2 = 0;
@@ -349,8 +504,8 @@ __device__ bool step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
             s1 += z;
             s2 += z * z;
         }
-        sz = block_isum<B>(s1, S.ired);
-        sz2 = block_isum<B>(s2, S.ired);
+        sz = T::isum(s1, S);
+        sz2 = T::isum(s2, S);
     };
 
     long long we, wb, sz, sz2;
@@ -369,21 +524,21 @@ __device__ bool step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
     const double n_i = ((double)wi * w0) / vol;
     const double zbar = wi > 0 ? (double)sz / (double)wi : 0.0;
     const double zstar = sz > 0 ? (double)sz2 / (double)sz : 0.0;
-    if (tid < 13) S.mom[16 + tid] = ipd(R->ipd_model, tid, t_e, n_e, n_i, zbar, zstar);
-    if (tid == 13)
+    for (int z = tid; z < 13; z += B) S.mom[16 + z] = ipd(R->ipd_model, z, t_e, n_e, n_i, zbar, zstar);
+    if (tid == 13 % B)
         S.mom[10] = R->lnl_fixed > 0.0 ? R->lnl_fixed : coulomb_log(t_e, n_e, zbar);
     if (tid == 0) {
         S.mom[0] = (double)we; S.mom[1] = (double)wi; S.mom[2] = (double)sz;
         S.mom[3] = (double)sz2; S.mom[4] = ke; S.mom[5] = t_e; S.mom[6] = n_e;
         S.mom[7] = n_i; S.mom[8] = zbar; S.mom[9] = zstar;
     }
-    __syncthreads();
+    T::sync();
     const double* dE = S.mom + 16;
     const double lnl = S.mom[10];
 
     // ------------- random permutations: sort (Philox key, slot) ---------------
     auto make_perm = [&](uint32_t purpose, int n, int32_t* out) {
-        make_perm_fn<B>(n, step, lcell, purpose << 24, key0, key1, out, L.sbuf);
+        make_perm_fn<T>(n, step, lcell, purpose << 24, key0, key1, out, L.sbuf);
     };
 
     const double fe_ei = mi / (ME + mi);   // electron side of an e-i pair
@@ -462,7 +617,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
                                   step, lcell, idx, purpose << 24, key0, key1, S.cnt);
                 }
             }
-            __syncthreads();
+            T::sync();
         }
         if (tid == 0) {
             if (ion) {
@@ -496,16 +651,16 @@ __device__ bool step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
 #pragma unroll
             for (int q = 0; q < 5; ++q)
                 if (oc.s[q] > 0 && pp[q] < pmin) pmin = pp[q];
-            const double ssum = block_tree_sum<B>(ne0, [&](int j) {
+            const double ssum = T::tree(ne0, [&](int j) {
                 return lotz_leaf(L.evx[j], L.evy[j], L.evz[j], L.ew[j], oc.s, pp, lnp, pmin, tb);
-            }, S.red);
+            }, S);
             double p = ((ssum * w0) * dt) / vol;
             if (p > 1.0) {
                 p = 1.0;
                 if (tid == 0) S.cnt[XP_C_P_CLAMPED] += 1;
             }
             if (tid == 0) S.mom[12] = p;
-            const int nfired = block_ordered_select<B>(
+            const int nfired = T::select(
                 ni,
                 [&](int i) {
                     if (L.iz[i] >= 13 || !(p > 0.0)) return false;
@@ -516,20 +671,20 @@ __device__ bool step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
                     L.fwok[i] = 1;
                     return u32(d.x0) < p;
                 },
-                [&](int i, int pos) { L.list[pos] = i; }, S.sel);
+                [&](int i, int pos) { L.list[pos] = i; }, S);
             if (tid == 0) S.cnt[XP_C_ION_FIRED] += nfired;
-            __syncthreads();
+            T::sync();
             if (nfired > 0) {
                 long long ws_loc = 0;
                 for (int j = tid; j < ne0; j += B) ws_loc += L.ew[j];
-                const long long ws = block_isum<B>(ws_loc, S.ired);
-                const double ux = block_tree_sum<B>(ne0, [&](int j) { return (double)L.ew[j] * L.evx[j]; }, S.red) / (double)ws;
-                const double uy = block_tree_sum<B>(ne0, [&](int j) { return (double)L.ew[j] * L.evy[j]; }, S.red) / (double)ws;
-                const double uz = block_tree_sum<B>(ne0, [&](int j) { return (double)L.ew[j] * L.evz[j]; }, S.red) / (double)ws;
-                const double kth = block_tree_sum<B>(ne0, [&](int j) {
+                const long long ws = T::isum(ws_loc, S);
+                const double ux = T::tree(ne0, [&](int j) { return (double)L.ew[j] * L.evx[j]; }, S) / (double)ws;
+                const double uy = T::tree(ne0, [&](int j) { return (double)L.ew[j] * L.evy[j]; }, S) / (double)ws;
+                const double uz = T::tree(ne0, [&](int j) { return (double)L.ew[j] * L.evz[j]; }, S) / (double)ws;
+                const double kth = T::tree(ne0, [&](int j) {
                     const double dx = L.evx[j] - ux, dy = L.evy[j] - uy, dz = L.evz[j] - uz;
                     return (double)L.ew[j] * (HALF_ME_OVER_QE * ((dx * dx + dy * dy) + dz * dz));
-                }, S.red);
+                }, S);
                 if (tid == 0) {
                     S.mom[13] = kth;
                     double debit = 0.0;
@@ -561,7 +716,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
                     S.dbl[0] = debit;
                     S.ints[1] = acc;
                 }
-                __syncthreads();
+                T::sync();
                 if (S.ints[0] == 1) overflow = true;
                 if (S.ints[0] == 2) deferred = true;
                 const double debit = S.dbl[0];
@@ -576,7 +731,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
                     }
                 }
                 ne = ne0 + acc;
-                __syncthreads();
+                T::sync();
             }
         }
     }
@@ -600,7 +755,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
             long long nrec = (long long)floor(dd + 0.5);
             long long el = 0;
             for (int j = tid; j < ni; j += B) el += L.iz[j] > R->z_floor ? 1 : 0;
-            const long long nelig = block_isum<B>(el, S.ired);
+            const long long nelig = T::isum(el, S);
             if (nrec > nelig) nrec = nelig;
             if (nrec > ne) nrec = ne;
             if (nrec > 0) {
@@ -608,29 +763,29 @@ __device__ bool step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
                 make_perm(RP_REC_I, ni, L.perm_i);
                 make_perm(RP_REC_E, ne, L.perm_e);
                 const int zf = R->z_floor;
-                block_ordered_select<B>(
+                T::select(
                     ni, [&](int q) { return (int)L.iz[L.perm_i[q]] > zf; },
                     [&](int q, int pos) {
                         if (pos < nr) L.list[pos] = L.perm_i[q];
                     },
-                    S.sel);
+                    S);
                 for (int j = tid; j < ne; j += B) L.esel[j] = 0;
-                __syncthreads();
+                T::sync();
                 for (int t = tid; t < nr; t += B) L.esel[L.perm_e[t]] = 1;
-                __syncthreads();
+                T::sync();
                 auto wp = [&](int j) { return (long long)L.ew[j] - (long long)L.esel[j]; };
                 long long wsl = 0;
                 for (int j = tid; j < ne; j += B) wsl += wp(j);
-                const long long ws = block_isum<B>(wsl, S.ired);
+                const long long ws = T::isum(wsl, S);
                 double ux = 0.0, uy = 0.0, uz = 0.0, kth = 0.0;
                 if (ws != 0) {
-                    ux = block_tree_sum<B>(ne, [&](int j) { return (double)wp(j) * L.evx[j]; }, S.red) / (double)ws;
-                    uy = block_tree_sum<B>(ne, [&](int j) { return (double)wp(j) * L.evy[j]; }, S.red) / (double)ws;
-                    uz = block_tree_sum<B>(ne, [&](int j) { return (double)wp(j) * L.evz[j]; }, S.red) / (double)ws;
-                    kth = block_tree_sum<B>(ne, [&](int j) {
+                    ux = T::tree(ne, [&](int j) { return (double)wp(j) * L.evx[j]; }, S) / (double)ws;
+                    uy = T::tree(ne, [&](int j) { return (double)wp(j) * L.evy[j]; }, S) / (double)ws;
+                    uz = T::tree(ne, [&](int j) { return (double)wp(j) * L.evz[j]; }, S) / (double)ws;
+                    kth = T::tree(ne, [&](int j) {
                         const double dx = L.evx[j] - ux, dy = L.evy[j] - uy, dz = L.evz[j] - uz;
                         return (double)wp(j) * (HALF_ME_OVER_QE * ((dx * dx + dy * dy) + dz * dz));
-                    }, S.red);
+                    }, S);
                 }
                 if (ws == 0 || !(kth > 0.0)) {
                     if (tid == 0) S.cnt[XP_C_REC_SKIPPED] += 1;
@@ -666,7 +821,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
                         S.led[XP_L_REC_ADD] += eadd;
                         S.dbl[1] = eadd;
                     }
-                    __syncthreads();
+                    T::sync();
                     const double alpha = sqrt(1.0 + S.dbl[1] / kth);
                     for (int j = tid; j < ne; j += B) {
                         const long long w2 = wp(j);
@@ -677,7 +832,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
                         }
                         L.ew[j] = (uint32_t)(w2 > 0 ? w2 : 0);
                     }
-                    __syncthreads();
+                    T::sync();
                     // stable compaction of the electrons whose weight reached 0,
                     // chunk by chunk (positions only move down)
                     int out = 0;
@@ -692,23 +847,23 @@ __device__ bool step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
                             w = L.ew[j]; org = L.eorg[j];
                         }
                         int dst = 0;
-                        const int tot = block_ordered_select<B>(
+                        const int tot = T::select(
                             (c0 + B < ne ? B : ne - c0),
                             [&](int q) { return L.ew[c0 + q] > 0; },
-                            [&](int q, int pos) { (void)q; dst = pos; }, S.sel);
-                        __syncthreads();
+                            [&](int q, int pos) { (void)q; dst = pos; }, S);
+                        T::sync();
                         if (alive) {
                             const int d = out + dst;
                             L.evx[d] = vx; L.evy[d] = vy; L.evz[d] = vz;
                             L.ew[d] = w; L.eorg[d] = org;
                         }
                         out += tot;
-                        __syncthreads();
+                        T::sync();
                     }
                     if (tid == 0) S.cnt[XP_C_E_REMOVED] += ne - out;
                     ne = out;
                 }
-                __syncthreads();
+                T::sync();
             }
         }
     }
@@ -722,7 +877,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
         if (photo) {
             const double* rs = a.run_sig + (size_t)run * (XP_MAX_BINS * 3);
             for (int q = tid; q < 3 * nb; q += B) S.sig[q / 3][q % 3] = rs[q];
-            __syncthreads();
+            T::sync();
             for (int q = tid; q < 39; q += B) {
                 const int z = q / 3, s = q % 3;
                 const double pp = lowered(tb, z, s, dE);
@@ -731,7 +886,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
                     if (R->hv[bq] >= pp) acc = acc + nhv[bq] * S.sig[bq][s];
                 S.ssum[z][s] = acc;
             }
-            __syncthreads();
+            T::sync();
         }
         // pass 1: decisions per ion from its pre-S5 state
         for (int i = tid; i < ni; i += B) {
@@ -824,33 +979,16 @@ __device__ bool step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
             L.emask[i] = mask;
             L.ebins[i] = bins;
         }
-        __syncthreads();
+        T::sync();
         // pass 2: new electrons in ion-slot order (Auger, photo 1s, 2s, 2p)
         int base_pos = ne;
         for (int c0 = 0; c0 < ni; c0 += B) {
             const int i = c0 + tid;
             const int cnt = i < ni ? __popc((unsigned)L.emask[i]) : 0;
             // exclusive prefix of cnt over the chunk (slot order)
-            int incl = cnt;
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const int o = __shfl_up(incl, off, 64);
-                if ((tid & 63) >= off) incl += o;
-            }
-            if (B > 64) {
-                __syncthreads();
-                if ((tid & 63) == 63) S.sel[tid >> 6] = incl;
-                __syncthreads();
-            }
-            int woff = 0, tot = __shfl(incl, 63, 64);
-            if (B > 64) {
-                tot = 0;
-                for (int w = 0; w < B / 64; ++w) {
-                    if (w < (tid >> 6)) woff += S.sel[w];
-                    tot += S.sel[w];
-                }
-            }
-            int pos = base_pos + woff + incl - cnt;
+            int tot;
+            const int before = T::prefix(cnt, tot, S);
+            int pos = base_pos + before;
             if (cnt > 0) {
                 const int z0 = L.z0[i], k0 = L.k0[i];
                 const Occ o0 = occupancy(z0, k0);
@@ -890,13 +1028,13 @@ __device__ bool step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
                 }
             }
             base_pos += tot;
-            if (B > 64) __syncthreads();
+            T::sync();
         }
         if (tid == 0) S.cnt[XP_C_E_NEW] += base_pos - ne;
         if (base_pos > ecap) overflow = true;
         else if (base_pos > lim) deferred = true;
         ne = base_pos;
-        __syncthreads();
+        T::sync();
     }
 
     // ---------------- commit ----------------
@@ -925,7 +1063,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
         a.ik[io + j] = L.ik[j];
     }
     if (bad) atomicOr(a.status, XP_ST_NONFINITE);
-    __syncthreads();
+    T::sync();
     // positions of moved or new electrons: gather into LDS first, then write
     for (int j = tid; j < ne; j += B) {
         const int org = L.eorg[j];
@@ -939,7 +1077,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
             L.evy[j] = a.iy ? a.iy[io + i] : 0.0;
         }
     }
-    __syncthreads();
+    T::sync();
     for (int j = tid; j < ne; j += B) {
         if (L.eorg[j] == j) continue;
         a.ex[eo + j] = L.evx[j];
@@ -960,6 +1098,9 @@ __device__ bool step_cell(const StepArgs& a, int cell, CellShared& S, const Lds&
 
 template __global__ void k_step<64>(StepArgs);
 template __global__ void k_step<256>(StepArgs);
+template __global__ void k_step_g<32>(StepArgs);
+template __global__ void k_step_g<16>(StepArgs);
+template __global__ void k_step_g<8>(StepArgs);
 
 __global__ void k_step_prep(int32_t* counts, int32_t* stats)
 {

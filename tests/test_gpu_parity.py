@@ -157,16 +157,41 @@ def test_c3_strip_parity(ctx):
 
 
 def test_schedule_invariance(ctx):
-    spec, parts = W.config_c2(nx=8, ny=8)
-    outs = []
-    for sched in (1, 2):
-        bat = RT.Batch(ctx, [(spec, parts)])
-        for s in range(15):
-            bat.step(s, O.ALL, schedule=sched)
-        st = bat.state()
-        outs.append(st)
-    for f in ("evx", "evy", "evz", "ew", "iz", "ik", "ivx", "e_start"):
-        assert np.array_equal(getattr(outs[0], f), getattr(outs[1], f)), f
+    # one wave per cell, one block per cell, and 2, 4, 8 cells per wave give
+    # the same bits (the uneven strip exercises the small-cell groups)
+    for spec, parts in (W.config_c2(nx=8, ny=8), W.config_c3(nx=64, ny=2)):
+        outs = []
+        for sched in (1, 2, 4, 5, 6):
+            bat = RT.Batch(ctx, [(spec, parts)])
+            for s in range(12):
+                bat.step(s, O.ALL, schedule=sched)
+            torch.cuda.synchronize()
+            assert bat.status() == 0
+            outs.append(bat.state())
+        for k in range(1, len(outs)):
+            for f in ("evx", "evy", "evz", "ew", "iz", "ik", "ivx", "e_start", "ex"):
+                assert np.array_equal(getattr(outs[0], f), getattr(outs[k], f)), (k, f)
+        say("schedules agree on %d cells" % spec.ncells)
+
+
+@pytest.mark.parametrize("sched", [4, 5, 6])
+def test_group_schedules_match_oracle(ctx, sched):
+    # slabs of at most 32 electron and 16 ion slots, so that even groups of
+    # 8 lanes take every cell (the oracle keeps these cells within 32
+    # electrons over the 10 steps)
+    rng = np.random.default_rng(5)
+    ne = np.array([0, 1, 2, 3, 0, 5, 7, 1, 0, 12, 11, 9, 4, 6, 2, 8])
+    ni = np.array([0, 0, 1, 1, 3, 2, 5, 1, 1, 5, 1, 3, 5, 4, 5, 2])
+    spec, parts = cases.one_run(ne.size, ne, ni, 200.0, 1.0, seed=88, lnl=3.0,
+                                photon_hv=(1800.0,), photon_n=(3e30,))
+    parts.iz[:] = rng.integers(3, 14, parts.ni)
+    parts.ik[:] = np.where(parts.iz < 12, rng.integers(0, 2, parts.ni), 0)
+    parts.ew[:] = rng.choice([1, 2, 3], parts.ne)
+    run_pair(ctx, spec, parts, 10, check_every=1, label="groups/%d" % sched, schedule=sched,
+             capacity=(3, 4))
+    spec, parts = W.config_c3(nx=48, ny=3)
+    run_pair(ctx, spec, parts, 10, check_every=5, label="C3s/%d" % sched, schedule=sched,
+             capacity=(1, 16))
 
 
 def test_photo_auger_step_alone(ctx):
@@ -198,6 +223,16 @@ def test_edge_cells(ctx):
     parts.ik[:] = np.where(parts.iz < 12, rng.integers(0, 2, parts.ni), 0)
     parts.ew[:] = rng.choice([1, 2, 3], parts.ne)
     run_pair(ctx, spec, parts, 12, check_every=1, label="edge")
+
+
+def test_ion_heavy_cells(ctx):
+    # far more ions than electrons: small plans defer these cells for their
+    # ions, and the last plan takes them
+    ne = np.array([1, 2, 0, 3, 4, 64, 9, 0])
+    ni = np.array([100, 60, 70, 5, 47, 2, 130, 1])
+    spec, parts = cases.one_run(ne.size, ne, ni, 100.0, 1.0, seed=61, lnl=3.0)
+    bat, _ = run_pair(ctx, spec, parts, 6, check_every=1, label="ion-heavy")
+    assert bat.stats()[1] > 0
 
 
 def test_diagnostics_match_oracle(ctx):
