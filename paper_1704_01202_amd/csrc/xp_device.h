@@ -202,10 +202,70 @@ __device__ __forceinline__ int ilog2_ceil(int n)
     return b;
 }
 
+// Cross-lane moves within a wave on the VALU (DPP): CTRL is the dpp_ctrl code
+// (quad permutations 0x00-0xff, row shifts 0x101-0x11f, row mirror 0x140,
+// half-row mirror 0x141).  Every source lane used here lies inside the row.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
+}
+// As dpp32, with 0 in lanes whose source lies outside the row.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32z(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, true);
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v)
+{
+    const uint32_t lo = dpp32<CTRL>((uint32_t)v), hi = dpp32<CTRL>((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) { return bits_to_f64(dpp64<CTRL>(f64_to_bits(v))); }
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Canonical pairwise sum of the 64 lanes' values (lane = leaf), returned to
+// every lane.  Levels 1 and 2 pair lane l with l ^ 1 and l ^ 2; after them
+// every aligned block of 4 lanes holds its node, so the mirror within a half
+// row (8 lanes) and within a row (16 lanes) meet the sibling node exactly as
+// l ^ 4 and l ^ 8 would.  The four row sums are then added as
+// (r0 + r1) + (r2 + r3).  Addition is commutative in IEEE-754, so every lane
+// holds the same bits as the tree evaluated in slot order.
+__device__ __forceinline__ double wave_tree_sum64(double acc)
+{
+    acc = acc + dpp_f64<0xb1>(acc);     // quad_perm [1,0,3,2]: lane ^ 1
+    acc = acc + dpp_f64<0x4e>(acc);     // quad_perm [2,3,0,1]: lane ^ 2
+    acc = acc + dpp_f64<0x141>(acc);    // half-row mirror: the other block of 4
+    acc = acc + dpp_f64<0x140>(acc);    // row mirror: the other block of 8
+    const uint64_t b = f64_to_bits(acc);
+    const double r0 = bits_to_f64(readlane64(b, 0)), r1 = bits_to_f64(readlane64(b, 16));
+    const double r2 = bits_to_f64(readlane64(b, 32)), r3 = bits_to_f64(readlane64(b, 48));
+    return (r0 + r1) + (r2 + r3);
+}
+
+// Sum of the 64 lanes' integers (any order), returned to every lane.
+__device__ __forceinline__ long long wave_isum64(long long v)
+{
+    v += (long long)dpp64<0xb1>((uint64_t)v);
+    v += (long long)dpp64<0x4e>((uint64_t)v);
+    v += (long long)dpp64<0x141>((uint64_t)v);
+    v += (long long)dpp64<0x140>((uint64_t)v);
+    const uint64_t b = (uint64_t)v;
+    return (long long)(readlane64(b, 0) + readlane64(b, 16) + readlane64(b, 32) + readlane64(b, 48));
+}
+
 // Canonical pairwise sum of n leaves produced by leaf(j), over a block of B
 // threads (B a multiple of 64).  Leaves are padded with +0 to P = 2^k.  Rows of
 // 64 consecutive leaves are owned by waves (lane = leaf mod 64): each row is
-// reduced by shuffles, which is levels 1..6 of the tree; the row sums (the
+// reduced across lanes (wave_tree_sum64), which is levels 1..6 of the tree; the row sums (the
 // level-6 nodes) are then reduced pairwise in LDS, out of place, level by
 // level.  For P < 64 the row is padded with zeros, which adds only +0 above
 // the root.  red must hold 2 * max(1, P/64) doubles; the result (+0.0) is
@@ -221,10 +281,9 @@ __device__ double block_tree_sum(int n, F leaf, double* red)
         double acc = 0.0;
         if (wid == 0) {
             acc = lane < n ? leaf(lane) : 0.0;
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) acc = acc + __shfl_down(acc, off, 64);
+            acc = wave_tree_sum64(acc);
         }
-        if (B == 64) return __shfl(acc, 0, 64) + 0.0;
+        if (B == 64) return acc + 0.0;
         __syncthreads();
         if (threadIdx.x == 0) red[0] = acc;
         __syncthreads();
@@ -235,8 +294,7 @@ __device__ double block_tree_sum(int n, F leaf, double* red)
     for (int r = wid; r < rows; r += B / 64) {
         const int j = (r << 6) + lane;
         double acc = j < n ? leaf(j) : 0.0;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) acc = acc + __shfl_down(acc, off, 64);
+        acc = wave_tree_sum64(acc);
         if (lane == 0) red[r] = acc;
     }
     __syncthreads();
@@ -259,8 +317,7 @@ __device__ double block_tree_sum(int n, F leaf, double* red)
 template <int B>
 __device__ long long block_isum(long long v, long long* red)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    v = wave_isum64(v);
     if (B == 64) return v;
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
@@ -315,13 +372,26 @@ __device__ T block_exclusive_sum(T v, T* red, T& total)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     T incl = v;
+    if constexpr (sizeof(T) == 4) {
+        // inclusive scan on the VALU: shifts by 1, 2, 4, 8 within rows of 16
+        // (lanes whose source lies before the row read 0), then the last lane
+        // of row 0 into row 1 and of row 2 into row 3, then lane 31 into rows 2, 3
+        incl += (T)dpp32z<0x111>((uint32_t)incl);
+        incl += (T)dpp32z<0x112>((uint32_t)incl);
+        incl += (T)dpp32z<0x114>((uint32_t)incl);
+        incl += (T)dpp32z<0x118>((uint32_t)incl);
+        incl += (T)__builtin_amdgcn_update_dpp(0, (int)incl, 0x142, 0xa, 0xf, false);
+        incl += (T)__builtin_amdgcn_update_dpp(0, (int)incl, 0x143, 0xc, 0xf, false);
+    } else {
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const T o = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += o;
+        for (int off = 1; off < 64; off <<= 1) {
+            const T o = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += o;
+        }
     }
     if (B == 64) {
-        total = __shfl(incl, 63, 64);
+        if constexpr (sizeof(T) == 4) total = (T)__builtin_amdgcn_readlane((int)incl, 63);
+        else total = __shfl(incl, 63, 64);
         return incl - v;
     }
     __syncthreads();
@@ -366,6 +436,23 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// The value of lane ^ j: strides 1 and 2 by quad permutations, 4 and 8 by
+// row shifts (the partner lies in the same row of 16), 16 and 32 by shuffles.
+__device__ __forceinline__ uint64_t xor_lane_u64(uint64_t v, int j, int lane)
+{
+    if (j == 1) return dpp64<0xb1>(v);
+    if (j == 2) return dpp64<0x4e>(v);
+    if (j == 4) {
+        const uint64_t dn = dpp64<0x114>(v), up = dpp64<0x104>(v);   // lane - 4, lane + 4
+        return (lane & 4) ? dn : up;
+    }
+    if (j == 8) {
+        const uint64_t dn = dpp64<0x118>(v), up = dpp64<0x108>(v);   // lane - 8, lane + 8
+        return (lane & 8) ? dn : up;
+    }
+    return shfl_xor_u64(v, j);
+}
+
 // Bitonic sort of P = 64 K keys held by one wave in registers: element
 // e = lane + 64 m is key[m].  Strides below 64 exchange across lanes with
 // shuffles, larger strides exchange between a lane's own registers.
@@ -393,7 +480,7 @@ __device__ __forceinline__ void wave_bitonic(uint64_t (&key)[K])
 #pragma unroll
                 for (int m = 0; m < K; ++m) {
                     const int e = lane + 64 * m;
-                    const uint64_t o = shfl_xor_u64(key[m], j);
+                    const uint64_t o = xor_lane_u64(key[m], j, lane);
                     const bool up = (e & k) == 0;
                     const bool lower = (lane & j) == 0;
                     // the lower element of an ascending pair keeps the minimum
