@@ -438,6 +438,7 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m)
 
 // The value of lane ^ j: strides 1 and 2 by quad permutations, 4 and 8 by
 // row shifts (the partner lies in the same row of 16), 16 and 32 by shuffles.
+// lane: the lane index or any index with the same low four bits.
 __device__ __forceinline__ uint64_t xor_lane_u64(uint64_t v, int j, int lane)
 {
     if (j == 1) return dpp64<0xb1>(v);
@@ -452,47 +453,6 @@ __device__ __forceinline__ uint64_t xor_lane_u64(uint64_t v, int j, int lane)
     }
     return shfl_xor_u64(v, j);
 }
-
-// Bitonic sort of P = 64 K keys held by one wave in registers: element
-// e = lane + 64 m is key[m].  Strides below 64 exchange across lanes with
-// shuffles, larger strides exchange between a lane's own registers.
-template <int K>
-__device__ __forceinline__ void wave_bitonic(uint64_t (&key)[K])
-{
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int k = 2; k <= 64 * K; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            if (j >= 64) {
-                const int mj = j >> 6;
-#pragma unroll
-                for (int m = 0; m < K; ++m) {
-                    if (m & mj) continue;
-                    const int e = lane + 64 * m;
-                    const bool up = (e & k) == 0;
-                    const uint64_t x = key[m], y = key[m | mj];
-                    const bool sw = up ? (x > y) : (x < y);
-                    key[m] = sw ? y : x;
-                    key[m | mj] = sw ? x : y;
-                }
-            } else {
-#pragma unroll
-                for (int m = 0; m < K; ++m) {
-                    const int e = lane + 64 * m;
-                    const uint64_t o = xor_lane_u64(key[m], j, lane);
-                    const bool up = (e & k) == 0;
-                    const bool lower = (lane & j) == 0;
-                    // the lower element of an ascending pair keeps the minimum
-                    const bool take_min = lower == up;
-                    const bool less = o < key[m];
-                    key[m] = (take_min == less) ? o : key[m];
-                }
-            }
-        }
-    }
-}
-
 
 __device__ __forceinline__ uint64_t shfl_xor_u64w(uint64_t v, int m, int width)
 {
@@ -529,7 +489,7 @@ __device__ __forceinline__ void group_bitonic(uint64_t (&key)[K])
 #pragma unroll
                 for (int m = 0; m < K; ++m) {
                     const int e = t + W * m;
-                    const uint64_t o = shfl_xor_u64w(key[m], j, W);
+                    const uint64_t o = j <= 8 ? xor_lane_u64(key[m], j, t) : shfl_xor_u64w(key[m], j, W);
                     const bool up = (e & k) == 0;
                     const bool lower = (t & j) == 0;
                     const bool take_min = lower == up;
