@@ -107,6 +107,26 @@ def measured_traffic():
     return float(b.group(1))
 
 
+SQ_PROFILE = os.path.join(ROOT, "profiles", "k_step_c2_512x512_sq_counters.md")
+# VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per 4 cycles
+VALU_PEAK = 256 * 4 * 2.4e9 / 4
+
+
+def measured_valu():
+    """VALU wave-instructions per tier-0 k_step launch from the committed SQ
+    counter summary, or None when it is missing or was taken on other sources."""
+    try:
+        with open(SQ_PROFILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    m = re.search(r"^source_digest:\s*(\w+)", text, re.M)
+    b = re.search(r"^valu_insts_per_launch:\s*([0-9.eE+]+)", text, re.M)
+    if not m or not b or m.group(1) != source_digest():
+        return None
+    return float(b.group(1))
+
+
 def copy_reference(mib):
     """A plain device-to-device copy of known size (mib MiB read, mib MiB
     written), three times: the reference the HBM counters are scaled by."""
@@ -461,6 +481,14 @@ def main():
                      "bytes_per_launch": bytes_total / args.steps},
         "collisions_total": coll,
     }
+    valu = measured_valu()
+    if valu is not None and args.nx == 512 and args.ny == 512:
+        # the step is bound by instruction issue, not by HBM: VALU instructions
+        # of a launch (profiled) over the launch time measured here
+        rate = valu / (avg_ms * 1e-3)
+        out["valu_issue"] = {"bound": "alu", "achieved": rate, "peak": VALU_PEAK,
+                             "unit": "wave-instructions/s", "frac": rate / VALU_PEAK,
+                             "insts_per_launch": valu}
     if args.copy_ref > 0:
         copy_reference(args.copy_ref)
     if not args.no_cpu:
