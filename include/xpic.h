@@ -323,6 +323,11 @@ xp_status diagnostics(xp_ctx *ctx, const xp_batch *b, xp_diag *d_out, uint32_t w
  *   which 3 sin, cos of 2 pi (d_u[i] + 1/2) / 2^52       -> d_out[2i], d_out[2i+1]
  *   which 4 Philox4x32-10 of counter/key words packed as six uint32 in
  *         d_u[3i .. 3i+2] (c0 c1 c2 c3 k0 k1)             -> d_words[4i .. 4i+3]
+ *   which 7, 8, 9 the canonical pairwise sum (leaves padded with +0 to a power
+ *         of two, summed level by level, + 0.0) of the first m_j = (37 j) % R + 1
+ *         values of row j of d_x (rows of R values, n a multiple of R) -> d_out[j]:
+ *         7 one wave per row (R = 64), 8 one block of 256 per row (R = 256),
+ *         9 groups of 16 lanes, one row each (R = 64).
  * Device arrays are caller-owned; unused ones may be NULL. */
 xp_status xp_selftest(xp_ctx *ctx, int32_t which, int64_t n, const double *d_x,
                       const uint64_t *d_u, double *d_out, uint32_t *d_words, void *stream);

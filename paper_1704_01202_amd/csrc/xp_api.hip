@@ -487,7 +487,11 @@ xp_status xp_selftest(xp_ctx* ctx, int32_t which, int64_t n, const double* d_x, 
                       double* d_out, uint32_t* d_words, void* stream)
 {
     if (!ctx) return fail(XP_ERR_INVALID_ARG, "null context");
-    if (which < 0 || which > 6 || n < 0) return fail(XP_ERR_INVALID_ARG, "unknown self-test");
+    if (which < 0 || which > 9 || n < 0) return fail(XP_ERR_INVALID_ARG, "unknown self-test");
+    if (which == 7 && n % 64 != 0) return fail(XP_ERR_INVALID_ARG, "tree self-test needs rows of 64");
+    if (which == 8 && n % 256 != 0) return fail(XP_ERR_INVALID_ARG, "tree self-test needs rows of 256");
+    if (which == 9 && n % 64 != 0) return fail(XP_ERR_INVALID_ARG, "tree self-test needs rows of 64");
+    if (which >= 7 && n / 64 > 0x7fffffff) return fail(XP_ERR_INVALID_ARG, "too many rows");
     const bool need_x = which <= 2 || which >= 5;
     if ((need_x && !d_x) || ((which == 3 || which == 4) && !d_u) || (which != 4 && !d_out) ||
         (which == 4 && !d_words))

@@ -164,14 +164,48 @@ __global__ void k_selftest(int which, int64_t n, const double* x, const uint64_t
     }
 }
 
+// Canonical sums of the first m_j leaves of row j (rows of R values of x): a
+// block of B threads per row, or (G > 1) G lane groups of 64 / G lanes per
+// wave, one row each.  m_j = (j * 37) % R + 1 exercises the padding.
+template <int B, int R>
+__global__ __launch_bounds__(B) void k_selftest_tree(int64_t rows, const double* x, double* out)
+{
+    __shared__ double red[2 * (R / 64 > 1 ? R / 64 : 1)];
+    const int64_t j = blockIdx.x;
+    if (j >= rows) return;
+    const int m = (int)((j * 37) % R) + 1;
+    const double* row = x + j * R;
+    const double t = block_tree_sum<B>(m, [&](int k) { return row[k]; }, red);
+    if (threadIdx.x == 0) out[j] = t;
+}
+
+template <int W>
+__global__ __launch_bounds__(64) void k_selftest_group_tree(int64_t rows, const double* x, double* out)
+{
+    const int64_t j = (int64_t)blockIdx.x * (64 / W) + threadIdx.x / W;
+    const int m = (int)((j * 37) % (4 * W)) + 1;
+    const double* row = x + (j < rows ? j : 0) * (4 * W);
+    const double t = group_tree_sum<W>(m, [&](int k) { return row[k]; });
+    if ((threadIdx.x & (W - 1)) == 0 && j < rows) out[j] = t;
+}
+
 }  // namespace
 
 hipError_t selftest_launch(int which, int64_t n, const double* x, const uint64_t* u, double* out,
                            uint32_t* words, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_selftest, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, which, n, x, u,
-                       out, words);
+    if (which == 7) {
+        hipLaunchKernelGGL((k_selftest_tree<64, 64>), dim3((unsigned)(n / 64)), dim3(64), 0, s, n / 64, x, out);
+    } else if (which == 8) {
+        hipLaunchKernelGGL((k_selftest_tree<256, 256>), dim3((unsigned)(n / 256)), dim3(256), 0, s, n / 256, x, out);
+    } else if (which == 9) {
+        const int64_t rows = n / 64;   // groups of 16 lanes, 64 leaves per row
+        hipLaunchKernelGGL(k_selftest_group_tree<16>, dim3((unsigned)((rows + 3) / 4)), dim3(64), 0, s, rows, x, out);
+    } else {
+        hipLaunchKernelGGL(k_selftest, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, which, n, x, u,
+                           out, words);
+    }
     return hipGetLastError();
 }
 

@@ -64,6 +64,17 @@ def compare(gs, os_, label, vtol=1e-12):
     return worst, nbits
 
 
+def canonical_sum(leaves):
+    """Pairwise sum, leaves padded with +0 to a power of two, level by level, + 0.0."""
+    p = 1
+    while p < len(leaves):
+        p <<= 1
+    v = list(leaves) + [0.0] * (p - len(leaves))
+    while len(v) > 1:
+        v = [v[2 * i] + v[2 * i + 1] for i in range(len(v) // 2)]
+    return v[0] + 0.0
+
+
 def run_pair(ctx, spec, parts, steps, flags=O.ALL, schedule=0, capacity=(7, 16),
              check_every=1, label="", big="auto"):
     tab = ctx.tables
@@ -108,6 +119,26 @@ def test_device_building_blocks(ctx):
     # sqrt and division are IEEE correctly rounded on both sides
     B.xp_selftest(ctx.h, 5, n, dx.data_ptr(), None, out.data_ptr(), None, RT._stream())
     assert np.array_equal(out.cpu().numpy(), np.sqrt(xs))
+    # canonical tree sums (one wave, a block of 256, groups of 16 lanes) on
+    # values of mixed sign and magnitude, where the order of the additions
+    # shows in the bits
+    for which, r, rows in ((7, 64, 400), (8, 256, 120), (9, 64, 400)):
+        v = rng.choice([-1.0, 1.0], rows * r) * 10.0 ** rng.uniform(-18, 18, rows * r)
+        dv = torch.from_numpy(v).to(dev)
+        o = torch.empty(rows, dtype=torch.float64, device=dev)
+        B.xp_selftest(ctx.h, which, v.size, dv.data_ptr(), None, o.data_ptr(), None, RT._stream())
+        got = o.cpu().numpy()
+        want, seq_differs = [], 0
+        for j in range(rows):
+            leaves = [float(t) for t in v[j * r: j * r + (j * 37) % r + 1]]
+            want.append(canonical_sum(leaves))
+            acc = 0.0
+            for t in leaves:
+                acc += t
+            seq_differs += acc != want[-1]
+        assert seq_differs > rows // 10, "the values do not tell summation orders apart"
+        assert np.array_equal(got, np.array(want)), "tree self-test %d" % which
+        say("tree self-test %d ok (%d of %d rows differ from the sequential sum)" % (which, seq_differs, rows))
     pairs = np.exp(rng.uniform(-300, 300, 2 * n))
     dp = torch.from_numpy(pairs).to(dev)
     B.xp_selftest(ctx.h, 6, n, dp.data_ptr(), None, out.data_ptr(), None, RT._stream())
