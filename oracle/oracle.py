@@ -25,12 +25,14 @@ NMOM = 32
 
 EE, EI, ION, REC, PHOTO, DECAY = 0x01, 0x02, 0x04, 0x08, 0x10, 0x20
 ALL = EE | EI | ION | REC | PHOTO | DECAY
+THERM = 0x40   # variant: forced thermalization after S5 (Sec. VI.C), not in ALL
 
 COUNTERS = ["EE", "EI", "TRIPLET", "ACCEPT", "U0", "DELTA2_GT1",
             "ION_FIRED", "ION_ACCEPTED", "ION_STARVED",
             "REC", "REC_SKIPPED", "E_REMOVED",
             "PHOTO_1S", "PHOTO_2S", "PHOTO_2P", "PHOTO_SKIPPED",
-            "DECAY", "AUGER", "KALPHA", "P_CLAMPED", "IPD_CLAMPED", "E_NEW"]
+            "DECAY", "AUGER", "KALPHA", "P_CLAMPED", "IPD_CLAMPED", "E_NEW",
+            "THERM", "THERM_SKIPPED"]
 NCOUNT = 24
 LEDGER = ["PHOTO_E", "AUGER_E", "ION_DEBIT", "REC_ADD", "REC_BIND", "KALPHA",
           "PHOTON_ABS"]

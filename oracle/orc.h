@@ -40,6 +40,7 @@ extern "C" {
 #define ORC_REC     0x08u
 #define ORC_PHOTO   0x10u
 #define ORC_DECAY   0x20u
+#define ORC_THERM   0x40u   /* variant: forced thermalization after S5 (Sec. VI.C) */
 
 /* Per-cell, per-step event counters. */
 enum {
@@ -49,6 +50,7 @@ enum {
     OC_PHOTO_1S, OC_PHOTO_2S, OC_PHOTO_2P, OC_PHOTO_SKIPPED,
     OC_DECAY, OC_AUGER, OC_KALPHA,
     OC_P_CLAMPED, OC_IPD_CLAMPED, OC_E_NEW,
+    OC_THERM, OC_THERM_SKIPPED,
     OC_NCOUNT = 24
 };
 

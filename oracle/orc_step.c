@@ -11,6 +11,9 @@
  *   S4 three-body recombination constrained by Zbar_EOS(n_i, T_e) (Sec. IV).
  *   S5 K-vacancy decay with Auger / K-alpha branching and subshell
  *      photoionization (Eq. 3) (Sec. III).
+ *   Optionally (ORC_THERM) the forced thermalization of Sec. VI.C right after
+ *      S5: every free electron gets a new Maxwellian velocity at the cell
+ *      temperature, corrected so that momentum and energy are unchanged.
  * Every random decision uses Philox4x32-10 keyed by the run seed with counter
  * (step, cell, index, purpose << 24 | sub): a uniform r in (0, 1) decides an
  * event with probability P iff r < P (Sec. III).
@@ -29,7 +32,8 @@
 /* Random-number purposes.  P_ION is one call per ion and step whose four
  * words decide collisional ionization and the photo events of 1s, 2s, 2p. */
 enum { P_PERM_E = 1, P_PERM_I = 2, P_REC_I = 3, P_REC_E = 4, P_EE = 5,
-       P_EE_TRI = 6, P_EI = 7, P_ION = 8, P_DECAY = 9, P_DIR = 10, P_BIN = 11 };
+       P_EE_TRI = 6, P_EI = 7, P_ION = 8, P_DECAY = 9, P_DIR = 10, P_BIN = 11,
+       P_THERM = 12 };
 
 #define NMOM 32
 
@@ -389,6 +393,80 @@ static void new_electron_dir(const cctx *x, ocell *c, int ion, uint32_t sub, dou
     x->cnt[OC_E_NEW]++;
 }
 
+/* Forced thermalization (Sec. VI.C).  T from the average kinetic energy of
+ * all free electrons, k T = (2/3) K / W (Sec. II); each electron's velocity
+ * components are drawn from a normal distribution of zero mean and spread
+ * sqrt(k T / m_e) (one Philox call per electron slot: Box-Muller on words 0, 1
+ * gives the x and y components, on words 2, 3 the z component).  The draw's
+ * mean velocity is replaced by the cell's drift velocity u and its spread
+ * about it scaled by beta = sqrt(K_th / K_draw), where K_th is the cell's
+ * kinetic energy in the drift frame before, so momentum and energy are those
+ * of the cell before (the correction the paper asks for).  Cells with fewer
+ * than two electrons or no energy in the drift frame keep their velocities. */
+static void thermalize(cctx *x, ocell *c)
+{
+    int ne = c->ne;
+    double *y = x->scratch;
+    int64_t ws = 0;
+    for (int j = 0; j < ne; ++j) ws += c->ew[j];
+    if (ne < 2 || ws <= 0) { x->cnt[OC_THERM_SKIPPED]++; return; }
+    double w = (double)ws;
+    for (int j = 0; j < ne; ++j) y[j] = (double)c->ew[j] * e_kin(c, j);
+    double kin = tree_sum(y, ne);
+    double u[3];
+    double *vv[3] = {c->evx, c->evy, c->evz};
+    for (int d = 0; d < 3; ++d) {
+        for (int j = 0; j < ne; ++j) y[j] = (double)c->ew[j] * vv[d][j];
+        u[d] = tree_sum(y, ne) / w;
+    }
+    for (int j = 0; j < ne; ++j) {
+        double dx = c->evx[j] - u[0], dy = c->evy[j] - u[1], dz = c->evz[j] - u[2];
+        y[j] = (double)c->ew[j] * (HALF_ME_OVER_QE * ((dx * dx + dy * dy) + dz * dz));
+    }
+    double kth = tree_sum(y, ne);
+    if (!(kin > 0.0) || !(kth > 0.0)) { x->cnt[OC_THERM_SKIPPED]++; return; }
+    double kt = (2.0 * kin) / (3.0 * w);
+    double sig = sqrt(kt * (ORC_QE / ORC_ME));
+    /* the draws replace the velocities (the originals are no longer needed) */
+    for (int j = 0; j < ne; ++j) {
+        uint32_t d[4];
+        rng(x, (uint32_t)j, P_THERM, 0, d);
+        double s1, c1, s2, c2;
+        orc_sincos2pi(((uint64_t)d[1]) << 20, &s1, &c1);
+        orc_sincos2pi(((uint64_t)d[3]) << 20, &s2, &c2);
+        double r1 = sqrt(-2.0 * orc_log(orc_u32(d[0])));
+        double r2 = sqrt(-2.0 * orc_log(orc_u32(d[2])));
+        c->evx[j] = sig * (r1 * c1);
+        c->evy[j] = sig * (r1 * s1);
+        c->evz[j] = sig * (r2 * c2);
+    }
+    double q[3];
+    for (int d = 0; d < 3; ++d) {
+        for (int j = 0; j < ne; ++j) y[j] = (double)c->ew[j] * vv[d][j];
+        q[d] = tree_sum(y, ne) / w;
+    }
+    for (int j = 0; j < ne; ++j) {
+        c->evx[j] = c->evx[j] - q[0];
+        c->evy[j] = c->evy[j] - q[1];
+        c->evz[j] = c->evz[j] - q[2];
+    }
+    for (int j = 0; j < ne; ++j) y[j] = (double)c->ew[j] * e_kin(c, j);
+    double kd = tree_sum(y, ne);
+    if (!(kd > 0.0)) {
+        /* only if every draw coincides: every electron gets the drift velocity */
+        for (int j = 0; j < ne; ++j) { c->evx[j] = u[0]; c->evy[j] = u[1]; c->evz[j] = u[2]; }
+        x->cnt[OC_THERM_SKIPPED]++;
+        return;
+    }
+    double beta = sqrt(kth / kd);
+    for (int j = 0; j < ne; ++j) {
+        c->evx[j] = u[0] + beta * c->evx[j];
+        c->evy[j] = u[1] + beta * c->evy[j];
+        c->evz[j] = u[2] + beta * c->evz[j];
+    }
+    x->cnt[OC_THERM]++;
+}
+
 static void step_cell(cctx *x, ocell *c, uint32_t flags)
 {
     const orc_sim *s = x->s;
@@ -711,6 +789,7 @@ static void step_cell(cctx *x, ocell *c, uint32_t flags)
             c->ik[i] = (uint8_t)kv;
         }
     }
+    if (flags & ORC_THERM) thermalize(x, c);
 }
 
 void orc_step(orc_sim *s, uint32_t step, uint32_t flags, int32_t nthreads)
