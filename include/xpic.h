@@ -43,7 +43,8 @@ typedef int32_t xp_status;
 #define XP_ERR_UNSUPPORTED     -5   /* size beyond what this build supports */
 
 /* Stage switches (xp_step_params.flags).  Order within a step is always
- * moments -> e-e -> e-i -> ionization -> recombination -> decay/photo. */
+ * moments -> e-e -> e-i -> ionization -> recombination -> decay/photo
+ * [-> forced thermalization]. */
 #define XP_EE      0x01u   /* electron-electron binary collisions (Sec. IV) */
 #define XP_EI      0x02u   /* electron-ion binary collisions (Sec. IV) */
 #define XP_ION     0x04u   /* collisional ionization, Lotz (Sec. IV, Eq. 4) */
@@ -51,6 +52,15 @@ typedef int32_t xp_status;
 #define XP_PHOTO   0x10u   /* subshell photoionization (Sec. III, Eq. 3) */
 #define XP_DECAY   0x20u   /* K-vacancy decay, KLL Auger or K-alpha (Sec. III) */
 #define XP_ALL     0x3Fu
+/* Variant, not part of XP_ALL: forced thermalization right after S5 (Sec. VI.C).
+ * Every free electron of a cell gets a Maxwellian velocity at the cell
+ * temperature kT = (2/3) E_ave of all free electrons; the draws' mean is
+ * replaced by the cell's drift velocity and their spread scaled to the cell's
+ * drift-frame energy before, so momentum and energy are unchanged.  One
+ * Philox call per electron slot (purpose 12): Box-Muller on words 0, 1 gives
+ * the x and y components, on words 2, 3 the z component.  Cells with fewer
+ * than two electrons or no drift-frame energy keep their velocities. */
+#define XP_THERM   0x40u
 
 /* Device status bits (xp_batch.d_status, OR-ed by kernels). */
 #define XP_ST_CAPACITY  0x1u   /* a cell needed more electron slots than its capacity */
@@ -65,6 +75,7 @@ enum {
     XP_C_PHOTO_1S, XP_C_PHOTO_2S, XP_C_PHOTO_2P, XP_C_PHOTO_SKIPPED,
     XP_C_DECAY, XP_C_AUGER, XP_C_KALPHA,
     XP_C_P_CLAMPED, XP_C_IPD_CLAMPED, XP_C_E_NEW,
+    XP_C_THERM, XP_C_THERM_SKIPPED,   /* cells thermalized / left as they were (XP_THERM) */
     XP_NCOUNT = 24
 };
 
@@ -275,7 +286,8 @@ xp_status bin_particles(xp_ctx *ctx, const xp_particles *in, xp_batch *b,
  * moments and continuum lowering, e-e and e-i binary collisions, collisional
  * ionization, three-body recombination, and -- when XP_PHOTO / XP_DECAY are in
  * p->flags -- the XFEL source terms of photo_auger_step, fused in the same
- * pass with dt_rad of the run table.  Cells stay in canonical slot order:
+ * pass with dt_rad of the run table, then with XP_THERM the forced
+ * thermalization of Sec. VI.C.  Cells stay in canonical slot order:
  * survivors keep their order, new electrons are appended (ionization events
  * in ion-slot order, then per ion Auger, photo 1s, 2s, 2p), electrons whose
  * weight reaches 0 are removed.  Moments record (when d_cell_moments is set):
@@ -293,7 +305,8 @@ xp_status collide_ionize_step(xp_ctx *ctx, xp_batch *b, const xp_step_params *p,
 /* Source terms alone (Sec. III): moments and continuum lowering of the current
  * state, then K-vacancy decay with KLL Auger / K-alpha branching and subshell
  * photoionization (Eq. 3) with the run's prescribed photon field, over
- * dt_rad.  p->flags is masked to XP_PHOTO | XP_DECAY. */
+ * dt_rad, then with XP_THERM the forced thermalization of Sec. VI.C.
+ * p->flags is masked to XP_PHOTO | XP_DECAY | XP_THERM. */
 xp_status photo_auger_step(xp_ctx *ctx, xp_batch *b, const xp_step_params *p,
                            void *stream);
 

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libxpic.so")
 
 XP_EE, XP_EI, XP_ION, XP_REC, XP_PHOTO, XP_DECAY = 0x01, 0x02, 0x04, 0x08, 0x10, 0x20
 XP_ALL = 0x3F
+XP_THERM = 0x40   # variant: forced thermalization after S5 (Sec. VI.C), not in XP_ALL
 XP_ST_CAPACITY, XP_ST_NONFINITE, XP_ST_BIN_SIZE = 0x1, 0x2, 0x4
 XP_NCOUNT, XP_NLEDGER, XP_NMOM, XP_MAX_BINS = 24, 8, 32, 16
 XP_NSTATS = 68
@@ -27,7 +28,8 @@ COUNTERS = ["EE", "EI", "TRIPLET", "ACCEPT", "U0", "DELTA2_GT1",
             "ION_FIRED", "ION_ACCEPTED", "ION_STARVED",
             "REC", "REC_SKIPPED", "E_REMOVED",
             "PHOTO_1S", "PHOTO_2S", "PHOTO_2P", "PHOTO_SKIPPED",
-            "DECAY", "AUGER", "KALPHA", "P_CLAMPED", "IPD_CLAMPED", "E_NEW"]
+            "DECAY", "AUGER", "KALPHA", "P_CLAMPED", "IPD_CLAMPED", "E_NEW",
+            "THERM", "THERM_SKIPPED"]
 
 _vp = C.c_void_p
 _d = C.c_double

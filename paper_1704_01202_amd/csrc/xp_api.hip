@@ -442,13 +442,13 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
 xp_status collide_ionize_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, void* stream)
 {
     if (!p) return fail(XP_ERR_INVALID_ARG, "null step parameters");
-    return launch_step(ctx, b, p, p->flags & XP_ALL, stream);
+    return launch_step(ctx, b, p, p->flags & (XP_ALL | XP_THERM), stream);
 }
 
 xp_status photo_auger_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, void* stream)
 {
     if (!p) return fail(XP_ERR_INVALID_ARG, "null step parameters");
-    return launch_step(ctx, b, p, p->flags & (XP_PHOTO | XP_DECAY), stream);
+    return launch_step(ctx, b, p, p->flags & (XP_PHOTO | XP_DECAY | XP_THERM), stream);
 }
 
 xp_status diagnostics(xp_ctx* ctx, const xp_batch* b, xp_diag* d_out, uint32_t what, void* stream)

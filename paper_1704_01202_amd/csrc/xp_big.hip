@@ -1517,6 +1517,181 @@ __global__ __launch_bounds__(BT) void k_big_s5b(BigArgs a)
     }
 }
 
+// ----------------------------------- forced thermalization (variant, Sec. VI.C)
+// The LDS step's thermalization over chunks: the cell's electrons now include
+// the ones S5 appended; every sum is the chunked canonical sum.  The draws go
+// to the rank-order velocity arrays (free after S2), indexed by population.
+
+__global__ __launch_bounds__(64) void k_big_th0(BigArgs a)
+{
+    const int nb = a.hdr->count;
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) {
+        BigRec& r = a.rec[b];
+        if (r.state) continue;
+        r.ne += r.nnew5;
+        r.nnew5 = 0;
+        r.tw = 0;
+        r.tkeep = 0;
+        r.tkin = r.tkth = r.tsig = 0.0;
+        r.tbeta = 0.0;
+        r.tq[0] = r.tq[1] = r.tq[2] = 0.0;
+    }
+}
+
+// phase 0: weights, w E and w v of the velocities; 1: w E about the drift
+// and the draws with their w v; 2: the draws about their mean and their w E.
+__global__ __launch_bounds__(BT) void k_big_thpart(BigArgs a, int phase)
+{
+    __shared__ double red[2 * (BIG_CH / 64)];
+    __shared__ long long ired[BT / 64];
+    const int tid = threadIdx.x;
+    const StepArgs& s = a.s;
+    const int nce = a.hdr->n_e_chunks;
+    for (int g = blockIdx.x; g < nce; g += gridDim.x) {
+        BigRec& r = a.rec[a.e_chunk_cell[g]];
+        if (r.state || r.tkeep) continue;
+        const int base = (g - r.ce0) * BIG_CH;
+        const int n = r.epn - base < BIG_CH ? r.epn - base : BIG_CH;
+        const int64_t o = r.eo + base;
+        const int64_t po = r.ep0 + base;
+        const uint32_t* w = s.ew + o;
+        if (phase == 0) {
+            long long wl = 0;
+            for (int j = tid; j < n; j += BT) wl += w[j];
+            wl = block_isum<BT>(wl, ired);
+            const double k = block_tree_sum<BT>(BIG_CH, [&](int j) {
+                return j < n ? (double)w[j] * kin_at(s, o + j) : 0.0;
+            }, red);
+            if (tid == 0) {
+                a.part[0][g] = k;
+                if (wl) atomicAdd(&r.tw, (unsigned long long)wl);
+            }
+            const double* v3[3] = {s.evx + o, s.evy + o, s.evz + o};
+            for (int d = 0; d < 3; ++d) {
+                const double* v = v3[d];
+                const double t = block_tree_sum<BT>(BIG_CH, [&](int j) {
+                    return j < n ? (double)w[j] * v[j] : 0.0;
+                }, red);
+                if (tid == 0) a.part[1 + d][g] = t;
+            }
+        } else if (phase == 1) {
+            const double ux = r.u[0], uy = r.u[1], uz = r.u[2], sig = r.tsig;
+            const double k = block_tree_sum<BT>(BIG_CH, [&](int j) {
+                if (j >= n) return 0.0;
+                const double dx = s.evx[o + j] - ux, dy = s.evy[o + j] - uy, dz = s.evz[o + j] - uz;
+                return (double)w[j] * (HALF_ME_OVER_QE * ((dx * dx + dy * dy) + dz * dz));
+            }, red);
+            if (tid == 0) a.part[0][g] = k;
+            for (int j = tid; j < n; j += BT) {
+                double gx, gy, gz;
+                therm_normals(draw(s, r, (uint32_t)(base + j), RP_THERM, 0), gx, gy, gz);
+                a.gev[0][po + j] = sig * gx;
+                a.gev[1][po + j] = sig * gy;
+                a.gev[2][po + j] = sig * gz;
+            }
+            __syncthreads();
+            for (int d = 0; d < 3; ++d) {
+                const double* v = a.gev[d] + po;
+                const double t = block_tree_sum<BT>(BIG_CH, [&](int j) {
+                    return j < n ? (double)w[j] * v[j] : 0.0;
+                }, red);
+                if (tid == 0) a.part[1 + d][g] = t;
+            }
+        } else {
+            const double qx = r.tq[0], qy = r.tq[1], qz = r.tq[2];
+            for (int j = tid; j < n; j += BT) {
+                a.gev[0][po + j] = a.gev[0][po + j] - qx;
+                a.gev[1][po + j] = a.gev[1][po + j] - qy;
+                a.gev[2][po + j] = a.gev[2][po + j] - qz;
+            }
+            __syncthreads();
+            const double k = block_tree_sum<BT>(BIG_CH, [&](int j) {
+                if (j >= n) return 0.0;
+                const double x = a.gev[0][po + j], y = a.gev[1][po + j], z = a.gev[2][po + j];
+                return (double)w[j] * (HALF_ME_OVER_QE * ((x * x + y * y) + z * z));
+            }, red);
+            if (tid == 0) a.part[0][g] = k;
+        }
+    }
+}
+
+// Per-cell ends of the phases: drift velocity, temperature and spread; the
+// drift-frame energy and the draws' mean; the scale of the draws.
+__global__ __launch_bounds__(BT) void k_big_thfin(BigArgs a, int phase)
+{
+    __shared__ double red[2 * (BIG_MAX_CHUNKS / 64)];
+    const int nb = a.hdr->count;
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+        BigRec& r = a.rec[b];
+        if (r.state || r.tkeep) continue;
+        const long long ws = (long long)r.tw;
+        if (phase == 0 && (r.ne < 2 || ws <= 0)) {
+            if (threadIdx.x == 0) {
+                r.tkeep = 1;
+                r.cnt[XP_C_THERM_SKIPPED] += 1;
+            }
+            __syncthreads();
+            continue;
+        }
+        const double w = (double)ws;
+        const double k = block_tree_sum<BT>(r.nce, [&](int j) { return a.part[0][r.ce0 + j]; }, red);
+        double m[3];
+        if (phase < 2)
+            for (int d = 0; d < 3; ++d)
+                m[d] = block_tree_sum<BT>(r.nce, [&](int j) { return a.part[1 + d][r.ce0 + j]; }, red) / w;
+        if (threadIdx.x == 0) {
+            if (phase == 0) {
+                r.tkin = k;
+                r.u[0] = m[0]; r.u[1] = m[1]; r.u[2] = m[2];
+                if (!(k > 0.0)) {
+                    r.tkeep = 1;
+                    r.cnt[XP_C_THERM_SKIPPED] += 1;
+                } else {
+                    r.tsig = sqrt(((2.0 * k) / (3.0 * w)) * (QE / ME));
+                }
+            } else if (phase == 1) {
+                r.tkth = k;
+                r.tq[0] = m[0]; r.tq[1] = m[1]; r.tq[2] = m[2];
+                if (!(k > 0.0)) {
+                    r.tkeep = 1;
+                    r.cnt[XP_C_THERM_SKIPPED] += 1;
+                }
+            } else {
+                // k is 0 only if every draw coincides: drift velocity for all
+                if (k > 0.0) {
+                    r.tbeta = sqrt(r.tkth / k);
+                    r.cnt[XP_C_THERM] += 1;
+                } else {
+                    r.tkeep = 2;
+                    r.cnt[XP_C_THERM_SKIPPED] += 1;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(BT) void k_big_thapply(BigArgs a)
+{
+    const StepArgs& s = a.s;
+    const int nce = a.hdr->n_e_chunks;
+    for (int g = blockIdx.x; g < nce; g += gridDim.x) {
+        const BigRec& r = a.rec[a.e_chunk_cell[g]];
+        if (r.state || r.tkeep == 1) continue;
+        const int base = (g - r.ce0) * BIG_CH;
+        const int n = r.epn - base < BIG_CH ? r.epn - base : BIG_CH;
+        const int64_t o = r.eo + base;
+        const int64_t po = r.ep0 + base;
+        const double ux = r.u[0], uy = r.u[1], uz = r.u[2], be = r.tbeta;
+        const bool drift_only = r.tkeep == 2;
+        for (int j = threadIdx.x; j < n; j += BT) {
+            s.evx[o + j] = drift_only ? ux : ux + be * a.gev[0][po + j];
+            s.evy[o + j] = drift_only ? uy : uy + be * a.gev[1][po + j];
+            s.evz[o + j] = drift_only ? uz : uz + be * a.gev[2][po + j];
+        }
+    }
+}
+
 // ---------------------------------------------------------------- commit
 
 __global__ __launch_bounds__(64) void k_big_commit(BigArgs a)
@@ -1676,6 +1851,15 @@ hipError_t big_launch(BigArgs& a, bool all_cells, hipStream_t s)
         hipLaunchKernelGGL(k_big_s5a, dim3(gch), dim3(BT), 0, s, a);
         hipLaunchKernelGGL(k_big_cscan, dim3(gcell), dim3(BT), 0, s, a, 2);
         hipLaunchKernelGGL(k_big_s5b, dim3(gch), dim3(BT), 0, s, a);
+    }
+    if (flags & XP_THERM) {
+        hipLaunchKernelGGL(k_big_th0, dim3((gcell + 63) / 64), dim3(64), 0, s, a);
+        hipLaunchKernelGGL(k_big_plan, dim3(1), dim3(1024), 0, s, a, 0);
+        for (int ph = 0; ph < 3; ++ph) {
+            hipLaunchKernelGGL(k_big_thpart, dim3(gch), dim3(BT), 0, s, a, ph);
+            hipLaunchKernelGGL(k_big_thfin, dim3(gcell), dim3(BT), 0, s, a, ph);
+        }
+        hipLaunchKernelGGL(k_big_thapply, dim3(gch), dim3(BT), 0, s, a);
     }
     hipLaunchKernelGGL(k_big_commit, dim3(gcell), dim3(64), 0, s, a);
     return hipGetLastError();

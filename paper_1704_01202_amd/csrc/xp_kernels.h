@@ -146,6 +146,13 @@ struct BigRec {
     double ssum[13][3];
     int32_t cnt[XP_NCOUNT];
     double led[XP_NLEDGER];
+    // forced thermalization (variant): weight units, lab-frame and drift-frame
+    // kinetic energy, draw spread, draw mean, scale; keep: 0 resample, 1 keep
+    // the velocities, 2 drift velocity only
+    unsigned long long tw;
+    double tkin, tkth, tsig, tbeta;
+    double tq[3];
+    int32_t tkeep, tpad;
 };
 
 enum : int32_t {

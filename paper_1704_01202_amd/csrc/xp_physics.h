@@ -14,6 +14,21 @@ constexpr double THREE_OVER_4PI = 3.0 / (4.0 * PI);
 constexpr double HALF_ME_OVER_QE = (0.5 * ME) / QE;
 constexpr double TWO_QE_OVER_ME = (2.0 * QE) / ME;
 
+// Standard normal velocity components of one electron for the forced
+// thermalization (Sec. VI.C), from its RP_THERM draw: Box-Muller on words
+// 0, 1 (radius, angle) gives x and y, on words 2, 3 gives z.
+__device__ __forceinline__ void therm_normals(const Words& d, double& gx, double& gy, double& gz)
+{
+    double s1, c1, s2, c2;
+    xsincos2pi((uint64_t)d.x1 << 20, s1, c1);
+    xsincos2pi((uint64_t)d.x3 << 20, s2, c2);
+    const double r1 = sqrt(-2.0 * xlog(u32(d.x0)));
+    const double r2 = sqrt(-2.0 * xlog(u32(d.x2)));
+    gx = r1 * c1;
+    gy = r1 * s1;
+    gz = r2 * c2;
+}
+
 // Lowest-energy configuration of charge state z with k K vacancies (Sec. III):
 // counts of 1s 2s 2p 3s 3p.
 struct Occ { int s[5]; };

@@ -1037,6 +1037,60 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
         T::sync();
     }
 
+    // ------------- forced thermalization (variant, Sec. VI.C) -------------
+    if (!overflow && !deferred && (flags & XP_THERM)) {
+        long long wl = 0;
+        for (int j = tid; j < ne; j += B) wl += L.ew[j];
+        const long long ws = T::isum(wl, S);
+        bool kept = ne < 2 || ws <= 0;
+        if (!kept) {
+            const double w = (double)ws;
+            auto wsum = [&](const double* v) {
+                return T::tree(ne, [&](int j) { return (double)L.ew[j] * v[j]; }, S);
+            };
+            const double kall = T::tree(ne, [&](int j) { return (double)L.ew[j] * kin(j); }, S);
+            const double ux = wsum(L.evx) / w, uy = wsum(L.evy) / w, uz = wsum(L.evz) / w;
+            const double kth = T::tree(ne, [&](int j) {
+                const double dx = L.evx[j] - ux, dy = L.evy[j] - uy, dz = L.evz[j] - uz;
+                return (double)L.ew[j] * (HALF_ME_OVER_QE * ((dx * dx + dy * dy) + dz * dz));
+            }, S);
+            kept = !(kall > 0.0) || !(kth > 0.0);
+            if (!kept) {
+                const double sig = sqrt(((2.0 * kall) / (3.0 * w)) * (QE / ME));
+                T::sync();
+                for (int j = tid; j < ne; j += B) {
+                    double gx, gy, gz;
+                    therm_normals(rng((uint32_t)j, RP_THERM, 0), gx, gy, gz);
+                    L.evx[j] = sig * gx;
+                    L.evy[j] = sig * gy;
+                    L.evz[j] = sig * gz;
+                }
+                T::sync();
+                const double qx = wsum(L.evx) / w, qy = wsum(L.evy) / w, qz = wsum(L.evz) / w;
+                T::sync();
+                for (int j = tid; j < ne; j += B) {
+                    L.evx[j] = L.evx[j] - qx;
+                    L.evy[j] = L.evy[j] - qy;
+                    L.evz[j] = L.evz[j] - qz;
+                }
+                T::sync();
+                const double kd = T::tree(ne, [&](int j) { return (double)L.ew[j] * kin(j); }, S);
+                T::sync();
+                // kd is 0 only if every draw coincides: then every electron
+                // gets the drift velocity
+                const double beta = kd > 0.0 ? sqrt(kth / kd) : 0.0;
+                for (int j = tid; j < ne; j += B) {
+                    L.evx[j] = kd > 0.0 ? ux + beta * L.evx[j] : ux;
+                    L.evy[j] = kd > 0.0 ? uy + beta * L.evy[j] : uy;
+                    L.evz[j] = kd > 0.0 ? uz + beta * L.evz[j] : uz;
+                }
+                T::sync();
+                if (tid == 0) S.cnt[kd > 0.0 ? XP_C_THERM : XP_C_THERM_SKIPPED] += 1;
+            }
+        }
+        if (kept && tid == 0) S.cnt[XP_C_THERM_SKIPPED] += 1;
+    }
+
     // ---------------- commit ----------------
     if (overflow) {
         if (tid == 0) atomicOr(a.status, XP_ST_CAPACITY);

@@ -72,6 +72,28 @@ def test_oversized_cells_take_global_path(ctx):
     assert d.te_ev == out[5]
 
 
+def test_big_path_thermalization(ctx):
+    # the forced thermalization of Sec. VI.C through the global-memory path:
+    # C1 and edge cells with every cell on the path, then oversized cells
+    # beside LDS cells
+    from tests.test_gpu_parity import _therm_edge_case
+    spec, parts = W.config_c1()
+    run_pair(ctx, spec, parts, 8, check_every=4, capacity=(3, 16), label="C1/global/therm",
+             schedule=3, big="all", flags=O.ALL | O.THERM)
+    spec, parts = _therm_edge_case(43)
+    bat, sim = run_pair(ctx, spec, parts, 6, check_every=1, capacity=(3, 4), label="therm/global",
+                        schedule=3, big="all", flags=O.ALL | O.THERM)
+    oc = sim.counters()[0]
+    assert oc[:, O.COUNTERS.index("THERM_SKIPPED")].sum() > 0
+    ne = np.array([60, 3000, 2600, 45, 0])
+    ni = np.array([50, 1500, 600, 40, 20])
+    spec, parts = cases.one_run(ne.size, ne, ni, 30.0, 0.1, seed=95, e_weight=1, dt=0.05e-15,
+                                photon_hv=(1850.0,), photon_n=(4e29,))
+    bat, sim = run_pair(ctx, spec, parts, 4, check_every=2, label="oversized/therm",
+                        flags=O.ALL | O.THERM)
+    assert bat.stats()[2] == 2
+
+
 def test_big_path_capacity_flag(ctx):
     spec, parts = cases.one_run(2, 30, 30, 3000.0, 1.0, seed=79, e_weight=3)
     bat = RT.Batch(ctx, [(spec, parts)], capacity=(0, 0), big="all")

@@ -36,7 +36,7 @@ def test_c2_full_size_parity(ctx):
     sim.bin(parts)
     bat = RT.Batch(ctx, [(spec, parts)], capacity=(7, 16))
     th = host_threads()
-    total = np.zeros(22, dtype=np.int64)
+    total = np.zeros(24, dtype=np.int64)
     for s in range(3):
         bat.step(s)
         sim.step(s, O.ALL, th)
@@ -44,9 +44,9 @@ def test_c2_full_size_parity(ctx):
         assert bat.status() == 0
         w, nb = compare(bat.state(), sim.state(), "C2 full step %d" % s)
         cnt, _ = sim.counters()
-        total += cnt[:, :22].sum(axis=0).astype(np.int64)
+        total += cnt[:, :24].sum(axis=0).astype(np.int64)
         # the run's accumulated counters equal the oracle's per-step sums
-        assert np.array_equal(bat.run_counters()[0][:22].astype(np.int64), total), s
+        assert np.array_equal(bat.run_counters()[0][:24].astype(np.int64), total), s
         say("C2 full step %d ok (differing words %d)" % (s, nb))
 
 

@@ -91,7 +91,7 @@ def run_pair(ctx, spec, parts, steps, flags=O.ALL, schedule=0, capacity=(7, 16),
             w, nb = compare(bat.state(), sim.state(), "%s step %d" % (label, s))
             gc, gl, gm = bat.cell_records_of()
             oc, ol = sim.counters()
-            assert np.array_equal(gc[:, :22], oc[:, :22]), "%s step %d counters" % (label, s)
+            assert np.array_equal(gc[:, :24], oc[:, :24]), "%s step %d counters" % (label, s)
             om = sim.moments()
             assert np.array_equal(gm[:, :29], om[:, :29]), "%s step %d moments" % (label, s)
             assert np.allclose(gl, ol, rtol=1e-12, atol=1e-9), "%s step %d ledger" % (label, s)
@@ -239,8 +239,60 @@ def test_photo_auger_step_alone(ctx):
         compare(bat.state(), sim.state(), "photo step %d" % s)
         gc, _, _ = bat.cell_records_of()
         oc, _ = sim.counters()
-        assert np.array_equal(gc[:, :22], oc[:, :22])
+        assert np.array_equal(gc[:, :24], oc[:, :24])
     assert sim.counters()[0][:, O.COUNTERS.index("DECAY")].sum() >= 0
+
+
+def _therm_edge_case(seed):
+    # empty cells, lone electrons, one velocity for a whole cell (no thermal
+    # energy), keV electrons among cold ones, mixed weights
+    rng = np.random.default_rng(seed)
+    ne = np.array([0, 1, 2, 5, 7, 12, 3, 9, 0, 4])
+    ni = np.array([1, 0, 2, 3, 1, 2, 4, 3, 2, 1])
+    spec, parts = cases.one_run(ne.size, ne, ni, 50.0, 0.5, seed=seed, lnl=3.0,
+                                photon_hv=(1800.0,), photon_n=(3e30,))
+    cell = np.floor(parts.ex / spec.dx).astype(int)
+    one = cell == 3
+    parts.evx[one], parts.evy[one], parts.evz[one] = 2.0e5, -1.0e5, 4.0e5
+    hot = rng.random(parts.ne) < 0.2
+    parts.evx[hot] *= 8.0
+    parts.ew[:] = rng.choice([1, 2, 3], parts.ne)
+    return spec, parts
+
+
+def test_forced_thermalization(ctx):
+    # the variant of Sec. VI.C after the whole step: C1 (keV source electrons
+    # among 10 eV ones) and edge cells on every LDS schedule
+    spec, parts = W.config_c1()
+    bat, sim = run_pair(ctx, spec, parts, 8, flags=O.ALL | O.THERM, check_every=4, label="C1/therm")
+    oc = sim.counters()[0]
+    assert oc[:, O.COUNTERS.index("THERM")].sum() == 64
+    for sched in (1, 2, 5):
+        spec, parts = _therm_edge_case(41)
+        bat, sim = run_pair(ctx, spec, parts, 6, flags=O.ALL | O.THERM, check_every=1,
+                            capacity=(3, 4), schedule=sched, label="therm/%d" % sched)
+        oc = sim.counters()[0]
+        assert oc[:, O.COUNTERS.index("THERM")].sum() > 0
+        assert oc[:, O.COUNTERS.index("THERM_SKIPPED")].sum() > 0
+
+
+def test_thermalization_after_source_terms_alone(ctx):
+    n = 120
+    spec, parts = cases.one_run(5, 3 * n, n, 10.0, 0.1, k0=1, seed=79, dt=0.1e-15,
+                                photon_hv=(1650.0, 1900.0), photon_n=(2e29, 1e29))
+    sim = O.Sim(ctx.tables, spec)
+    sim.bin(parts)
+    bat = RT.Batch(ctx, [(spec, parts)], capacity=(1, 16), cell_records=True)
+    for s in range(3):
+        bat.photo_auger(s, flags=B.XP_PHOTO | B.XP_DECAY | B.XP_THERM)
+        sim.step(s, O.PHOTO | O.DECAY | O.THERM)
+        torch.cuda.synchronize()
+        compare(bat.state(), sim.state(), "photo+therm step %d" % s)
+        gc, _, _ = bat.cell_records_of()
+        oc, _ = sim.counters()
+        assert np.array_equal(gc[:, :24], oc[:, :24])
+        assert oc[:, O.COUNTERS.index("THERM")].sum() == 5
+    say("photo_auger_step + thermalization ok")
 
 
 def test_edge_cells(ctx):
