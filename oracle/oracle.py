@@ -26,6 +26,7 @@ NMOM = 32
 EE, EI, ION, REC, PHOTO, DECAY = 0x01, 0x02, 0x04, 0x08, 0x10, 0x20
 ALL = EE | EI | ION | REC | PHOTO | DECAY
 THERM = 0x40   # variant: forced thermalization after S5 (Sec. VI.C), not in ALL
+ION_Z = 0x80   # variant: S3 cross section per ion charge state (Sec. IV), not in ALL
 
 COUNTERS = ["EE", "EI", "TRIPLET", "ACCEPT", "U0", "DELTA2_GT1",
             "ION_FIRED", "ION_ACCEPTED", "ION_STARVED",

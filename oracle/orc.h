@@ -41,6 +41,7 @@ extern "C" {
 #define ORC_PHOTO   0x10u
 #define ORC_DECAY   0x20u
 #define ORC_THERM   0x40u   /* variant: forced thermalization after S5 (Sec. VI.C) */
+#define ORC_ION_Z   0x80u   /* variant: S3 cross section per ion charge state (Sec. IV) */
 
 /* Per-cell, per-step event counters. */
 enum {

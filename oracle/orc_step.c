@@ -7,7 +7,8 @@
  *      charge state by Ecker-Kroll (Eq. 5) or Stewart-Pyatt (Eq. 6) (Sec. V).
  *   S1 electron-electron and S2 electron-ion binary collisions (Sec. IV).
  *   S3 collisional ionization against the average cell ion with the Lotz cross
- *      section (Eq. 4) and the energy debit of Sec. IV.
+ *      section (Eq. 4) and the energy debit of Sec. IV; with ORC_ION_Z every
+ *      ion's probability uses the cross section of its own charge state.
  *   S4 three-body recombination constrained by Zbar_EOS(n_i, T_e) (Sec. IV).
  *   S5 K-vacancy decay with Auger / K-alpha branching and subshell
  *      photoionization (Eq. 3) (Sec. III).
@@ -537,28 +538,47 @@ static void step_cell(cctx *x, ocell *c, uint32_t flags)
         int zc = (int)((2 * sz + wi) / (2 * wi));
         m[11] = zc;
         int ne0 = ne;
-        if (zc < ORC_ZMAX) {
+        /* the charge states whose cross section is evaluated: the average cell
+         * ion Z_c, or (ORC_ION_Z) every charge state an ion of the cell holds */
+        int eval[ORC_ZMAX] = {0};
+        if (flags & ORC_ION_Z) {
+            for (int i = 0; i < ni; ++i)
+                if (c->iz[i] < ORC_ZMAX) eval[c->iz[i]] = 1;
+        } else if (zc < ORC_ZMAX) {
+            eval[zc] = 1;
+        }
+        double pz[ORC_ZMAX];
+        int nz = 0;
+        double pmax = 0.0;
+        for (int z = 0; z < ORC_ZMAX; ++z) {
+            pz[z] = 0.0;
+            if (!eval[z]) continue;
             for (int j = 0; j < ne0; ++j) {
                 double v2 = (c->evx[j] * c->evx[j] + c->evy[j] * c->evy[j]) + c->evz[j] * c->evz[j];
                 double e = HALF_ME_OVER_QE * v2;
-                double sig = orc_lotz(t, zc, dE, e);
+                double sig = orc_lotz(t, z, dE, e);
                 x->scratch[j] = ((double)c->ew[j] * sig) * sqrt(v2);
             }
             double ssum = tree_sum(x->scratch, ne0);
             double p = ((ssum * r->w0) * r->dt) / r->volume;
             if (p > 1.0) { p = 1.0; x->cnt[OC_P_CLAMPED]++; }
-            m[12] = p;
+            pz[z] = p;
+            if (p > pmax) pmax = p;
+            ++nz;
             /* clamp events of the per-cell lowered levels used by Lotz */
-            {
-                int occ[ORC_NSUB];
-                orc_occupancy(zc, 0, occ);
-                for (int q = 0; q < ORC_NSUB; ++q)
-                    if (occ[q] > 0 && t->bind[zc][q] - dE[zc] < 1.0) x->cnt[OC_IPD_CLAMPED]++;
-            }
+            int occ[ORC_NSUB];
+            orc_occupancy(z, 0, occ);
+            for (int q = 0; q < ORC_NSUB; ++q)
+                if (occ[q] > 0 && t->bind[z][q] - dE[z] < 1.0) x->cnt[OC_IPD_CLAMPED]++;
+        }
+        if (flags & ORC_ION_Z) m[11] = nz;
+        if (nz > 0) {
+            m[12] = pmax;
             int nfired = 0;
             for (int i = 0; i < ni; ++i) {
                 x->perm_a[i] = 0;
                 if (c->iz[i] >= ORC_ZMAX) continue;
+                double p = (flags & ORC_ION_Z) ? pz[c->iz[i]] : pz[zc];
                 uint32_t d[4];
                 rng(x, (uint32_t)i, P_ION, 0, d);
                 if (orc_u32(d[0]) < p) { x->perm_a[i] = 1; nfired++; }
