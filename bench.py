@@ -46,7 +46,7 @@ def cpu_threads():
     return max(1, min(n, os.cpu_count() or n))
 
 
-def cpu_baseline(spec, parts, budget_s=15.0, max_steps=40, therm=False):
+def cpu_baseline(spec, parts, budget_s=15.0, max_steps=40, therm=False, ion_z=False):
     """The oracle on a bounded sample of the same workload: every cell of the
     same initial state, stepped from step 0 until about budget_s of work."""
     from oracle import oracle as O
@@ -59,7 +59,7 @@ def cpu_baseline(spec, parts, budget_s=15.0, max_steps=40, therm=False):
     steps = 0
     t0 = time.perf_counter()
     while steps < max_steps:
-        sim.step(steps, O.ALL | (O.THERM if therm else 0), threads)
+        sim.step(steps, O.ALL | (O.THERM if therm else 0) | (O.ION_Z if ion_z else 0), threads)
         cnt, _ = sim.counters()
         coll += int(cnt[:, 0].sum() + cnt[:, 1].sum() + cnt[:, 2].sum())
         steps += 1
@@ -377,6 +377,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--therm", action="store_true",
                     help="c2: add the forced thermalization variant (Sec. VI.C) after S5")
+    ap.add_argument("--ion-z", action="store_true",
+                    help="c2: collisional ionization per ion charge state (variant of Sec. IV)")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run a plain device copy of MIB MiB "
                          "(calibrates the HBM byte counters under a profiler)")
@@ -426,7 +428,7 @@ def main():
     log("binned into slabs: e_slots %d, max cap %d (%.1f s)"
         % (bat.e_slots, bat.e_cap_max, time.perf_counter() - t0))
     stream = torch.cuda.current_stream()
-    flags = B.XP_ALL | (B.XP_THERM if args.therm else 0)
+    flags = B.XP_ALL | (B.XP_THERM if args.therm else 0) | (B.XP_ION_Z if args.ion_z else 0)
     for s in range(args.warmup):
         bat.step(s, flags, schedule=args.schedule)
     torch.cuda.synchronize()
@@ -476,7 +478,8 @@ def main():
         "config": {"workload": "2D uniform solid Al, %dx%d cells x (64 e + 64 Al3+), EK IPD, "
                                "dt 0.05 fs, 1.7e17 W/cm^2 1.85 keV photoionization fused%s"
                                % (args.nx, args.ny,
-                                  ", forced thermalization after S5" if args.therm else ""),
+                                  (", forced thermalization after S5" if args.therm else "")
+                                  + (", ionization per ion charge state" if args.ion_z else "")),
                    "cells": spec.ncells, "electrons_start": parts.ne, "ions": ni,
                    "electrons_timed": [ne_before, ne_after], "status": status},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -486,7 +489,7 @@ def main():
         "collisions_total": coll,
     }
     valu = measured_valu()
-    if valu is not None and args.nx == 512 and args.ny == 512 and not args.therm:
+    if valu is not None and args.nx == 512 and args.ny == 512 and not args.therm and not args.ion_z:
         # the step is bound by instruction issue, not by HBM: VALU instructions
         # of a launch (profiled) over the launch time measured here
         rate = valu / (avg_ms * 1e-3)
@@ -499,7 +502,7 @@ def main():
         del bat
         torch.cuda.empty_cache()
         log("timing the CPU oracle on a sample ...")
-        out["cpu_baseline"] = cpu_baseline(spec, parts, therm=args.therm)
+        out["cpu_baseline"] = cpu_baseline(spec, parts, therm=args.therm, ion_z=args.ion_z)
     print(json.dumps(out), flush=True)
 
 

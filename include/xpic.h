@@ -61,6 +61,14 @@ typedef int32_t xp_status;
  * the x and y components, on words 2, 3 the z component.  Cells with fewer
  * than two electrons or no drift-frame energy keep their velocities. */
 #define XP_THERM   0x40u
+/* Variant, not part of XP_ALL: collisional ionization (S3) with the Lotz cross
+ * section of every ion's own charge state instead of the average cell ion
+ * (Sec. IV): for each charge state z < 13 held by an ion of the cell,
+ * P_z = (w0 dt / V) sum_j w_j sigma(E_j; z) v_j (canonical sum, clamped at 1),
+ * and an ion of charge z fires with its ION draw r < P_z.  Acceptance, energy
+ * debit and rescale are those of S3.  Moments record: [11] the number of
+ * charge states evaluated, [12] the largest P_z. */
+#define XP_ION_Z   0x80u
 
 /* Device status bits (xp_batch.d_status, OR-ed by kernels). */
 #define XP_ST_CAPACITY  0x1u   /* a cell needed more electron slots than its capacity */

@@ -336,6 +336,7 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
         g.wp = (uint32_t*)(w + bp.wp);
         g.sel = (int32_t*)(w + bp.sel);
         g.fip = (double*)(w + bp.fip);
+        g.partz = (double*)(w + bp.partz);
         const size_t ev_stride = ((8 * (size_t)(b->big_e_slots > 0 ? b->big_e_slots : 1) + 255) & ~size_t(255));
         const size_t iv_stride = ((8 * (size_t)(b->big_i_slots > 0 ? b->big_i_slots : 1) + 255) & ~size_t(255));
         for (int q = 0; q < 3; ++q) {
@@ -442,7 +443,7 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
 xp_status collide_ionize_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, void* stream)
 {
     if (!p) return fail(XP_ERR_INVALID_ARG, "null step parameters");
-    return launch_step(ctx, b, p, p->flags & (XP_ALL | XP_THERM), stream);
+    return launch_step(ctx, b, p, p->flags & (XP_ALL | XP_THERM | XP_ION_Z), stream);
 }
 
 xp_status photo_auger_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, void* stream)

@@ -94,6 +94,7 @@ __global__ void k_big_init(BigArgs a)
         r.state = 0;
         r.need = 0;
         r.zc = 0;
+        r.zmask = r.zeval = 0;
         r.acc = 0;
         r.nrec = 0;
         r.epn = 0;
@@ -225,13 +226,16 @@ __global__ __launch_bounds__(BT) void k_big_s0(BigArgs a)
         const int n = r.ni - base < BIG_CH ? r.ni - base : BIG_CH;
         const int64_t o = r.io + base;
         long long s1 = 0, s2 = 0;
+        uint32_t zm = 0;
         for (int j = tid; j < n; j += BT) {
             const long long z = s.iz[o + j];
             s1 += z;
             s2 += z * z;
+            if (z < 13) zm |= 1u << z;
         }
         s1 = block_isum<BT>(s1, ired);
         s2 = block_isum<BT>(s2, ired);
+        if (zm) atomicOr(&r.zmask, zm);
         if (tid == 0) {
             atomicAdd(&r.sz, (unsigned long long)s1);
             atomicAdd(&r.sz2, (unsigned long long)s2);
@@ -285,17 +289,24 @@ __global__ __launch_bounds__(BT) void k_big_s0fin(BigArgs a)
                 // charge states are unchanged until S3: the moments' sum serves
                 const int zc = (int)((2 * sz + wi) / (2 * wi));
                 r.zc = zc;
-                r.mom[11] = (double)zc;
-                if (zc < 13) {
+                // the evaluated charge states: Z_c, or (XP_ION_Z) every state
+                // an ion holds
+                const bool perz = (flags & XP_ION_Z) != 0;
+                const uint32_t ze = perz ? r.zmask : (zc < 13 ? 1u << zc : 0u);
+                r.zeval = ze;
+                r.mom[11] = perz ? (double)__popc(ze) : (double)zc;
+                if (ze) {
                     need |= BN_ION;
-                    const Occ oc = occupancy(zc, 0);
                     int clamped = 0;
-                    for (int q = 0; q < 5; ++q) {
-                        const double raw = tb->bind[zc][q] - dE[zc];
-                        r.pp[q] = raw < 1.0 ? 1.0 : raw;
-                        r.lnp[q] = oc.s[q] > 0 ? xlog(r.pp[q]) : 0.0;
-                        r.occ[q] = oc.s[q];
-                        if (oc.s[q] > 0 && raw < 1.0) ++clamped;
+                    for (int z = 0; z < 13; ++z) {
+                        if (!(ze & (1u << z))) continue;
+                        const Occ oc = occupancy(z, 0);
+                        for (int q = 0; q < 5; ++q) {
+                            const double raw = tb->bind[z][q] - dE[z];
+                            r.ppz[z][q] = raw < 1.0 ? 1.0 : raw;
+                            r.lnpz[z][q] = oc.s[q] > 0 ? xlog(r.ppz[z][q]) : 0.0;
+                            if (oc.s[q] > 0 && raw < 1.0) ++clamped;
+                        }
                     }
                     r.cnt[XP_C_IPD_CLAMPED] += clamped;
                 }
@@ -709,24 +720,26 @@ __global__ __launch_bounds__(BT) void k_big_lotz(BigArgs a)
     for (int g = blockIdx.x; g < nce; g += gridDim.x) {
         const BigRec& r = a.rec[a.e_chunk_cell[g]];
         if (!big_live(r, BN_ION)) continue;
-        int oc[5];
-        double pp[5], lnp[5];
-        double pmin = __builtin_inf();
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            oc[q] = r.occ[q];
-            pp[q] = r.pp[q];
-            lnp[q] = r.lnp[q];
-            if (oc[q] > 0 && pp[q] < pmin) pmin = pp[q];
-        }
         const int base = (g - r.ce0) * BIG_CH;
         const int n = r.epn - base < BIG_CH ? r.epn - base : BIG_CH;
         const int64_t o = r.eo + base;
-        const double sum = block_tree_sum<BT>(BIG_CH, [&](int j) {
-            if (j >= n) return 0.0;
-            return lotz_leaf(s.evx[o + j], s.evy[o + j], s.evz[o + j], s.ew[o + j], oc, pp, lnp, pmin, tb);
-        }, red);
-        if (tid == 0) a.part[1][g] = sum;
+        for (int z = 0; z < 13; ++z) {
+            if (!(r.zeval & (1u << z))) continue;
+            const Occ occ = occupancy(z, 0);
+            double pp[5], lnp[5];
+            double pmin = __builtin_inf();
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                pp[q] = r.ppz[z][q];
+                lnp[q] = r.lnpz[z][q];
+                if (occ.s[q] > 0 && pp[q] < pmin) pmin = pp[q];
+            }
+            const double sum = block_tree_sum<BT>(BIG_CH, [&](int j) {
+                if (j >= n) return 0.0;
+                return lotz_leaf(s.evx[o + j], s.evy[o + j], s.evz[o + j], s.ew[o + j], occ.s, pp, lnp, pmin, tb);
+            }, red);
+            if (tid == 0) a.partz[(size_t)z * a.e_chunks_max + g] = sum;
+        }
     }
 }
 
@@ -739,16 +752,20 @@ __global__ __launch_bounds__(BT) void k_big_s3p(BigArgs a)
         BigRec& r = a.rec[b];
         if (!big_live(r, BN_ION)) continue;
         const xp_run& R = s.runs[r.run];
-        const double ssum = block_tree_sum<BT>(r.nce, [&](int j) { return a.part[1][r.ce0 + j]; }, red);
-        if (threadIdx.x == 0) {
+        double pmax = 0.0;
+        for (int z = 0; z < 13; ++z) {
+            if (!(r.zeval & (1u << z))) continue;
+            const double* pz = a.partz + (size_t)z * a.e_chunks_max + r.ce0;
+            const double ssum = block_tree_sum<BT>(r.nce, [&](int j) { return pz[j]; }, red);
             double p = ((ssum * R.w0) * R.dt) / R.volume;
             if (p > 1.0) {
                 p = 1.0;
-                r.cnt[XP_C_P_CLAMPED] += 1;
+                if (threadIdx.x == 0) r.cnt[XP_C_P_CLAMPED] += 1;
             }
-            r.p = p;
-            r.mom[12] = p;
+            if (threadIdx.x == 0) r.pz[z] = p;
+            if (p > pmax) pmax = p;
         }
+        if (threadIdx.x == 0) r.mom[12] = pmax;
         __syncthreads();
     }
 }
@@ -762,14 +779,18 @@ __global__ __launch_bounds__(BT) void k_big_fire(BigArgs a)
     for (int g = blockIdx.x; g < nci; g += gridDim.x) {
         BigRec& r = a.rec[a.i_chunk_cell[g]];
         if (!big_live(r, BN_ION)) continue;
-        const double p = r.p;
+        const bool perz = (s.flags & XP_ION_Z) != 0;
         const int base = (g - r.ci0) * BIG_CH;
         const int n = r.ni - base < BIG_CH ? r.ni - base : BIG_CH;
         long long c = 0;
         for (int q = tid; q < n; q += BT) {
             const int i = base + q;
             bool f = false;
-            if (s.iz[r.io + i] < 13 && p > 0.0) f = u32(draw(s, r, (uint32_t)i, RP_ION, 0).x0) < p;
+            const int zi = s.iz[r.io + i];
+            if (zi < 13) {
+                const double p = r.pz[perz ? zi : r.zc];
+                if (p > 0.0) f = u32(draw(s, r, (uint32_t)i, RP_ION, 0).x0) < p;
+            }
             a.iflag[r.ip0 + i] = f ? 1 : 0;
             c += f ? 1 : 0;
         }
@@ -1760,6 +1781,7 @@ BigPlan big_plan(int32_t big_max, int64_t e_pop, int64_t i_pop)
     p.gew = o; o += up(4 * (size_t)ep);
     p.giv = o; o += 3 * up(8 * (size_t)ip);
     p.giz = o; o += up((size_t)ip);
+    p.partz = o; o += 13 * up(8 * (size_t)p.e_chunks);
     p.bytes = o;
     return p;
 }

@@ -139,8 +139,9 @@ struct BigRec {
     unsigned long long we, wb, sz, sz2, ws, nelig, nfired, we4, wb4, sz4;
     double p, kth, debit, alpha;
     double u[3];
-    double pp[5], lnp[5];
-    int32_t occ[5], pad;
+    uint32_t zmask, zeval;             // charge states held by ions (< 13); evaluated in S3
+    double ppz[13][5], lnpz[13][5];    // S3 lowered bindings and their logarithms per state
+    double pz[13];                     // S3 probability per evaluated state
     double mom[XP_NMOM];
     double sig[XP_MAX_BINS][3];
     double ssum[13][3];
@@ -187,6 +188,7 @@ struct BigArgs {
     uint32_t* wp;               // per electron reduced weights (S4)
     int32_t* sel;               // per ion selected for recombination (S4)
     double* fip;                // per fired ion (rank order) lowered potential (S3)
+    double* partz;              // [13][e_chunks_max] per charge state chunk sums (S3)
     double* gev[3];             // electron velocities in permutation-rank order (S1, S2)
     uint32_t* gew;              // electron weights in rank order
     double* giv[3];             // ion velocities in rank order (S2)
@@ -199,7 +201,7 @@ struct BigArgs {
 
 struct BigPlan {
     size_t list, hdr, rec, e_chunk_cell, i_chunk_cell, part, key_a, val_a, key_b, val_b, key_c,
-        val_c, hist, iflag, ccnt, iaux, wp, sel, fip, gev, gew, giv, giz;
+        val_c, hist, iflag, ccnt, iaux, wp, sel, fip, gev, gew, giv, giz, partz;
     size_t bytes;
     int32_t e_chunks, i_chunks;
 };

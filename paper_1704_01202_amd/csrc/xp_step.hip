@@ -35,6 +35,7 @@ struct CellSharedT {
     double mom[XP_NMOM];
     double sig[XP_MAX_BINS][3];
     double ssum[13][3];
+    double pz[13];        // S3 probability per evaluated charge state
     double dbl[8];
     int ints[8];
 };
@@ -636,34 +637,55 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
         // charge states are unchanged since the moments: reuse their sum
         const int zc = (int)((2 * sz + wi) / (2 * wi));
         const int ne0 = ne;
-        if (tid == 0) S.mom[11] = (double)zc;
-        if (zc < 13) {
-            const Occ oc = occupancy(zc, 0);
-            double pp[5], lnp[5];
+        // the charge states whose cross section is evaluated: the average
+        // cell ion Z_c, or (XP_ION_Z) every state an ion of the cell holds
+        const bool perz = (flags & XP_ION_Z) != 0;
+        if (perz) {
+            uint32_t ml = 0;
+            for (int i = tid; i < ni; i += B)
+                if (L.iz[i] < 13) ml |= 1u << L.iz[i];
+            if (ml) atomicOr((unsigned*)&S.ints[2], ml);
+            T::sync();
+        }
+        const uint32_t zmask = perz ? (uint32_t)S.ints[2] : (zc < 13 ? 1u << zc : 0u);
+        if (tid == 0) S.mom[11] = perz ? (double)__popc(zmask) : (double)zc;
+        if (zmask) {
+            double pmax = 0.0;
+#pragma unroll 1
+            for (int z = 0; z < 13; ++z) {
+                if (!(zmask & (1u << z))) continue;
+                const Occ oc = occupancy(z, 0);
+                double pp[5], lnp[5];
 #pragma unroll
-            for (int q = 0; q < 5; ++q) {
-                const double raw = tb->bind[zc][q] - dE[zc];
-                pp[q] = raw < 1.0 ? 1.0 : raw;
-                lnp[q] = oc.s[q] > 0 ? xlog(pp[q]) : 0.0;
-                if (tid == 0 && oc.s[q] > 0 && raw < 1.0) S.cnt[XP_C_IPD_CLAMPED] += 1;
-            }
-            double pmin = __builtin_inf();
+                for (int q = 0; q < 5; ++q) {
+                    const double raw = tb->bind[z][q] - dE[z];
+                    pp[q] = raw < 1.0 ? 1.0 : raw;
+                    lnp[q] = oc.s[q] > 0 ? xlog(pp[q]) : 0.0;
+                    if (tid == 0 && oc.s[q] > 0 && raw < 1.0) S.cnt[XP_C_IPD_CLAMPED] += 1;
+                }
+                double pmin = __builtin_inf();
 #pragma unroll
-            for (int q = 0; q < 5; ++q)
-                if (oc.s[q] > 0 && pp[q] < pmin) pmin = pp[q];
-            const double ssum = T::tree(ne0, [&](int j) {
-                return lotz_leaf(L.evx[j], L.evy[j], L.evz[j], L.ew[j], oc.s, pp, lnp, pmin, tb);
-            }, S);
-            double p = ((ssum * w0) * dt) / vol;
-            if (p > 1.0) {
-                p = 1.0;
-                if (tid == 0) S.cnt[XP_C_P_CLAMPED] += 1;
+                for (int q = 0; q < 5; ++q)
+                    if (oc.s[q] > 0 && pp[q] < pmin) pmin = pp[q];
+                const double ssum = T::tree(ne0, [&](int j) {
+                    return lotz_leaf(L.evx[j], L.evy[j], L.evz[j], L.ew[j], oc.s, pp, lnp, pmin, tb);
+                }, S);
+                double p = ((ssum * w0) * dt) / vol;
+                if (p > 1.0) {
+                    p = 1.0;
+                    if (tid == 0) S.cnt[XP_C_P_CLAMPED] += 1;
+                }
+                if (tid == 0) S.pz[z] = p;
+                if (p > pmax) pmax = p;
             }
-            if (tid == 0) S.mom[12] = p;
+            if (tid == 0) S.mom[12] = pmax;
+            T::sync();
             const int nfired = T::select(
                 ni,
                 [&](int i) {
-                    if (L.iz[i] >= 13 || !(p > 0.0)) return false;
+                    if (L.iz[i] >= 13) return false;
+                    const double p = S.pz[perz ? L.iz[i] : zc];
+                    if (!(p > 0.0)) return false;
                     const Words d = rng((uint32_t)i, RP_ION, 0);
                     L.fw[3 * i] = d.x1;
                     L.fw[3 * i + 1] = d.x2;

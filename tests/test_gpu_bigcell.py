@@ -94,6 +94,18 @@ def test_big_path_thermalization(ctx):
     assert bat.stats()[2] == 2
 
 
+def test_big_path_per_charge_state_ionization(ctx):
+    from tests.test_gpu_parity import _mixed_charge_case
+    spec, parts = _mixed_charge_case(53)
+    bat, sim = run_pair(ctx, spec, parts, 8, check_every=1, label="ionz/global", schedule=3,
+                        big="all", flags=O.ALL | O.ION_Z)
+    assert (sim.moments()[:, 11] > 1).any()
+    spec, parts = W.config_c1()
+    parts.iz[:] = np.random.default_rng(7).integers(3, 9, parts.ni)
+    run_pair(ctx, spec, parts, 8, check_every=4, capacity=(3, 16), label="C1/global/ionz+therm",
+             schedule=3, big="all", flags=O.ALL | O.ION_Z | O.THERM)
+
+
 def test_big_path_capacity_flag(ctx):
     spec, parts = cases.one_run(2, 30, 30, 3000.0, 1.0, seed=79, e_weight=3)
     bat = RT.Batch(ctx, [(spec, parts)], capacity=(0, 0), big="all")

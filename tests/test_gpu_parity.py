@@ -276,6 +276,35 @@ def test_forced_thermalization(ctx):
         assert oc[:, O.COUNTERS.index("THERM_SKIPPED")].sum() > 0
 
 
+def _mixed_charge_case(seed, n_cells=12, ne_hi=40, ni_hi=20):
+    rng = np.random.default_rng(seed)
+    ne = rng.integers(0, ne_hi, n_cells)
+    ni = rng.integers(0, ni_hi, n_cells)
+    spec, parts = cases.one_run(n_cells, ne, ni, 120.0, 0.5, seed=seed, lnl=3.0,
+                                photon_hv=(1800.0,), photon_n=(3e30,))
+    parts.iz[:] = rng.integers(3, 14, parts.ni)
+    parts.ik[:] = np.where(parts.iz < 12, rng.integers(0, 2, parts.ni), 0)
+    parts.ew[:] = rng.choice([1, 2, 3], parts.ne)
+    return spec, parts
+
+
+def test_per_charge_state_ionization(ctx):
+    # the S3 variant with every ion's own charge state (Sec. IV), alone and
+    # with the forced thermalization, on every LDS schedule
+    spec, parts = _mixed_charge_case(51)
+    bat, sim = run_pair(ctx, spec, parts, 8, flags=O.ALL | O.ION_Z, check_every=1,
+                        label="ionz")
+    assert (sim.moments()[:, 11] > 1).any()
+    for sched in (1, 2, 5):
+        # small slabs for the lane groups: at most 48 electron slots per cell
+        # (the oracle keeps these cells within them over the 6 steps)
+        spec, parts = _mixed_charge_case(52, ne_hi=12, ni_hi=6)
+        run_pair(ctx, spec, parts, 6, flags=O.ALL | O.ION_Z | O.THERM, check_every=2,
+                 capacity=(5, 4), schedule=sched, label="ionz+therm/%d" % sched)
+    spec, parts = W.config_c2(nx=6, ny=6)
+    run_pair(ctx, spec, parts, 16, flags=O.ALL | O.ION_Z, check_every=8, label="C2r/ionz")
+
+
 def test_thermalization_after_source_terms_alone(ctx):
     n = 120
     spec, parts = cases.one_run(5, 3 * n, n, 10.0, 0.1, k0=1, seed=79, dt=0.1e-15,
