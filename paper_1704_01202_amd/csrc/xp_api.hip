@@ -374,6 +374,8 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
             ce = ((ce + 15) / 16) * 16;
             if (ce > ce_top) ce = ce_top;
         }
+        // the variants are compiled into their own kernels
+        const bool xv = (flags & (XP_THERM | XP_ION_Z)) != 0;
         for (int tier = 0;; ++tier) {
             const bool last = ce >= ce_top || tier >= xpd::BIG_COUNT_SLOT - 1;
             a.lds_ce = ce;
@@ -402,11 +404,23 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
             const void* fn;
             int threads = 64, per_cell_groups = 1;
             switch (sched) {
-            case 1: fn = (const void*)xpd::k_step<64>; break;
-            case 2: fn = (const void*)xpd::k_step<256>; threads = 256; break;
-            case 4: fn = (const void*)xpd::k_step_g<32>; per_cell_groups = 2; break;
-            case 5: fn = (const void*)xpd::k_step_g<16>; per_cell_groups = 4; break;
-            default: fn = (const void*)xpd::k_step_g<8>; per_cell_groups = 8; break;
+            case 1: fn = xv ? (const void*)xpd::k_step<64, true> : (const void*)xpd::k_step<64, false>; break;
+            case 2:
+                fn = xv ? (const void*)xpd::k_step<256, true> : (const void*)xpd::k_step<256, false>;
+                threads = 256;
+                break;
+            case 4:
+                fn = xv ? (const void*)xpd::k_step_g<32, true> : (const void*)xpd::k_step_g<32, false>;
+                per_cell_groups = 2;
+                break;
+            case 5:
+                fn = xv ? (const void*)xpd::k_step_g<16, true> : (const void*)xpd::k_step_g<16, false>;
+                per_cell_groups = 4;
+                break;
+            default:
+                fn = xv ? (const void*)xpd::k_step_g<8, true> : (const void*)xpd::k_step_g<8, false>;
+                per_cell_groups = 8;
+                break;
             }
             const size_t lds = sched >= 4 ? (size_t)per_cell_groups * ((lds1 + 15) & ~size_t(15)) : lds1;
             if (lds > ctx->max_lds) return fail(XP_ERR_UNSUPPORTED, "LDS plan too large");

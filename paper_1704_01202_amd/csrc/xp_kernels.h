@@ -61,11 +61,13 @@ size_t step_lds_bytes(int ce, int ci);
 void lds_limits(size_t max_lds, int* e_lds, int* i_lds);
 size_t lds_budget(size_t max_lds);
 
-template <int B>
+// XV: compiled with the method's variants (XP_THERM, XP_ION_Z); the plain
+// step leaves them out, which keeps its registers for the main path.
+template <int B, bool XV>
 __global__ void k_step(StepArgs a);
 // 64 / W cells per wave, W lanes per cell (W = 32, 16, 8); plans with at most
 // 4 W electrons and 4 W ions.
-template <int W>
+template <int W, bool XV>
 __global__ void k_step_g(StepArgs a);
 
 }  // namespace xpd

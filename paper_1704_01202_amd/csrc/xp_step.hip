@@ -179,7 +179,7 @@ __host__ __device__ size_t step_lds_bytes_dev(int ce, int ci)
     return n;
 }
 
-template <class T>
+template <class T, bool XV>
 __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, const Lds& L);
 
 size_t step_lds_bytes(int ce, int ci) { return step_lds_bytes_dev(ce, ci); }
@@ -192,7 +192,7 @@ size_t step_lds_bytes(int ce, int ci) { return step_lds_bytes_dev(ce, ci); }
 // rather than per cell.  Three waves per SIMD: the step is bound by the
 // latency of its FP64 chains, and the register budget of three waves holds it
 // with almost no spilling.
-template <int B>
+template <int B, bool XV>
 __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(3))) void k_step(StepArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(3))) void k_s
     const int nitems = a.cell_list ? *a.cell_list_count : a.n_cells;
     for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
         const int cell = a.cell_list ? a.cell_list[item] : item;
-        const bool done = step_cell<BlockTeam<B>>(a, cell, S, L);
+        const bool done = step_cell<BlockTeam<B>, XV>(a, cell, S, L);
         __syncthreads();
         if (done) {
             const int run = a.cell_run[cell];
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(3))) void k_s
 // records are summed per group and flushed like those of k_step.  Per-cell
 // values differ between the groups of a wave, so they live in vector
 // registers: two waves per SIMD, each carrying G cells.
-template <int W>
+template <int W, bool XV>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_step_g(StepArgs a)
 {
     constexpr int G = 64 / W;
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     for (int it = blockIdx.x; it * G < nitems; it += gridDim.x) {
         const int item = it * G + g;
         const int cell = item < nitems ? (a.cell_list ? a.cell_list[item] : item) : -1;
-        const bool done = step_cell<T>(a, cell, S[g], L);
+        const bool done = step_cell<T, XV>(a, cell, S[g], L);
         T::sync();
         if (done) {
             const int run = a.cell_run[cell];
@@ -392,7 +392,7 @@ __device__ __noinline__ void make_perm_fn(int n, uint32_t c0, uint32_t c1, uint3
 
 // Steps one cell; true when its new state was committed (the caller then adds
 // S.cnt / S.led to the run records and S.ints[6] holds its electron count).
-template <class T>
+template <class T, bool XV>
 __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, const Lds& L)
 {
     constexpr int B = T::N;
@@ -639,7 +639,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
         const int ne0 = ne;
         // the charge states whose cross section is evaluated: the average
         // cell ion Z_c, or (XP_ION_Z) every state an ion of the cell holds
-        const bool perz = (flags & XP_ION_Z) != 0;
+        const bool perz = XV && (flags & XP_ION_Z) != 0;
         if (perz) {
             uint32_t ml = 0;
             for (int i = tid; i < ni; i += B)
@@ -650,7 +650,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
         const uint32_t zmask = perz ? (uint32_t)S.ints[2] : (zc < 13 ? 1u << zc : 0u);
         if (tid == 0) S.mom[11] = perz ? (double)__popc(zmask) : (double)zc;
         if (zmask) {
-            double pmax = 0.0;
+            double pmax = 0.0, pavg = 0.0;
 #pragma unroll 1
             for (int z = 0; z < 13; ++z) {
                 if (!(zmask & (1u << z))) continue;
@@ -675,16 +675,17 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
                     p = 1.0;
                     if (tid == 0) S.cnt[XP_C_P_CLAMPED] += 1;
                 }
-                if (tid == 0) S.pz[z] = p;
+                if (perz && tid == 0) S.pz[z] = p;
                 if (p > pmax) pmax = p;
+                pavg = p;
             }
             if (tid == 0) S.mom[12] = pmax;
-            T::sync();
+            if (perz) T::sync();
             const int nfired = T::select(
                 ni,
                 [&](int i) {
                     if (L.iz[i] >= 13) return false;
-                    const double p = S.pz[perz ? L.iz[i] : zc];
+                    const double p = perz ? S.pz[L.iz[i]] : pavg;
                     if (!(p > 0.0)) return false;
                     const Words d = rng((uint32_t)i, RP_ION, 0);
                     L.fw[3 * i] = d.x1;
@@ -1060,7 +1061,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
     }
 
     // ------------- forced thermalization (variant, Sec. VI.C) -------------
-    if (!overflow && !deferred && (flags & XP_THERM)) {
+    if (XV && !overflow && !deferred && (flags & XP_THERM)) {
         long long wl = 0;
         for (int j = tid; j < ne; j += B) wl += L.ew[j];
         const long long ws = T::isum(wl, S);
@@ -1172,11 +1173,16 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
     return true;
 }
 
-template __global__ void k_step<64>(StepArgs);
-template __global__ void k_step<256>(StepArgs);
-template __global__ void k_step_g<32>(StepArgs);
-template __global__ void k_step_g<16>(StepArgs);
-template __global__ void k_step_g<8>(StepArgs);
+template __global__ void k_step<64, false>(StepArgs);
+template __global__ void k_step<256, false>(StepArgs);
+template __global__ void k_step_g<32, false>(StepArgs);
+template __global__ void k_step_g<16, false>(StepArgs);
+template __global__ void k_step_g<8, false>(StepArgs);
+template __global__ void k_step<64, true>(StepArgs);
+template __global__ void k_step<256, true>(StepArgs);
+template __global__ void k_step_g<32, true>(StepArgs);
+template __global__ void k_step_g<16, true>(StepArgs);
+template __global__ void k_step_g<8, true>(StepArgs);
 
 __global__ void k_step_prep(int32_t* counts, int32_t* stats)
 {
