@@ -325,7 +325,9 @@ def bench_c5(args):
     torch.cuda.synchronize()
     log("pool: %d electron slots, %d ion slots, workspace %.1f GB"
         % (pool.E, pool.I, pool.work_bytes / 2**30))
-    recs, waited = SV.serve(pool, trace, k=args.serve_k)
+    def served_one(pool_, r, rec):
+        log("served request %d (%d steps) done at %.1f s" % (rec["rid"], rec["steps"], rec["done"]))
+    recs, waited = SV.serve(pool, trace, k=args.serve_k, on_done=served_one)
     served = SV.latency_summary(recs)
     status = pool.status()
     log("served: %s; peak resident %d, longest queue %d, status %d"
@@ -334,7 +336,8 @@ def bench_c5(args):
     coll = sum(int(r["counters"][0] + r["counters"][1] + r["counters"][2]) for r in recs.values())
     del pool
     torch.cuda.empty_cache()
-    seq_recs = SV.sequential(ctx, trace, capacity=cap)
+    seq_recs = SV.sequential(ctx, trace, capacity=cap, on_done=lambda rec: log(
+        "sequential request %d (%d steps) done at %.1f s" % (rec["rid"], rec["steps"], rec["done"])))
     seq = SV.latency_summary(seq_recs)
     seq["status"] = max(r.get("status", 0) for r in seq_recs.values())
     log("sequential: %s" % seq)
@@ -390,7 +393,8 @@ def main():
     ap.add_argument("--size-hi", type=float, default=2e6, help="c5: largest run, particles")
     ap.add_argument("--steps-lo", type=int, default=100, help="c5: fewest steps of a run")
     ap.add_argument("--steps-hi", type=int, default=600, help="c5: most steps of a run")
-    ap.add_argument("--budget-gb", type=float, default=64.0, help="c5: pool budget, GiB")
+    ap.add_argument("--budget-gb", type=float, default=200.0,
+                    help="c5: pool budget (slabs and workspace), GiB")
     ap.add_argument("--serve-k", type=int, default=8, help="c5: steps between admission checks")
     ap.add_argument("--runs", type=int, default=256, help="c4: runs in the scan")
     ap.add_argument("--run-steps", type=int, default=500, help="c4: steps of every run")

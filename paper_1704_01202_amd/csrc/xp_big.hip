@@ -418,7 +418,19 @@ __global__ __launch_bounds__(1024) void k_big_rscan(BigArgs a, int species, int 
         const int k0 = qt * per, k1 = k0 + per < nc ? k0 + per : nc;
         uint32_t* h = a.hist + (size_t)256 * c0 + d;
         uint32_t run = 0;
-        for (int k = k0; k < k1; ++k) {
+        int k = k0;
+        // eight loads in flight at a time: the walk is bound by memory latency
+        for (; k + 8 <= k1; k += 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = h[(size_t)256 * (k + u)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                h[(size_t)256 * (k + u)] = run;
+                run += v[u];
+            }
+        }
+        for (; k < k1; ++k) {
             const uint32_t v = h[(size_t)256 * k];
             h[(size_t)256 * k] = run;
             run += v;
@@ -441,8 +453,17 @@ __global__ __launch_bounds__(1024) void k_big_rscan(BigArgs a, int species, int 
             for (int q = 0; q < 4; ++q) qsum[q][d] += dbase;
         __syncthreads();
         const uint32_t off = qsum[qt][d];
-        if (off)
-            for (int k = k0; k < k1; ++k) h[(size_t)256 * k] += off;
+        if (off) {
+            int k2 = k0;
+            for (; k2 + 8 <= k1; k2 += 8) {
+                uint32_t v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = h[(size_t)256 * (k2 + u)];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) h[(size_t)256 * (k2 + u)] = v[u] + off;
+            }
+            for (; k2 < k1; ++k2) h[(size_t)256 * k2] += off;
+        }
         __syncthreads();
     }
 }
@@ -940,20 +961,17 @@ __global__ __launch_bounds__(BT) void k_big_firelist(BigArgs a)
     }
 }
 
-__device__ __forceinline__ double readlane_f64(double v, int lane)
-{
-    const uint64_t b = (uint64_t)__double_as_longlong(v);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
-    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-
 // One wave per cell: K_th, then the fired ions accepted in slot order while
-// the running debit (a left-to-right sum) stays within K_th.  The wave loads
-// 64 potentials at a time and walks them with lane reads.
+// the running debit (a left-to-right sum) stays within K_th.  The wave stages
+// 64 potentials at a time in LDS (the next 64 already loading) and first adds
+// all of them in order: the potentials are positive and rounding is
+// monotone, so if the block's running sum stays within K_th (and the slab has
+// room) every ion of the block is accepted with exactly that sum.  Only the
+// block where the walk stops is walked again ion by ion.
 __global__ __launch_bounds__(64) void k_big_accept(BigArgs a)
 {
     __shared__ double red[2 * (BIG_MAX_CHUNKS / 64)];
+    __shared__ double blk[64];
     const int lane = threadIdx.x;
     const StepArgs& s = a.s;
     const int nb = a.hdr->count;
@@ -964,14 +982,27 @@ __global__ __launch_bounds__(64) void k_big_accept(BigArgs a)
         const int ne0 = r.ne0;
         const int nfired = (int)r.nfired;
         const int room = r.ecap - ne0;
+        const double* fip = a.fip + r.ip0;
         double debit = 0.0;
         int acc = 0;
         bool stop = false, over = false;
+        double next = lane < nfired ? fip[lane] : 0.0;
         for (int t0 = 0; t0 < nfired && !stop; t0 += 64) {
             const int m = nfired - t0 < 64 ? nfired - t0 : 64;
-            const double ip = lane < m ? a.fip[r.ip0 + t0 + lane] : 0.0;
+            __syncthreads();
+            blk[lane] = next;   // +0 beyond the fired ions: adds nothing
+            __syncthreads();
+            next = t0 + 64 + lane < nfired ? fip[t0 + 64 + lane] : 0.0;
+            double run = debit;
+#pragma unroll 16
+            for (int l = 0; l < 64; ++l) run = run + blk[l];
+            if (run <= kth && acc + m <= room) {
+                debit = run;
+                acc += m;
+                continue;
+            }
             for (int l = 0; l < m; ++l) {
-                const double ipv = readlane_f64(ip, l);
+                const double ipv = blk[l];
                 if (!(debit + ipv <= kth)) {
                     stop = true;
                     break;

@@ -32,10 +32,10 @@ import torch
 from . import binding as B
 from . import runtime as RT
 
-# device bytes per slot: particle arrays plus the global-memory path's
-# per-particle workspace
-E_SLOT_BYTES = 44 + 20
-I_SLOT_BYTES = 42 + 21
+# device bytes per slot of the particle arrays (the step's workspace for the
+# same slots is sized by the library and counted in the budget as well)
+E_SLOT_BYTES = 44
+I_SLOT_BYTES = 42
 
 
 class RangeAlloc:
@@ -101,9 +101,22 @@ class Pool:
         dev = ctx.device
         self.device = dev
         self.capacity = B.XpCapacity(int(capacity[0]), int(capacity[1]))
-        self.E = int(budget_bytes * e_share) // E_SLOT_BYTES
-        self.I = int(budget_bytes * (1.0 - e_share)) // I_SLOT_BYTES
         self.max_cells, self.max_runs = int(max_cells), int(max_runs)
+        # the budget covers the slabs and the step's workspace for any set of
+        # resident runs (every slot possibly on the global-memory path)
+        scale = 1.0
+        for _ in range(6):
+            self.E = int(budget_bytes * scale * e_share) // E_SLOT_BYTES
+            self.I = int(budget_bytes * scale * (1.0 - e_share)) // I_SLOT_BYTES
+            sizing = B.XpBatch()
+            sizing.n_runs, sizing.n_cells = self.max_runs, self.max_cells
+            sizing.big_cells_max = self.max_cells
+            sizing.big_e_slots, sizing.big_i_slots = self.E, self.I
+            work = B.xp_step_work_bytes(sizing)
+            total = self.E * E_SLOT_BYTES + self.I * I_SLOT_BYTES + work
+            if total <= budget_bytes:
+                break
+            scale *= 0.995 * budget_bytes / total
         f64 = lambda n: torch.empty(n, dtype=torch.float64, device=dev)
         E, I = max(self.E, 1), max(self.I, 1)
         self.ex, self.ey, self.evx, self.evy, self.evz = (f64(E) for _ in range(5))
@@ -383,9 +396,9 @@ def serve(pool: Pool, trace, k=8, on_done=None, clock=time.perf_counter):
     return out, waited
 
 
-def sequential(ctx: RT.Context, trace, capacity=(7, 16), clock=time.perf_counter):
+def sequential(ctx: RT.Context, trace, capacity=(7, 16), clock=time.perf_counter, on_done=None):
     """The plain baseline: first come, first served, one run at a time, each
-    alone in its own batch with eager steps."""
+    alone in its own batch with eager steps.  on_done(record) after each run."""
     out = {}
     t0 = clock()
     for q in sorted(trace, key=lambda q: q.arrival):
@@ -401,6 +414,8 @@ def sequential(ctx: RT.Context, trace, capacity=(7, 16), clock=time.perf_counter
         out[q.rid] = {"rid": q.rid, "arrival": q.arrival, "admit": start, "done": t,
                       "ttr": t - q.arrival, "steps": q.nsteps,
                       "counters": bat.run_counters()[0].copy(), "status": bat.status()}
+        if on_done is not None:
+            on_done(out[q.rid])
         del bat
     return out
 
