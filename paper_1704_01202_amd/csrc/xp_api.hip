@@ -374,8 +374,10 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
             ce = ((ce + 15) / 16) * 16;
             if (ce > ce_top) ce = ce_top;
         }
-        // the variants are compiled into their own kernels
-        const bool xv = (flags & (XP_THERM | XP_ION_Z)) != 0;
+        // the variants, per-cell records and per-cell photon fields are
+        // compiled into their own kernels
+        const bool xv = (flags & (XP_THERM | XP_ION_Z)) != 0 || b->d_cell_counters || b->d_cell_ledger ||
+                        b->d_cell_moments || b->d_cell_nhv;
         for (int tier = 0;; ++tier) {
             const bool last = ce >= ce_top || tier >= xpd::BIG_COUNT_SLOT - 1;
             a.lds_ce = ce;

@@ -61,8 +61,9 @@ size_t step_lds_bytes(int ce, int ci);
 void lds_limits(size_t max_lds, int* e_lds, int* i_lds);
 size_t lds_budget(size_t max_lds);
 
-// XV: compiled with the method's variants (XP_THERM, XP_ION_Z); the plain
-// step leaves them out, which keeps its registers for the main path.
+// XV: compiled with the method's variants (XP_THERM, XP_ION_Z), the per-cell
+// records and per-cell photon fields; the plain step leaves them out, which
+// keeps its registers for the main path.
 template <int B, bool XV>
 __global__ void k_step(StepArgs a);
 // 64 / W cells per wave, W lanes per cell (W = 32, 16, 8); plans with at most

@@ -895,7 +895,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
     if (!overflow && !deferred && (flags & (XP_PHOTO | XP_DECAY))) {
         const int nb = R->n_bins;
         const bool photo = (flags & XP_PHOTO) && nb > 0;
-        const double* nhv = (R->field_per_cell && a.cell_nhv) ? a.cell_nhv + (size_t)cell * XP_MAX_BINS : R->nhv;
+        const double* nhv = (XV && R->field_per_cell && a.cell_nhv) ? a.cell_nhv + (size_t)cell * XP_MAX_BINS : R->nhv;
         const double dtr = R->dt_rad;
         if (photo) {
             const double* rs = a.run_sig + (size_t)run * (XP_MAX_BINS * 3);
@@ -1164,11 +1164,11 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
         a.e_cnt[cell] = ne;
         S.ints[6] = ne;
     }
-    if (a.cell_cnt)
+    if (XV && a.cell_cnt)
         for (int q = tid; q < XP_NCOUNT; q += B) a.cell_cnt[(size_t)cell * XP_NCOUNT + q] = S.cnt[q];
-    if (a.cell_led)
+    if (XV && a.cell_led)
         for (int q = tid; q < XP_NLEDGER; q += B) a.cell_led[(size_t)cell * XP_NLEDGER + q] = S.led[q];
-    if (a.cell_mom)
+    if (XV && a.cell_mom)
         for (int q = tid; q < XP_NMOM; q += B) a.cell_mom[(size_t)cell * XP_NMOM + q] = S.mom[q];
     return true;
 }
