@@ -401,8 +401,9 @@ def main():
     ap.add_argument("--no-seq", action="store_true", help="c4: skip the sequential leg (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the step has no cross-GPU work here and only "
-              "--gpus 1 is supported (see DESIGN.md for how runs and cells would shard)",
+        print("bench.py measures one GPU: the step has no cross-GPU work and only --gpus 1 "
+              "is supported (cells and runs are independent within a step; a multi-GPU run "
+              "would shard them by cell slab or by run)",
               file=sys.stderr)
         sys.exit(2)
 

@@ -40,7 +40,7 @@ typedef int32_t xp_status;
 #define XP_ERR_HIP             -2   /* a HIP runtime call failed */
 #define XP_ERR_TOO_SMALL       -3   /* a caller buffer is smaller than required */
 #define XP_ERR_NOT_INITIALIZED -4   /* init_species has not been called */
-#define XP_ERR_UNSUPPORTED     -5   /* size beyond what this build supports */
+#define XP_ERR_UNSUPPORTED     -5   /* size beyond what the library supports */
 
 /* Stage switches (xp_step_params.flags).  Order within a step is always
  * moments -> e-e -> e-i -> ionization -> recombination -> decay/photo
