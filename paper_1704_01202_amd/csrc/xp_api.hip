@@ -337,6 +337,8 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
         g.sel = (int32_t*)(w + bp.sel);
         g.fip = (double*)(w + bp.fip);
         g.partz = (double*)(w + bp.partz);
+        g.ev4 = (double*)(w + bp.ev4);
+        g.iv4 = (double*)(w + bp.iv4);
         const size_t ev_stride = ((8 * (size_t)(b->big_e_slots > 0 ? b->big_e_slots : 1) + 255) & ~size_t(255));
         const size_t iv_stride = ((8 * (size_t)(b->big_i_slots > 0 ? b->big_i_slots : 1) + 255) & ~size_t(255));
         for (int q = 0; q < 3; ++q) {

@@ -198,12 +198,22 @@ __global__ __launch_bounds__(BT) void k_big_s0(BigArgs a)
         const int64_t o = r.eo + base;
         long long wl = 0, bl = 0;
         bool bad = false;
+        // the collisions gather electrons in permutation order: one 32-byte
+        // record per electron in slot order turns three random reads into one
+        const bool stage = (s.flags & (XP_EE | XP_EI)) != 0;
+        double* e4 = a.ev4 + 4 * (r.ep0 + base);
         for (int j = tid; j < n; j += BT) {
             const double x = s.evx[o + j], y = s.evy[o + j], z = s.evz[o + j];
             bad |= !(__builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z));
             const long long w = s.ew[o + j];
             wl += w;
             if (HALF_ME_OVER_QE * ((x * x + y * y) + z * z) < ebulk) bl += w;
+            if (stage) {
+                e4[4 * j] = x;
+                e4[4 * j + 1] = y;
+                e4[4 * j + 2] = z;
+                e4[4 * j + 3] = (double)w;
+            }
         }
         if (bad) atomicOr(s.status, XP_ST_NONFINITE);
         const long long we = block_isum<BT>(wl, ired);
@@ -227,11 +237,19 @@ __global__ __launch_bounds__(BT) void k_big_s0(BigArgs a)
         const int64_t o = r.io + base;
         long long s1 = 0, s2 = 0;
         uint32_t zm = 0;
+        const bool stage = (s.flags & XP_EI) != 0;
+        double* i4 = a.iv4 + 4 * (r.ip0 + base);
         for (int j = tid; j < n; j += BT) {
             const long long z = s.iz[o + j];
             s1 += z;
             s2 += z * z;
             if (z < 13) zm |= 1u << z;
+            if (stage) {
+                i4[4 * j] = s.ivx[o + j];
+                i4[4 * j + 1] = s.ivy[o + j];
+                i4[4 * j + 2] = s.ivz[o + j];
+                i4[4 * j + 3] = (double)z;
+            }
         }
         s1 = block_isum<BT>(s1, ired);
         s2 = block_isum<BT>(s2, ired);
@@ -568,36 +586,70 @@ __global__ __launch_bounds__(BT) void k_big_gather(BigArgs a, int species, int s
         const int64_t pop = species == 0 ? r.ep0 : r.ip0;
         const int base = (g - c0) * BIG_CH;
         const int n = cnt - base < BIG_CH ? cnt - base : BIG_CH;
+        // the slot-order side is the 32-byte records staged by k_big_s0 (one
+        // random access per particle); the rank-order side is coalesced
         if (species == 0) {
             const uint32_t* perm = a.val_a + pop;
             for (int q = threadIdx.x; q < n; q += BT) {
-                const int64_t gi = pop + base + q, sl = r.eo + perm[base + q];
+                const int64_t gi = pop + base + q;
+                double* rec = a.ev4 + 4 * (pop + perm[base + q]);
                 if (!scatter) {
-                    a.gev[0][gi] = s.evx[sl];
-                    a.gev[1][gi] = s.evy[sl];
-                    a.gev[2][gi] = s.evz[sl];
-                    a.gew[gi] = s.ew[sl];
+                    const double2 xy = *(const double2*)rec, zw = *(const double2*)(rec + 2);
+                    a.gev[0][gi] = xy.x;
+                    a.gev[1][gi] = xy.y;
+                    a.gev[2][gi] = zw.x;
+                    a.gew[gi] = (uint32_t)zw.y;
                 } else {
-                    s.evx[sl] = a.gev[0][gi];
-                    s.evy[sl] = a.gev[1][gi];
-                    s.evz[sl] = a.gev[2][gi];
+                    *(double2*)rec = make_double2(a.gev[0][gi], a.gev[1][gi]);
+                    *(double2*)(rec + 2) = make_double2(a.gev[2][gi], (double)a.gew[gi]);
                 }
             }
         } else {
             const uint32_t* perm = a.val_c + pop;
             for (int q = threadIdx.x; q < n; q += BT) {
-                const int64_t gi = pop + base + q, sl = r.io + perm[base + q];
+                const int64_t gi = pop + base + q;
+                double* rec = a.iv4 + 4 * (pop + perm[base + q]);
                 if (!scatter) {
-                    a.giv[0][gi] = s.ivx[sl];
-                    a.giv[1][gi] = s.ivy[sl];
-                    a.giv[2][gi] = s.ivz[sl];
-                    a.giz[gi] = s.iz[sl];
+                    const double2 xy = *(const double2*)rec, zw = *(const double2*)(rec + 2);
+                    a.giv[0][gi] = xy.x;
+                    a.giv[1][gi] = xy.y;
+                    a.giv[2][gi] = zw.x;
+                    a.giz[gi] = (uint8_t)zw.y;
                 } else {
-                    s.ivx[sl] = a.giv[0][gi];
-                    s.ivy[sl] = a.giv[1][gi];
-                    s.ivz[sl] = a.giv[2][gi];
+                    *(double2*)rec = make_double2(a.giv[0][gi], a.giv[1][gi]);
+                    *(double2*)(rec + 2) = make_double2(a.giv[2][gi], (double)a.giz[gi]);
                 }
             }
+        }
+    }
+}
+
+// After the collisions: the staged records back into the particle arrays, in
+// slot order (coalesced).
+__global__ __launch_bounds__(BT) void k_big_unstage(BigArgs a, int species)
+{
+    const StepArgs& s = a.s;
+    const int nch = species == 0 ? a.hdr->n_e_chunks : a.hdr->n_i_chunks;
+    const int32_t* map = species == 0 ? a.e_chunk_cell : a.i_chunk_cell;
+    const int needbit = species == 0 ? BN_PERM_E : BN_EI;
+    for (int g = blockIdx.x; g < nch; g += gridDim.x) {
+        const BigRec& r = a.rec[map[g]];
+        if (!big_live(r, needbit)) continue;
+        const int c0 = species == 0 ? r.ce0 : r.ci0;
+        const int cnt = species == 0 ? r.epn : r.ni;
+        const int64_t pop = species == 0 ? r.ep0 : r.ip0;
+        const int base = (g - c0) * BIG_CH;
+        const int n = cnt - base < BIG_CH ? cnt - base : BIG_CH;
+        const int64_t o = (species == 0 ? r.eo : r.io) + base;
+        const double* rec = (species == 0 ? a.ev4 : a.iv4) + 4 * (pop + base);
+        double* vx = species == 0 ? s.evx : s.ivx;
+        double* vy = species == 0 ? s.evy : s.ivy;
+        double* vz = species == 0 ? s.evz : s.ivz;
+        for (int q = threadIdx.x; q < n; q += BT) {
+            const double2 xy = *(const double2*)(rec + 4 * q);
+            vx[o + q] = xy.x;
+            vy[o + q] = xy.y;
+            vz[o + q] = rec[4 * q + 2];
         }
     }
 }
@@ -1813,6 +1865,8 @@ BigPlan big_plan(int32_t big_max, int64_t e_pop, int64_t i_pop)
     p.giv = o; o += 3 * up(8 * (size_t)ip);
     p.giz = o; o += up((size_t)ip);
     p.partz = o; o += 13 * up(8 * (size_t)p.e_chunks);
+    p.ev4 = o; o += up(32 * (size_t)ep);
+    p.iv4 = o; o += up(32 * (size_t)ip);
     p.bytes = o;
     return p;
 }
@@ -1865,8 +1919,10 @@ hipError_t big_launch(BigArgs& a, bool all_cells, hipStream_t s)
             hipLaunchKernelGGL(k_big_gather, dim3(gch), dim3(BT), 0, s, a, 1, 0);
             hipLaunchKernelGGL(k_big_ei, dim3(gch), dim3(BT), 0, s, a);
             hipLaunchKernelGGL(k_big_gather, dim3(gch), dim3(BT), 0, s, a, 1, 1);
+            hipLaunchKernelGGL(k_big_unstage, dim3(gch), dim3(BT), 0, s, a, 1);
         }
         hipLaunchKernelGGL(k_big_gather, dim3(gch), dim3(BT), 0, s, a, 0, 1);
+        hipLaunchKernelGGL(k_big_unstage, dim3(gch), dim3(BT), 0, s, a, 0);
     }
     if (flags & XP_ION) {
         hipLaunchKernelGGL(k_big_lotz, dim3(gch), dim3(BT), 0, s, a);

@@ -192,6 +192,8 @@ struct BigArgs {
     int32_t* sel;               // per ion selected for recombination (S4)
     double* fip;                // per fired ion (rank order) lowered potential (S3)
     double* partz;              // [13][e_chunks_max] per charge state chunk sums (S3)
+    double* ev4;                // [e_pop][4] electron (vx, vy, vz, w) in slot order (S1, S2)
+    double* iv4;                // [i_pop][4] ion (vx, vy, vz, Z) in slot order (S2)
     double* gev[3];             // electron velocities in permutation-rank order (S1, S2)
     uint32_t* gew;              // electron weights in rank order
     double* giv[3];             // ion velocities in rank order (S2)
@@ -204,7 +206,7 @@ struct BigArgs {
 
 struct BigPlan {
     size_t list, hdr, rec, e_chunk_cell, i_chunk_cell, part, key_a, val_a, key_b, val_b, key_c,
-        val_c, hist, iflag, ccnt, iaux, wp, sel, fip, gev, gew, giv, giz, partz;
+        val_c, hist, iflag, ccnt, iaux, wp, sel, fip, gev, gew, giv, giz, partz, ev4, iv4;
     size_t bytes;
     int32_t e_chunks, i_chunks;
 };
