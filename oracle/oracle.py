@@ -27,6 +27,7 @@ EE, EI, ION, REC, PHOTO, DECAY = 0x01, 0x02, 0x04, 0x08, 0x10, 0x20
 ALL = EE | EI | ION | REC | PHOTO | DECAY
 THERM = 0x40   # variant: forced thermalization after S5 (Sec. VI.C), not in ALL
 ION_Z = 0x80   # variant: S3 cross section per ion charge state (Sec. IV), not in ALL
+NANBU = 0x100  # variant: Nanbu's cumulative scattering law in S1, S2, not in ALL
 
 COUNTERS = ["EE", "EI", "TRIPLET", "ACCEPT", "U0", "DELTA2_GT1",
             "ION_FIRED", "ION_ACCEPTED", "ION_STARVED",
@@ -110,6 +111,10 @@ def lib():
         L.orc_coulomb_log.restype = d; L.orc_coulomb_log.argtypes = [d, d, d]
         L.orc_ta77.restype = d
         L.orc_ta77.argtypes = [vp, vp, d, d, u32, u32, d, d, vp, vp, vp]
+        L.orc_collide.restype = d
+        L.orc_collide.argtypes = [vp, vp, d, d, u32, u32, d, d, vp, i32, vp, vp]
+        L.orc_nanbu_a.restype = d; L.orc_nanbu_a.argtypes = [d]
+        L.orc_nanbu_omc.restype = d; L.orc_nanbu_omc.argtypes = [d, d]
         L.orc_u32.restype = d; L.orc_u32.argtypes = [u32]
         L.orc_create.restype = vp; L.orc_create.argtypes = [vp, vp]
         L.orc_destroy.restype = None; L.orc_destroy.argtypes = [vp]
@@ -269,6 +274,25 @@ def ta77(va, vb, ma, mb, wa, wb, coef, nunit, draws):
     d2 = lib().orc_ta77(_p(va), _p(vb), float(ma), float(mb), int(wa), int(wb),
                         float(coef), float(nunit), _p(d), C.byref(aa), C.byref(ab))
     return va, vb, d2, aa.value, ab.value
+
+
+def collide(va, vb, ma, mb, wa, wb, coef, nunit, draws, law):
+    """One collision with scattering law 0 (Takizuka-Abe) or 1 (Nanbu)."""
+    va = np.array(va, dtype=np.float64)
+    vb = np.array(vb, dtype=np.float64)
+    d = np.ascontiguousarray(draws, dtype=np.uint32)
+    aa, ab = C.c_int32(), C.c_int32()
+    d2 = lib().orc_collide(_p(va), _p(vb), float(ma), float(mb), int(wa), int(wb),
+                           float(coef), float(nunit), _p(d), int(law), C.byref(aa), C.byref(ab))
+    return va, vb, d2, aa.value, ab.value
+
+
+def nanbu_a(s):
+    return lib().orc_nanbu_a(float(s))
+
+
+def nanbu_omc(s, u):
+    return lib().orc_nanbu_omc(float(s), float(u))
 
 
 # --- whole-run simulation -----------------------------------------------------

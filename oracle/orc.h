@@ -42,6 +42,7 @@ extern "C" {
 #define ORC_DECAY   0x20u
 #define ORC_THERM   0x40u   /* variant: forced thermalization after S5 (Sec. VI.C) */
 #define ORC_ION_Z   0x80u   /* variant: S3 cross section per ion charge state (Sec. IV) */
+#define ORC_NANBU   0x100u  /* variant: Nanbu's cumulative scattering law in S1, S2 */
 
 /* Per-cell, per-step event counters. */
 enum {
@@ -121,6 +122,13 @@ double orc_coulomb_log(double t_ev, double n_e, double zbar);
 double orc_ta77(double va[3], double vb[3], double ma, double mb, uint32_t wa,
                 uint32_t wb, double qq_coef, double nunit, const uint32_t draws[4],
                 int32_t *accept_a, int32_t *accept_b);
+/* The same collision with the scattering law chosen: 0 Takizuka-Abe, 1 Nanbu. */
+double orc_collide(double va[3], double vb[3], double ma, double mb, uint32_t wa,
+                   uint32_t wb, double qq_coef, double nunit, const uint32_t draws[4],
+                   int32_t law, int32_t *accept_a, int32_t *accept_b);
+/* Nanbu (1997): A with coth A - 1/A = exp(-s), and 1 - cos chi for uniform u. */
+double orc_nanbu_a(double s);
+double orc_nanbu_omc(double s, double u);
 
 /* --- simulation of one run --- */
 orc_sim *orc_create(const orc_tables *t, const orc_run *r);

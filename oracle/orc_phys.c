@@ -147,21 +147,107 @@ double orc_photo_sigma(const orc_tables *t, int32_t s, double hv)
     return orc_exp(ls) * 1.0e-4;
 }
 
+/* Nanbu's cumulative small-angle scattering (Nanbu, Phys. Rev. E 55, 4642
+ * (1997)): over one step the many small deflections of a pair add up to one
+ * angle chi whose cosine has the density A exp(A cos chi) / (2 sinh A), with A
+ * fixed by the mean deflection, <cos chi> = coth A - 1/A = exp(-s).
+ *
+ * orc_nanbu_a(s) returns that A.
+ *   s <= 0.05: A >= 20, where coth A differs from 1 by less than 2 exp(-40),
+ *     so the equation reads 1 - 1/A = exp(-s): A = 1 / (1 - exp(-s)), with
+ *     1 - exp(-s) from its series s (1 - s/2 (1 - s/3 (1 - ... (1 - s/11)))).
+ *   0.05 < s < 15: four Newton steps on L(A) = coth A - 1/A = m, m = exp(-s),
+ *     from the Pade start A = m (3 - m^2) / (1 - m^2).  L and L' come from the
+ *     Laurent series of coth (Bernoulli coefficients 2^2n B_2n / (2n)!,
+ *     eleven terms) for A < 0.5 and from E = exp(-2A) above:
+ *     L = (1 + E) / (1 - E) - 1/A, L' = 1/A^2 - 4E / (1 - E)^2.
+ *   s >= 15: 0, the isotropic limit (<cos chi> = exp(-15) = 3e-7).
+ * Pinned by tests/test_oracle_nanbu.py: L(A) against exp(-s) in 50-digit
+ * decimal arithmetic, the sampled law against its distribution function, and
+ * the composition of deflections over steps. */
+static void langevin(double a, double *l, double *dl)
+{
+    if (a < 0.5) {
+        static const double c[11] = {
+            1.0 / 3.0, -1.0 / 45.0, 2.0 / 945.0, -1.0 / 4725.0, 2.0 / 93555.0,
+            -1382.0 / 638512875.0, 4.0 / 18243225.0, -3617.0 / 162820783125.0,
+            87734.0 / 38979295480125.0, -349222.0 / 1531329465290625.0,
+            310732.0 / 13447856940643125.0};
+        double z = a * a;
+        double v = c[10], dv = 21.0 * c[10];
+        for (int k = 9; k >= 0; --k) {
+            v = c[k] + z * v;
+            dv = (double)(2 * k + 1) * c[k] + z * dv;
+        }
+        *l = a * v;
+        *dl = dv;
+        return;
+    }
+    double e = orc_exp(-2.0 * a);
+    double ome = 1.0 - e;
+    *l = (1.0 + e) / ome - 1.0 / a;
+    *dl = 1.0 / (a * a) - (4.0 * e) / (ome * ome);
+}
+
+double orc_nanbu_a(double s)
+{
+    if (s >= 15.0) return 0.0;
+    if (s <= 0.05) {
+        double q = 1.0;
+        for (int k = 11; k >= 2; --k) q = 1.0 - (s * (1.0 / (double)k)) * q;
+        return 1.0 / (s * q);
+    }
+    double m = orc_exp(-s);
+    double m2 = m * m;
+    double a = (m * (3.0 - m2)) / (1.0 - m2);
+    for (int it = 0; it < 4; ++it) {
+        double l, dl;
+        langevin(a, &l, &dl);
+        a = a - (l - m) / dl;
+    }
+    return a;
+}
+
+/* 1 - cos chi for s and a uniform u in (0, 1): inverting the distribution
+ * function, cos chi = 1 + ln(u + (1 - u) exp(-2A)) / A; for A = 0 (isotropic)
+ * cos chi = 2u - 1.  Clamped to [0, 2]; s <= 0 gives no deflection. */
+double orc_nanbu_omc(double s, double u)
+{
+    if (!(s > 0.0)) return 0.0;
+    double a = orc_nanbu_a(s);
+    double omc;
+    if (a == 0.0) {
+        omc = 2.0 * (1.0 - u);
+    } else {
+        double e2 = orc_exp(-2.0 * a);
+        omc = -orc_log(u + (1.0 - u) * e2) / a;
+    }
+    if (omc < 0.0) omc = 0.0;
+    if (omc > 2.0) omc = 2.0;
+    return omc;
+}
+
 /*
  * One binary Coulomb collision (Takizuka & Abe, J. Comput. Phys. 25, 205
  * (1977)), non-relativistic, with weighted acceptance.
  *   qq_coef = q_a^2 q_b^2 lnL dt / (8 pi eps0^2 m_ab^2)  (per unit density),
- *   <delta^2> = qq_coef * max(w_a, w_b) * nunit / u^3,
- *   delta = sqrt(<delta^2>) * sqrt(-2 ln r1) cos(2 pi r2), Phi = 2 pi r3,
- *   sin(Theta) = 2 delta/(1+delta^2), 1 - cos(Theta) = 2 delta^2/(1+delta^2);
- *   the heavier-weight side accepts with probability w_light / w_heavy (r4).
- * draws = the four Philox words of the pair: [0] -> r1, [1] -> the angle
- * 2 pi r2, [2] -> Phi, [3] -> r4 (r1 and r4 as 32-bit uniforms).
+ *   <delta^2> = qq_coef * max(w_a, w_b) * nunit / u^3.
+ * The relative velocity u = va - vb is turned by the scattering angle Theta
+ * and an azimuth Phi = 2 pi r3 (draw 2); each side moves by its reduced-mass
+ * fraction of the change.  The scattering law:
+ *   law 0 (Takizuka-Abe): delta = sqrt(<delta^2>) sqrt(-2 ln r1) cos(2 pi r2),
+ *     r1 from draw 0 and the angle from draw 1; sin(Theta) = 2 delta/(1+delta^2),
+ *     1 - cos(Theta) = 2 delta^2/(1+delta^2);
+ *   law 1 (Nanbu): 1 - cos(Theta) = orc_nanbu_omc(2 <delta^2>, U52(draws 0, 1)),
+ *     sin(Theta) = sqrt((1 - cos)(1 + cos)); s = 2 <delta^2> gives both laws
+ *     the same small-angle mean of 1 - cos(Theta).
+ * The heavier-weight side accepts with probability w_light / w_heavy (r4 from
+ * draw 3, a 32-bit uniform).
  * Returns <delta^2>, or -1 when the relative velocity is zero (no collision).
  */
-double orc_ta77(double va[3], double vb[3], double ma, double mb, uint32_t wa,
-              uint32_t wb, double qq_coef, double nunit, const uint32_t draws[4],
-              int32_t *acc_a, int32_t *acc_b)
+double orc_collide(double va[3], double vb[3], double ma, double mb, uint32_t wa,
+                   uint32_t wb, double qq_coef, double nunit, const uint32_t draws[4],
+                   int32_t law, int32_t *acc_a, int32_t *acc_b)
 {
     double ux = va[0] - vb[0], uy = va[1] - vb[1], uz = va[2] - vb[2];
     double u2 = (ux * ux + uy * uy) + uz * uz;
@@ -171,15 +257,21 @@ double orc_ta77(double va[3], double vb[3], double ma, double mb, uint32_t wa,
     uint32_t wmax = wa > wb ? wa : wb;
     double u = sqrt(u2);
     double d2 = ((qq_coef * (double)wmax) * nunit) / (u2 * u);
-    double r1 = orc_u32(draws[0]);
-    double s2, c2;
-    orc_sincos2pi((uint64_t)draws[1] << 20, &s2, &c2);
-    double g = sqrt(-2.0 * orc_log(r1)) * c2;
-    double d = sqrt(d2) * g;
-    double dd = d * d;
-    double den = 1.0 + dd;
-    double st = (2.0 * d) / den;
-    double omc = (2.0 * dd) / den;
+    double st, omc;
+    if (law == 1) {
+        omc = orc_nanbu_omc(2.0 * d2, orc_u52(draws[0], draws[1]));
+        st = sqrt(omc * (2.0 - omc));
+    } else {
+        double r1 = orc_u32(draws[0]);
+        double s2, c2;
+        orc_sincos2pi((uint64_t)draws[1] << 20, &s2, &c2);
+        double g = sqrt(-2.0 * orc_log(r1)) * c2;
+        double d = sqrt(d2) * g;
+        double dd = d * d;
+        double den = 1.0 + dd;
+        st = (2.0 * d) / den;
+        omc = (2.0 * dd) / den;
+    }
     double sp, cp;
     orc_sincos2pi((uint64_t)draws[2] << 20, &sp, &cp);
     double a = st * cp;
@@ -214,4 +306,11 @@ double orc_ta77(double va[3], double vb[3], double ma, double mb, uint32_t wa,
     *acc_a = ta;
     *acc_b = tb;
     return d2;
+}
+
+double orc_ta77(double va[3], double vb[3], double ma, double mb, uint32_t wa,
+                uint32_t wb, double qq_coef, double nunit, const uint32_t draws[4],
+                int32_t *acc_a, int32_t *acc_b)
+{
+    return orc_collide(va, vb, ma, mb, wa, wb, qq_coef, nunit, draws, 0, acc_a, acc_b);
 }

@@ -5,7 +5,8 @@
  *   S0 moments: weights, charge sums, bulk temperature k T_e = (2/3) E_ave
  *      (Sec. II), densities, Zbar, z* and the continuum lowering dE[Z] of every
  *      charge state by Ecker-Kroll (Eq. 5) or Stewart-Pyatt (Eq. 6) (Sec. V).
- *   S1 electron-electron and S2 electron-ion binary collisions (Sec. IV).
+ *   S1 electron-electron and S2 electron-ion binary collisions (Sec. IV), by
+ *      Takizuka-Abe's scattering law or (ORC_NANBU) Nanbu's cumulative law.
  *   S3 collisional ionization against the average cell ion with the Lotz cross
  *      section (Eq. 4) and the energy debit of Sec. IV; with ORC_ION_Z every
  *      ion's probability uses the cross section of its own charge state.
@@ -259,6 +260,7 @@ typedef struct {
     uint32_t *keys;
     int64_t *cnt;
     double *led;
+    int32_t law;          /* scattering law of S1, S2: 0 Takizuka-Abe, 1 Nanbu */
 } cctx;
 
 static void rng(const cctx *x, uint32_t idx, uint32_t purpose, uint32_t sub, uint32_t out[4])
@@ -347,7 +349,7 @@ static void collide_pair(const cctx *x, ocell *c, int e_a, int is_ion_b, int b,
     uint32_t d[4];
     rng(x, idx, purpose, sub, d);
     int32_t aa, ab;
-    double d2 = orc_ta77(va, vb, ORC_ME, mb, wa, wb, coef, nunit, d, &aa, &ab);
+    double d2 = orc_collide(va, vb, ORC_ME, mb, wa, wb, coef, nunit, d, x->law, &aa, &ab);
     if (d2 < 0.0) { x->cnt[OC_U0]++; return; }
     if (d2 > 1.0) x->cnt[OC_DELTA2_GT1]++;
     x->cnt[OC_ACCEPT] += aa + ab;
@@ -834,6 +836,7 @@ void orc_step(orc_sim *s, uint32_t step, uint32_t flags, int32_t nthreads)
         cctx x;
         x.s = s;
         x.step = step;
+        x.law = (flags & ORC_NANBU) ? 1 : 0;
         x.key[0] = (uint32_t)s->r.seed;
         x.key[1] = (uint32_t)(s->r.seed >> 32);
         x.scratch = malloc(sizeof(double) * (size_t)pad);

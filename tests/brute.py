@@ -40,6 +40,32 @@ def u32(x):
     return (x + 0.5) / 2.0 ** 32
 
 
+def nanbu_omc(s, u):
+    """1 - cos(chi) of Nanbu's cumulative scattering law (Phys. Rev. E 55, 4642):
+    cos(chi) has density A exp(A cos chi) / (2 sinh A) with coth A - 1/A =
+    exp(-s); sampled by inverting its distribution function at u.  A is found
+    by bracketing (scipy's brentq) on 1 - L(A) = -expm1(-s); s >= 15 is taken
+    as isotropic."""
+    from scipy.optimize import brentq
+    if s <= 0.0:
+        return 0.0
+    if s >= 15.0:
+        cos = 2.0 * u - 1.0
+    else:
+        target = -math.expm1(-s)
+
+        def one_minus_l(a):
+            if a < 0.01:
+                return 1.0 - (a / 3.0 - a ** 3 / 45.0 + 2.0 * a ** 5 / 945.0)
+            tail = 0.0 if a > 350.0 else 2.0 / math.expm1(2.0 * a)
+            return 1.0 / a - tail
+
+        a = brentq(lambda a: one_minus_l(a) - target, 1e-10, 1e12, xtol=1e-300, rtol=1e-15,
+                   maxiter=500)
+        cos = 1.0 + math.log(u + (1.0 - u) * math.exp(-2.0 * a)) / a
+    return min(2.0, max(0.0, 1.0 - cos))
+
+
 def occ(z, k):
     nb = 13 - z
     o = [max(0, min(2 - k, nb))]
@@ -61,6 +87,7 @@ class Brute:
         self.t = tables
         self.s = spec
         self.key = (spec.seed & M32, (spec.seed >> 32) & M32)
+        self.law = 0   # scattering law: 0 Takizuka-Abe, 1 Nanbu
         self.sig = [[self._sigma(q, h) for q in range(3)] for h in spec.photon_hv]
 
     def _sigma(self, q, hv):
@@ -133,6 +160,9 @@ class Brute:
         g = math.sqrt(-2 * math.log(u32(w[0]))) * math.cos(2 * math.pi * ((w[1] << 20) + 0.5) / 2 ** 52)
         d = math.sqrt(d2) * g
         st, omc = 2 * d / (1 + d * d), 2 * d * d / (1 + d * d)
+        if self.law == 1:
+            omc = nanbu_omc(2.0 * d2, u52(w[0], w[1]))
+            st = math.sqrt(omc * (2.0 - omc))
         phi = 2 * math.pi * ((w[2] << 20) + 0.5) / 2 ** 52
         up = math.hypot(ua[0], ua[1])
         ux, uy, uz = ua
@@ -167,6 +197,7 @@ class Brute:
 
     def step(self, cell_id, c, step, flags):
         s, t = self.s, self.t
+        self.law = 1 if flags & 0x100 else 0
         mi = t.mass_ion
         counts = {"pairs": 0, "ion": 0, "rec": 0, "photo": 0, "decay": 0, "auger": 0}
         es, ions = c.e, c.i

@@ -20,8 +20,9 @@ def _cells_from_state(st):
     return cells
 
 
-@pytest.mark.parametrize("ipd,seed", [(0, 41), (1, 42), (1, 43)])
-def test_oracle_matches_brute_force(orc, tables, ipd, seed):
+@pytest.mark.parametrize("ipd,seed,nanbu", [(0, 41, False), (1, 42, False), (1, 43, False),
+                                            (1, 44, True)])
+def test_oracle_matches_brute_force(orc, tables, ipd, seed, nanbu):
     rng = np.random.default_rng(seed)
     ncell = 10
     ne = rng.integers(1, 7, ncell)
@@ -37,7 +38,7 @@ def test_oracle_matches_brute_force(orc, tables, ipd, seed):
     bf = brute.Brute(tables, spec)
     totals = {"pairs": 0, "ion": 0, "rec": 0, "photo": 0, "decay": 0, "auger": 0}
     for step in range(5):
-        flags = orc.ALL
+        flags = orc.ALL | (orc.NANBU if nanbu else 0)
         for c, cell in enumerate(cells):
             cnt = bf.step(c, cell, step, flags)
             for k in totals:
