@@ -46,9 +46,11 @@ def cpu_threads():
     return max(1, min(n, os.cpu_count() or n))
 
 
-def cpu_baseline(spec, parts, budget_s=15.0, max_steps=40, therm=False, ion_z=False):
+def cpu_baseline(spec, parts, budget_s=15.0, max_steps=40, therm=False, ion_z=False, nanbu=False,
+                 single=True):
     """The oracle on a bounded sample of the same workload: every cell of the
-    same initial state, stepped from step 0 until about budget_s of work."""
+    same initial state, stepped from step 0 until about budget_s of work on the
+    host's threads; then (single) step 0 again on one thread."""
     from oracle import oracle as O
     from paper_1704_01202_amd import workloads as W
     tab = W.make_tables()
@@ -58,17 +60,32 @@ def cpu_baseline(spec, parts, budget_s=15.0, max_steps=40, therm=False, ion_z=Fa
     coll = 0
     steps = 0
     t0 = time.perf_counter()
+    flags = O.ALL | (O.THERM if therm else 0) | (O.ION_Z if ion_z else 0) | (O.NANBU if nanbu else 0)
     while steps < max_steps:
-        sim.step(steps, O.ALL | (O.THERM if therm else 0) | (O.ION_Z if ion_z else 0), threads)
+        sim.step(steps, flags, threads)
         cnt, _ = sim.counters()
         coll += int(cnt[:, 0].sum() + cnt[:, 1].sum() + cnt[:, 2].sum())
         steps += 1
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
-    return {"value": coll / dt, "unit": "collisions/s", "cores": threads, "kind": "oracle",
-            "sample": "all %d cells of the same workload, steps 0-%d (%d collisions) in %.1f s"
-                      % (spec.ncells, steps - 1, coll, dt)}
+    out = {"value": coll / dt, "unit": "collisions/s", "cores": threads, "kind": "oracle",
+           "sample": "all %d cells of the same workload, steps 0-%d (%d collisions) in %.1f s"
+                     % (spec.ncells, steps - 1, coll, dt)}
+    if single and threads > 1:
+        # one host thread on the first step of the same state, for scale
+        del sim
+        sim = O.Sim(tab, spec)
+        sim.bin(parts)
+        t1 = time.perf_counter()
+        sim.step(0, flags, 1)
+        d1 = time.perf_counter() - t1
+        cnt, _ = sim.counters()
+        c1 = int(cnt[:, 0].sum() + cnt[:, 1].sum() + cnt[:, 2].sum())
+        out["single_thread_value"] = c1 / d1
+        out["single_thread_sample"] = "step 0 of all %d cells on 1 thread (%d collisions) in %.1f s" \
+            % (spec.ncells, c1, d1)
+    return out
 
 
 def source_digest():
@@ -382,6 +399,8 @@ def main():
                     help="c2: add the forced thermalization variant (Sec. VI.C) after S5")
     ap.add_argument("--ion-z", action="store_true",
                     help="c2: collisional ionization per ion charge state (variant of Sec. IV)")
+    ap.add_argument("--nanbu", action="store_true",
+                    help="c2: Nanbu's cumulative scattering law in the e-e and e-i collisions")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run a plain device copy of MIB MiB "
                          "(calibrates the HBM byte counters under a profiler)")
@@ -433,7 +452,8 @@ def main():
     log("binned into slabs: e_slots %d, max cap %d (%.1f s)"
         % (bat.e_slots, bat.e_cap_max, time.perf_counter() - t0))
     stream = torch.cuda.current_stream()
-    flags = B.XP_ALL | (B.XP_THERM if args.therm else 0) | (B.XP_ION_Z if args.ion_z else 0)
+    flags = (B.XP_ALL | (B.XP_THERM if args.therm else 0) | (B.XP_ION_Z if args.ion_z else 0)
+             | (B.XP_NANBU if args.nanbu else 0))
     for s in range(args.warmup):
         bat.step(s, flags, schedule=args.schedule)
     torch.cuda.synchronize()
@@ -484,7 +504,8 @@ def main():
                                "dt 0.05 fs, 1.7e17 W/cm^2 1.85 keV photoionization fused%s"
                                % (args.nx, args.ny,
                                   (", forced thermalization after S5" if args.therm else "")
-                                  + (", ionization per ion charge state" if args.ion_z else "")),
+                                  + (", ionization per ion charge state" if args.ion_z else "")
+                                  + (", Nanbu scattering law" if args.nanbu else "")),
                    "cells": spec.ncells, "electrons_start": parts.ne, "ions": ni,
                    "electrons_timed": [ne_before, ne_after], "status": status},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -494,7 +515,8 @@ def main():
         "collisions_total": coll,
     }
     valu = measured_valu()
-    if valu is not None and args.nx == 512 and args.ny == 512 and not args.therm and not args.ion_z:
+    if (valu is not None and args.nx == 512 and args.ny == 512 and not args.therm and not args.ion_z
+            and not args.nanbu):
         # the step is bound by instruction issue, not by HBM: VALU instructions
         # of a launch (profiled) over the launch time measured here
         rate = valu / (avg_ms * 1e-3)
@@ -507,7 +529,8 @@ def main():
         del bat
         torch.cuda.empty_cache()
         log("timing the CPU oracle on a sample ...")
-        out["cpu_baseline"] = cpu_baseline(spec, parts, therm=args.therm, ion_z=args.ion_z)
+        out["cpu_baseline"] = cpu_baseline(spec, parts, therm=args.therm, ion_z=args.ion_z,
+                                           nanbu=args.nanbu)
     print(json.dumps(out), flush=True)
 
 

@@ -69,6 +69,16 @@ typedef int32_t xp_status;
  * debit and rescale are those of S3.  Moments record: [11] the number of
  * charge states evaluated, [12] the largest P_z. */
 #define XP_ION_Z   0x80u
+/* Variant, not part of XP_ALL: Nanbu's cumulative scattering law (Nanbu,
+ * Phys. Rev. E 55, 4642 (1997)) in the e-e and e-i collisions (Sec. IV cites
+ * Monte-Carlo binary collisions without fixing the law).  Pairing, weights and
+ * the rotation are those of Takizuka-Abe; the angle chi of one step has the
+ * density of cos chi  A exp(A cos chi) / (2 sinh A) with coth A - 1/A =
+ * exp(-s), s = 2 <delta^2>, drawn by inverting its distribution function at
+ * U52(words 0, 1) of the pair's Philox call.  s >= 15 is isotropic.  Suited
+ * to nu dt >> 1, where Takizuka-Abe's single small-angle step is out of its
+ * range. */
+#define XP_NANBU   0x100u
 
 /* Device status bits (xp_batch.d_status, OR-ed by kernels). */
 #define XP_ST_CAPACITY  0x1u   /* a cell needed more electron slots than its capacity */
@@ -291,7 +301,8 @@ xp_status bin_particles(xp_ctx *ctx, const xp_particles *in, xp_batch *b,
                         const xp_capacity *cap, int64_t *d_need, void *stream);
 
 /* One Monte-Carlo step of every cell of every run in the batch (Sec. II-V):
- * moments and continuum lowering, e-e and e-i binary collisions, collisional
+ * moments and continuum lowering, e-e and e-i binary collisions (Takizuka-Abe,
+ * or Nanbu's law with XP_NANBU), collisional
  * ionization, three-body recombination, and -- when XP_PHOTO / XP_DECAY are in
  * p->flags -- the XFEL source terms of photo_auger_step, fused in the same
  * pass with dt_rad of the run table, then with XP_THERM the forced

@@ -378,7 +378,7 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
         }
         // the variants, per-cell records and per-cell photon fields are
         // compiled into their own kernels
-        const bool xv = (flags & (XP_THERM | XP_ION_Z)) != 0 || b->d_cell_counters || b->d_cell_ledger ||
+        const bool xv = (flags & (XP_THERM | XP_ION_Z | XP_NANBU)) != 0 || b->d_cell_counters || b->d_cell_ledger ||
                         b->d_cell_moments || b->d_cell_nhv;
         for (int tier = 0;; ++tier) {
             const bool last = ce >= ce_top || tier >= xpd::BIG_COUNT_SLOT - 1;
@@ -461,7 +461,7 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
 xp_status collide_ionize_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, void* stream)
 {
     if (!p) return fail(XP_ERR_INVALID_ARG, "null step parameters");
-    return launch_step(ctx, b, p, p->flags & (XP_ALL | XP_THERM | XP_ION_Z), stream);
+    return launch_step(ctx, b, p, p->flags & (XP_ALL | XP_THERM | XP_ION_Z | XP_NANBU), stream);
 }
 
 xp_status photo_auger_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, void* stream)

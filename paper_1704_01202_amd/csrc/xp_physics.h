@@ -136,13 +136,95 @@ struct Coll {
     int acc_a, acc_b;
 };
 
-// Takizuka-Abe binary collision with weighted acceptance (the heavier-weight
-// partner accepts with probability w_light / w_heavy).  The four Philox words
-// of the pair give r1 (word 0), the Box-Muller angle (word 1), Phi (word 2)
-// and the acceptance draw r4 (word 3).  fa = m_b/(m_a+m_b), fb = m_a/(m_a+m_b).
+// Nanbu's cumulative small-angle scattering (Phys. Rev. E 55, 4642 (1997)):
+// the deflections of one step add up to one angle chi whose cosine has the
+// density A exp(A cos chi) / (2 sinh A), A fixed by <cos chi> = coth A - 1/A
+// = exp(-s).  nanbu_a(s):
+//   s <= 0.05: A >= 20 and coth A = 1 to working precision, so
+//     A = 1 / (1 - exp(-s)), the denominator from its nested series to s/11;
+//   0.05 < s < 15: four Newton steps on L(A) = exp(-s) from the Pade start
+//     A = m (3 - m^2) / (1 - m^2); L, L' by the Laurent series of coth
+//     (eleven Bernoulli terms) below A = 0.5, by E = exp(-2A) above;
+//   s >= 15: 0, the isotropic limit.
+__device__ __forceinline__ void langevin(double a, double& l, double& dl)
+{
+    if (a < 0.5) {
+        constexpr double c1 = 1.0 / 3.0, c2 = -1.0 / 45.0, c3 = 2.0 / 945.0, c4 = -1.0 / 4725.0,
+                         c5 = 2.0 / 93555.0, c6 = -1382.0 / 638512875.0, c7 = 4.0 / 18243225.0,
+                         c8 = -3617.0 / 162820783125.0, c9 = 87734.0 / 38979295480125.0,
+                         c10 = -349222.0 / 1531329465290625.0, c11 = 310732.0 / 13447856940643125.0;
+        const double z = a * a;
+        double v = c11;
+        v = c10 + z * v; v = c9 + z * v; v = c8 + z * v; v = c7 + z * v; v = c6 + z * v;
+        v = c5 + z * v; v = c4 + z * v; v = c3 + z * v; v = c2 + z * v; v = c1 + z * v;
+        // derivative coefficients (2k - 1) c_k, each a rounded product
+        double dv = 21.0 * c11;
+        dv = 19.0 * c10 + z * dv; dv = 17.0 * c9 + z * dv; dv = 15.0 * c8 + z * dv;
+        dv = 13.0 * c7 + z * dv;  dv = 11.0 * c6 + z * dv; dv = 9.0 * c5 + z * dv;
+        dv = 7.0 * c4 + z * dv;   dv = 5.0 * c3 + z * dv;  dv = 3.0 * c2 + z * dv;
+        dv = 1.0 * c1 + z * dv;
+        l = a * v;
+        dl = dv;
+        return;
+    }
+    const double e = xexp(-2.0 * a);
+    const double ome = 1.0 - e;
+    l = (1.0 + e) / ome - 1.0 / a;
+    dl = 1.0 / (a * a) - (4.0 * e) / (ome * ome);
+}
+
+__device__ __noinline__ double nanbu_a(double s)
+{
+    if (s >= 15.0) return 0.0;
+    if (s <= 0.05) {
+        double q = 1.0;
+        q = 1.0 - (s * (1.0 / 11.0)) * q; q = 1.0 - (s * (1.0 / 10.0)) * q;
+        q = 1.0 - (s * (1.0 / 9.0)) * q;  q = 1.0 - (s * (1.0 / 8.0)) * q;
+        q = 1.0 - (s * (1.0 / 7.0)) * q;  q = 1.0 - (s * (1.0 / 6.0)) * q;
+        q = 1.0 - (s * (1.0 / 5.0)) * q;  q = 1.0 - (s * (1.0 / 4.0)) * q;
+        q = 1.0 - (s * (1.0 / 3.0)) * q;  q = 1.0 - (s * (1.0 / 2.0)) * q;
+        return 1.0 / (s * q);
+    }
+    const double m = xexp(-s);
+    const double m2 = m * m;
+    double a = (m * (3.0 - m2)) / (1.0 - m2);
+#pragma unroll 1
+    for (int it = 0; it < 4; ++it) {
+        double l, dl;
+        langevin(a, l, dl);
+        a = a - (l - m) / dl;
+    }
+    return a;
+}
+
+// 1 - cos chi for s and a uniform u in (0, 1), by inverting the distribution
+// function: cos chi = 1 + ln(u + (1 - u) exp(-2A)) / A (A = 0: 2u - 1).
+// Clamped to [0, 2]; s <= 0 gives no deflection.
+__device__ __forceinline__ double nanbu_omc(double s, double u)
+{
+    if (!(s > 0.0)) return 0.0;
+    const double a = nanbu_a(s);
+    double omc;
+    if (a == 0.0) {
+        omc = 2.0 * (1.0 - u);
+    } else {
+        const double e2 = xexp(-2.0 * a);
+        omc = -xlog(u + (1.0 - u) * e2) / a;
+    }
+    if (omc < 0.0) omc = 0.0;
+    if (omc > 2.0) omc = 2.0;
+    return omc;
+}
+
+// Binary collision with weighted acceptance (the heavier-weight partner
+// accepts with probability w_light / w_heavy).  Scattering law: Takizuka-Abe,
+// tan(theta/2) = delta normal with variance <delta^2> (r1 from word 0, the
+// Box-Muller angle from word 1), or with nanbu Nanbu's cumulative law with
+// s = 2 <delta^2> and u = U52(words 0, 1).  Phi comes from word 2, the
+// acceptance draw r4 from word 3.  fa = m_b/(m_a+m_b), fb = m_a/(m_a+m_b).
 __device__ __forceinline__ Coll ta77(double& ax, double& ay, double& az, double& bx, double& by,
                                      double& bz, double fa, double fb, uint32_t wa, uint32_t wb,
-                                     double coef, double nunit, const Words& d)
+                                     double coef, double nunit, const Words& d, bool nanbu)
 {
     Coll out{-1.0, 0, 0};
     const double ux = ax - bx, uy = ay - by, uz = az - bz;
@@ -151,14 +233,20 @@ __device__ __forceinline__ Coll ta77(double& ax, double& ay, double& az, double&
     const uint32_t wmax = wa > wb ? wa : wb;
     const double u = sqrt(u2);
     const double d2 = ((coef * (double)wmax) * nunit) / (u2 * u);
-    double s2, c2;
-    xsincos2pi((uint64_t)d.x1 << 20, s2, c2);
-    const double g = sqrt(-2.0 * xlog(u32(d.x0))) * c2;
-    const double dl = sqrt(d2) * g;
-    const double dd = dl * dl;
-    const double den = 1.0 + dd;
-    const double st = (2.0 * dl) / den;
-    const double omc = (2.0 * dd) / den;
+    double st, omc;
+    if (nanbu) {
+        omc = nanbu_omc(2.0 * d2, u52(d.x0, d.x1));
+        st = sqrt(omc * (2.0 - omc));
+    } else {
+        double s2, c2;
+        xsincos2pi((uint64_t)d.x1 << 20, s2, c2);
+        const double g = sqrt(-2.0 * xlog(u32(d.x0))) * c2;
+        const double dl = sqrt(d2) * g;
+        const double dd = dl * dl;
+        const double den = 1.0 + dd;
+        st = (2.0 * dl) / den;
+        omc = (2.0 * dd) / den;
+    }
     double sp, cp;
     xsincos2pi((uint64_t)d.x2 << 20, sp, cp);
     const double a = st * cp;
@@ -199,17 +287,19 @@ __device__ __forceinline__ Coll ta77(double& ax, double& ay, double& az, double&
 
 // One binary collision between slot e of (avx, avy, avz, aw) and slot b of
 // (bvx, bvy, bvz) with weight wb, on LDS arrays; draws from Philox counter
-// (c0, c1, idx, c3).  Counts go to cnt (XP_C_* indices).
+// (c0, c1, idx, c3).  Counts go to cnt (XP_C_* indices).  nanbu selects
+// Nanbu's scattering law instead of Takizuka-Abe's.
 __device__ __forceinline__ void collide_slots(double* avx, double* avy, double* avz, const uint32_t* aw,
                                            double* bvx, double* bvy, double* bvz, int e, int b,
                                            uint32_t wb, double fa, double fb, double coef,
                                            double nunit, uint32_t c0, uint32_t c1, uint32_t idx,
-                                           uint32_t c3, uint32_t k0, uint32_t k1, int* cnt)
+                                           uint32_t c3, uint32_t k0, uint32_t k1, int* cnt,
+                                           bool nanbu)
 {
     double ax = avx[e], ay = avy[e], az = avz[e];
     double bx = bvx[b], by = bvy[b], bz = bvz[b];
     const Words d = philox(c0, c1, idx, c3, k0, k1);
-    const Coll c = ta77(ax, ay, az, bx, by, bz, fa, fb, aw[e], wb, coef, nunit, d);
+    const Coll c = ta77(ax, ay, az, bx, by, bz, fa, fb, aw[e], wb, coef, nunit, d, nanbu);
     if (c.d2 < 0.0) {
         atomicAdd(&cnt[XP_C_U0], 1);
         return;

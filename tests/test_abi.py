@@ -76,3 +76,16 @@ def test_header_names_every_entry_point_with_citation():
         i = text.index(name + "(")
         block = text[max(0, i - 1500):i]
         assert "Sec." in block or "Eq." in block, name
+
+
+def test_flag_values_agree():
+    # the header's stage and variant switches, the binding's and the oracle's
+    from oracle import oracle as O
+    text = open(HEADER).read()
+    vals = {m.group(1): int(m.group(2), 16)
+            for m in re.finditer(r"#define (XP_\w+)\s+0x([0-9A-Fa-f]+)u", text)}
+    pairs = {"XP_EE": O.EE, "XP_EI": O.EI, "XP_ION": O.ION, "XP_REC": O.REC,
+             "XP_PHOTO": O.PHOTO, "XP_DECAY": O.DECAY, "XP_ALL": O.ALL, "XP_THERM": O.THERM,
+             "XP_ION_Z": O.ION_Z, "XP_NANBU": O.NANBU}
+    for name, oval in pairs.items():
+        assert vals[name] == getattr(B, name) == oval, name

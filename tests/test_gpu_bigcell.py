@@ -116,3 +116,18 @@ def test_big_path_capacity_flag(ctx):
     # either nothing fired, or the overflow was flagged and the count kept
     assert st in (0, 1)
     assert after.e_start[-1] == parts.ne
+
+
+def test_big_path_nanbu(ctx):
+    # Nanbu's scattering law through the global-memory path: C1 with every
+    # cell on the path, then oversized cells beside LDS cells
+    spec, parts = W.config_c1()
+    run_pair(ctx, spec, parts, 6, check_every=3, capacity=(3, 16), label="C1/global/nanbu",
+             schedule=3, big="all", flags=O.ALL | O.NANBU)
+    ne = np.array([60, 3000, 2600, 45, 0])
+    ni = np.array([50, 1500, 600, 40, 20])
+    spec, parts = cases.one_run(ne.size, ne, ni, 30.0, 0.1, seed=97, e_weight=1, dt=0.05e-15,
+                                photon_hv=(1850.0,), photon_n=(4e29,))
+    bat, sim = run_pair(ctx, spec, parts, 4, check_every=2, label="oversized/nanbu",
+                        flags=O.ALL | O.NANBU)
+    assert bat.stats()[2] == 2

@@ -305,6 +305,24 @@ def test_per_charge_state_ionization(ctx):
     run_pair(ctx, spec, parts, 16, flags=O.ALL | O.ION_Z, check_every=8, label="C2r/ionz")
 
 
+def test_nanbu_scattering(ctx):
+    # Nanbu's cumulative scattering law in S1/S2: C1 (nu dt >> 1 for its 10 eV
+    # electrons, small angles for the keV ones), edge cells, mixed charges with
+    # the other variants on every LDS schedule, and a reduced C2
+    spec, parts = W.config_c1()
+    bat, sim = run_pair(ctx, spec, parts, 8, flags=O.ALL | O.NANBU, check_every=4, label="C1/nanbu")
+    assert sim.counters()[0][:, O.COUNTERS.index("DELTA2_GT1")].sum() > 0
+    spec, parts = _therm_edge_case(47)
+    run_pair(ctx, spec, parts, 6, flags=O.ALL | O.NANBU, check_every=1, capacity=(3, 4),
+             label="nanbu/edge")
+    for sched in (1, 2, 5):
+        spec, parts = _mixed_charge_case(54, ne_hi=12, ni_hi=6)
+        run_pair(ctx, spec, parts, 6, flags=O.ALL | O.NANBU | O.ION_Z | O.THERM, check_every=2,
+                 capacity=(5, 4), schedule=sched, label="nanbu+ionz+therm/%d" % sched)
+    spec, parts = W.config_c2(nx=6, ny=6)
+    run_pair(ctx, spec, parts, 12, flags=O.ALL | O.NANBU, check_every=6, label="C2r/nanbu")
+
+
 def test_thermalization_after_source_terms_alone(ctx):
     n = 120
     spec, parts = cases.one_run(5, 3 * n, n, 10.0, 0.1, k0=1, seed=79, dt=0.1e-15,
