@@ -129,6 +129,9 @@ def lib():
         L.orc_last_counters.restype = None; L.orc_last_counters.argtypes = [vp, vp, vp]
         L.orc_last_moments.restype = None; L.orc_last_moments.argtypes = [vp, vp]
         L.orc_diag.restype = None; L.orc_diag.argtypes = [vp, vp, vp, vp]
+        L.orc_last_absorbed.restype = None; L.orc_last_absorbed.argtypes = [vp, vp]
+        L.orc_get_cell_field.restype = None; L.orc_get_cell_field.argtypes = [vp, vp]
+        L.orc_transport.restype = None; L.orc_transport.argtypes = [vp, vp]
         _lib = L
     return _lib
 
@@ -322,6 +325,7 @@ class Sim:
         self.run = make_run(spec)
         self.spec = spec
         self.ncells = spec.nx * spec.ny
+        self.n_bins = len(spec.photon_hv)
         self.h = lib().orc_create(C.byref(self.tables), C.byref(self.run))
 
     def __del__(self):
@@ -385,6 +389,25 @@ class Sim:
         m = np.zeros((self.ncells, NMOM), dtype=np.float64)
         lib().orc_last_moments(self.h, _p(m))
         return m
+
+    def absorbed(self):
+        """Photon events per bin of the last step, [ncells][MAX_BINS]."""
+        a = np.zeros((self.ncells, MAX_BINS), dtype=np.int32)
+        lib().orc_last_absorbed(self.h, _p(a))
+        return a
+
+    def cell_field(self):
+        """The photon field per cell, [ncells][n_bins]."""
+        f = np.zeros((self.ncells, self.n_bins), dtype=np.float64)
+        lib().orc_get_cell_field(self.h, _p(f))
+        return f
+
+    def transport(self):
+        """Reduced radiation transport after a step; returns the mean row
+        transmission per bin."""
+        t = np.zeros(MAX_BINS, dtype=np.float64)
+        lib().orc_transport(self.h, _p(t))
+        return t[:self.n_bins]
 
     def diag(self):
         csd = np.zeros(ZMAX + 1, dtype=np.int64)

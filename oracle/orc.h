@@ -156,6 +156,14 @@ void     orc_export(const orc_sim *s, int64_t *e_start, double *ex, double *ey,
                     double *ivy, double *ivz, uint8_t *iz, uint8_t *ik);
 /* Counters and tallies of the last step, [ncells][OC_NCOUNT] / [ncells][OL_NLEDGER]. */
 void     orc_last_counters(const orc_sim *s, int64_t *cnt, double *ledger);
+/* Photon events per bin of the last step, [ncells][ORC_MAX_BINS]. */
+void     orc_last_absorbed(const orc_sim *s, int32_t *nabs);
+/* Current photon field per cell, [ncells][n_bins] (the uniform one if unset). */
+void     orc_get_cell_field(const orc_sim *s, double *nhv);
+/* Reduced radiation transport along x after a step (see orc_step.c):
+ * new per-cell field from the incident density and the last step's
+ * absorption; trans[n_bins] gets the mean transmission of the rows. */
+void     orc_transport(orc_sim *s, double *trans);
 /* Cell moments after S0 of the last step: [ncells][16] (see orc_step.c). */
 void     orc_last_moments(const orc_sim *s, double *mom);
 /* Run diagnostics of the current state. */

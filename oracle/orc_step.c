@@ -57,6 +57,7 @@ struct orc_sim {
     double *led;         /* [ncells][OL_NLEDGER] */
     double *mom;         /* [ncells][NMOM] */
     double *cell_nhv;    /* optional [ncells][n_bins] */
+    int32_t *nabs;       /* [ncells][ORC_MAX_BINS] photons absorbed per bin, last step */
     double sigma[ORC_MAX_BINS][3];   /* photo cross section at each bin, m^2 */
 };
 
@@ -113,6 +114,7 @@ orc_sim *orc_create(const orc_tables *t, const orc_run *r)
     s->cnt = calloc((size_t)s->ncells * OC_NCOUNT, sizeof(int64_t));
     s->led = calloc((size_t)s->ncells * OL_NLEDGER, sizeof(double));
     s->mom = calloc((size_t)s->ncells * NMOM, sizeof(double));
+    s->nabs = calloc((size_t)s->ncells * ORC_MAX_BINS, sizeof(int32_t));
     for (int b = 0; b < r->n_bins; ++b)
         for (int q = 0; q < 3; ++q) s->sigma[b][q] = orc_photo_sigma(t, q, r->hv[b]);
     return s;
@@ -122,7 +124,7 @@ void orc_destroy(orc_sim *s)
 {
     if (!s) return;
     for (int c = 0; c < s->ncells; ++c) cell_free(&s->cells[c]);
-    free(s->cells); free(s->cnt); free(s->led); free(s->mom); free(s->cell_nhv);
+    free(s->cells); free(s->cnt); free(s->led); free(s->mom); free(s->cell_nhv); free(s->nabs);
     free(s);
 }
 
@@ -237,6 +239,68 @@ void orc_last_moments(const orc_sim *s, double *mom)
     memcpy(mom, s->mom, sizeof(double) * (size_t)s->ncells * NMOM);
 }
 
+void orc_last_absorbed(const orc_sim *s, int32_t *nabs)
+{
+    memcpy(nabs, s->nabs, sizeof(int32_t) * (size_t)s->ncells * ORC_MAX_BINS);
+}
+
+void orc_get_cell_field(const orc_sim *s, double *nhv)
+{
+    size_t n = (size_t)s->ncells * (size_t)s->r.n_bins;
+    if (s->cell_nhv) {
+        memcpy(nhv, s->cell_nhv, sizeof(double) * n);
+        return;
+    }
+    for (int c = 0; c < s->ncells; ++c)
+        for (int b = 0; b < s->r.n_bins; ++b) nhv[(size_t)c * s->r.n_bins + b] = s->r.nhv[b];
+}
+
+/* Reduced radiation transport along x (the beam axis), after a step of the
+ * source terms (Sec. II, Sec. III).  The incident density of each bin, the
+ * run's prescribed n_hv, enters every row of cells at its low-x face.  Cell i
+ * of a row absorbed nabs photon events of w0 real photons during the step,
+ * out of the c dt_rad n (V / dx) photons that crossed its entrance face at its
+ * density n of that step, so its transmission is
+ *   tau = 1 - nabs w0 dx / (V c dt_rad n)   (0 if negative; 1 if n = 0),
+ * the photons the Monte-Carlo events took out of the bin (Sec. III).  The
+ * new density of cell i is the density entering it, the incident density
+ * times the transmissions of the cells before it in the row (a quasi-static
+ * Beer-Lambert profile: the crossing time of a row is taken as short against
+ * the pulse).  trans[b] (if not NULL) is the mean over rows of the density
+ * leaving the row divided by the incident density (0 for an empty bin).
+ * The per-cell field is created from the uniform one if not set. */
+void orc_transport(orc_sim *s, double *trans)
+{
+    const orc_run *r = &s->r;
+    int nb = r->n_bins;
+    if (nb <= 0) return;
+    if (!s->cell_nhv) {
+        double *f = malloc(sizeof(double) * (size_t)s->ncells * (size_t)nb);
+        orc_get_cell_field(s, f);
+        s->cell_nhv = f;
+    }
+    const double cross = (r->volume * (ORC_CLIGHT * r->dt_rad)) / r->dx;
+    for (int b = 0; b < nb; ++b) {
+        double out_sum = 0.0;
+        for (int j = 0; j < r->ny; ++j) {
+            double carry = r->nhv[b];
+            for (int i = 0; i < r->nx; ++i) {
+                size_t c = (size_t)j * (size_t)r->nx + (size_t)i;
+                double n = s->cell_nhv[c * nb + b];
+                s->cell_nhv[c * nb + b] = carry;
+                double tau = 1.0;
+                if (n > 0.0) {
+                    double a = ((double)s->nabs[c * ORC_MAX_BINS + b] * r->w0) / (cross * n);
+                    tau = a < 1.0 ? 1.0 - a : 0.0;
+                }
+                carry = carry * tau;
+            }
+            out_sum = out_sum + carry;
+        }
+        if (trans) trans[b] = r->nhv[b] > 0.0 ? (out_sum / (double)r->ny) / r->nhv[b] : 0.0;
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Canonical pairwise sum: leaves padded with +0 to the next power of two,
  * y[i] = y[2i] + y[2i+1] level by level; the result is normalized by + 0.0. */
@@ -261,6 +325,7 @@ typedef struct {
     int64_t *cnt;
     double *led;
     int32_t law;          /* scattering law of S1, S2: 0 Takizuka-Abe, 1 Nanbu */
+    int32_t *nabs;        /* this cell's photons absorbed per bin */
 } cctx;
 
 static void rng(const cctx *x, uint32_t idx, uint32_t purpose, uint32_t sub, uint32_t out[4])
@@ -805,6 +870,7 @@ static void step_cell(cctx *x, ocell *c, uint32_t flags)
                     x->cnt[OC_PHOTO_1S + q]++;
                     x->led[OL_PHOTO_E] += ep;
                     x->led[OL_PHOTON_ABS] += r->hv[sel];
+                    x->nabs[sel]++;
                 }
             }
             c->iz[i] = (uint8_t)z;
@@ -826,6 +892,7 @@ void orc_step(orc_sim *s, uint32_t step, uint32_t flags, int32_t nthreads)
     while (pad < maxp) pad *= 2;
     memset(s->cnt, 0, sizeof(int64_t) * (size_t)s->ncells * OC_NCOUNT);
     memset(s->led, 0, sizeof(double) * (size_t)s->ncells * OL_NLEDGER);
+    memset(s->nabs, 0, sizeof(int32_t) * (size_t)s->ncells * ORC_MAX_BINS);
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #else
@@ -850,6 +917,7 @@ void orc_step(orc_sim *s, uint32_t step, uint32_t flags, int32_t nthreads)
             x.cell = (uint32_t)c;
             x.cnt = s->cnt + (size_t)c * OC_NCOUNT;
             x.led = s->led + (size_t)c * OL_NLEDGER;
+            x.nabs = s->nabs + (size_t)c * ORC_MAX_BINS;
             step_cell(&x, &s->cells[c], flags);
         }
         free(x.scratch); free(x.perm_e); free(x.perm_i); free(x.perm_a); free(x.perm_b); free(x.keys);
