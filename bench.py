@@ -401,6 +401,9 @@ def main():
                     help="c2: collisional ionization per ion charge state (variant of Sec. IV)")
     ap.add_argument("--nanbu", action="store_true",
                     help="c2: Nanbu's cumulative scattering law in the e-e and e-i collisions")
+    ap.add_argument("--transport", action="store_true",
+                    help="c2: per-cell photon field rebuilt after every step by the reduced "
+                         "radiation transport (transport_photons)")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run a plain device copy of MIB MiB "
                          "(calibrates the HBM byte counters under a profiler)")
@@ -447,7 +450,11 @@ def main():
     log("workload generated (%.1f s): %d electrons, %d ions, %d cells"
         % (time.perf_counter() - t0, parts.ne, parts.ni, spec.ncells))
     ctx = RT.Context(tab)
-    bat = RT.Batch(ctx, [(spec, parts)], capacity=(7, 16))
+    field = None
+    if args.transport:
+        import numpy as np
+        field = np.tile(np.asarray(spec.photon_n, dtype=np.float64), (spec.ncells, 1))
+    bat = RT.Batch(ctx, [(spec, parts)], capacity=(7, 16), cell_nhv=field)
     torch.cuda.synchronize()
     log("binned into slabs: e_slots %d, max cap %d (%.1f s)"
         % (bat.e_slots, bat.e_cap_max, time.perf_counter() - t0))
@@ -456,6 +463,8 @@ def main():
              | (B.XP_NANBU if args.nanbu else 0))
     for s in range(args.warmup):
         bat.step(s, flags, schedule=args.schedule)
+        if args.transport:
+            bat.transport()
     torch.cuda.synchronize()
     bat.d_run_cnt.zero_()
     ne_before = int(bat.d_e_cnt.sum().item())
@@ -466,10 +475,16 @@ def main():
     ne_steps = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
+    tev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps if args.transport else 0)]
     for k in range(args.steps):
         ev[k][0].record(stream)
         bat.step(args.warmup + k, flags, schedule=args.schedule)
         ev[k][1].record(stream)
+        if args.transport:
+            tev[k][0].record(stream)
+            bat.transport()
+            tev[k][1].record(stream)
     torch.cuda.synchronize()
     t_end = time.perf_counter()
     wall = t_end - t_start
@@ -505,7 +520,9 @@ def main():
                                % (args.nx, args.ny,
                                   (", forced thermalization after S5" if args.therm else "")
                                   + (", ionization per ion charge state" if args.ion_z else "")
-                                  + (", Nanbu scattering law" if args.nanbu else "")),
+                                  + (", Nanbu scattering law" if args.nanbu else "")
+                                  + (", reduced radiation transport after every step"
+                                     if args.transport else "")),
                    "cells": spec.ncells, "electrons_start": parts.ne, "ions": ni,
                    "electrons_timed": [ne_before, ne_after], "status": status},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -516,13 +533,18 @@ def main():
     }
     valu = measured_valu()
     if (valu is not None and args.nx == 512 and args.ny == 512 and not args.therm and not args.ion_z
-            and not args.nanbu):
+            and not args.nanbu and not args.transport):
         # the step is bound by instruction issue, not by HBM: VALU instructions
         # of a launch (profiled) over the launch time measured here
         rate = valu / (avg_ms * 1e-3)
         out["valu_issue"] = {"bound": "alu", "achieved": rate, "peak": VALU_PEAK,
                              "unit": "wave-instructions/s", "frac": rate / VALU_PEAK,
                              "insts_per_launch": valu}
+    if args.transport:
+        # the step's time covers collide_ionize_step; the transport is timed apart
+        tr_ms = [a.elapsed_time(b) for a, b in tev]
+        out["transport"] = {"kernel": "k_tr_rows + k_tr_sum", "avg_ms": sum(tr_ms) / len(tr_ms),
+                            "transmission": float(bat.d_trans[0, 0].item())}
     if args.copy_ref > 0:
         copy_reference(args.copy_ref)
     if not args.no_cpu:

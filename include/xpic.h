@@ -209,7 +209,9 @@ typedef struct {
     uint32_t *d_ew;                                /* [e_slots] weight units */
     double *d_ix, *d_iy, *d_ivx, *d_ivy, *d_ivz;   /* [i_slots] */
     uint8_t *d_iz, *d_ik;           /* charge state, K vacancies (0..2) */
-    const double *d_cell_nhv;       /* optional [n_cells][XP_MAX_BINS] */
+    double *d_cell_nhv;             /* optional [n_cells][XP_MAX_BINS] photons / m^3, read by
+                                       runs with field_per_cell; rewritten by
+                                       transport_photons */
     uint64_t *d_run_counters;       /* [n_runs][XP_NCOUNT], accumulated */
     double *d_run_ledger;           /* [n_runs][XP_NLEDGER], accumulated (order-free) */
     int64_t *d_cell_counters;       /* optional [n_cells][XP_NCOUNT], last step */
@@ -233,6 +235,9 @@ typedef struct {
     int32_t big_cells_max;
     int32_t reserved0;
     int64_t big_e_slots, big_i_slots;
+    int32_t *d_cell_nabs;           /* optional [n_cells][XP_MAX_BINS]: photon events per bin of
+                                       the last step (photoionizations, one macro-photon of w0
+                                       real photons each, Sec. III); needed by transport_photons */
 } xp_batch;
 
 /* Unsorted input particles of a batch for bin_particles.  Particle p belongs
@@ -328,6 +333,25 @@ xp_status collide_ionize_step(xp_ctx *ctx, xp_batch *b, const xp_step_params *p,
  * p->flags is masked to XP_PHOTO | XP_DECAY | XP_THERM. */
 xp_status photo_auger_step(xp_ctx *ctx, xp_batch *b, const xp_step_params *p,
                            void *stream);
+
+/* Reduced radiation transport after a step of the source terms (Sec. II:
+ * the radiation field and the plasma exchange energy every dt_rad; Sec. III:
+ * every photoionization takes its photon's energy out of the selected bin).
+ * For every run with field_per_cell = 1 and n_bins > 0, row by row along x
+ * (the beam axis; row j holds cells j nx .. j nx + nx - 1 of the run) and bin
+ * by bin: the run's nhv[b] enters the row at its low-x face; cell i passes on
+ * the fraction tau_i = 1 - nabs_i w0 dx / (V c dt_rad n_i) (0 if negative, 1
+ * if n_i = 0) of the density n_i it had during the step, nabs_i being its
+ * photon events of bin b in d_cell_nabs; its new density is the incident
+ * density times tau_0 ... tau_{i-1} (multiplied left to right).  The profile
+ * is quasi-static: the light crossing time of a row is taken as short
+ * against the pulse.  Call after collide_ionize_step / photo_auger_step
+ * with d_cell_nabs set.  d_trans (optional, [n_runs][XP_MAX_BINS]) gets
+ * each run's mean density leaving its rows over the incident density (0 for
+ * an empty bin or a run without a per-cell field; rows summed in order).
+ * Needs d_cell_nhv, d_cell_nabs and a workspace of xp_step_work_bytes.
+ * Other runs are left as they are. */
+xp_status transport_photons(xp_ctx *ctx, xp_batch *b, double *d_trans, void *stream);
 
 /* Run diagnostics (Sec. II, Sec. VI.B, Fig. 7-9): charge-state distribution,
  * electron energy histogram (64 log bins from 0.1 eV to 1e5 eV, weight

@@ -72,7 +72,7 @@ class XpBatch(C.Structure):
                 ("d_work", _vp), ("work_bytes", C.c_size_t),
                 ("e_cap_max", _i32), ("i_cap_max", _i32), ("d_stats", _vp),
                 ("big_cells_max", _i32), ("reserved0", _i32), ("big_e_slots", _i64),
-                ("big_i_slots", _i64)]
+                ("big_i_slots", _i64), ("d_cell_nabs", _vp)]
 
 
 class XpParticles(C.Structure):
@@ -101,7 +101,7 @@ class XpDiag(C.Structure):
 EXPORTS = ["xp_abi_version", "xp_last_error", "xp_ctx_create", "xp_ctx_destroy",
            "xp_table_bytes", "init_species", "xp_work_bytes", "xp_step_work_bytes",
            "xp_lds_limits", "bin_particles", "collide_ionize_step", "photo_auger_step",
-           "diagnostics", "xp_selftest"]
+           "diagnostics", "transport_photons", "xp_selftest"]
 
 _lib = None
 
@@ -144,6 +144,8 @@ def load(path=LIB_PATH):
     L.collide_ionize_step.argtypes = [_vp, C.POINTER(XpBatch), C.POINTER(XpStepParams), _vp]
     L.photo_auger_step.restype = _i32
     L.photo_auger_step.argtypes = [_vp, C.POINTER(XpBatch), C.POINTER(XpStepParams), _vp]
+    L.transport_photons.restype = _i32
+    L.transport_photons.argtypes = [_vp, C.POINTER(XpBatch), _vp, _vp]
     L.diagnostics.restype = _i32
     L.diagnostics.argtypes = [_vp, C.POINTER(XpBatch), _vp, _u32, _vp]
     L.xp_selftest.restype = _i32
@@ -195,6 +197,10 @@ def bin_particles(ctx, parts, batch, cap, d_need, stream):
 
 def collide_ionize_step(ctx, batch, params, stream):
     check(load().collide_ionize_step(ctx, C.byref(batch), C.byref(params), _vp(stream)))
+
+
+def transport_photons(ctx, batch, d_trans, stream):
+    check(load().transport_photons(ctx, C.byref(batch), _vp(d_trans), _vp(stream)))
 
 
 def photo_auger_step(ctx, batch, params, stream):

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libxpic.so")
-SOURCES = ["xp_api.hip", "xp_step.hip", "xp_big.hip", "xp_bin.hip", "xp_diag.hip"]
+SOURCES = ["xp_api.hip", "xp_step.hip", "xp_big.hip", "xp_bin.hip", "xp_diag.hip", "xp_rad.hip"]
 ARCH = os.environ.get("XPIC_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=" + ARCH, "-fPIC", "-ffp-contract=off",
          "-fno-fast-math", "-Werror=return-type", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

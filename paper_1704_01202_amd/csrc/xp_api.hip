@@ -241,7 +241,8 @@ static StepPlan step_plan(const xp_batch* b)
 size_t xp_step_work_bytes(const xp_batch* b)
 {
     if (!b) return 0;
-    const size_t cells = 8 * (size_t)(b->n_cells > 0 ? b->n_cells : 1) + 256;
+    // diagnostics: 8 B per cell; transport_photons: one exit density per cell and bin
+    const size_t cells = 8 * XP_MAX_BINS * (size_t)(b->n_cells > 0 ? b->n_cells : 1) + 256;
     const StepPlan p = step_plan(b);
     return p.bytes > cells ? p.bytes : cells;
 }
@@ -290,6 +291,7 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
     a.cell_cnt = b->d_cell_counters;
     a.cell_led = b->d_cell_ledger;
     a.cell_mom = b->d_cell_moments;
+    a.cell_nabs = b->d_cell_nabs;
     a.status = b->d_status;
     a.tab = ctx->d_tables;
     a.d_step = p->d_step;
@@ -379,7 +381,7 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
         // the variants, per-cell records and per-cell photon fields are
         // compiled into their own kernels
         const bool xv = (flags & (XP_THERM | XP_ION_Z | XP_NANBU)) != 0 || b->d_cell_counters || b->d_cell_ledger ||
-                        b->d_cell_moments || b->d_cell_nhv;
+                        b->d_cell_moments || b->d_cell_nhv || b->d_cell_nabs;
         for (int tier = 0;; ++tier) {
             const bool last = ce >= ce_top || tier >= xpd::BIG_COUNT_SLOT - 1;
             a.lds_ce = ce;
@@ -499,6 +501,30 @@ xp_status diagnostics(xp_ctx* ctx, const xp_batch* b, xp_diag* d_out, uint32_t w
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     e = xpd::diag_launch(a, what, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "diagnostics launch");
+    return XP_OK;
+}
+
+xp_status transport_photons(xp_ctx* ctx, xp_batch* b, double* d_trans, void* stream)
+{
+    xp_status st = check_batch(ctx, b);
+    if (st != XP_OK) return st;
+    if (!b->d_cell_nhv || !b->d_cell_nabs)
+        return fail(XP_ERR_INVALID_ARG, "transport_photons needs d_cell_nhv and d_cell_nabs");
+    if (!b->d_work || b->work_bytes < xp_step_work_bytes(b))
+        return fail(XP_ERR_TOO_SMALL, "workspace smaller than xp_step_work_bytes");
+    xpd::TransportArgs a{};
+    a.runs = b->d_runs;
+    a.cell_run = b->d_cell_run;
+    a.nhv = b->d_cell_nhv;
+    a.nabs = b->d_cell_nabs;
+    a.exit = (double*)b->d_work;
+    a.trans = d_trans;
+    a.n_runs = b->n_runs;
+    a.n_cells = b->n_cells;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    e = xpd::transport_launch(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "transport launch");
     return XP_OK;
 }
 

@@ -106,6 +106,7 @@ __global__ void k_big_init(BigArgs a)
         r.u[0] = r.u[1] = r.u[2] = 0.0;
         for (int q = 0; q < XP_NMOM; ++q) r.mom[q] = 0.0;
         for (int q = 0; q < XP_NCOUNT; ++q) r.cnt[q] = 0;
+        for (int q = 0; q < XP_MAX_BINS; ++q) r.nabs[q] = 0;
         for (int q = 0; q < XP_NLEDGER; ++q) r.led[q] = 0.0;
         const int64_t lim = (int64_t)BIG_MAX_CHUNKS * BIG_CH;
         if ((int64_t)r.ecap > lim || (int64_t)r.ni > lim) {
@@ -1601,6 +1602,7 @@ __global__ __launch_bounds__(BT) void k_big_s5b(BigArgs a)
                         en = R.hv[sel] - lowered(tb, z0, sh, dE);
                         atomicAdd(&led[XP_L_PHOTO_E], en);
                         atomicAdd(&led[XP_L_PHOTON_ABS], R.hv[sel]);
+                        if (s.cell_nabs) atomicAdd(&r.nabs[sel], 1);
                     }
                     const Words d = draw(s, r, (uint32_t)i, RP_DIR, (uint32_t)bit);
                     const double mu = 2.0 * u52(d.x0, d.x1) - 1.0;
@@ -1823,6 +1825,9 @@ __global__ __launch_bounds__(64) void k_big_commit(BigArgs a)
             for (int q = threadIdx.x; q < XP_NLEDGER; q += 64) s.cell_led[(size_t)cell * XP_NLEDGER + q] = r.led[q];
         if (s.cell_mom)
             for (int q = threadIdx.x; q < XP_NMOM; q += 64) s.cell_mom[(size_t)cell * XP_NMOM + q] = r.mom[q];
+        if (s.cell_nabs)
+            for (int q = threadIdx.x; q < XP_MAX_BINS; q += 64)
+                s.cell_nabs[(size_t)cell * XP_MAX_BINS + q] = r.nabs[q];
         if (s.run_cnt)
             for (int q = threadIdx.x; q < XP_NCOUNT; q += 64)
                 if (r.cnt[q]) atomicAdd((unsigned long long*)&s.run_cnt[(size_t)r.run * XP_NCOUNT + q], (unsigned long long)r.cnt[q]);

@@ -29,6 +29,7 @@ struct StepArgs {
     int64_t* cell_cnt;
     double* cell_led;
     double* cell_mom;
+    int32_t* cell_nabs;         // optional [n_cells][XP_MAX_BINS] photon events per bin
     uint32_t* status;
     const DevTables* tab;
     const double* run_sig;      // [n_runs][XP_MAX_BINS][3] photo cross sections (k_run_prep)
@@ -61,8 +62,8 @@ size_t step_lds_bytes(int ce, int ci);
 void lds_limits(size_t max_lds, int* e_lds, int* i_lds);
 size_t lds_budget(size_t max_lds);
 
-// XV: compiled with the method's variants (XP_THERM, XP_ION_Z), the per-cell
-// records and per-cell photon fields; the plain step leaves them out, which
+// XV: compiled with the method's variants (XP_THERM, XP_ION_Z, XP_NANBU), the
+// per-cell records and per-cell photon fields; the plain step leaves them out, which
 // keeps its registers for the main path.
 template <int B, bool XV>
 __global__ void k_step(StepArgs a);
@@ -114,6 +115,18 @@ constexpr int DIAG_MAX_CHUNKS = 4096;
 
 hipError_t diag_launch(const DiagArgs& a, uint32_t what, hipStream_t s);
 
+// Reduced radiation transport (transport_photons).
+struct TransportArgs {
+    const xp_run* runs;
+    const int32_t* cell_run;
+    double* nhv;            // [n_cells][XP_MAX_BINS], rewritten
+    const int32_t* nabs;    // [n_cells][XP_MAX_BINS], photon events of the last step
+    double* exit;           // workspace [n_cells][XP_MAX_BINS]: exit density at each row start
+    double* trans;          // optional [n_runs][XP_MAX_BINS]
+    int32_t n_runs, n_cells;
+};
+hipError_t transport_launch(const TransportArgs& a, hipStream_t s);
+
 }  // namespace xpd
 
 namespace xpd {
@@ -150,6 +163,7 @@ struct BigRec {
     double ssum[13][3];
     int32_t cnt[XP_NCOUNT];
     double led[XP_NLEDGER];
+    int32_t nabs[XP_MAX_BINS];         // photon events per bin (S5)
     // forced thermalization (variant): weight units, lab-frame and drift-frame
     // kinetic energy, draw spread, draw mean, scale; keep: 0 resample, 1 keep
     // the velocities, 2 drift velocity only

@@ -31,6 +31,7 @@ struct CellSharedT {
     long long ired[16];
     int sel[16];
     int cnt[XP_NCOUNT];
+    int nabs[XP_MAX_BINS];   // photon events per bin (S5)
     double led[XP_NLEDGER];
     double mom[XP_NMOM];
     double sig[XP_MAX_BINS][3];
@@ -473,6 +474,8 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
         L.fwok[j] = 0;
     }
     for (int q = tid; q < XP_NCOUNT; q += B) S.cnt[q] = 0;
+    if (XV)
+        for (int q = tid; q < XP_MAX_BINS; q += B) S.nabs[q] = 0;
     for (int q = tid; q < XP_NLEDGER; q += B) S.led[q] = 0.0;
     for (int q = tid; q < XP_NMOM; q += B) S.mom[q] = 0.0;
     for (int q = tid; q < 8; q += B) S.ints[q] = 0;
@@ -1035,6 +1038,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
                         en = R->hv[sel] - lowered(tb, z0, s, dE);
                         atomicAdd(&S.led[XP_L_PHOTO_E], en);
                         atomicAdd(&S.led[XP_L_PHOTON_ABS], R->hv[sel]);
+                        if (XV) atomicAdd(&S.nabs[sel], 1);
                     }
                     if (pos < lim) {
                         const Words d = rng((uint32_t)i, RP_DIR, (uint32_t)bit);
@@ -1172,6 +1176,8 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
         for (int q = tid; q < XP_NLEDGER; q += B) a.cell_led[(size_t)cell * XP_NLEDGER + q] = S.led[q];
     if (XV && a.cell_mom)
         for (int q = tid; q < XP_NMOM; q += B) a.cell_mom[(size_t)cell * XP_NMOM + q] = S.mom[q];
+    if (XV && a.cell_nabs)
+        for (int q = tid; q < XP_MAX_BINS; q += B) a.cell_nabs[(size_t)cell * XP_MAX_BINS + q] = S.nabs[q];
     return true;
 }
 

@@ -115,6 +115,9 @@ class Batch:
     runs: list of (workloads.RunSpec, workloads.Particles).  capacity =
     (electron slots per ion, extra slots) of every cell's electron slab.
     cell_records keeps per-cell counters, tallies and moments of the last step.
+    cell_nhv: initial photon field per cell ([n_cells][n_bins], photons / m^3);
+    the runs then read it instead of their uniform field, and transport()
+    rebuilds it after a step (the batch records photon events per cell).
     big: workspace of the global-memory path -- "auto" for the cells whose
     slabs may outgrow one workgroup's LDS, "all" so that every cell can take it
     (step(..., schedule=3)).
@@ -161,6 +164,12 @@ class Batch:
             f = np.zeros((self.n_cells, B.XP_MAX_BINS))
             f[:, :np.asarray(cell_nhv).shape[1]] = cell_nhv
             self.d_cell_nhv = _dev(f, dev)
+        self.d_cell_nabs = None
+        self.d_trans = None
+        if cell_nhv is not None:
+            self.d_cell_nabs = torch.zeros((max(self.n_cells, 1), B.XP_MAX_BINS), dtype=torch.int32,
+                                           device=dev)
+            self.d_trans = torch.zeros((self.n_runs, B.XP_MAX_BINS), dtype=torch.float64, device=dev)
         self.cell_records = cell_records
         if cell_records:
             self.d_cell_cnt = torch.zeros((nc, B.XP_NCOUNT), dtype=torch.int64, device=dev)
@@ -244,6 +253,7 @@ class Batch:
         b.d_stats = _ptr(self.d_stats)
         b.big_cells_max = self.big_cells_max
         b.big_e_slots, b.big_i_slots = self.big_e_slots, self.big_i_slots
+        b.d_cell_nabs = _ptr(self.d_cell_nabs)
         return b
 
     def _bin(self):
@@ -303,6 +313,27 @@ class Batch:
         B.photo_auger_step(self.ctx.h, self.struct(), p, _stream())
         if record_stats:
             self._after()
+
+    def transport(self):
+        """Reduced radiation transport after a step (transport_photons): the
+        per-cell field is rebuilt from the runs' incident densities and the
+        step's photon events.  Returns the device array of run transmissions
+        [n_runs][XP_MAX_BINS] (no host sync)."""
+        if self.d_cell_nhv is None:
+            raise ValueError("transport needs a batch created with cell_nhv")
+        B.transport_photons(self.ctx.h, self.struct(), _ptr(self.d_trans), _stream())
+        return self.d_trans
+
+    def cell_field(self, run=0):
+        c0 = self.cell_begin[run]
+        nc = self.specs[run].nx * self.specs[run].ny
+        nb = len(self.specs[run].photon_hv)
+        return self.d_cell_nhv[c0:c0 + nc, :nb].cpu().numpy()
+
+    def absorbed(self, run=0):
+        c0 = self.cell_begin[run]
+        nc = self.specs[run].nx * self.specs[run].ny
+        return self.d_cell_nabs[c0:c0 + nc].cpu().numpy()
 
     def diagnostics(self, reset=False):
         out = torch.zeros(self.n_runs * C.sizeof(B.XpDiag), dtype=torch.uint8, device=self.device)

@@ -1,0 +1,81 @@
+"""The reduced radiation transport on the GPU against the oracle: after every
+step the photon events per cell and bin, the rebuilt per-cell field and the
+run transmissions must be identical, with the particle state as in the other
+parity tests.  LDS schedules, the global-memory path, several bins, empty
+cells and a 1D run."""
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1704_01202_amd import runtime as RT
+from tests import cases
+from tests.test_gpu_parity import compare, ctx, say  # noqa: F401
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _run(ctx, spec, parts, steps, flags, schedule=0, big="auto", capacity=(7, 16), label=""):
+    nb = len(spec.photon_hv)
+    f0 = np.tile(np.asarray(spec.photon_n, dtype=np.float64), (spec.nx * spec.ny, 1))
+    sim = O.Sim(ctx.tables, spec)
+    sim.bin(parts)
+    sim.set_cell_field(f0)
+    bat = RT.Batch(ctx, [(spec, parts)], capacity=capacity, cell_records=True, cell_nhv=f0,
+                   big=big)
+    events = 0
+    for s in range(steps):
+        bat.step(s, flags, schedule=schedule)
+        sim.step(s, flags)
+        tg = bat.transport()
+        to = sim.transport()
+        torch.cuda.synchronize()
+        assert bat.status() == 0, "%s step %d status %d" % (label, s, bat.status())
+        compare(bat.state(), sim.state(), "%s step %d" % (label, s))
+        ga, oa = bat.absorbed()[:, :nb], sim.absorbed()[:, :nb]
+        assert np.array_equal(ga, oa), "%s step %d photon events" % (label, s)
+        events += int(oa.sum())
+        gf, of = bat.cell_field(), sim.cell_field()
+        assert np.array_equal(gf, of), "%s step %d field (max rel %.2e)" % (
+            label, s, np.max(np.abs(gf - of) / np.maximum(np.abs(of), 1e-300)))
+        assert np.array_equal(tg.cpu().numpy()[0, :nb], to), "%s step %d transmission" % (label, s)
+        say("%s step %d ok: %d photon events, transmission %s" % (label, s, int(oa.sum()), to))
+    assert events > 0
+    return bat, sim
+
+
+def _slab(seed, nx=24, ny=6, ni_hi=60, ne_hi=60, bins=((1650.0, 1850.0), (6e29, 9e29))):
+    rng = np.random.default_rng(seed)
+    ni = rng.integers(0, ni_hi, nx * ny)
+    ne = rng.integers(0, ne_hi, nx * ny)
+    ni[3] = 0          # a vacuum cell inside a row
+    spec, parts = cases.one_run(nx, ne, ni, 40.0, 0.2, seed=seed, ny=ny, lnl=3.0,
+                                photon_hv=bins[0], photon_n=bins[1])
+    parts.ik[:] = rng.integers(0, 2, parts.ni)
+    return spec, parts
+
+
+def test_transport_matches_oracle(ctx):
+    spec, parts = _slab(71)
+    _run(ctx, spec, parts, 5, O.ALL, label="transport/wave")
+    for sched in (2, 5):
+        spec, parts = _slab(72, ni_hi=12, ne_hi=12)
+        _run(ctx, spec, parts, 4, O.ALL | O.THERM, schedule=sched, capacity=(5, 4),
+             label="transport/%d" % sched)
+    # a 1D run of 300 cells (rows longer than a wave)
+    spec, parts = _slab(73, nx=300, ny=1, ni_hi=20, ne_hi=20, bins=((1850.0,), (2e30,)))
+    _run(ctx, spec, parts, 4, O.ALL, label="transport/1d")
+
+
+def test_transport_global_path(ctx):
+    spec, parts = _slab(74, nx=12, ny=4)
+    _run(ctx, spec, parts, 4, O.ALL, schedule=3, big="all", capacity=(3, 16),
+         label="transport/global")
+    # oversized cells beside LDS cells
+    ne = np.array([60, 3000, 2600, 45, 0, 30])
+    ni = np.array([50, 1500, 600, 40, 20, 0])
+    spec, parts = cases.one_run(ne.size, ne, ni, 30.0, 0.1, seed=75, e_weight=1, dt=0.05e-15,
+                                photon_hv=(1850.0,), photon_n=(4e30,))
+    bat, _ = _run(ctx, spec, parts, 3, O.ALL, label="transport/oversized")
+    assert bat.stats()[2] == 2
