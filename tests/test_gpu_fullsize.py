@@ -74,3 +74,29 @@ def test_c4_full_size_sample_parity(ctx):
             compare(bat.state(k), sim.state(), "C4 run %d step %d" % (pick[k], s))
         say("C4 sample step %d ok" % s)
     assert bat.stats()[2] >= 1, "no run took the global-memory path"
+
+
+def test_c2_full_size_variants_parity(ctx):
+    # the 512 x 512 target with Nanbu's scattering law and the reduced
+    # radiation transport after every step, as bench.py --nanbu --transport
+    # steps it: state, photon events, field and transmission against the oracle
+    spec, parts = W.config_c2()
+    f0 = np.tile(np.asarray(spec.photon_n, dtype=np.float64), (spec.ncells, 1))
+    sim = O.Sim(ctx.tables, spec)
+    sim.bin(parts)
+    sim.set_cell_field(f0)
+    bat = RT.Batch(ctx, [(spec, parts)], capacity=(7, 16), cell_nhv=f0)
+    th = host_threads()
+    flags = O.ALL | O.NANBU
+    for s in range(2):
+        bat.step(s, flags)
+        sim.step(s, flags, th)
+        tg = bat.transport()
+        to = sim.transport()
+        torch.cuda.synchronize()
+        assert bat.status() == 0
+        compare(bat.state(), sim.state(), "C2 full nanbu+transport step %d" % s)
+        assert np.array_equal(bat.absorbed()[:, :1], sim.absorbed()[:, :1]), s
+        assert np.array_equal(bat.cell_field(), sim.cell_field()), s
+        assert np.array_equal(tg.cpu().numpy()[0, :1], to), s
+        say("C2 full nanbu+transport step %d ok, transmission %.6f" % (s, to[0]))
