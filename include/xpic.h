@@ -32,7 +32,8 @@
 extern "C" {
 #endif
 
-#define XP_ABI_VERSION 1u
+/* Layout version of the structs below; 2 added xp_batch.d_cell_nabs. */
+#define XP_ABI_VERSION 2u
 
 typedef int32_t xp_status;
 #define XP_OK                   0

@@ -98,6 +98,8 @@ class XpDiag(C.Structure):
                 ("ledger", _d * XP_NLEDGER)]
 
 
+ABI_VERSION = 2   # struct layouts mirrored below (XP_ABI_VERSION of include/xpic.h)
+
 EXPORTS = ["xp_abi_version", "xp_last_error", "xp_ctx_create", "xp_ctx_destroy",
            "xp_table_bytes", "init_species", "xp_work_bytes", "xp_step_work_bytes",
            "xp_lds_limits", "bin_particles", "collide_ionize_step", "photo_auger_step",
@@ -121,6 +123,9 @@ def load(path=LIB_PATH):
     L = C.CDLL(path)
     L.xp_abi_version.restype = _u32
     L.xp_abi_version.argtypes = []
+    if L.xp_abi_version() != ABI_VERSION:
+        raise XpError("libxpic.so has ABI version %d, the binding mirrors %d: rebuild the library"
+                      % (L.xp_abi_version(), ABI_VERSION))
     L.xp_last_error.restype = C.c_char_p
     L.xp_last_error.argtypes = []
     L.xp_ctx_create.restype = _i32
