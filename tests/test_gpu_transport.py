@@ -79,3 +79,39 @@ def test_transport_global_path(ctx):
                                 photon_hv=(1850.0,), photon_n=(4e30,))
     bat, _ = _run(ctx, spec, parts, 3, O.ALL, label="transport/oversized")
     assert bat.stats()[2] == 2
+
+
+def test_transport_several_runs(ctx):
+    # runs of different shapes and bins in one batch: each run's rows start at
+    # its own first cell, each run's transmission is its own
+    specs = []
+    a = _slab(76, nx=12, ny=5, bins=((1650.0, 1850.0), (6e29, 9e29)))
+    b = _slab(77, nx=70, ny=1, ni_hi=30, ne_hi=30, bins=((1800.0,), (2e30,)))
+    c = _slab(78, nx=9, ny=3, ni_hi=40, ne_hi=40, bins=((1900.0,), (1e30,)))
+    runs = [a, b, c]
+    nbmax = max(len(s.photon_hv) for s, _ in runs)
+    fields = []
+    for spec, _ in runs:
+        f = np.zeros((spec.nx * spec.ny, nbmax))
+        f[:, :len(spec.photon_n)] = spec.photon_n
+        fields.append(f)
+    bat = RT.Batch(ctx, runs, capacity=(7, 16), cell_records=True, cell_nhv=np.concatenate(fields))
+    sims = []
+    for (spec, parts), f in zip(runs, fields):
+        sim = O.Sim(ctx.tables, spec)
+        sim.bin(parts)
+        sim.set_cell_field(f[:, :len(spec.photon_n)])
+        sims.append(sim)
+    for s in range(4):
+        bat.step(s, O.ALL)
+        tg = bat.transport().cpu().numpy()
+        for r, ((spec, _), sim) in enumerate(zip(runs, sims)):
+            sim.step(s, O.ALL)
+            to = sim.transport()
+            nb = len(spec.photon_hv)
+            compare(bat.state(r), sim.state(), "runs/%d step %d" % (r, s))
+            assert np.array_equal(bat.absorbed(r)[:, :nb], sim.absorbed()[:, :nb]), (r, s)
+            assert np.array_equal(bat.cell_field(r), sim.cell_field()), (r, s)
+            assert np.array_equal(tg[r, :nb], to), (r, s)
+            assert np.all(tg[r, nb:] == 0.0)
+        say("several runs step %d ok: %s" % (s, tg[:, :2].tolist()))
