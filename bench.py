@@ -216,11 +216,23 @@ def bench_c4(args):
     seq_steps = timed
     del sc
     torch.cuda.empty_cache()
+    per_run = []
     if args.no_seq:
         stepping, total = float("nan"), float("nan")
     else:
-        stepping, total, _ = SC.sequential(ctx, runs, seq_steps, capacity=cap)
+        stepping, total, _ = SC.sequential(ctx, runs, seq_steps, capacity=cap, per_run=per_run)
     seq_rph = len(runs) * 3600.0 / (args.run_steps * stepping / seq_steps)
+    # time to result of each run at its full length (run_steps), stepping time
+    # only: in the batch every run finishes with the last step; in the
+    # sequential loop run r finishes after the runs before it
+    scale = args.run_steps / timed
+    t_all = ms_step * 1e-3 * timed * scale
+    ttr_batched = {"p50": t_all, "p99": t_all}
+    ttr_seq = None
+    if per_run:
+        import numpy as np
+        done = np.cumsum(per_run) * (args.run_steps / seq_steps)
+        ttr_seq = {"p50": float(np.percentile(done, 50)), "p99": float(np.percentile(done, 99))}
     log("sequential: %.2f s stepping (%.2f s with set-up) for %d steps of every run"
         % (stepping, total, seq_steps))
     out = {
@@ -241,6 +253,8 @@ def bench_c4(args):
                                % (len(runs), args.run_steps),
                    "particles": n_part, "autotuned": best, "graph_steps": k, "status": status},
         "collisions_per_s": coll / wall,
+        "time_to_result_s": ttr_batched,
+        "sequential_time_to_result_s": ttr_seq,
         "sequential_runs_per_hour": seq_rph,
         "vs_sequential": batched_rph / seq_rph if seq_rph == seq_rph else None,
         "sequential_steps": seq_steps,

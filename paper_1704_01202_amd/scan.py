@@ -116,10 +116,12 @@ class Scan:
         return self.bat.status()
 
 
-def sequential(ctx: RT.Context, runs, nsteps, capacity=(7, 16), flags=B.XP_ALL, keep=False):
+def sequential(ctx: RT.Context, runs, nsteps, capacity=(7, 16), flags=B.XP_ALL, keep=False,
+               per_run=None):
     """Every run alone in its own batch, stepped eagerly one after another.
     Returns (seconds spent stepping, seconds including each run's set-up,
-    list of batches if keep)."""
+    list of batches if keep); per_run (a list) receives each run's stepping
+    seconds in order."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stepping = 0.0
@@ -131,7 +133,10 @@ def sequential(ctx: RT.Context, runs, nsteps, capacity=(7, 16), flags=B.XP_ALL, 
         for s in range(nsteps):
             bat.step(s, flags)
         torch.cuda.synchronize()
-        stepping += time.perf_counter() - t1
+        dt = time.perf_counter() - t1
+        stepping += dt
+        if per_run is not None:
+            per_run.append(dt)
         if keep:
             kept.append(bat)
         else:
