@@ -33,7 +33,7 @@ __global__ __launch_bounds__(64) void k_tr_rows(TransportArgs a)
         bool start = false;
         if (c < a.n_cells) {
             const xp_run& R = a.runs[a.cell_run[c]];
-            start = R.field_per_cell && R.n_bins > 0 && (c - R.cell_begin) % R.nx == 0;
+            start = R.field_per_cell && R.n_bins > 0 && R.nx > 0 && (c - R.cell_begin) % R.nx == 0;
         }
         unsigned long long m = __ballot(start);
         while (m) {
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(64) void k_tr_sum(TransportArgs a)
     if (run >= a.n_runs || !a.trans) return;
     const xp_run& R = a.runs[run];
     const int lane = threadIdx.x;
-    const int nb = R.field_per_cell ? R.n_bins : 0;
+    const int nb = R.field_per_cell && R.nx > 0 && R.ny > 0 ? R.n_bins : 0;
     const int ny = R.ny, nx = R.nx, c0 = R.cell_begin;
     if (lane < XP_MAX_BINS && lane >= nb) a.trans[(size_t)run * XP_MAX_BINS + lane] = 0.0;
     for (int b = 0; b < nb; ++b) {
