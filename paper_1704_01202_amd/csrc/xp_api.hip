@@ -407,24 +407,30 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
                 const int w = sched == 4 ? 32 : (sched == 5 ? 16 : 8);
                 if (m > 4 * w) sched = m > 128 ? 2 : 1;   // plan too large for the group
             }
+            // kernel instance: plain, extended, or extended with Nanbu's law
+            const int level = (flags & XP_NANBU) ? 2 : (xv ? 1 : 0);
+            auto pick = [level](void (*k0)(xpd::StepArgs), void (*k1)(xpd::StepArgs),
+                                void (*k2)(xpd::StepArgs)) {
+                return level == 2 ? (const void*)k2 : (level == 1 ? (const void*)k1 : (const void*)k0);
+            };
             const void* fn;
             int threads = 64, per_cell_groups = 1;
             switch (sched) {
-            case 1: fn = xv ? (const void*)xpd::k_step<64, true> : (const void*)xpd::k_step<64, false>; break;
+            case 1: fn = pick(xpd::k_step<64, 0>, xpd::k_step<64, 1>, xpd::k_step<64, 2>); break;
             case 2:
-                fn = xv ? (const void*)xpd::k_step<256, true> : (const void*)xpd::k_step<256, false>;
+                fn = pick(xpd::k_step<256, 0>, xpd::k_step<256, 1>, xpd::k_step<256, 2>);
                 threads = 256;
                 break;
             case 4:
-                fn = xv ? (const void*)xpd::k_step_g<32, true> : (const void*)xpd::k_step_g<32, false>;
+                fn = pick(xpd::k_step_g<32, 0>, xpd::k_step_g<32, 1>, xpd::k_step_g<32, 2>);
                 per_cell_groups = 2;
                 break;
             case 5:
-                fn = xv ? (const void*)xpd::k_step_g<16, true> : (const void*)xpd::k_step_g<16, false>;
+                fn = pick(xpd::k_step_g<16, 0>, xpd::k_step_g<16, 1>, xpd::k_step_g<16, 2>);
                 per_cell_groups = 4;
                 break;
             default:
-                fn = xv ? (const void*)xpd::k_step_g<8, true> : (const void*)xpd::k_step_g<8, false>;
+                fn = pick(xpd::k_step_g<8, 0>, xpd::k_step_g<8, 1>, xpd::k_step_g<8, 2>);
                 per_cell_groups = 8;
                 break;
             }

@@ -180,7 +180,7 @@ __host__ __device__ size_t step_lds_bytes_dev(int ce, int ci)
     return n;
 }
 
-template <class T, bool XV>
+template <class T, int XV>
 __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, const Lds& L);
 
 size_t step_lds_bytes(int ce, int ci) { return step_lds_bytes_dev(ce, ci); }
@@ -193,7 +193,7 @@ size_t step_lds_bytes(int ce, int ci) { return step_lds_bytes_dev(ce, ci); }
 // rather than per cell.  Three waves per SIMD: the step is bound by the
 // latency of its FP64 chains, and the register budget of three waves holds it
 // with almost no spilling.
-template <int B, bool XV>
+template <int B, int XV>
 __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(3))) void k_step(StepArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(3))) void k_s
 // records are summed per group and flushed like those of k_step.  Per-cell
 // values differ between the groups of a wave, so they live in vector
 // registers: two waves per SIMD, each carrying G cells.
-template <int W, bool XV>
+template <int W, int XV>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_step_g(StepArgs a)
 {
     constexpr int G = 64 / W;
@@ -393,7 +393,7 @@ __device__ __noinline__ void make_perm_fn(int n, uint32_t c0, uint32_t c1, uint3
 
 // Steps one cell; true when its new state was committed (the caller then adds
 // S.cnt / S.led to the run records and S.ints[6] holds its electron count).
-template <class T, bool XV>
+template <class T, int XV>
 __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, const Lds& L)
 {
     constexpr int B = T::N;
@@ -557,8 +557,8 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
     // other items are adjacent pairs of the permutation.  Phase 1 is e-i:
     // round robin over the smaller population, round by round.
     const bool do_ee = (flags & XP_EE) && ne >= 2;
-    // scattering law: Takizuka-Abe, or (XP_NANBU, variant instances only) Nanbu
-    const bool nanbu = XV && (flags & XP_NANBU) != 0;
+    // scattering law: Takizuka-Abe, or (XP_NANBU, the Nanbu instances only) Nanbu
+    const bool nanbu = XV == 2 && (flags & XP_NANBU) != 0;
     const bool do_ei = (flags & XP_EI) && ne >= 1 && ni >= 1;
     if ((flags & (XP_EE | XP_EI)) && ne >= 1 && (ne >= 2 || ni >= 1)) make_perm(RP_PERM_E, ne, L.perm_e);
     const double mee = (ME * ME) / (ME + ME);
@@ -1181,16 +1181,21 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
     return true;
 }
 
-template __global__ void k_step<64, false>(StepArgs);
-template __global__ void k_step<256, false>(StepArgs);
-template __global__ void k_step_g<32, false>(StepArgs);
-template __global__ void k_step_g<16, false>(StepArgs);
-template __global__ void k_step_g<8, false>(StepArgs);
-template __global__ void k_step<64, true>(StepArgs);
-template __global__ void k_step<256, true>(StepArgs);
-template __global__ void k_step_g<32, true>(StepArgs);
-template __global__ void k_step_g<16, true>(StepArgs);
-template __global__ void k_step_g<8, true>(StepArgs);
+template __global__ void k_step<64, 0>(StepArgs);
+template __global__ void k_step<256, 0>(StepArgs);
+template __global__ void k_step_g<32, 0>(StepArgs);
+template __global__ void k_step_g<16, 0>(StepArgs);
+template __global__ void k_step_g<8, 0>(StepArgs);
+template __global__ void k_step<64, 1>(StepArgs);
+template __global__ void k_step<256, 1>(StepArgs);
+template __global__ void k_step_g<32, 1>(StepArgs);
+template __global__ void k_step_g<16, 1>(StepArgs);
+template __global__ void k_step_g<8, 1>(StepArgs);
+template __global__ void k_step<64, 2>(StepArgs);
+template __global__ void k_step<256, 2>(StepArgs);
+template __global__ void k_step_g<32, 2>(StepArgs);
+template __global__ void k_step_g<16, 2>(StepArgs);
+template __global__ void k_step_g<8, 2>(StepArgs);
 
 __global__ void k_step_prep(int32_t* counts, int32_t* stats)
 {
