@@ -20,12 +20,16 @@ namespace xpd {
 
 namespace {
 
-// One wave per row: the lanes compute the transmissions of 64 cells at once,
-// lane 0 carries the running product through them in order.
+// Cells (or rows) one wave handles per round trip to memory: 8 per lane.
+constexpr int TR_CH = 8;
+constexpr int TR_SPAN = 64 * TR_CH;
+
+// One wave per row: the lanes fetch and compute the transmissions of 512 cells
+// at once, lane 0 carries the running product through them in order.
 __global__ __launch_bounds__(64) void k_tr_rows(TransportArgs a)
 {
-    __shared__ double tau[64];
-    __shared__ double ent[64];
+    __shared__ double tau[TR_SPAN];
+    __shared__ double ent[TR_SPAN];
     __shared__ double carry_s;
     const int lane = threadIdx.x;
     for (int c0 = blockIdx.x * 64; c0 < a.n_cells; c0 += gridDim.x * 64) {
@@ -47,30 +51,54 @@ __global__ __launch_bounds__(64) void k_tr_rows(TransportArgs a)
             const double w0 = R.w0;
             for (int b = 0; b < nb; ++b) {
                 double carry = R.nhv[b];
-                for (int i0 = 0; i0 < nx; i0 += 64) {
-                    const int i = i0 + lane;
-                    double t = 1.0;
-                    if (i < nx) {
-                        const size_t k = (size_t)(rc + i) * XP_MAX_BINS + b;
-                        const double n = a.nhv[k];
-                        if (n > 0.0) {
-                            const double ab = ((double)a.nabs[k] * w0) / (cross * n);
-                            t = ab < 1.0 ? 1.0 - ab : 0.0;
+                for (int i0 = 0; i0 < nx; i0 += TR_SPAN) {
+                    double n[TR_CH];
+                    int32_t k[TR_CH];
+#pragma unroll
+                    for (int q = 0; q < TR_CH; ++q) {
+                        const int i = i0 + q * 64 + lane;
+                        n[q] = 0.0;
+                        k[q] = 0;
+                        if (i < nx) {
+                            const size_t at = (size_t)(rc + i) * XP_MAX_BINS + b;
+                            n[q] = a.nhv[at];
+                            k[q] = a.nabs[at];
                         }
                     }
-                    tau[lane] = t;
+#pragma unroll
+                    for (int q = 0; q < TR_CH; ++q) {
+                        double t = 1.0;
+                        if (n[q] > 0.0) {
+                            const double ab = ((double)k[q] * w0) / (cross * n[q]);
+                            t = ab < 1.0 ? 1.0 - ab : 0.0;
+                        }
+                        tau[q * 64 + lane] = t;
+                    }
                     __syncthreads();
                     if (lane == 0) {
-                        const int cnt = nx - i0 < 64 ? nx - i0 : 64;
-#pragma unroll 8
-                        for (int q = 0; q < cnt; ++q) {
-                            ent[q] = carry;
-                            carry = carry * tau[q];
+                        // eight transmissions fetched ahead of their products; past
+                        // the row's end tau = 1, which leaves the carry unchanged
+                        const int cnt = nx - i0 < TR_SPAN ? nx - i0 : TR_SPAN;
+                        for (int q = 0; q < cnt; q += 8) {
+                            double tt[8], ee[8];
+#pragma unroll
+                            for (int j = 0; j < 8; ++j) tt[j] = tau[q + j];
+#pragma unroll
+                            for (int j = 0; j < 8; ++j) {
+                                ee[j] = carry;
+                                carry = carry * tt[j];
+                            }
+#pragma unroll
+                            for (int j = 0; j < 8; ++j) ent[q + j] = ee[j];
                         }
                         carry_s = carry;
                     }
                     __syncthreads();
-                    if (i < nx) a.nhv[(size_t)(rc + i) * XP_MAX_BINS + b] = ent[lane];
+#pragma unroll
+                    for (int q = 0; q < TR_CH; ++q) {
+                        const int i = i0 + q * 64 + lane;
+                        if (i < nx) a.nhv[(size_t)(rc + i) * XP_MAX_BINS + b] = ent[q * 64 + lane];
+                    }
                     carry = carry_s;
                     __syncthreads();
                 }
@@ -81,10 +109,11 @@ __global__ __launch_bounds__(64) void k_tr_rows(TransportArgs a)
 }
 
 // Mean exit density of a run's rows over its incident density, per bin: the
-// lanes fetch 64 rows' exit densities at a time, lane 0 adds them in row order.
+// lanes fetch 512 rows' exit densities at a time, lane 0 adds them in row
+// order.
 __global__ __launch_bounds__(64) void k_tr_sum(TransportArgs a)
 {
-    __shared__ double v[64];
+    __shared__ double v[TR_SPAN];
     const int run = blockIdx.x;
     if (run >= a.n_runs || !a.trans) return;
     const xp_run& R = a.runs[run];
@@ -94,14 +123,24 @@ __global__ __launch_bounds__(64) void k_tr_sum(TransportArgs a)
     if (lane < XP_MAX_BINS && lane >= nb) a.trans[(size_t)run * XP_MAX_BINS + lane] = 0.0;
     for (int b = 0; b < nb; ++b) {
         double s = 0.0;
-        for (int j0 = 0; j0 < ny; j0 += 64) {
-            const int j = j0 + lane;
-            const int c = c0 + j * nx;
-            v[lane] = (j < ny && c < a.n_cells) ? a.exit[(size_t)c * XP_MAX_BINS + b] : 0.0;
+        for (int j0 = 0; j0 < ny; j0 += TR_SPAN) {
+#pragma unroll
+            for (int q = 0; q < TR_CH; ++q) {
+                const int j = j0 + q * 64 + lane;
+                const int c = c0 + j * nx;
+                v[q * 64 + lane] = (j < ny && c < a.n_cells) ? a.exit[(size_t)c * XP_MAX_BINS + b] : 0.0;
+            }
             __syncthreads();
             if (lane == 0) {
-                const int cnt = ny - j0 < 64 ? ny - j0 : 64;
-                for (int q = 0; q < cnt; ++q) s = s + v[q];
+                // past the last row v = +0, which leaves the (non-negative) sum as it is
+                const int cnt = ny - j0 < TR_SPAN ? ny - j0 : TR_SPAN;
+                for (int q = 0; q < cnt; q += 8) {
+                    double vv[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) vv[j] = v[q + j];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) s = s + vv[j];
+                }
             }
             __syncthreads();
         }
