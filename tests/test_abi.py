@@ -91,3 +91,24 @@ def test_flag_values_agree():
              "XP_ION_Z": O.ION_Z, "XP_NANBU": O.NANBU}
     for name, oval in pairs.items():
         assert vals[name] == getattr(B, name) == oval, name
+
+
+def test_entry_points_reject_null_arguments_without_a_device():
+    # argument checks come before any device call: every entry point answers a
+    # null context or batch with XP_ERR_INVALID_ARG and a message
+    if not os.path.exists(B.LIB_PATH):
+        pytest.skip("libxpic.so not built")
+    L = B.load()
+    calls = {
+        "init_species": lambda: L.init_species(None, None, None, 0, None),
+        "bin_particles": lambda: L.bin_particles(None, None, None, None, None, None),
+        "collide_ionize_step": lambda: L.collide_ionize_step(None, None, None, None),
+        "photo_auger_step": lambda: L.photo_auger_step(None, None, None, None),
+        "transport_photons": lambda: L.transport_photons(None, None, None, None),
+        "diagnostics": lambda: L.diagnostics(None, None, None, 0, None),
+        "xp_selftest": lambda: L.xp_selftest(None, 0, 0, None, None, None, None, None),
+    }
+    for name, call in calls.items():
+        assert call() == -1, name
+        assert L.xp_last_error().decode(), name
+    assert L.xp_step_work_bytes(None) == 0
