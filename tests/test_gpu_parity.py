@@ -310,7 +310,8 @@ def test_nanbu_scattering(ctx):
     # electrons, small angles for the keV ones), edge cells, mixed charges with
     # the other variants on every LDS schedule, and a reduced C2
     spec, parts = W.config_c1()
-    bat, sim = run_pair(ctx, spec, parts, 8, flags=O.ALL | O.NANBU, check_every=4, label="C1/nanbu")
+    bat, sim = run_pair(ctx, spec, parts, 100, flags=O.ALL | O.NANBU, check_every=25,
+                        label="C1/nanbu")
     assert sim.counters()[0][:, O.COUNTERS.index("DELTA2_GT1")].sum() > 0
     spec, parts = _therm_edge_case(47)
     run_pair(ctx, spec, parts, 6, flags=O.ALL | O.NANBU, check_every=1, capacity=(3, 4),

@@ -115,3 +115,12 @@ def test_transport_several_runs(ctx):
             assert np.array_equal(tg[r, :nb], to), (r, s)
             assert np.all(tg[r, nb:] == 0.0)
         say("several runs step %d ok: %s" % (s, tg[:, :2].tolist()))
+
+
+def test_transport_long_run(ctx):
+    # 60 steps of a 1D slab of 64 cells under an intense beam: the field,
+    # the events and the transmission stay identical while the target opens up
+    spec, parts = _slab(79, nx=64, ny=1, ni_hi=40, ne_hi=40, bins=((1850.0,), (3e30,)))
+    # slabs for full ionization: Al3+ can give up 10 electrons
+    bat, sim = _run(ctx, spec, parts, 60, O.ALL, capacity=(10, 16), label="transport/long")
+    assert bat.status() == 0
