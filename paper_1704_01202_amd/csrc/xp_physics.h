@@ -93,11 +93,13 @@ __device__ __noinline__ double coulomb_log(double t, double n_e, double zbar)
     return lnl < 2.0 ? 2.0 : lnl;
 }
 
-__device__ __noinline__ double eos_zbar(const DevTables* tb, double n_i, double tev)
+// Zbar_EOS(n_i, T_e), bilinear in (ln n_i, ln T) on the table grid, from the
+// two logarithms.
+__device__ __noinline__ double eos_zbar_ln(const DevTables* tb, double ln_ni, double ln_t)
 {
     const double* zt = (const double*)((const char*)tb + tb->off_eos);
-    const double u = (xlog(n_i) - tb->eos_lnn0) / tb->eos_dlnn;
-    const double v = (xlog(tev) - tb->eos_lnt0) / tb->eos_dlnt;
+    const double u = (ln_ni - tb->eos_lnn0) / tb->eos_dlnn;
+    const double v = (ln_t - tb->eos_lnt0) / tb->eos_dlnt;
     const int nn = tb->eos_nn, nt = tb->eos_nt;
     const double fu = floor(u), fv = floor(v);
     double au = u - fu, av = v - fv;
@@ -109,6 +111,11 @@ __device__ __noinline__ double eos_zbar(const DevTables* tb, double n_i, double 
     const double a = (1.0 - av) * z00 + av * z01;
     const double b = (1.0 - av) * z10 + av * z11;
     return (1.0 - au) * a + au * b;
+}
+
+__device__ __forceinline__ double eos_zbar(const DevTables* tb, double n_i, double tev)
+{
+    return eos_zbar_ln(tb, xlog(n_i), xlog(tev));
 }
 
 // Per-electron subshell photoionization cross section, m^2 (Fig. 2a table).

@@ -37,6 +37,7 @@ struct CellSharedT {
     double sig[XP_MAX_BINS][3];
     double ssum[13][3];
     double pz[13];        // S3 probability per evaluated charge state
+    double lnp[5];        // S3 logarithms of the lowered bindings, one per subshell
     double dbl[8];
     int ints[8];
 };
@@ -665,9 +666,21 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
                 for (int q = 0; q < 5; ++q) {
                     const double raw = tb->bind[z][q] - dE[z];
                     pp[q] = raw < 1.0 ? 1.0 : raw;
-                    lnp[q] = oc.s[q] > 0 ? xlog(pp[q]) : 0.0;
                     if (tid == 0 && oc.s[q] > 0 && raw < 1.0) S.cnt[XP_C_IPD_CLAMPED] += 1;
                 }
+                // the logarithms of the occupied subshells' lowered bindings, one
+                // subshell per thread, shared through LDS
+                if (tid < 5) {
+                    double arg = pp[0];
+                    int occ = oc.s[0];
+#pragma unroll
+                    for (int q = 1; q < 5; ++q)
+                        if (tid == q) { arg = pp[q]; occ = oc.s[q]; }
+                    S.lnp[tid] = occ > 0 ? xlog(arg) : 0.0;
+                }
+                T::sync();
+#pragma unroll
+                for (int q = 0; q < 5; ++q) lnp[q] = S.lnp[q];
                 double pmin = __builtin_inf();
 #pragma unroll
                 for (int q = 0; q < 5; ++q)
@@ -777,7 +790,10 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
             if (tp < 0.01) tp = 0.01;
         }
         if (tid == 0) S.mom[15] = tp;
-        const double zeos = eos_zbar(tb, n_i, tp);
+        // Zbar_EOS: its two logarithms on two threads, shared through LDS
+        if (tid < 2) S.dbl[2 + tid] = xlog(tid == 0 ? n_i : tp);
+        T::sync();
+        const double zeos = eos_zbar_ln(tb, S.dbl[2], S.dbl[3]);
         const double dd = (double)szr - (double)ni * zeos;
         if (dd > 0.0) {
             long long nrec = (long long)floor(dd + 0.5);
