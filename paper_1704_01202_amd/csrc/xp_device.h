@@ -42,7 +42,7 @@ __device__ __forceinline__ double two_pow(int n) { return bits_to_f64((uint64_t)
 
 // Natural logarithm for x > 0 (finite): reduction to m in (sqrt(1/2), sqrt(2)],
 // log(1+f) = f - s (f - V), s = f / (2 + f), V = s^2 (2/3 + s^2 (2/5 + ...)).
-__device__ __noinline__ double xlog(double x)
+__device__ __forceinline__ double xlog(double x)
 {
     if (!(x > 0.0)) return x == 0.0 ? -__builtin_inf() : __builtin_nan("");
     if (x == __builtin_inf()) return x;
