@@ -124,3 +124,60 @@ def test_transport_long_run(ctx):
     # slabs for full ionization: Al3+ can give up 10 electrons
     bat, sim = _run(ctx, spec, parts, 60, O.ALL, capacity=(10, 16), label="transport/long")
     assert bat.status() == 0
+
+
+def test_transport_graph_replays(ctx):
+    # steps and transports captured in a HIP graph (per-run device step
+    # counter) against the same batch stepped eagerly and the oracle; eager
+    # work and synchronisation between the replays
+    spec, parts = _slab(80, nx=40, ny=3, bins=((1650.0, 1850.0), (6e29, 9e29)))
+    nb = len(spec.photon_hv)
+    f0 = np.tile(np.asarray(spec.photon_n, dtype=np.float64), (spec.nx * spec.ny, 1))
+    flags = O.ALL | O.NANBU
+    gb = RT.Batch(ctx, [(spec, parts)], capacity=(10, 16), cell_nhv=f0)
+    eb = RT.Batch(ctx, [(spec, parts)], capacity=(10, 16), cell_nhv=f0)
+    sim = O.Sim(ctx.tables, spec)
+    sim.bin(parts)
+    sim.set_cell_field(f0)
+    d_step = torch.zeros(1, dtype=torch.int32, device=ctx.device)
+    for s in range(2):
+        gb.step(0, flags, d_step=d_step)
+        gb.transport()
+        d_step.add_(1)
+        eb.step(s, flags)
+        eb.transport()
+        sim.step(s, flags)
+        sim.transport()
+    torch.cuda.synchronize()
+    hint = int(RT.plan_hint(gb.h_stats.numpy()))
+    k = 2
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(g, stream=side):
+        for _ in range(k):
+            gb.step(0, flags, d_step=d_step, e_hint=hint, record_stats=False)
+            gb.transport()
+            d_step.add_(1)
+    torch.cuda.current_stream().wait_stream(side)
+    step = 2
+    for rep in range(3):
+        g.replay()
+        for _ in range(k):
+            eb.step(step, flags)
+            te = eb.transport()
+            sim.step(step, flags)
+            to = sim.transport()
+            step += 1
+        torch.cuda.synchronize()
+        assert gb.status() == 0 and eb.status() == 0
+        _ = gb.diagnostics()
+        gs, es = gb.state(), eb.state()
+        for f in ("e_start", "ew", "iz", "ik", "evx", "evy", "evz", "ivx", "ex"):
+            assert np.array_equal(getattr(gs, f), getattr(es, f)), (rep, f)
+        assert np.array_equal(gb.cell_field(), eb.cell_field()), rep
+        assert np.array_equal(gb.d_trans.cpu().numpy(), te.cpu().numpy()), rep
+        compare(gs, sim.state(), "transport replay %d" % rep)
+        assert np.array_equal(gb.cell_field(), sim.cell_field()), rep
+        assert np.array_equal(gb.d_trans.cpu().numpy()[0, :nb], to), rep
+        say("transport replay %d ok at step %d" % (rep, step))
