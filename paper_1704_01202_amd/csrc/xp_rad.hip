@@ -26,13 +26,19 @@ constexpr int TR_SPAN = 64 * TR_CH;
 
 // One wave per row: the lanes fetch and compute the transmissions of 512 cells
 // at once, lane 0 carries the running product through them in order.
+// The grid is a multiple of 8 and workgroup b takes the cells of logical block
+// (b mod 8) (grid / 8) + b / 8, a bijection.  Workgroups are handed to the 8
+// XCDs in turn, and rows start at a fixed stride of cells (every 8th block
+// for rows of 512 cells), so the identity mapping would put every row on one
+// XCD and push the whole launch through that XCD's L2.
 __global__ __launch_bounds__(64) void k_tr_rows(TransportArgs a)
 {
     __shared__ double tau[TR_SPAN];
     __shared__ double ent[TR_SPAN];
     __shared__ double carry_s;
     const int lane = threadIdx.x;
-    for (int c0 = blockIdx.x * 64; c0 < a.n_cells; c0 += gridDim.x * 64) {
+    const int lb = (int)(blockIdx.x % 8) * (int)(gridDim.x / 8) + (int)(blockIdx.x / 8);
+    for (int c0 = lb * 64; c0 < a.n_cells; c0 += gridDim.x * 64) {
         const int c = c0 + lane;
         bool start = false;
         if (c < a.n_cells) {
@@ -157,7 +163,7 @@ hipError_t transport_launch(const TransportArgs& a, hipStream_t s)
 {
     if (a.n_cells <= 0) return hipSuccess;
     const int64_t blocks = ((int64_t)a.n_cells + 63) / 64;
-    const unsigned g = (unsigned)(blocks < 65536 ? blocks : 65536);
+    const unsigned g = (unsigned)((blocks < 65536 ? blocks : 65536) + 7) & ~7u;   // multiple of 8
     hipLaunchKernelGGL(k_tr_rows, dim3(g), dim3(64), 0, s, a);
     if (a.trans && a.n_runs > 0) hipLaunchKernelGGL(k_tr_sum, dim3(a.n_runs), dim3(64), 0, s, a);
     return hipGetLastError();
