@@ -248,3 +248,33 @@ def test_coulomb_log_limits(orc):
     # classical weakly coupled limit: ~ ln(lambda_D / b) >> 2
     assert hot > 8
     assert orc.coulomb_log(5000.0, 1e25, 1.0) > orc.coulomb_log(5000.0, 1e27, 1.0)
+
+
+def _nrl_lnl_ei(t_ev, n_e_m3, z, quantum):
+    """Electron-ion Coulomb logarithm of the NRL Plasma Formulary (n_e in
+    cm^-3, T in eV): 24 - ln(n_e^1/2 / T) above 10 Z^2 eV, where the quantum
+    closest approach sets b_min, else 23 - ln(n_e^1/2 Z T^-3/2)."""
+    n = n_e_m3 * 1e-6
+    if quantum:
+        return 24.0 - math.log(math.sqrt(n) / t_ev)
+    return 23.0 - math.log(math.sqrt(n) * z * t_ev ** -1.5)
+
+
+@pytest.mark.parametrize("quantum", [False, True])
+def test_coulomb_log_against_nrl_formulary(orc, quantum):
+    # Deep in each regime (classical T <= 2 Z^2 eV, quantum T >= 200 Z^2 eV)
+    # and where lnL >= 5 (so the clamp and 1/2 ln(1 + x^2) - ln x are below
+    # 1e-4), the oracle and the textbook differ only by the constant their
+    # b_min conventions give: equal T, n_e and Z dependence, offset below 1.5.
+    offs = []
+    for z in (1.0, 2.0, 3.0, 7.0, 12.0):
+        for f in (0.5, 1.0, 2.0) if not quantum else (200.0, 1000.0, 5000.0):
+            t = f * z * z
+            for ne in (1e22, 1e24, 1e26, 1e28, 1e30):
+                ours = orc.coulomb_log(t, ne, z)
+                if ours < 5.0:
+                    continue
+                offs.append(ours - _nrl_lnl_ei(t, ne, z, quantum))
+    assert len(offs) >= 20
+    assert max(offs) - min(offs) < 2e-4
+    assert abs(offs[0]) < 1.5
