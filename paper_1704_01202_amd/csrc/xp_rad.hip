@@ -20,36 +20,47 @@ namespace xpd {
 
 namespace {
 
-// Cells (or rows) one wave handles per round trip to memory: 8 per lane.
-constexpr int TR_CH = 8;
-constexpr int TR_SPAN = 64 * TR_CH;
+// Row kernel: a block of four waves fetches 512 cells per round trip, two per
+// thread.  Row-sum kernel: one wave fetches 512 rows, eight per lane.
+constexpr int TR_THREADS = 256;
+constexpr int TR_CH = 2;
+constexpr int TR_SPAN = TR_THREADS * TR_CH;
+constexpr int TS_CH = 8;
+constexpr int TS_SPAN = 64 * TS_CH;
 
-// One wave per row: the lanes fetch and compute the transmissions of 512 cells
-// at once, lane 0 carries the running product through them in order.
+// One block per row: the threads fetch and compute the transmissions of 512
+// cells at once, thread 0 carries the running product through them in order.
 // The grid is a multiple of 8 and workgroup b takes the cells of logical block
 // (b mod 8) (grid / 8) + b / 8, a bijection.  Workgroups are handed to the 8
 // XCDs in turn, and rows start at a fixed stride of cells (every 8th block
 // for rows of 512 cells), so the identity mapping would put every row on one
 // XCD and push the whole launch through that XCD's L2.
-__global__ __launch_bounds__(64) void k_tr_rows(TransportArgs a)
+__global__ __launch_bounds__(TR_THREADS) void k_tr_rows(TransportArgs a)
 {
     __shared__ double tau[TR_SPAN];
     __shared__ double ent[TR_SPAN];
     __shared__ double carry_s;
+    __shared__ unsigned long long starts[TR_THREADS / 64];
     const int lane = threadIdx.x;
     const int lb = (int)(blockIdx.x % 8) * (int)(gridDim.x / 8) + (int)(blockIdx.x / 8);
-    for (int c0 = lb * 64; c0 < a.n_cells; c0 += gridDim.x * 64) {
+    for (int c0 = lb * TR_THREADS; c0 < a.n_cells; c0 += gridDim.x * TR_THREADS) {
         const int c = c0 + lane;
         bool start = false;
         if (c < a.n_cells) {
             const xp_run& R = a.runs[a.cell_run[c]];
             start = R.field_per_cell && R.n_bins > 0 && R.nx > 0 && (c - R.cell_begin) % R.nx == 0;
         }
-        unsigned long long m = __ballot(start);
+        const unsigned long long wm = __ballot(start);
+        if ((lane & 63) == 0) starts[lane >> 6] = wm;
+        __syncthreads();
+        // the row starts of the block's cells, in cell order; every thread reads
+        // the same masks, so the loops below are uniform over the block
+        for (int w = 0; w < TR_THREADS / 64; ++w) {
+        unsigned long long m = starts[w];
         while (m) {
             const int l = __ffsll(m) - 1;
             m &= m - 1;
-            const int rc = c0 + l;
+            const int rc = c0 + w * 64 + l;
             const xp_run& R = a.runs[a.cell_run[rc]];
             const int nx = R.nx, nb = R.n_bins;
             if (rc + nx > a.n_cells) continue;   // inconsistent run table: leave the row
@@ -62,7 +73,7 @@ __global__ __launch_bounds__(64) void k_tr_rows(TransportArgs a)
                     int32_t k[TR_CH];
 #pragma unroll
                     for (int q = 0; q < TR_CH; ++q) {
-                        const int i = i0 + q * 64 + lane;
+                        const int i = i0 + q * TR_THREADS + lane;
                         n[q] = 0.0;
                         k[q] = 0;
                         if (i < nx) {
@@ -78,7 +89,7 @@ __global__ __launch_bounds__(64) void k_tr_rows(TransportArgs a)
                             const double ab = ((double)k[q] * w0) / (cross * n[q]);
                             t = ab < 1.0 ? 1.0 - ab : 0.0;
                         }
-                        tau[q * 64 + lane] = t;
+                        tau[q * TR_THREADS + lane] = t;
                     }
                     __syncthreads();
                     if (lane == 0) {
@@ -102,8 +113,8 @@ __global__ __launch_bounds__(64) void k_tr_rows(TransportArgs a)
                     __syncthreads();
 #pragma unroll
                     for (int q = 0; q < TR_CH; ++q) {
-                        const int i = i0 + q * 64 + lane;
-                        if (i < nx) a.nhv[(size_t)(rc + i) * XP_MAX_BINS + b] = ent[q * 64 + lane];
+                        const int i = i0 + q * TR_THREADS + lane;
+                        if (i < nx) a.nhv[(size_t)(rc + i) * XP_MAX_BINS + b] = ent[q * TR_THREADS + lane];
                     }
                     carry = carry_s;
                     __syncthreads();
@@ -111,6 +122,8 @@ __global__ __launch_bounds__(64) void k_tr_rows(TransportArgs a)
                 if (lane == 0) a.exit[(size_t)rc * XP_MAX_BINS + b] = carry;
             }
         }
+        }
+        __syncthreads();   // starts[] is rewritten by the next round
     }
 }
 
@@ -119,7 +132,7 @@ __global__ __launch_bounds__(64) void k_tr_rows(TransportArgs a)
 // order.
 __global__ __launch_bounds__(64) void k_tr_sum(TransportArgs a)
 {
-    __shared__ double v[TR_SPAN];
+    __shared__ double v[TS_SPAN];
     const int run = blockIdx.x;
     if (run >= a.n_runs || !a.trans) return;
     const xp_run& R = a.runs[run];
@@ -129,9 +142,9 @@ __global__ __launch_bounds__(64) void k_tr_sum(TransportArgs a)
     if (lane < XP_MAX_BINS && lane >= nb) a.trans[(size_t)run * XP_MAX_BINS + lane] = 0.0;
     for (int b = 0; b < nb; ++b) {
         double s = 0.0;
-        for (int j0 = 0; j0 < ny; j0 += TR_SPAN) {
+        for (int j0 = 0; j0 < ny; j0 += TS_SPAN) {
 #pragma unroll
-            for (int q = 0; q < TR_CH; ++q) {
+            for (int q = 0; q < TS_CH; ++q) {
                 const int j = j0 + q * 64 + lane;
                 const int c = c0 + j * nx;
                 v[q * 64 + lane] = (j < ny && c < a.n_cells) ? a.exit[(size_t)c * XP_MAX_BINS + b] : 0.0;
@@ -139,7 +152,7 @@ __global__ __launch_bounds__(64) void k_tr_sum(TransportArgs a)
             __syncthreads();
             if (lane == 0) {
                 // past the last row v = +0, which leaves the (non-negative) sum as it is
-                const int cnt = ny - j0 < TR_SPAN ? ny - j0 : TR_SPAN;
+                const int cnt = ny - j0 < TS_SPAN ? ny - j0 : TS_SPAN;
                 for (int q = 0; q < cnt; q += 8) {
                     double vv[8];
 #pragma unroll
@@ -162,9 +175,9 @@ __global__ __launch_bounds__(64) void k_tr_sum(TransportArgs a)
 hipError_t transport_launch(const TransportArgs& a, hipStream_t s)
 {
     if (a.n_cells <= 0) return hipSuccess;
-    const int64_t blocks = ((int64_t)a.n_cells + 63) / 64;
+    const int64_t blocks = ((int64_t)a.n_cells + TR_THREADS - 1) / TR_THREADS;
     const unsigned g = (unsigned)((blocks < 65536 ? blocks : 65536) + 7) & ~7u;   // multiple of 8
-    hipLaunchKernelGGL(k_tr_rows, dim3(g), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_tr_rows, dim3(g), dim3(TR_THREADS), 0, s, a);
     if (a.trans && a.n_runs > 0) hipLaunchKernelGGL(k_tr_sum, dim3(a.n_runs), dim3(64), 0, s, a);
     return hipGetLastError();
 }
