@@ -278,3 +278,68 @@ def test_coulomb_log_against_nrl_formulary(orc, quantum):
     assert len(offs) >= 20
     assert max(offs) - min(offs) < 2e-4
     assert abs(offs[0]) < 1.5
+
+
+# Lotz constants with the full form of Eq. 4 (b, c != 0); any table the ABI
+# accepts may carry them, so the factor (1 - b exp(-c (E/P - 1))) is pinned
+# against its own Maxwellian closed form.
+LOTZ_B = np.array([0.7, 0.45, 0.6, 0.35, 0.25])
+LOTZ_C = np.array([0.3, 1.1, 0.85, 0.5, 2.0])
+
+
+def _lotz_bc_rate(tables, zc, dE, tev):
+    """sum_s a N_s vbar / (P_s T) [E1(x) - b e^c x / (x + c) E1(x + c)], x = P_s / T.
+
+    Derivation: <sigma v> = sqrt(8 / (pi m)) T^(-3/2) int sigma(E) E exp(-E/T) dE;
+    the log term integrates to T E1(x) / P and the damped term, whose exponent
+    is E (1/T + c/P), to T x/(x + c) e^c E1(x + c) / P.
+    """
+    occ = np.array([2, 2, 6, 2, 6])
+    vbar = math.sqrt(8 * tev * QE / (math.pi * ME))
+    ref = 0.0
+    from oracle import oracle as O
+    occ = O.occupancy(zc)
+    for s in range(5):
+        if occ[s] == 0:
+            continue
+        p = max(tables.bind[zc, s] - dE[zc], 1.0)
+        x, b, c = p / tev, LOTZ_B[s], LOTZ_C[s]
+        bracket = special.exp1(x) - b * math.exp(c) * x / (x + c) * special.exp1(x + c)
+        ref += tables.lotz_a[s] * 1e-4 * occ[s] * vbar / (p * tev) * bracket
+    return ref
+
+
+def test_lotz_full_form_maxwell_rate_closed_form(orc, tables):
+    import dataclasses
+    tb = dataclasses.replace(tables, lotz_b=LOTZ_B.copy(), lotz_c=LOTZ_C.copy())
+    T = orc.Tables(tb)
+    T0 = orc.Tables(tables)
+    dE = np.zeros(13)
+    dE[3] = 57.7
+    dE[7] = 120.0
+    for tev in (10.0, 50.0, 200.0, 1000.0):
+        for zc in (3, 7, 11):
+            occ = orc.occupancy(zc)
+
+            def integrand(e):
+                f = 2 * math.sqrt(e / math.pi) * tev ** -1.5 * math.exp(-e / tev)
+                return T.lotz(zc, dE, e) * math.sqrt(2 * e * QE / ME) * f
+
+            edges = sorted({max(tb.bind[zc, s] - dE[zc], 1.0) for s in range(5) if occ[s] > 0})
+            pts = [0.0] + edges + [edges[-1] + 60 * tev]
+            num = sum(integrate.quad(integrand, a, b, limit=200, epsrel=1e-11)[0]
+                      for a, b in zip(pts[:-1], pts[1:]))
+            ref = _lotz_bc_rate(tb, zc, dE, tev)
+            assert num == pytest.approx(ref, rel=1e-7), (tev, zc)
+    # the factor itself at chosen energies: 1 - b exp(-c (E/P - 1)) of the one
+    # open subshell just above its threshold, where the damping is largest
+    p2s = max(tb.bind[10, 1] - dE[10], 1.0)   # Al10+: 1s2 2s, 2s is the valence
+    p1s = max(tb.bind[10, 0] - dE[10], 1.0)
+    checked = 0
+    for ratio in (1.01, 1.5, 3.0, 6.0):
+        e = ratio * p2s
+        assert e < p1s
+        want = 1.0 - LOTZ_B[1] * math.exp(-LOTZ_C[1] * (ratio - 1.0))
+        assert T.lotz(10, dE, e) / T0.lotz(10, dE, e) == pytest.approx(want, rel=1e-12)
+        checked += 1
+    assert checked == 4
