@@ -17,7 +17,9 @@
  * completed is left exactly as it was before the step; a cell stepped on the
  * global-memory path (see xp_step_params.schedule) keeps the collisions of that
  * step and skips its later stages.  Either way the batch needs re-binning with
- * more capacity before its results mean anything.
+ * more capacity before its results mean anything.  When the batch carries
+ * d_run_status, each such bit is also OR-ed into the word of the run the cell
+ * belongs to, so that runs sharing a batch can be judged one by one.
  *
  * Units: SI for positions, velocities, volumes and densities; energies and
  * temperatures in eV; table cross sections in cm^2.
@@ -32,8 +34,9 @@
 extern "C" {
 #endif
 
-/* Layout version of the structs below; 2 added xp_batch.d_cell_nabs. */
-#define XP_ABI_VERSION 2u
+/* Layout version of the structs below; 2 added xp_batch.d_cell_nabs, 3 added
+ * xp_batch.d_run_status. */
+#define XP_ABI_VERSION 3u
 
 typedef int32_t xp_status;
 #define XP_OK                   0
@@ -85,6 +88,8 @@ typedef int32_t xp_status;
 #define XP_ST_CAPACITY  0x1u   /* a cell needed more electron slots than its capacity */
 #define XP_ST_NONFINITE 0x2u   /* a non-finite velocity was produced */
 #define XP_ST_BIN_SIZE  0x4u   /* bin_particles: output capacity too small, nothing written */
+#define XP_ST_RUN_TABLE 0x8u   /* transport_photons: a run's grid does not match its cell range;
+                                  its rows were left as they were */
 
 /* Per-cell event counters (indices into counter records). */
 enum {
@@ -239,6 +244,10 @@ typedef struct {
     int32_t *d_cell_nabs;           /* optional [n_cells][XP_MAX_BINS]: photon events per bin of
                                        the last step (photoionizations, one macro-photon of w0
                                        real photons each, Sec. III); needed by transport_photons */
+    uint32_t *d_run_status;         /* optional [n_runs]: the XP_ST_* bits of each run, OR-ed
+                                       beside d_status by the step, the global-memory path and
+                                       transport_photons (bin_particles sets d_status only);
+                                       the caller clears a run's word */
 } xp_batch;
 
 /* Unsorted input particles of a batch for bin_particles.  Particle p belongs

@@ -293,6 +293,7 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
     a.cell_mom = b->d_cell_moments;
     a.cell_nabs = b->d_cell_nabs;
     a.status = b->d_status;
+    a.run_status = b->d_run_status;
     a.tab = ctx->d_tables;
     a.d_step = p->d_step;
     a.step = p->step;
@@ -525,6 +526,8 @@ xp_status transport_photons(xp_ctx* ctx, xp_batch* b, double* d_trans, void* str
     a.nabs = b->d_cell_nabs;
     a.exit = (double*)b->d_work;
     a.trans = d_trans;
+    a.status = b->d_status;
+    a.run_status = b->d_run_status;
     a.n_runs = b->n_runs;
     a.n_cells = b->n_cells;
     hipError_t e = hipSetDevice(ctx->device);

@@ -76,6 +76,7 @@ __global__ void k_big_init(BigArgs a)
         a.hdr->count = nb;
         a.hdr->n_e_chunks = 0;
         a.hdr->n_i_chunks = 0;
+        // cells beyond the list's capacity were flagged with their runs when listed
         if (requested > a.big_max) atomicOr(a.s.status, XP_ST_CAPACITY);
         if (a.s.stats) a.s.stats[2] = nb;
     }
@@ -111,7 +112,7 @@ __global__ void k_big_init(BigArgs a)
         const int64_t lim = (int64_t)BIG_MAX_CHUNKS * BIG_CH;
         if ((int64_t)r.ecap > lim || (int64_t)r.ni > lim) {
             r.state = 1;
-            atomicOr(a.s.status, XP_ST_CAPACITY);
+            flag_status(a.s, r.run, XP_ST_CAPACITY);
         }
     }
 }
@@ -161,11 +162,9 @@ __global__ __launch_bounds__(1024) void k_big_plan(BigArgs a, int species)
             BigRec& r = a.rec[b];
             r.state = 1;
             if (species == 0) { r.nce = 0; r.epn = 0; } else { r.nci = 0; }
+            flag_status(a.s, r.run, XP_ST_CAPACITY);
         }
-        if (tid == 0) {
-            bad = 1;
-            atomicOr(a.s.status, XP_ST_CAPACITY);
-        }
+        if (tid == 0) bad = 1;
     }
     __syncthreads();
     if (tid == 0) {
@@ -216,7 +215,7 @@ __global__ __launch_bounds__(BT) void k_big_s0(BigArgs a)
                 e4[4 * j + 3] = (double)w;
             }
         }
-        if (bad) atomicOr(s.status, XP_ST_NONFINITE);
+        if (bad) flag_status(s, r.run, XP_ST_NONFINITE);
         const long long we = block_isum<BT>(wl, ired);
         const long long wb = block_isum<BT>(bl, ired);
         const double ke = block_tree_sum<BT>(BIG_CH, [&](int j) {
@@ -910,7 +909,7 @@ __global__ __launch_bounds__(BT) void k_big_cscan(BigArgs a, int mode)
             } else if (mode == 2) {
                 if ((long long)r.ne + carry > (long long)r.ecap) {
                     r.state = 1;
-                    atomicOr(a.s.status, XP_ST_CAPACITY);
+                    flag_status(a.s, r.run, XP_ST_CAPACITY);
                 } else {
                     r.nnew5 = carry;
                     r.cnt[XP_C_E_NEW] += carry;
@@ -1080,7 +1079,7 @@ __global__ __launch_bounds__(64) void k_big_accept(BigArgs a)
             r.mom[13] = kth;
             if (over) {
                 r.state = 1;
-                atomicOr(s.status, XP_ST_CAPACITY);
+                flag_status(s, r.run, XP_ST_CAPACITY);
             } else {
                 r.acc = acc;
                 r.debit = debit;

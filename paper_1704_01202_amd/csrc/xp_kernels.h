@@ -31,6 +31,7 @@ struct StepArgs {
     double* cell_mom;
     int32_t* cell_nabs;         // optional [n_cells][XP_MAX_BINS] photon events per bin
     uint32_t* status;
+    uint32_t* run_status;       // optional [n_runs]
     const DevTables* tab;
     const double* run_sig;      // [n_runs][XP_MAX_BINS][3] photo cross sections (k_run_prep)
     const uint32_t* d_step;
@@ -52,6 +53,13 @@ struct StepArgs {
 // counts the cells handed to the global-memory path.
 constexpr int STEP_COUNTS = 16;
 constexpr int BIG_COUNT_SLOT = STEP_COUNTS - 1;
+
+// Sets status bits for the batch and, when the batch keeps them, for the run.
+__device__ __forceinline__ void flag_status(const StepArgs& a, int run, uint32_t bits)
+{
+    atomicOr(a.status, bits);
+    if (a.run_status && run >= 0) atomicOr(&a.run_status[run], bits);
+}
 
 __global__ void k_step_prep(int32_t* counts, int32_t* stats);
 __global__ void k_run_prep(const xp_run* runs, int n_runs, const DevTables* tb, double* run_sig);
@@ -124,6 +132,8 @@ struct TransportArgs {
     const int32_t* nabs;    // [n_cells][XP_MAX_BINS], photon events of the last step
     double* exit;           // workspace [n_cells][XP_MAX_BINS]: exit density at each row start
     double* trans;          // optional [n_runs][XP_MAX_BINS]
+    uint32_t* status;
+    uint32_t* run_status;   // optional [n_runs]
     int32_t n_runs, n_cells;
 };
 hipError_t transport_launch(const TransportArgs& a, hipStream_t s);

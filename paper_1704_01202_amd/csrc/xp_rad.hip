@@ -61,9 +61,19 @@ __global__ __launch_bounds__(TR_THREADS) void k_tr_rows(TransportArgs a)
             const int l = __ffsll(m) - 1;
             m &= m - 1;
             const int rc = c0 + w * 64 + l;
-            const xp_run& R = a.runs[a.cell_run[rc]];
+            const int run = a.cell_run[rc];
+            const xp_run& R = a.runs[run];
             const int nx = R.nx, nb = R.n_bins;
-            if (rc + nx > a.n_cells) continue;   // inconsistent run table: leave the row
+            // the row must lie inside its run's cells, and the run's grid must
+            // be its cell count; otherwise the row is left as it is and flagged
+            const long long run_end = (long long)R.cell_begin + R.ncells;
+            if ((long long)R.nx * R.ny != R.ncells || run_end > a.n_cells || (long long)rc + nx > run_end) {
+                if (lane == 0) {
+                    atomicOr(a.status, XP_ST_RUN_TABLE);
+                    if (a.run_status) atomicOr(&a.run_status[run], XP_ST_RUN_TABLE);
+                }
+                continue;
+            }
             const double cross = (R.volume * (CLIGHT * R.dt_rad)) / R.dx;
             const double w0 = R.w0;
             for (int b = 0; b < nb; ++b) {
@@ -137,7 +147,10 @@ __global__ __launch_bounds__(64) void k_tr_sum(TransportArgs a)
     if (run >= a.n_runs || !a.trans) return;
     const xp_run& R = a.runs[run];
     const int lane = threadIdx.x;
-    const int nb = R.field_per_cell && R.nx > 0 && R.ny > 0 ? R.n_bins : 0;
+    // a run whose grid does not match its cell range (flagged by the row
+    // kernel) reports no transmission
+    const bool fits = (long long)R.nx * R.ny == R.ncells && (long long)R.cell_begin + R.ncells <= a.n_cells;
+    const int nb = fits && R.field_per_cell && R.nx > 0 && R.ny > 0 ? R.n_bins : 0;
     const int ny = R.ny, nx = R.nx, c0 = R.cell_begin;
     if (lane < XP_MAX_BINS && lane >= nb) a.trans[(size_t)run * XP_MAX_BINS + lane] = 0.0;
     for (int b = 0; b < nb; ++b) {

@@ -425,9 +425,9 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
             if (a.big_out) {
                 const int k = atomicAdd(a.big_out_count, 1);
                 if (k < a.big_out_cap) a.big_out[k] = cell;
-                else atomicOr(a.status, XP_ST_CAPACITY);
+                else flag_status(a, run, XP_ST_CAPACITY);
             } else {
-                atomicOr(a.status, XP_ST_CAPACITY);
+                flag_status(a, run, XP_ST_CAPACITY);
             }
         }
     };
@@ -448,7 +448,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
     }
     if (ne > ce || ne > ecap) {
         if (ne > ecap) {
-            if (tid == 0) atomicOr(a.status, XP_ST_CAPACITY);
+            if (tid == 0) flag_status(a, run, XP_ST_CAPACITY);
         } else {
             defer();
         }
@@ -1138,7 +1138,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
 
     // ---------------- commit ----------------
     if (overflow) {
-        if (tid == 0) atomicOr(a.status, XP_ST_CAPACITY);
+        if (tid == 0) flag_status(a, run, XP_ST_CAPACITY);
         return false;
     }
     if (deferred) {
@@ -1161,7 +1161,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
         a.iz[io + j] = L.iz[j];
         a.ik[io + j] = L.ik[j];
     }
-    if (bad) atomicOr(a.status, XP_ST_NONFINITE);
+    if (bad) flag_status(a, run, XP_ST_NONFINITE);
     T::sync();
     // positions of moved or new electrons: gather into LDS first, then write
     for (int j = tid; j < ne; j += B) {

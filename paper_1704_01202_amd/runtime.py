@@ -153,6 +153,7 @@ class Batch:
         self.d_e_cnt = torch.zeros(nc, dtype=torch.int32, device=dev)
         self.d_i_cnt = torch.zeros(nc, dtype=torch.int32, device=dev)
         self.d_status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.d_run_status = torch.zeros(self.n_runs, dtype=torch.int32, device=dev)
         self.d_need = torch.zeros(8, dtype=torch.int64, device=dev)
         self.d_stats = torch.zeros(B.XP_NSTATS, dtype=torch.int32, device=dev)
         self.h_stats = torch.zeros(B.XP_NSTATS, dtype=torch.int32, pin_memory=True)
@@ -254,6 +255,7 @@ class Batch:
         b.big_cells_max = self.big_cells_max
         b.big_e_slots, b.big_i_slots = self.big_e_slots, self.big_i_slots
         b.d_cell_nabs = _ptr(self.d_cell_nabs)
+        b.d_run_status = _ptr(self.d_run_status)
         return b
 
     def _bin(self):
@@ -345,6 +347,10 @@ class Batch:
 
     def status(self):
         return int(self.d_status.item())
+
+    def run_status(self):
+        """XP_ST_* bits of each run since the batch was built."""
+        return self.d_run_status.cpu().numpy().view(np.uint32).copy()
 
     def stats(self):
         """Of the last step: [0] largest electron count of an LDS cell, [1] LDS

@@ -137,6 +137,8 @@ class Pool:
         self.run_cnt = torch.zeros((self.max_runs, B.XP_NCOUNT), dtype=torch.int64, device=dev)
         self.run_led = torch.zeros((self.max_runs, B.XP_NLEDGER), dtype=torch.float64, device=dev)
         self.d_status = torch.zeros(1, dtype=torch.int32, device=dev)
+        # XP_ST_* bits per resident run (cleared on admission, read on retirement)
+        self.d_run_status = torch.zeros(self.max_runs, dtype=torch.int32, device=dev)
         self.d_stats = torch.zeros(B.XP_NSTATS, dtype=torch.int32, device=dev)
         self.h_stats = torch.zeros(B.XP_NSTATS, dtype=torch.int32, pin_memory=True)
         self.ealloc, self.ialloc = RangeAlloc(self.E), RangeAlloc(self.I)
@@ -173,6 +175,9 @@ class Pool:
         b.d_iz, b.d_ik = p(self.iz) + i_lo, p(self.ik) + i_lo
         b.d_run_counters, b.d_run_ledger = p(self.run_cnt), p(self.run_led)
         b.d_status = status_ptr if status_ptr is not None else p(self.d_status)
+        # admission views carry a run table of their own: no per-run words there
+        b.d_run_status = p(self.d_run_status) if runs_ptr is None and hasattr(self, "d_run_status") \
+            else None
         if work is None:
             b.d_work, b.work_bytes = p(self.d_work) if hasattr(self, "d_work") else None, \
                 getattr(self, "work_bytes", 0)
@@ -254,6 +259,7 @@ class Pool:
         k = len(self.active)
         self.cell_run[cell_lo:cell_lo + nc] = k
         self.d_step[k] = 0
+        self.d_run_status[k] = 0
         self.run_cnt[k].zero_()
         self.run_led[k].zero_()
         n = need.cpu().numpy()
@@ -320,6 +326,11 @@ class Pool:
         k = self.active.index(r)
         return self.run_cnt[k].cpu().numpy().view(np.uint64)
 
+    def run_status(self, r: Resident):
+        """XP_ST_* bits raised by the run's own cells since its admission."""
+        k = self.active.index(r)
+        return int(self.d_run_status[k].item()) & 0xFFFFFFFF
+
     def retire(self, done):
         """Drop finished runs: free their slabs, compact the cell and run tables."""
         if not done:
@@ -344,6 +355,7 @@ class Pool:
                 lo += r.ncells
             idx = torch.tensor(old_idx, dtype=torch.int64, device=self.device)
             self.d_step[:len(keep)] = self.d_step[idx].clone()
+            self.d_run_status[:len(keep)] = self.d_run_status[idx].clone()
             self.run_cnt[:len(keep)] = self.run_cnt[idx].clone()
             self.run_led[:len(keep)] = self.run_led[idx].clone()
         self.active = keep
@@ -388,7 +400,7 @@ def serve(pool: Pool, trace, k=8, on_done=None, clock=time.perf_counter):
                 r.t_done = t
                 rec = {"rid": r.req.rid, "arrival": r.req.arrival, "admit": r.t_admit,
                        "done": t, "ttr": t - r.req.arrival, "steps": r.req.nsteps,
-                       "counters": pool.counters(r).copy()}
+                       "counters": pool.counters(r).copy(), "status": pool.run_status(r)}
                 if on_done is not None:
                     on_done(pool, r, rec)
                 out[r.req.rid] = rec

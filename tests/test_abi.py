@@ -35,7 +35,7 @@ def test_library_exports_every_declared_function():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(B.EXPORTS)
-    assert lib.xp_abi_version() == B.ABI_VERSION == 2
+    assert lib.xp_abi_version() == B.ABI_VERSION == 3
     text = open(HEADER).read()
     assert re.search(r"#define XP_ABI_VERSION %du" % B.ABI_VERSION, text)
 

@@ -42,8 +42,14 @@ def ctx():
     return RT.Context(tab)
 
 
-def compare(gs, os_, label, vtol=1e-12):
-    """gs: GPU CompactState, os_: oracle State."""
+def compare(gs, os_, label, vtol=1e-12, strict=True):
+    """gs: GPU CompactState, os_: oracle State.
+
+    Integers must be identical.  Velocities must agree element by element to
+    vtol relative, with an absolute floor of vtol times 1e-3 of the array's rms
+    speed for components near 0; with strict (the default) every word must be
+    identical, since both sides evaluate the same IEEE operation sequence.
+    """
     assert np.array_equal(gs.e_start, os_.e_start), label + " electron counts"
     assert np.array_equal(gs.i_start, os_.i_start), label + " ion counts"
     assert np.array_equal(gs.ew, os_.ew), label + " weights"
@@ -56,11 +62,13 @@ def compare(gs, os_, label, vtol=1e-12):
                  (gs.ivx, os_.ivx), (gs.ivy, os_.ivy), (gs.ivz, os_.ivz)):
         if a.size == 0:
             continue
-        scale = max(float(np.abs(b).max()), 1e-300)
-        d = np.abs(a - b)
-        worst = max(worst, float(d.max()) / scale)
-        nbits += int((a != b).sum())
+        floor = 1e-3 * max(float(np.sqrt(np.mean(b * b))), 1e-300)
+        rel = np.abs(a - b) / np.maximum(np.abs(b), floor)
+        worst = max(worst, float(rel.max()))
+        nbits += int((a.view(np.uint64) != b.view(np.uint64)).sum())
     assert worst <= vtol, "%s velocities differ: max rel %.3e" % (label, worst)
+    if strict:
+        assert nbits == 0, "%s: %d velocity words differ (max rel %.3e)" % (label, nbits, worst)
     return worst, nbits
 
 
@@ -384,17 +392,39 @@ def test_diagnostics_match_oracle(ctx):
 
 
 def test_capacity_overflow_leaves_cell_unchanged(ctx):
-    # a cell whose ionization needs more slots than its slab fails visibly
+    # a cell whose ionization needs more slots than its slab fails visibly: the
+    # oracle accepts more ionizations than the two spare slots of a 32-slot
+    # slab holding 30 electrons, so the step must flag XP_ST_CAPACITY and
+    # leave every particle of the batch as it was
     spec, parts = cases.one_run(2, 30, 30, 3000.0, 1.0, seed=79, e_weight=3)
+    sim = O.Sim(ctx.tables, spec)
+    sim.bin(parts)
+    sim.step(0, O.ION)
+    acc = sim.counters()[0][:, O.COUNTERS.index("ION_ACCEPTED")]
+    assert (30 + acc > 32).all(), acc
     bat = RT.Batch(ctx, [(spec, parts)], capacity=(0, 0))
     before = bat.state()
     bat.step(0, O.ION)
     torch.cuda.synchronize()
     after = bat.state()
-    st = bat.status()
-    if st & B.XP_ST_CAPACITY:
-        assert np.array_equal(before.evx, after.evx)
-        assert np.array_equal(before.iz, after.iz)
-    else:
-        # nothing fired: the step was legal
-        assert np.array_equal(before.iz, after.iz)
+    assert bat.status() & B.XP_ST_CAPACITY
+    for f in ("e_start", "evx", "evy", "evz", "ew", "iz", "ik", "ivx", "ex"):
+        assert np.array_equal(getattr(before, f), getattr(after, f)), f
+
+
+def test_lotz_full_form_parity(ctx):
+    # the Lotz factor (1 - b exp(-c (E/P - 1))) of Eq. 4 with b, c != 0 on
+    # the LDS step (C1, where the keV source electrons ionize every step) and
+    # on the global-memory path
+    import dataclasses
+    tb = dataclasses.replace(ctx.tables,
+                             lotz_b=np.array([0.7, 0.45, 0.6, 0.35, 0.25]),
+                             lotz_c=np.array([0.3, 1.1, 0.85, 0.5, 2.0]))
+    c2 = RT.Context(tb)
+    spec, parts = W.config_c1()
+    bat, sim = run_pair(c2, spec, parts, 20, check_every=5, capacity=(3, 16), label="C1/lotz-bc")
+    assert bat.run_counters()[0][O.COUNTERS.index("ION_ACCEPTED")] > 0
+    run_pair(c2, spec, parts, 6, check_every=3, capacity=(3, 16), label="C1/lotz-bc/global",
+             schedule=3, big="all")
+    spec, parts = W.config_c2(nx=6, ny=6)
+    run_pair(c2, spec, parts, 8, check_every=4, label="C2r/lotz-bc")

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
+from paper_1704_01202_amd import binding as B
 from paper_1704_01202_amd import runtime as RT
 from tests import cases
 from tests.test_gpu_parity import compare, ctx, say  # noqa: F401
@@ -181,3 +182,42 @@ def test_transport_graph_replays(ctx):
         assert np.array_equal(gb.cell_field(), sim.cell_field()), rep
         assert np.array_equal(gb.d_trans.cpu().numpy()[0, :nb], to), rep
         say("transport replay %d ok at step %d" % (rep, step))
+
+
+def test_transport_long_rows_and_many_rows(ctx):
+    # rows longer than one 512-cell fetch: 1301 cells are three fetches, the
+    # last one ragged and not a multiple of 8, so the carried product crosses
+    # two fetch boundaries and the padded tail (tau = 1) is walked
+    spec, parts = _slab(91, nx=1301, ny=2, ni_hi=8, ne_hi=8, bins=((1850.0,), (3e30,)))
+    _run(ctx, spec, parts, 3, O.ALL, capacity=(10, 16), label="transport/1301x2")
+    # more rows than one fetch of the row sum (1100 rows of two cells)
+    spec, parts = _slab(92, nx=2, ny=1100, ni_hi=8, ne_hi=8, bins=((1650.0, 1850.0), (6e29, 3e30)))
+    _run(ctx, spec, parts, 3, O.ALL, capacity=(10, 16), label="transport/2x1100")
+
+
+def test_transport_rejects_inconsistent_run_grid(ctx):
+    # a run table whose grid does not cover its cell range: every row of that
+    # run is left as it was and XP_ST_RUN_TABLE is raised for the batch and the
+    # run; the consistent run beside it is transported as usual
+    a = _slab(93, nx=10, ny=3, ni_hi=20, ne_hi=20, bins=((1850.0,), (3e30,)))
+    b = _slab(94, nx=8, ny=2, ni_hi=20, ne_hi=20, bins=((1850.0,), (3e30,)))
+    f = np.full((a[0].nx * a[0].ny + b[0].nx * b[0].ny, 1), 3e30)
+    bat = RT.Batch(ctx, [a, b], capacity=(7, 16), cell_records=True, cell_nhv=f)
+    bat.step(0, O.ALL)
+    torch.cuda.synchronize()
+    # corrupt run 0's nx on the device (its cell count stays 30)
+    off = B.XpRun.nx.offset
+    raw = bat.d_runs.cpu().numpy().copy()
+    raw[off:off + 4] = np.frombuffer(np.int32(7).tobytes(), dtype=np.uint8)
+    bat.d_runs.copy_(torch.from_numpy(raw).to(ctx.device))
+    before = bat.d_cell_nhv.cpu().numpy().copy()
+    bat.transport()
+    torch.cuda.synchronize()
+    after = bat.d_cell_nhv.cpu().numpy()
+    n0 = a[0].nx * a[0].ny
+    assert np.array_equal(after[:n0], before[:n0])
+    assert not np.array_equal(after[n0:], before[n0:])
+    assert bat.status() & B.XP_ST_RUN_TABLE
+    rs = bat.run_status()
+    assert rs[0] & B.XP_ST_RUN_TABLE and not rs[1] & B.XP_ST_RUN_TABLE
+    assert bat.d_trans.cpu().numpy()[0, 0] == 0.0 and bat.d_trans.cpu().numpy()[1, 0] > 0.0
