@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
+from paper_1704_01202_amd import binding as B
 from paper_1704_01202_amd import runtime as RT
 from paper_1704_01202_amd import workloads as W
 from tests import cases
@@ -113,8 +114,11 @@ def test_big_path_capacity_flag(ctx):
     torch.cuda.synchronize()
     st = bat.status()
     after = bat.state()
-    # either nothing fired, or the overflow was flagged and the count kept
-    assert st in (0, 1)
+    # the oracle accepts more ionizations than the slabs' two spare slots
+    # (test_capacity_overflow_leaves_cell_unchanged): the overflow is flagged
+    # and the electron count kept
+    assert st == B.XP_ST_CAPACITY
+    assert bat.run_status()[0] == B.XP_ST_CAPACITY
     assert after.e_start[-1] == parts.ne
 
 
