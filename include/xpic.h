@@ -336,6 +336,25 @@ xp_status bin_particles(xp_ctx *ctx, const xp_particles *in, xp_batch *b,
 xp_status collide_ionize_step(xp_ctx *ctx, xp_batch *b, const xp_step_params *p,
                               void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the step of
+ * collide_ionize_step with its workspace taken from a static device array of
+ * XP_STATIC_SCRATCH_BYTES per GPU instead of b->d_work (b->d_work and
+ * b->work_bytes are ignored; the batch is not modified).  The array is held
+ * by the loaded library until the process ends; its address on a device is
+ * taken when a context is created there.  Nothing is allocated and nothing is
+ * freed; the caller still owns every other buffer of the batch.  All calls on
+ * one GPU share its array and leave their contents in it, so calls that may
+ * overlap on one GPU (other streams, other threads, other contexts) race and
+ * must be ordered by the caller.  Errors: XP_ERR_UNSUPPORTED when
+ * xp_step_work_bytes(b) exceeds XP_STATIC_SCRATCH_BYTES (64 MiB covers a
+ * batch of up to about 520,000 cells on the LDS path, or a global-memory path
+ * of about 400,000 electron and 400,000 ion slots), plus those of
+ * collide_ionize_step. */
+#define XP_STATIC_SCRATCH_BYTES (64u << 20)
+xp_status collide_ionize_step_static(xp_ctx *ctx, const xp_batch *b, const xp_step_params *p,
+                                     void *stream);
+
 /* Source terms alone (Sec. III): moments and continuum lowering of the current
  * state, then K-vacancy decay with KLL Auger / K-alpha branching and subshell
  * photoionization (Eq. 3) with the run's prescribed photon field, over

@@ -98,11 +98,14 @@ class XpDiag(C.Structure):
                 ("ledger", _d * XP_NLEDGER)]
 
 
+XP_STATIC_SCRATCH_BYTES = 64 << 20   # static workspace of collide_ionize_step_static
+
 ABI_VERSION = 3   # struct layouts mirrored below (XP_ABI_VERSION of include/xpic.h)
 
 EXPORTS = ["xp_abi_version", "xp_last_error", "xp_ctx_create", "xp_ctx_destroy",
            "xp_table_bytes", "init_species", "xp_work_bytes", "xp_step_work_bytes",
-           "xp_lds_limits", "bin_particles", "collide_ionize_step", "photo_auger_step",
+           "xp_lds_limits", "bin_particles", "collide_ionize_step", "collide_ionize_step_static",
+           "photo_auger_step",
            "diagnostics", "transport_photons", "xp_selftest"]
 
 _lib = None
@@ -147,6 +150,8 @@ def load(path=LIB_PATH):
                                 C.POINTER(XpCapacity), _vp, _vp]
     L.collide_ionize_step.restype = _i32
     L.collide_ionize_step.argtypes = [_vp, C.POINTER(XpBatch), C.POINTER(XpStepParams), _vp]
+    L.collide_ionize_step_static.restype = _i32
+    L.collide_ionize_step_static.argtypes = [_vp, C.POINTER(XpBatch), C.POINTER(XpStepParams), _vp]
     L.photo_auger_step.restype = _i32
     L.photo_auger_step.argtypes = [_vp, C.POINTER(XpBatch), C.POINTER(XpStepParams), _vp]
     L.transport_photons.restype = _i32
@@ -202,6 +207,10 @@ def bin_particles(ctx, parts, batch, cap, d_need, stream):
 
 def collide_ionize_step(ctx, batch, params, stream):
     check(load().collide_ionize_step(ctx, C.byref(batch), C.byref(params), _vp(stream)))
+
+
+def collide_ionize_step_static(ctx, batch, params, stream):
+    check(load().collide_ionize_step_static(ctx, C.byref(batch), C.byref(params), _vp(stream)))
 
 
 def transport_photons(ctx, batch, d_trans, stream):

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -19,7 +20,17 @@ struct xp_ctx {
     std::vector<unsigned char> staging;
 };
 
+// Workspace of collide_ionize_step_static: one array per device, held by the
+// loaded code object until the process ends.  In host code `scratch` only
+// names the symbol; its device address on each GPU comes from
+// hipGetSymbolAddress, taken once per device when a context is created there.
+static __device__ __align__(256) unsigned char scratch[XP_STATIC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
 
 thread_local std::string g_err;
 
@@ -99,6 +110,17 @@ xp_status xp_ctx_create(xp_ctx** out, int32_t device_id)
         return hip_fail(e, "hipDeviceGetAttribute");
     }
     c->n_cu = ncu > 0 ? ncu : 1;
+    if (device_id < MAX_DEVICES) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[device_id]) {
+            void* ptr = nullptr;
+            if ((e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch))) != hipSuccess) {
+                delete c;
+                return hip_fail(e, "hipGetSymbolAddress(scratch)");
+            }
+            g_scratch_ptr[device_id] = ptr;
+        }
+    }
     *out = c;
     return XP_OK;
 }
@@ -471,6 +493,29 @@ xp_status collide_ionize_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p,
 {
     if (!p) return fail(XP_ERR_INVALID_ARG, "null step parameters");
     return launch_step(ctx, b, p, p->flags & (XP_ALL | XP_THERM | XP_ION_Z | XP_NANBU), stream);
+}
+
+xp_status collide_ionize_step_static(xp_ctx* ctx, const xp_batch* b, const xp_step_params* p, void* stream)
+{
+    if (!ctx) return fail(XP_ERR_INVALID_ARG, "null context");
+    if (!b) return fail(XP_ERR_INVALID_ARG, "null batch");
+    if (!p) return fail(XP_ERR_INVALID_ARG, "null step parameters");
+    const size_t need = xp_step_work_bytes(b);
+    if (need > (size_t)XP_STATIC_SCRATCH_BYTES)
+        return fail(XP_ERR_UNSUPPORTED, "the batch needs " + std::to_string(need) +
+                                            " bytes of step workspace, more than the " +
+                                            std::to_string((size_t)XP_STATIC_SCRATCH_BYTES) +
+                                            " of the static scratch");
+    void* ptr = nullptr;
+    if (ctx->device >= 0 && ctx->device < MAX_DEVICES) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        ptr = g_scratch_ptr[ctx->device];
+    }
+    if (!ptr) return fail(XP_ERR_NOT_INITIALIZED, "no static scratch address for the context's device");
+    xp_batch v = *b;
+    v.d_work = ptr;
+    v.work_bytes = (size_t)XP_STATIC_SCRATCH_BYTES;
+    return launch_step(ctx, &v, p, p->flags & (XP_ALL | XP_THERM | XP_ION_Z | XP_NANBU), stream);
 }
 
 xp_status photo_auger_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, void* stream)
