@@ -157,10 +157,13 @@ def copy_reference(mib):
     log("copy reference: 3 x %d MiB device copies" % mib)
 
 
-def bench_c4(args):
-    """Batched scan: independent 0D runs in one batch, graph-replayed steps,
-    knobs picked by the autotuner, against a sequential plain loop over the
-    same runs.  Prints one JSON line (runs/hour)."""
+def measure_scan(nruns=256, run_steps=500, seq=True, k=5):
+    """Batched scan of the C4 runs at their full length: every run stepped
+    run_steps times in one batch (two eager steps, then graph replays of k
+    steps), autotuned knobs, against a sequential plain loop over the same runs
+    for the same steps.  No extrapolation: both legs step every run run_steps
+    times.  Returns a dict of the measurements."""
+    import numpy as np
     import torch
     from paper_1704_01202_amd import runtime as RT
     from paper_1704_01202_amd import scan as SC
@@ -168,13 +171,15 @@ def bench_c4(args):
 
     t0 = time.perf_counter()
     tab = W.make_tables()
-    runs = W.config_c4_runs(nruns=args.runs, nsteps=args.run_steps)
+    runs = W.config_c4_runs(nruns=nruns, nsteps=run_steps)
     n_part = sum(p.ne + p.ni for _, p in runs)
     log("scan generated (%.1f s): %d runs, %d particles" % (time.perf_counter() - t0, len(runs), n_part))
     ctx = RT.Context(tab)
+    # slabs for any state the runs can reach: weight units are conserved with
+    # the charge (sum w_e = sum Z <= 13 units per ion) and every electron holds
+    # at least one unit, so n_e + 12 n_i + 16 slots (n_e = n_i here) never overflow
+    cap = (12, 16)
     # autotune on a throw-away copy: the knobs change speed, never results
-    # Al3+ can give up 10 electrons per ion: slabs sized for full ionization
-    cap = (10, 16)
     tuner = SC.Scan(ctx, runs, capacity=cap)
     for _ in range(2):
         tuner.eager_step()
@@ -182,84 +187,103 @@ def bench_c4(args):
     log("autotuned on steps 2-%d: %s (%.3f ms/step)" % (tuner.steps_done - 1, best, best_ms))
     del tuner
     torch.cuda.empty_cache()
-    # the timed scan: steps 0 .. steps-1 of every run, the first two eager
-    # (they give the LDS plan its size hint), the rest as graph replays
     sc = SC.Scan(ctx, runs, capacity=cap)
     sc.config = dict(best)
     torch.cuda.synchronize()
     log("batched: %d cells, e_slots %d, global-path cells %d (%.1f s)"
         % (sc.bat.n_cells, sc.bat.e_slots, sc.bat.big_cells_max, time.perf_counter() - t0))
-    k = 6
     stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    reps = max(0, (run_steps - 2) // k)
+    tail = run_steps - 2 - reps * k
+    marks = [ev() for _ in range(reps + 1)]
+    e0, e1 = ev(), ev()
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     e0.record(stream)
     sc.eager_step()
     sc.eager_step()
-    reps = max(1, (args.steps - 2) // k)
-    sc.capture(k)
-    for _ in range(reps):
+    if reps:
+        sc.capture(k)
+    marks[0].record(stream)
+    for q in range(reps):
         sc.replay()
+        marks[q + 1].record(stream)
+        if (q + 1) % 20 == 0:
+            # a progress line every 100 steps (the wait adds no GPU work)
+            torch.cuda.synchronize()
+            log("batched: %d of %d steps, %.1f s" % (2 + (q + 1) * k, run_steps, time.perf_counter() - w0))
+    for _ in range(tail):
+        sc.eager_step()
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
-    timed = 2 + reps * k
-    ms_step = e0.elapsed_time(e1) / timed
+    assert sc.steps_done == run_steps
+    ms_step = e0.elapsed_time(e1) / run_steps
+    step_ms = np.array([marks[q].elapsed_time(marks[q + 1]) / k for q in range(reps)]) if reps \
+        else np.array([ms_step])
     cnt = sc.bat.run_counters().sum(axis=0)
     coll = int(cnt[0] + cnt[1] + cnt[2])
     status = sc.status()
-    batched_rph = len(runs) * 3600.0 / (args.run_steps * wall / timed)
-    log("batched: %.3f ms/step over steps 0-%d (graph capture included), status %d"
-        % (ms_step, timed - 1, status))
-    # sequential plain loop: every run alone, eager, the same steps
-    seq_steps = timed
+    run_status = sc.bat.run_status()
+    rph = len(runs) * 3600.0 / wall
+    log("batched: %d steps of %d runs in %.2f s (%.3f ms/step), status %d"
+        % (run_steps, len(runs), wall, ms_step, status))
     del sc
     torch.cuda.empty_cache()
-    per_run = []
-    if args.no_seq:
-        stepping, total = float("nan"), float("nan")
-    else:
-        stepping, total, _ = SC.sequential(ctx, runs, seq_steps, capacity=cap, per_run=per_run)
-    seq_rph = len(runs) * 3600.0 / (args.run_steps * stepping / seq_steps)
-    # time to result of each run at its full length (run_steps), stepping time
-    # only: in the batch every run finishes with the last step; in the
-    # sequential loop run r finishes after the runs before it
-    scale = args.run_steps / timed
-    t_all = ms_step * 1e-3 * timed * scale
-    ttr_batched = {"p50": t_all, "p99": t_all}
-    ttr_seq = None
-    if per_run:
-        import numpy as np
-        done = np.cumsum(per_run) * (args.run_steps / seq_steps)
-        ttr_seq = {"p50": float(np.percentile(done, 50)), "p99": float(np.percentile(done, 99))}
-    log("sequential: %.2f s stepping (%.2f s with set-up) for %d steps of every run"
-        % (stepping, total, seq_steps))
+    out = {
+        "workload": "%d independent 0D runs, 1e4-2e6 particles log-uniform, 1e16-1e18 W/cm^2, "
+                    "1.55-1.9 keV, SP/EK alternating, dt 0.1 fs, %d steps per run, one batch, "
+                    "HIP-graph replays of %d steps" % (len(runs), run_steps, k),
+        "runs": len(runs), "steps_per_run": run_steps, "particles": n_part,
+        "autotuned": best, "wall_s": wall, "ms_per_step": ms_step,
+        "runs_per_hour": rph, "collisions_per_s": coll / wall,
+        # every run of the batch completes with its last step
+        "time_to_result_s": {"p50": wall, "p99": wall},
+        "step_latency_ms": {"p50": float(np.percentile(step_ms, 50)),
+                            "p99": float(np.percentile(step_ms, 99))},
+        "status": status, "runs_flagged": int((run_status != 0).sum()),
+    }
+    if seq:
+        per_run = []
+        def one(i, dt):
+            if i % 16 == 15:
+                log("sequential: %d of %d runs, %.1f s stepping so far" % (i + 1, len(runs), sum(per_run)))
+        stepping, total, _ = SC.sequential(ctx, runs, run_steps, capacity=cap, per_run=per_run,
+                                           on_run=one)
+        done = np.cumsum(per_run)
+        out["sequential"] = {
+            "runs_per_hour": len(runs) * 3600.0 / stepping, "stepping_s": stepping,
+            "with_setup_s": total,
+            "time_to_result_s": {"p50": float(np.percentile(done, 50)),
+                                 "p99": float(np.percentile(done, 99))},
+        }
+        out["vs_sequential"] = rph / out["sequential"]["runs_per_hour"]
+        log("sequential: %.2f s stepping (%.2f s with set-up) for %d steps of every run"
+            % (stepping, total, run_steps))
+    return out
+
+
+def bench_c4(args):
+    """Batched scan as its own JSON line (runs/hour), every run stepped
+    --run-steps times in both legs."""
+    m = measure_scan(nruns=args.runs, run_steps=args.run_steps, seq=not args.no_seq)
     out = {
         "metric": "runs/hour (batched scan)",
-        "value": batched_rph,
+        "value": m["runs_per_hour"],
         "unit": "runs/h",
         "n_gpus": 1,
-        "steps": timed,
+        "steps": m["steps_per_run"],
         "warmup": 0,
-        "ms_per_step": ms_step,
+        "ms_per_step": m["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "%d independent 0D runs, 1e4-2e6 particles log-uniform, 1e16-1e18 W/cm^2, "
-                               "1.55-1.9 keV, SP/EK alternating, dt 0.1 fs, %d steps per run"
-                               % (len(runs), args.run_steps),
-                   "particles": n_part, "autotuned": best, "graph_steps": k, "status": status},
-        "collisions_per_s": coll / wall,
-        "time_to_result_s": ttr_batched,
-        "sequential_time_to_result_s": ttr_seq,
-        "sequential_runs_per_hour": seq_rph,
-        "vs_sequential": batched_rph / seq_rph if seq_rph == seq_rph else None,
-        "sequential_steps": seq_steps,
-        "note": "both legs time steps 0..%d of every run from the same initial state; "
-                "runs/hour scales that to %d steps per run" % (timed - 1, args.run_steps),
+        "config": {"workload": m["workload"], "particles": m["particles"],
+                   "autotuned": m["autotuned"], "status": m["status"]},
+        "scan": m,
     }
     print(json.dumps(out), flush=True)
 
@@ -349,8 +373,8 @@ def bench_c5(args):
     log("trace generated (%.1f s): %d requests, %d particles, %d run-steps"
         % (time.perf_counter() - t0, len(trace), n_part, n_steps))
     ctx = RT.Context(tab)
-    # Al3+ can give up 10 electrons per ion: slabs sized for full ionization
-    cap = (10, 16)
+    # slabs for any reachable state (see measure_scan)
+    cap = (12, 16)
     pool = SV.Pool(ctx, budget_bytes=int(args.budget_gb * 2**30), max_cells=1 << 16, max_runs=512,
                    capacity=cap)
     torch.cuda.synchronize()
@@ -435,6 +459,10 @@ def main():
     ap.add_argument("--runs", type=int, default=256, help="c4: runs in the scan")
     ap.add_argument("--run-steps", type=int, default=500, help="c4: steps of every run")
     ap.add_argument("--no-seq", action="store_true", help="c4: skip the sequential leg (profiling)")
+    ap.add_argument("--no-scan", action="store_true",
+                    help="c2: leave out the batched-scan measurement (C4 runs at full length)")
+    ap.add_argument("--no-full-run", action="store_true",
+                    help="c2: leave out the whole configured run (200 steps from the initial state)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the step has no cross-GPU work and only --gpus 1 "
@@ -561,9 +589,44 @@ def main():
                             "transmission": float(bat.d_trans[0, 0].item())}
     if args.copy_ref > 0:
         copy_reference(args.copy_ref)
-    if not args.no_cpu:
-        del bat
+    del bat
+    torch.cuda.empty_cache()
+    if not args.no_full_run:
+        # the whole configured run: a fresh batch from the same initial state,
+        # every one of its steps timed by events on the step's stream
+        fb = RT.Batch(ctx, [(spec, parts)], capacity=(7, 16), cell_nhv=field)
+        torch.cuda.synchronize()
+        nfull = int(spec.nsteps)
+        fev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(nfull)]
+        ne0 = int(fb.d_e_cnt.sum().item())
+        torch.cuda.synchronize()
+        f0 = time.perf_counter()
+        for k in range(nfull):
+            fev[k][0].record(stream)
+            fb.step(k, flags, schedule=args.schedule)
+            fev[k][1].record(stream)
+            if args.transport:
+                fb.transport()
+        torch.cuda.synchronize()
+        fwall = time.perf_counter() - f0
+        fms = [a.elapsed_time(b) for a, b in fev]
+        fc = fb.run_counters()[0]
+        fcoll = int(fc[0] + fc[1] + fc[2])
+        ne1 = int(fb.d_e_cnt.sum().item())
+        fbytes = E_BYTES * 0.5 * (ne0 + ne1) * nfull + I_BYTES * ni * nfull + NEW_BYTES * int(fc[21])
+        out["full_run"] = {"steps": nfull, "wall_s": fwall, "ms_per_step": fwall * 1e3 / nfull,
+                           "collisions_per_s": fcoll / fwall, "collisions": fcoll,
+                           "step_kernels_ms": {"first": fms[0], "last": fms[-1],
+                                               "mean": sum(fms) / nfull},
+                           "hbm_frac": fbytes / (sum(fms) * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                           "electrons": [ne0, ne1], "status": fb.status()}
+        log("full run: %d steps in %.3f s, %.3e collisions/s" % (nfull, fwall, fcoll / fwall))
+        del fb
         torch.cuda.empty_cache()
+    if not args.no_scan:
+        out["batched_scan"] = measure_scan()
+    if not args.no_cpu:
         log("timing the CPU oracle on a sample ...")
         out["cpu_baseline"] = cpu_baseline(spec, parts, therm=args.therm, ion_z=args.ion_z,
                                            nanbu=args.nanbu)

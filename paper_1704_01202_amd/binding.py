@@ -120,6 +120,9 @@ def load(path=LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # the library must bind to the HIP runtime that torch brings (the device
+    # memory and streams it is handed come from there): load torch first
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise XpError("libxpic.so is not built: run __graft_entry__.build() or "
                       "python paper_1704_01202_amd/build.py")

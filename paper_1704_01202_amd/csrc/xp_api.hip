@@ -420,11 +420,12 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
             const int m = a.lds_ce > a.lds_ci ? a.lds_ce : a.lds_ci;
             int sched = p->schedule;
             if (sched == 0) {
-                // small plans: four cells per wave; mid-sized plans: a wave per
-                // cell; large plans (whose LDS leaves few workgroups per CU): a
-                // block of four waves per cell
+                // small plans: four cells per wave; a wave per cell while the
+                // e-i rounds (at most one pair per ion slot) fit one wave and
+                // the LDS of one cell still leaves a few waves per SIMD; a
+                // block of four waves per cell for many ions or long slabs
                 if (m <= 4 * 16) sched = 5;
-                else sched = m > 128 ? 2 : 1;
+                else sched = (a.lds_ci > 128 || a.lds_ce > 384) ? 2 : 1;
             }
             if (sched >= 4) {
                 const int w = sched == 4 ? 32 : (sched == 5 ? 16 : 8);
@@ -460,18 +461,17 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
             const size_t lds = sched >= 4 ? (size_t)per_cell_groups * ((lds1 + 15) & ~size_t(15)) : lds1;
             if (lds > ctx->max_lds) return fail(XP_ERR_UNSUPPORTED, "LDS plan too large");
             if (lds > 65536) hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            // tier 0: a few resident rounds of workgroups, each looping over its
-            // cells (run records are summed per workgroup); later tiers: the
-            // deferred cells, read from the list
+            // every tier: a few resident rounds of workgroups, each looping
+            // over its cells (run records are summed per workgroup); tier 0
+            // takes all cells, later tiers the cells deferred to them, read
+            // from a list whose length only the device knows, so their grid
+            // is sized for the whole batch and surplus workgroups exit at once
             const long long items = ((long long)b->n_cells + per_cell_groups - 1) / per_cell_groups;
-            unsigned grid = (unsigned)(items < 2048 ? items : 2048);
-            if (tier == 0) {
-                int per_cu = 0;
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess || per_cu < 1)
-                    per_cu = 1;
-                const long long g0 = 4ll * per_cu * ctx->n_cu;
-                grid = (unsigned)(items < g0 ? items : g0);
-            }
+            int per_cu = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess || per_cu < 1)
+                per_cu = 1;
+            const long long g0 = 4ll * per_cu * ctx->n_cu;
+            const unsigned grid = (unsigned)(items < g0 ? items : g0);
             void* kargs[] = {(void*)&a};
             e = hipLaunchKernel(fn, dim3(grid), dim3(threads), kargs, lds, s);
             if (e != hipSuccess) return hip_fail(e, "step launch");

@@ -1296,7 +1296,9 @@ __global__ __launch_bounds__(BT) void k_big_recsel(BigArgs a, int pass)
     }
 }
 
-// Reduced weights: the electrons of the first nrec REC_E ranks lose one unit.
+// Reduced weights: every electron's weight in slot order (coalesced copy),
+// then k_big_wpdec takes one unit from the electrons of the first nrec REC_E
+// ranks (nrec random writes instead of one per electron).
 __global__ __launch_bounds__(BT) void k_big_wp(BigArgs a)
 {
     const StepArgs& s = a.s;
@@ -1306,24 +1308,93 @@ __global__ __launch_bounds__(BT) void k_big_wp(BigArgs a)
         if (!big_live(r, BN_REC)) continue;
         const int base = (g - r.ce0) * BIG_CH;
         const int n = r.epn - base < BIG_CH ? r.epn - base : BIG_CH;
-        const uint32_t* perm = a.val_a + r.ep0;
-        for (int t = base + threadIdx.x; t < base + n; t += BT) {
-            const uint32_t e = perm[t];
-            a.wp[r.ep0 + e] = s.ew[r.eo + e] - (t < r.nrec ? 1u : 0u);
-        }
+        for (int j = threadIdx.x; j < n; j += BT) a.wp[r.ep0 + base + j] = s.ew[r.eo + base + j];
     }
 }
 
-// One wave per cell: K_th of the reduced population; recombinations paired
-// rank by rank (ion sel[t], electron REC_E rank t), their energies summed left
-// to right.
+__global__ __launch_bounds__(BT) void k_big_wpdec(BigArgs a)
+{
+    const int nce = a.hdr->n_e_chunks;
+    for (int g = blockIdx.x; g < nce; g += gridDim.x) {
+        const BigRec& r = a.rec[a.e_chunk_cell[g]];
+        if (!big_live(r, BN_REC)) continue;
+        const int base = (g - r.ce0) * BIG_CH;
+        if (base >= r.nrec) continue;
+        const int n = r.nrec - base < BIG_CH ? r.nrec - base : BIG_CH;
+        const uint32_t* perm = a.val_a + r.ep0;
+        for (int t = base + threadIdx.x; t < base + n; t += BT) a.wp[r.ep0 + perm[t]] -= 1u;
+    }
+}
+
+// The recombinations of a cell paired rank by rank (ion sel[t], electron
+// REC_E rank t), one thread per pair: the ion takes the electron's momentum
+// and drops one charge state; the pair's energy (unit kinetic energy +
+// lowered binding + ion kinetic energy change) goes to fip[ip0 + t] for the
+// ordered sum of k_big_recsum.  Pairs touch distinct ions and electrons.
+__global__ __launch_bounds__(BT) void k_big_recapply(BigArgs a)
+{
+    __shared__ double red[BT / 64];
+    const StepArgs& s = a.s;
+    const DevTables* tb = s.tab;
+    const double mi = tb->mass_ion;
+    const double half_mi = (0.5 * mi) / QE;
+    const double ratio = ME / mi;
+    const int nci = a.hdr->n_i_chunks;
+    for (int g = blockIdx.x; g < nci; g += gridDim.x) {
+        BigRec& r = a.rec[a.i_chunk_cell[g]];
+        if (!big_live(r, BN_REC_APPLY)) continue;
+        const int base = (g - r.ci0) * BIG_CH;
+        if (base >= r.nrec) continue;
+        const int n = r.nrec - base < BIG_CH ? r.nrec - base : BIG_CH;
+        const double* dE = r.mom + 16;
+        const uint32_t* pe = a.val_a + r.ep0;
+        double bind = 0.0;
+        for (int t = base + threadIdx.x; t < base + n; t += BT) {
+            const int64_t e = r.eo + pe[t];
+            const int64_t i = r.io + a.sel[r.ip0 + t];
+            const double keu = kin_at(s, e);
+            const double vx = s.ivx[i], vy = s.ivy[i], vz = s.ivz[i];
+            const double kib = half_mi * ((vx * vx + vy * vy) + vz * vz);
+            const double nx = vx + ratio * s.evx[e];
+            const double ny = vy + ratio * s.evy[e];
+            const double nz = vz + ratio * s.evz[e];
+            s.ivx[i] = nx;
+            s.ivy[i] = ny;
+            s.ivz[i] = nz;
+            const double kia = half_mi * ((nx * nx + ny * ny) + nz * nz);
+            const int z = s.iz[i], kv = s.ik[i];
+            const Occ o0 = occupancy(z, kv);
+            const int kn = (kv >= 1 && o0.s[1] + o0.s[2] == 8) ? kv - 1 : kv;
+            const Occ o1 = occupancy(z - 1, kn);
+            int sl = 0;
+            for (int q = 0; q < 5; ++q)
+                if (o1.s[q] > o0.s[q]) { sl = q; break; }
+            const double ipr = lowered(tb, z - 1, sl, dE);
+            s.iz[i] = (uint8_t)(z - 1);
+            s.ik[i] = (uint8_t)kn;
+            a.fip[r.ip0 + t] = (keu + ipr) + (kib - kia);
+            bind = bind + ipr;
+        }
+        // the released bindings are a tally (any order)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) bind += __shfl_xor(bind, off, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = bind;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int w = 0; w < BT / 64; ++w) t += red[w];
+            if (t != 0.0) atomicAdd(&r.led[XP_L_REC_BIND], t);
+        }
+        __syncthreads();
+    }
+}
+
+// One wave per cell: K_th of the reduced population (canonical sum of the
+// chunk partials); with K_th > 0 the recombination can be applied.
 __global__ __launch_bounds__(64) void k_big_recfin(BigArgs a)
 {
     __shared__ double red[2 * (BIG_MAX_CHUNKS / 64)];
     const int lane = threadIdx.x;
-    const StepArgs& s = a.s;
-    const DevTables* tb = s.tab;
-    const double mi = tb->mass_ion;
     const int nb = a.hdr->count;
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
         BigRec& r = a.rec[b];
@@ -1331,105 +1402,169 @@ __global__ __launch_bounds__(64) void k_big_recfin(BigArgs a)
         const long long ws = (long long)r.ws;
         double kth = 0.0;
         if (ws != 0) kth = block_tree_sum<64>(r.nce, [&](int j) { return a.part[0][r.ce0 + j]; }, red);
-        if (ws == 0 || !(kth > 0.0)) {
-            if (lane == 0) r.cnt[XP_C_REC_SKIPPED] += 1;
-            __syncthreads();
-            continue;
-        }
-        const double* dE = r.mom + 16;
-        const double half_mi = (0.5 * mi) / QE;
-        const double ratio = ME / mi;
-        const uint32_t* pe = a.val_a + r.ep0;
-        const int nr = r.nrec;
-        double eadd = 0.0, bind = 0.0;
-        for (int t0 = 0; t0 < nr; t0 += 64) {
-            const int t = t0 + lane;
-            double term = 0.0;
-            if (t < nr) {
-                const int64_t e = r.eo + pe[t];
-                const int64_t i = r.io + a.sel[r.ip0 + t];
-                const double keu = kin_at(s, e);
-                const double vx = s.ivx[i], vy = s.ivy[i], vz = s.ivz[i];
-                const double kib = half_mi * ((vx * vx + vy * vy) + vz * vz);
-                const double nx = vx + ratio * s.evx[e];
-                const double ny = vy + ratio * s.evy[e];
-                const double nz = vz + ratio * s.evz[e];
-                s.ivx[i] = nx;
-                s.ivy[i] = ny;
-                s.ivz[i] = nz;
-                const double kia = half_mi * ((nx * nx + ny * ny) + nz * nz);
-                const int z = s.iz[i], kv = s.ik[i];
-                const Occ o0 = occupancy(z, kv);
-                const int kn = (kv >= 1 && o0.s[1] + o0.s[2] == 8) ? kv - 1 : kv;
-                const Occ o1 = occupancy(z - 1, kn);
-                int sl = 0;
-                for (int q = 0; q < 5; ++q)
-                    if (o1.s[q] > o0.s[q]) { sl = q; break; }
-                const double ipr = lowered(tb, z - 1, sl, dE);
-                s.iz[i] = (uint8_t)(z - 1);
-                s.ik[i] = (uint8_t)kn;
-                term = (keu + ipr) + (kib - kia);
-                bind = bind + ipr;
-            }
-            const int m = nr - t0 < 64 ? nr - t0 : 64;
-            for (int l = 0; l < m; ++l) eadd = eadd + __shfl(term, l, 64);
-        }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) bind += __shfl_xor(bind, off, 64);
         if (lane == 0) {
             r.kth = kth;
-            r.cnt[XP_C_REC] += nr;
-            r.led[XP_L_REC_ADD] += eadd;
-            r.led[XP_L_REC_BIND] += bind;
-            r.alpha = sqrt(1.0 + eadd / kth);
-            r.need |= BN_REC_APPLY;
+            if (ws == 0 || !(kth > 0.0)) r.cnt[XP_C_REC_SKIPPED] += 1;
+            else r.need |= BN_REC_APPLY;
         }
         __syncthreads();
     }
 }
 
-// Stable in-place removal of electrons whose weight reached zero; one block
-// per cell walks the slots in order (positions only move down).
-__global__ __launch_bounds__(BT) void k_big_compact(BigArgs a)
+// One wave per cell: the pairs' energies summed left to right in pair order
+// (512 at a time staged in LDS, lane 0 adds them eight loads ahead), then the
+// rescale factor of the remaining electrons.
+__global__ __launch_bounds__(64) void k_big_recsum(BigArgs a)
 {
-    __shared__ int red[BT / 64];
-    const int tid = threadIdx.x;
-    const StepArgs& s = a.s;
+    constexpr int SPAN = 512;
+    __shared__ double v[SPAN];
+    const int lane = threadIdx.x;
     const int nb = a.hdr->count;
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
         BigRec& r = a.rec[b];
         if (!big_live(r, BN_REC_APPLY)) continue;
-        const int ne = r.ne;
-        const int64_t o = r.eo;
-        int out = 0;
-        for (int c0 = 0; c0 < ne; c0 += BT) {
-            const int j = c0 + tid;
-            const bool alive = j < ne && s.ew[o + j] > 0;
-            double x = 0, y = 0, vx = 0, vy = 0, vz = 0;
-            uint32_t w = 0;
-            if (alive) {
-                x = s.ex[o + j];
-                y = s.ey ? s.ey[o + j] : 0.0;
-                vx = s.evx[o + j]; vy = s.evy[o + j]; vz = s.evz[o + j];
-                w = s.ew[o + j];
+        const int nr = r.nrec;
+        const double* term = a.fip + r.ip0;
+        double eadd = 0.0;
+        for (int t0 = 0; t0 < nr; t0 += SPAN) {
+            const int cnt = nr - t0 < SPAN ? nr - t0 : SPAN;
+            for (int q = lane; q < SPAN; q += 64) v[q] = q < cnt ? term[t0 + q] : 0.0;
+            __syncthreads();
+            if (lane == 0) {
+                int q = 0;
+                for (; q + 8 <= cnt; q += 8) {
+                    double tt[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) tt[u] = v[q + u];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) eadd = eadd + tt[u];
+                }
+                for (; q < cnt; ++q) eadd = eadd + v[q];
             }
+            __syncthreads();
+        }
+        if (lane == 0) {
+            r.cnt[XP_C_REC] += nr;
+            r.led[XP_L_REC_ADD] += eadd;
+            r.alpha = sqrt(1.0 + eadd / r.kth);
+        }
+        __syncthreads();
+    }
+}
+
+// Stable removal of the electrons whose weight reached zero, chunk-parallel
+// and out of place: k_big_ecount counts the survivors of each electron chunk
+// (into hist), k_big_escan turns the counts into per-cell offsets, k_big_emove
+// stages each survivor at its final rank (x, y in gev[0], gev[1]; vx, vy, vz,
+// w in ev4) and k_big_eback copies the staged survivors to the front of the
+// cell's slab.  Survivors keep their order.
+__global__ __launch_bounds__(BT) void k_big_ecount(BigArgs a)
+{
+    __shared__ long long ired[BT / 64];
+    const StepArgs& s = a.s;
+    const int nce = a.hdr->n_e_chunks;
+    uint32_t* cnt = a.hist;
+    for (int g = blockIdx.x; g < nce; g += gridDim.x) {
+        const BigRec& r = a.rec[a.e_chunk_cell[g]];
+        if (!big_live(r, BN_REC_APPLY)) continue;
+        const int base = (g - r.ce0) * BIG_CH;
+        const int n = r.epn - base < BIG_CH ? r.epn - base : BIG_CH;
+        long long c = 0;
+        for (int j = threadIdx.x; j < n; j += BT) c += s.ew[r.eo + base + j] > 0 ? 1 : 0;
+        c = block_isum<BT>(c, ired);
+        if (threadIdx.x == 0) cnt[g] = (uint32_t)c;
+    }
+}
+
+__global__ __launch_bounds__(BT) void k_big_escan(BigArgs a)
+{
+    __shared__ uint32_t red[BT / 64];
+    const int tid = threadIdx.x;
+    const int nb = a.hdr->count;
+    uint32_t* cnt = a.hist;
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+        BigRec& r = a.rec[b];
+        if (!big_live(r, BN_REC_APPLY)) continue;
+        uint32_t carry = 0;
+        for (int k0 = 0; k0 < r.nce; k0 += BT) {
+            const int k = k0 + tid;
+            const uint32_t v = k < r.nce ? cnt[r.ce0 + k] : 0u;
+            uint32_t tot;
+            const uint32_t ex = block_exclusive_sum<BT, uint32_t>(v, red, tot);
+            if (k < r.nce) cnt[r.ce0 + k] = carry + ex;
+            carry += tot;
+        }
+        if (tid == 0) {
+            r.cnt[XP_C_E_REMOVED] += r.ne - (int32_t)carry;
+            r.nkeep = (int32_t)carry;   // r.ne follows in k_big_efin
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(BT) void k_big_emove(BigArgs a)
+{
+    __shared__ int red[BT / 64];
+    const StepArgs& s = a.s;
+    const int nce = a.hdr->n_e_chunks;
+    const uint32_t* off = a.hist;
+    for (int g = blockIdx.x; g < nce; g += gridDim.x) {
+        const BigRec& r = a.rec[a.e_chunk_cell[g]];
+        if (!big_live(r, BN_REC_APPLY)) continue;
+        const int base = (g - r.ce0) * BIG_CH;
+        const int n = r.epn - base < BIG_CH ? r.epn - base : BIG_CH;
+        const int64_t o = r.eo + base;
+        int out = (int)off[g];
+        for (int c0 = 0; c0 < n; c0 += BT) {
+            const int j = c0 + threadIdx.x;
+            const bool alive = j < n && s.ew[o + j] > 0;
             int tot;
             const int ex = block_exclusive_sum<BT, int>(alive ? 1 : 0, red, tot);
             if (alive) {
-                const int64_t d = o + out + ex;
-                s.ex[d] = x;
-                if (s.ey) s.ey[d] = y;
-                s.evx[d] = vx; s.evy[d] = vy; s.evz[d] = vz;
-                s.ew[d] = w;
+                const int64_t d = r.ep0 + out + ex;
+                a.gev[0][d] = s.ex[o + j];
+                a.gev[1][d] = s.ey ? s.ey[o + j] : 0.0;
+                double* rec = a.ev4 + 4 * d;
+                *(double2*)rec = make_double2(s.evx[o + j], s.evy[o + j]);
+                *(double2*)(rec + 2) = make_double2(s.evz[o + j], (double)s.ew[o + j]);
             }
             out += tot;
-            __syncthreads();
         }
-        if (tid == 0) {
-            r.cnt[XP_C_E_REMOVED] += ne - out;
-            r.ne = out;
+    }
+}
+
+__global__ __launch_bounds__(BT) void k_big_eback(BigArgs a)
+{
+    const StepArgs& s = a.s;
+    const int nce = a.hdr->n_e_chunks;
+    for (int g = blockIdx.x; g < nce; g += gridDim.x) {
+        BigRec& r = a.rec[a.e_chunk_cell[g]];
+        if (!big_live(r, BN_REC_APPLY)) continue;
+        const int base = (g - r.ce0) * BIG_CH;
+        const int keep = r.nkeep;
+        const int n = keep - base < BIG_CH ? keep - base : BIG_CH;
+        const int64_t o = r.eo + base;
+        for (int j = threadIdx.x; j < n; j += BT) {
+            const int64_t d = r.ep0 + base + j;
+            s.ex[o + j] = a.gev[0][d];
+            if (s.ey) s.ey[o + j] = a.gev[1][d];
+            const double* rec = a.ev4 + 4 * d;
+            const double2 xy = *(const double2*)rec, zw = *(const double2*)(rec + 2);
+            s.evx[o + j] = xy.x;
+            s.evy[o + j] = xy.y;
+            s.evz[o + j] = zw.x;
+            s.ew[o + j] = (uint32_t)zw.y;
         }
-        __syncthreads();
+    }
+}
+
+// Survivor count of the cells whose electrons were compacted.
+__global__ __launch_bounds__(64) void k_big_efin(BigArgs a)
+{
+    const int nb = a.hdr->count;
+    for (int b = blockIdx.x * 64 + threadIdx.x; b < nb; b += gridDim.x * 64) {
+        BigRec& r = a.rec[b];
+        if (big_live(r, BN_REC_APPLY)) r.ne = r.nkeep;
     }
 }
 
@@ -1963,12 +2098,19 @@ hipError_t big_launch(BigArgs& a, bool all_cells, hipStream_t s)
         hipLaunchKernelGGL(k_big_cscan, dim3(gcell), dim3(BT), 0, s, a, 1);
         hipLaunchKernelGGL(k_big_recsel, dim3(gch), dim3(BT), 0, s, a, 1);
         hipLaunchKernelGGL(k_big_wp, dim3(gch), dim3(BT), 0, s, a);
+        hipLaunchKernelGGL(k_big_wpdec, dim3(gch), dim3(BT), 0, s, a);
         hipLaunchKernelGGL(k_big_drift, dim3(gch), dim3(BT), 0, s, a, 1);
         hipLaunchKernelGGL(k_big_dfin, dim3(gcell), dim3(BT), 0, s, a, 1);
         hipLaunchKernelGGL(k_big_kth, dim3(gch), dim3(BT), 0, s, a, 1);
         hipLaunchKernelGGL(k_big_recfin, dim3(gcell), dim3(64), 0, s, a);
+        hipLaunchKernelGGL(k_big_recapply, dim3(gch), dim3(BT), 0, s, a);
+        hipLaunchKernelGGL(k_big_recsum, dim3(gcell), dim3(64), 0, s, a);
         hipLaunchKernelGGL(k_big_rescale, dim3(gch), dim3(BT), 0, s, a, 1);
-        hipLaunchKernelGGL(k_big_compact, dim3(gcell), dim3(BT), 0, s, a);
+        hipLaunchKernelGGL(k_big_ecount, dim3(gch), dim3(BT), 0, s, a);
+        hipLaunchKernelGGL(k_big_escan, dim3(gcell), dim3(BT), 0, s, a);
+        hipLaunchKernelGGL(k_big_emove, dim3(gch), dim3(BT), 0, s, a);
+        hipLaunchKernelGGL(k_big_eback, dim3(gch), dim3(BT), 0, s, a);
+        hipLaunchKernelGGL(k_big_efin, dim3((gcell + 63) / 64), dim3(64), 0, s, a);
     }
     if (flags & (XP_PHOTO | XP_DECAY)) {
         hipLaunchKernelGGL(k_big_s5a, dim3(gch), dim3(BT), 0, s, a);

@@ -61,6 +61,27 @@ struct BlockTeam {
         return block_ordered_select<B>(n, pred, emit, S.sel);
     }
     __device__ static int prefix(int v, int& tot, Shared& S) { return block_exclusive_sum<B, int>(v, S.sel, tot); }
+    // smallest value over the block, returned to every thread
+    __device__ static uint64_t umin(uint64_t v, Shared& S)
+    {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const uint64_t o = shfl_xor_u64(v, off);
+            v = o < v ? o : v;
+        }
+        if (B == 64) return v;
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) S.ired[threadIdx.x >> 6] = (long long)v;
+        __syncthreads();
+        uint64_t m = ~0ull;
+#pragma unroll
+        for (int w = 0; w < B / 64; ++w) {
+            const uint64_t o = (uint64_t)S.ired[w];
+            m = o < m ? o : m;
+        }
+        __syncthreads();
+        return m;
+    }
 };
 
 template <int W>
@@ -111,6 +132,15 @@ struct GroupTeam {
         }
         tot = __shfl(incl, W - 1, W);
         return incl - v;
+    }
+    __device__ static uint64_t umin(uint64_t v, Shared&)
+    {
+#pragma unroll
+        for (int off = W / 2; off > 0; off >>= 1) {
+            const uint64_t o = shfl_xor_u64w(v, off, W);
+            v = o < v ? o : v;
+        }
+        return v;
     }
 };
 
@@ -391,6 +421,46 @@ __device__ __noinline__ void make_perm_fn(int n, uint32_t c0, uint32_t c1, uint3
     for (int k = tid; k < n; k += W) out[k] = (int32_t)(uint32_t)sbuf[k];
     T::sync();
 }
+
+// The first k ranks of the permutation of make_perm_fn (slots sorted by
+// (Philox word, slot)), restricted to the slots with zq[i] > zf when zq is
+// given: out[r] = slot of rank r for r < k.  k extractions of the smallest
+// remaining key instead of a full sort, for the few recombinations of a step.
+// The caller guarantees at least k admissible slots.
+template <class T>
+__device__ __noinline__ void smallest_fn(int n, int k, uint32_t c0, uint32_t c1, uint32_t c3, uint32_t k0,
+                                         uint32_t k1, const uint8_t* zq, int zf, int32_t* out,
+                                         uint64_t* sbuf, typename T::Shared& S)
+{
+    constexpr int W = T::N;
+    const int tid = T::rank();
+    for (int g = tid; 4 * g < n; g += W) {
+        const Words w = philox(c0, c1, (uint32_t)g, c3, k0, k1);
+        const uint32_t k4[4] = {w.x0, w.x1, w.x2, w.x3};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = 4 * g + q;
+            if (i < n) sbuf[i] = (zq && !((int)zq[i] > zf)) ? ~0ull : (((uint64_t)k4[q] << 32) | (uint32_t)i);
+        }
+    }
+    T::sync();
+    uint64_t last = 0;
+    for (int r = 0; r < k; ++r) {
+        uint64_t m = ~0ull;
+        for (int i = tid; i < n; i += W) {
+            const uint64_t v = sbuf[i];
+            if ((r == 0 || v > last) && v < m) m = v;
+        }
+        m = T::umin(m, S);
+        if (tid == 0) out[r] = (int32_t)(uint32_t)m;
+        last = m;
+    }
+    T::sync();
+}
+
+// Recombinations of a step at most this many select their ions and electrons
+// by extraction; more sort the whole permutation.
+constexpr int REC_SELECT_MAX = 12;
 
 // Steps one cell; true when its new state was committed (the caller then adds
 // S.cnt / S.led to the run records and S.ints[6] holds its electron count).
@@ -804,15 +874,23 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
             if (nrec > ne) nrec = ne;
             if (nrec > 0) {
                 const int nr = (int)nrec;
-                make_perm(RP_REC_I, ni, L.perm_i);
-                make_perm(RP_REC_E, ne, L.perm_e);
                 const int zf = R->z_floor;
-                T::select(
-                    ni, [&](int q) { return (int)L.iz[L.perm_i[q]] > zf; },
-                    [&](int q, int pos) {
-                        if (pos < nr) L.list[pos] = L.perm_i[q];
-                    },
-                    S);
+                if (nr <= REC_SELECT_MAX) {
+                    // the first nr eligible ions of the REC_I order and the
+                    // first nr electrons of the REC_E order
+                    smallest_fn<T>(ni, nr, step, lcell, RP_REC_I << 24, key0, key1, L.iz, zf, L.list, L.sbuf, S);
+                    smallest_fn<T>(ne, nr, step, lcell, RP_REC_E << 24, key0, key1, nullptr, 0, L.perm_e,
+                                   L.sbuf, S);
+                } else {
+                    make_perm(RP_REC_I, ni, L.perm_i);
+                    make_perm(RP_REC_E, ne, L.perm_e);
+                    T::select(
+                        ni, [&](int q) { return (int)L.iz[L.perm_i[q]] > zf; },
+                        [&](int q, int pos) {
+                            if (pos < nr) L.list[pos] = L.perm_i[q];
+                        },
+                        S);
+                }
                 for (int j = tid; j < ne; j += B) L.esel[j] = 0;
                 T::sync();
                 for (int t = tid; t < nr; t += B) L.esel[L.perm_e[t]] = 1;

@@ -38,6 +38,66 @@ def plan_hint(stats, quantile=0.9):
     return max(16, 16 * b)
 
 
+def count_stats(e_cnt):
+    """d_stats-shaped record of the electron counts per cell (the largest and
+    the 16-electron histogram), for the plan of a batch's first step."""
+    n = np.asarray(e_cnt, dtype=np.int64)
+    st = np.zeros(B.XP_NSTATS, dtype=np.int32)
+    if n.size:
+        st[0] = int(n.max())
+        b = np.minimum((n + 15) // 16, 63)
+        st[4:4 + 64] = np.bincount(b, minlength=64)[:64]
+    return st
+
+
+class StatsMirror:
+    """Host copy of a batch's per-step stats (d_stats) for the LDS plan hint.
+
+    The copy after each step is asynchronous, into a ring of pinned buffers;
+    the hint uses the newest copy that has landed.  At most DEPTH copies are in
+    flight: a host that runs further ahead of the device waits for the oldest,
+    so the plan is never more than DEPTH steps old.
+    """
+
+    DEPTH = 4
+
+    def __init__(self, d_stats, initial):
+        self.d = d_stats
+        self.bufs = [torch.zeros(B.XP_NSTATS, dtype=torch.int32, pin_memory=True)
+                     for _ in range(self.DEPTH)]
+        self.pending = []          # (event, buffer index), oldest first
+        self.k = 0
+        self.last = np.asarray(initial, dtype=np.int32).copy()
+
+    def _harvest(self, wait_oldest=False):
+        while self.pending:
+            ev, i = self.pending[0]
+            if wait_oldest:
+                ev.synchronize()
+                wait_oldest = False
+            elif not ev.query():
+                break
+            self.last = self.bufs[i].numpy().copy()
+            self.pending.pop(0)
+
+    def after_step(self):
+        if len(self.pending) >= self.DEPTH:
+            self._harvest(wait_oldest=True)
+        i = self.k % self.DEPTH
+        self.k += 1
+        self.bufs[i].copy_(self.d, non_blocking=True)
+        ev = torch.cuda.Event()
+        ev.record()
+        self.pending.append((ev, i))
+
+    def stats(self):
+        self._harvest()
+        return self.last
+
+    def hint(self, quantile=0.9):
+        return plan_hint(self.stats(), quantile)
+
+
 def _stream():
     return torch.cuda.current_stream().cuda_stream
 
@@ -156,7 +216,7 @@ class Batch:
         self.d_run_status = torch.zeros(self.n_runs, dtype=torch.int32, device=dev)
         self.d_need = torch.zeros(8, dtype=torch.int64, device=dev)
         self.d_stats = torch.zeros(B.XP_NSTATS, dtype=torch.int32, device=dev)
-        self.h_stats = torch.zeros(B.XP_NSTATS, dtype=torch.int32, pin_memory=True)
+        self.mirror = None          # set after binning
         self.e_hint = 0
         self.d_run_cnt = torch.zeros((self.n_runs, B.XP_NCOUNT), dtype=torch.int64, device=dev)
         self.d_run_led = torch.zeros((self.n_runs, B.XP_NLEDGER), dtype=torch.float64, device=dev)
@@ -283,16 +343,21 @@ class Batch:
         if step_bytes > self.work_bytes:
             self.work_bytes = step_bytes
             self.d_work = torch.empty(self.work_bytes, dtype=torch.uint8, device=self.device)
+        # the first step plans for the binned counts
+        self.mirror = StatsMirror(self.d_stats, count_stats(self.d_e_cnt[:self.n_cells].cpu().numpy()))
 
     # -- the method ---------------------------------------------------------------
+    def plan_hint(self, quantile=0.9):
+        """LDS plan hint from the newest stats that reached the host."""
+        return self.mirror.hint(quantile)
+
     def _hint(self, use_hint, quantile=0.9):
         if not use_hint:
             return 0
-        # from the step before last (copied without waiting)
-        return plan_hint(self.h_stats.numpy(), quantile)
+        return self.plan_hint(quantile)
 
     def _after(self):
-        self.h_stats.copy_(self.d_stats, non_blocking=True)
+        self.mirror.after_step()
 
     def _params(self, step, flags, schedule, d_step, use_hint, e_hint, big_grid):
         hint = int(e_hint) if e_hint is not None else self._hint(use_hint)

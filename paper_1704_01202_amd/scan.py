@@ -41,7 +41,7 @@ class Scan:
 
     # -- stepping ---------------------------------------------------------
     def _hint(self):
-        return RT.plan_hint(self.bat.h_stats.numpy(), self.config["quantile"])
+        return self.bat.plan_hint(self.config["quantile"])
 
     def eager_step(self):
         c = self.config
@@ -117,11 +117,11 @@ class Scan:
 
 
 def sequential(ctx: RT.Context, runs, nsteps, capacity=(7, 16), flags=B.XP_ALL, keep=False,
-               per_run=None):
+               per_run=None, on_run=None):
     """Every run alone in its own batch, stepped eagerly one after another.
     Returns (seconds spent stepping, seconds including each run's set-up,
     list of batches if keep); per_run (a list) receives each run's stepping
-    seconds in order."""
+    seconds in order; on_run(index, seconds) is called after each run."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stepping = 0.0
@@ -137,6 +137,8 @@ def sequential(ctx: RT.Context, runs, nsteps, capacity=(7, 16), flags=B.XP_ALL, 
         stepping += dt
         if per_run is not None:
             per_run.append(dt)
+        if on_run is not None:
+            on_run(len(per_run) - 1 if per_run is not None else -1, dt)
         if keep:
             kept.append(bat)
         else:

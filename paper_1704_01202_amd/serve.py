@@ -140,7 +140,7 @@ class Pool:
         # XP_ST_* bits per resident run (cleared on admission, read on retirement)
         self.d_run_status = torch.zeros(self.max_runs, dtype=torch.int32, device=dev)
         self.d_stats = torch.zeros(B.XP_NSTATS, dtype=torch.int32, device=dev)
-        self.h_stats = torch.zeros(B.XP_NSTATS, dtype=torch.int32, pin_memory=True)
+        self.mirror = RT.StatsMirror(self.d_stats, np.zeros(B.XP_NSTATS, dtype=np.int32))
         self.ealloc, self.ialloc = RangeAlloc(self.E), RangeAlloc(self.I)
         self.active: list[Resident] = []
         self.cells_used = 0
@@ -284,13 +284,13 @@ class Pool:
         if not self.active:
             return
         b = self._struct(self.cells_used, len(self.active), self._big_bounds())
-        hint = RT.plan_hint(self.h_stats.numpy(), 0.9)
+        hint = self.mirror.hint(0.9)
         nr = len(self.active)
         for _ in range(k):
             prm = B.XpStepParams(B.XP_ALL, 0, RT._ptr(self.d_step), int(schedule), hint, 0, 0)
             B.collide_ionize_step(self.ctx.h, b, prm, RT._stream())
             self.d_step[:nr].add_(1)
-        self.h_stats.copy_(self.d_stats, non_blocking=True)
+        self.mirror.after_step()
         for r in self.active:
             r.steps_done += k
 

@@ -428,3 +428,21 @@ def test_lotz_full_form_parity(ctx):
              schedule=3, big="all")
     spec, parts = W.config_c2(nx=6, ny=6)
     run_pair(c2, spec, parts, 8, check_every=4, label="C2r/lotz-bc")
+
+
+def test_recombination_selection_lds(ctx):
+    # three-body recombination on the LDS step: the first step recombines
+    # 11-78 times per cell (more than the extraction limit of 12 in most
+    # cells, the full-sort path), the second 1-8 times (the extraction path);
+    # a wave and a block per cell
+    ne = [200, 120, 90, 60, 33, 140]
+    ni = [60, 100, 40, 30, 50, 12]
+    for sched in (0, 1, 2):
+        spec, parts = cases.one_run(6, ne, ni, 2.0, 0.1, seed=96, z0=4, e_weight=1)
+        parts.iz[:] = np.random.default_rng(3).integers(3, 8, parts.ni)
+        bat, sim = run_pair(ctx, spec, parts, 3, check_every=1, schedule=sched,
+                            flags=O.ALL & ~(O.PHOTO | O.DECAY), label="rec/lds/%d" % sched)
+        rec = bat.run_counters()[0][O.COUNTERS.index("REC")]
+        assert rec == 46 + 78 + 34 + 24 + 11 + 1 + 8, rec
+    # (C1 recombines a few times per cell and step from step 55 on, through
+    # both paths: test_c1_parity)

@@ -150,7 +150,7 @@ def test_transport_graph_replays(ctx):
         sim.step(s, flags)
         sim.transport()
     torch.cuda.synchronize()
-    hint = int(RT.plan_hint(gb.h_stats.numpy()))
+    hint = int(gb.plan_hint())
     k = 2
     g = torch.cuda.CUDAGraph()
     side = torch.cuda.Stream()
