@@ -28,6 +28,7 @@ ALL = EE | EI | ION | REC | PHOTO | DECAY
 THERM = 0x40   # variant: forced thermalization after S5 (Sec. VI.C), not in ALL
 ION_Z = 0x80   # variant: S3 cross section per ion charge state (Sec. IV), not in ALL
 NANBU = 0x100  # variant: Nanbu's cumulative scattering law in S1, S2, not in ALL
+REL = 0x200    # variant: relativistic binary collisions in S1, S2, not in ALL
 
 COUNTERS = ["EE", "EI", "TRIPLET", "ACCEPT", "U0", "DELTA2_GT1",
             "ION_FIRED", "ION_ACCEPTED", "ION_STARVED",
@@ -280,7 +281,7 @@ def ta77(va, vb, ma, mb, wa, wb, coef, nunit, draws):
 
 
 def collide(va, vb, ma, mb, wa, wb, coef, nunit, draws, law):
-    """One collision with scattering law 0 (Takizuka-Abe) or 1 (Nanbu)."""
+    """One collision: law bit 0 Nanbu (else Takizuka-Abe), bit 1 relativistic."""
     va = np.array(va, dtype=np.float64)
     vb = np.array(vb, dtype=np.float64)
     d = np.ascontiguousarray(draws, dtype=np.uint32)

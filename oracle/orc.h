@@ -43,6 +43,7 @@ extern "C" {
 #define ORC_THERM   0x40u   /* variant: forced thermalization after S5 (Sec. VI.C) */
 #define ORC_ION_Z   0x80u   /* variant: S3 cross section per ion charge state (Sec. IV) */
 #define ORC_NANBU   0x100u  /* variant: Nanbu's cumulative scattering law in S1, S2 */
+#define ORC_REL     0x200u  /* variant: relativistic binary collisions in S1, S2 */
 
 /* Per-cell, per-step event counters. */
 enum {
@@ -127,6 +128,11 @@ double orc_collide(double va[3], double vb[3], double ma, double mb, uint32_t wa
                    uint32_t wb, double qq_coef, double nunit, const uint32_t draws[4],
                    int32_t law, int32_t *accept_a, int32_t *accept_b);
 /* Nanbu (1997): A with coth A - 1/A = exp(-s), and 1 - cos chi for uniform u. */
+/* Relativistic binary collision (law bit 2 of orc_collide) on its own, for
+ * the tests: returns <delta^2> = s / 2 of the pair, or -1. */
+double orc_collide_rel(double va[3], double vb[3], double ma, double mb, uint32_t wa,
+                       uint32_t wb, double qq_coef, double nunit, const uint32_t draws[4],
+                       int32_t nanbu, int32_t *acc_a, int32_t *acc_b);
 double orc_nanbu_a(double s);
 double orc_nanbu_omc(double s, double u);
 

@@ -249,6 +249,8 @@ double orc_collide(double va[3], double vb[3], double ma, double mb, uint32_t wa
                    uint32_t wb, double qq_coef, double nunit, const uint32_t draws[4],
                    int32_t law, int32_t *acc_a, int32_t *acc_b)
 {
+    if (law & 2)
+        return orc_collide_rel(va, vb, ma, mb, wa, wb, qq_coef, nunit, draws, law & 1, acc_a, acc_b);
     double ux = va[0] - vb[0], uy = va[1] - vb[1], uz = va[2] - vb[2];
     double u2 = (ux * ux + uy * uy) + uz * uz;
     *acc_a = 0;
@@ -258,7 +260,7 @@ double orc_collide(double va[3], double vb[3], double ma, double mb, uint32_t wa
     double u = sqrt(u2);
     double d2 = ((qq_coef * (double)wmax) * nunit) / (u2 * u);
     double st, omc;
-    if (law == 1) {
+    if (law & 1) {
         omc = orc_nanbu_omc(2.0 * d2, orc_u52(draws[0], draws[1]));
         st = sqrt(omc * (2.0 - omc));
     } else {
@@ -303,6 +305,125 @@ double orc_collide(double va[3], double vb[3], double ma, double mb, uint32_t wa
         vb[1] = vb[1] - fb * duy;
         vb[2] = vb[2] - fb * duz;
     }
+    *acc_a = ta;
+    *acc_b = tb;
+    return d2;
+}
+
+/*
+ * Relativistic binary collision (the COM-frame Monte-Carlo collision of
+ * Perez, Gremillet, Decoster, Drouin, Lefebvre, Phys. Plasmas 19, 083104
+ * (2012); Sec. IV cites relativistic weighted binary collisions for PICLS).
+ * Velocities in, velocities out; c = 299792458 m/s.
+ *   1. momenta p = gamma m v, energies E = gamma m c^2, gamma = 1/sqrt(1 - v^2/c^2);
+ *   2. centre-of-momentum velocity v_C = (p_a + p_b) c^2 / (E_a + E_b),
+ *      gamma_C = 1/sqrt(1 - v_C^2/c^2), and g = (gamma_C - 1)/v_C^2 written as
+ *      gamma_C^2 / ((gamma_C + 1) c^2);
+ *   3. p_a* = p_a + (g (v_C . p_a) - gamma_C E_a / c^2) v_C, E* = gamma_C (E - v_C . p);
+ *   4. the scattering parameter
+ *        s = 2 qq n m_ab^2 / (m_a gamma_a m_b gamma_b) * gamma_C |p*| / (m_a gamma_a + m_b gamma_b)
+ *            * (m_a gamma_a* m_b gamma_b* c^2 / |p*|^2 + 1)^2 / c^4,
+ *      qq = qq_coef of orc_collide (q_a^2 q_b^2 lnL dt / (8 pi eps0^2 m_ab^2)),
+ *      n = max(w_a, w_b) nunit; for v << c it tends to 2 <delta^2> of
+ *      Takizuka-Abe;
+ *   5. the angle of p_a* from <delta^2> = s / 2 by Takizuka-Abe's law (draws
+ *      0, 1) or, with nanbu, Nanbu's law with s; the azimuth from draw 2; the
+ *      rotation is orc_collide's with u -> p_a*; p_b*' = -p_a*';
+ *   6. back to the lab: p' = p*' + (g (v_C . p*') + gamma_C E* / c^2) v_C, and
+ *      v' = p' c / sqrt(m^2 c^2 + p'^2);
+ *   7. weighted acceptance as in orc_collide (draw 3).
+ * |p*| = 0 is no collision (-1).
+ */
+double orc_collide_rel(double va[3], double vb[3], double ma, double mb, uint32_t wa,
+                       uint32_t wb, double qq_coef, double nunit, const uint32_t draws[4],
+                       int32_t nanbu, int32_t *acc_a, int32_t *acc_b)
+{
+    const double c = ORC_CLIGHT, c2 = c * c;
+    *acc_a = 0;
+    *acc_b = 0;
+    double va2 = (va[0] * va[0] + va[1] * va[1]) + va[2] * va[2];
+    double vb2 = (vb[0] * vb[0] + vb[1] * vb[1]) + vb[2] * vb[2];
+    double ga = 1.0 / sqrt(1.0 - va2 / c2);
+    double gb = 1.0 / sqrt(1.0 - vb2 / c2);
+    double pa[3], pb[3], vc[3];
+    for (int d = 0; d < 3; ++d) {
+        pa[d] = (ga * ma) * va[d];
+        pb[d] = (gb * mb) * vb[d];
+    }
+    double ea = (ga * ma) * c2, eb = (gb * mb) * c2;
+    double etot = ea + eb;
+    for (int d = 0; d < 3; ++d) vc[d] = ((pa[d] + pb[d]) * c2) / etot;
+    double vc2 = (vc[0] * vc[0] + vc[1] * vc[1]) + vc[2] * vc[2];
+    double gc = 1.0 / sqrt(1.0 - vc2 / c2);
+    double g = (gc * gc) / ((gc + 1.0) * c2);
+    double vpa = (vc[0] * pa[0] + vc[1] * pa[1]) + vc[2] * pa[2];
+    double vpb = (vc[0] * pb[0] + vc[1] * pb[1]) + vc[2] * pb[2];
+    double ka = g * vpa - (gc * ea) / c2;
+    double ps[3];
+    for (int d = 0; d < 3; ++d) ps[d] = pa[d] + ka * vc[d];
+    double eas = gc * (ea - vpa), ebs = gc * (eb - vpb);
+    double p2 = (ps[0] * ps[0] + ps[1] * ps[1]) + ps[2] * ps[2];
+    if (p2 == 0.0) return -1.0;
+    double p = sqrt(p2);
+    double gas = eas / (ma * c2), gbs = ebs / (mb * c2);
+    uint32_t wmax = wa > wb ? wa : wb;
+    double mab = (ma * mb) / (ma + mb);
+    double x = (((ma * gas) * (mb * gbs)) * c2) / p2 + 1.0;
+    double s = ((((2.0 * qq_coef) * ((double)wmax * nunit)) * (mab * mab)) / ((ma * ga) * (mb * gb)))
+               * ((gc * p) / (ma * ga + mb * gb)) * ((x * x) / (c2 * c2));
+    double d2 = 0.5 * s;
+    double st, omc;
+    if (nanbu) {
+        omc = orc_nanbu_omc(s, orc_u52(draws[0], draws[1]));
+        st = sqrt(omc * (2.0 - omc));
+    } else {
+        double r1 = orc_u32(draws[0]);
+        double s2, cc2;
+        orc_sincos2pi((uint64_t)draws[1] << 20, &s2, &cc2);
+        double gg = sqrt(-2.0 * orc_log(r1)) * cc2;
+        double dl = sqrt(d2) * gg;
+        double dd = dl * dl;
+        double den = 1.0 + dd;
+        st = (2.0 * dl) / den;
+        omc = (2.0 * dd) / den;
+    }
+    double sp, cp;
+    orc_sincos2pi((uint64_t)draws[2] << 20, &sp, &cp);
+    double a = st * cp, bb = st * sp;
+    double up = sqrt(ps[0] * ps[0] + ps[1] * ps[1]);
+    double dpx, dpy, dpz;
+    if (up > 0.0) {
+        dpx = ((ps[0] / up) * ps[2]) * a - ((ps[1] / up) * p) * bb - ps[0] * omc;
+        dpy = ((ps[1] / up) * ps[2]) * a + ((ps[0] / up) * p) * bb - ps[1] * omc;
+        dpz = -(up * a) - ps[2] * omc;
+    } else {
+        double apz = fabs(ps[2]);
+        dpx = apz * a;
+        dpy = apz * bb;
+        dpz = -(ps[2] * omc);
+    }
+    double qa[3] = {ps[0] + dpx, ps[1] + dpy, ps[2] + dpz};
+    double qb[3] = {-qa[0], -qa[1], -qa[2]};
+    double vqa = (vc[0] * qa[0] + vc[1] * qa[1]) + vc[2] * qa[2];
+    double vqb = (vc[0] * qb[0] + vc[1] * qb[1]) + vc[2] * qb[2];
+    double la = g * vqa + (gc * eas) / c2;
+    double lb = g * vqb + (gc * ebs) / c2;
+    double na[3], nb[3];
+    for (int d = 0; d < 3; ++d) {
+        na[d] = qa[d] + la * vc[d];
+        nb[d] = qb[d] + lb * vc[d];
+    }
+    double na2 = (na[0] * na[0] + na[1] * na[1]) + na[2] * na[2];
+    double nb2 = (nb[0] * nb[0] + nb[1] * nb[1]) + nb[2] * nb[2];
+    double ra = c / sqrt((ma * ma) * c2 + na2);
+    double rb = c / sqrt((mb * mb) * c2 + nb2);
+    double r4 = orc_u32(draws[3]);
+    int ta = (wa <= wb) || (r4 < (double)wb / (double)wa);
+    int tb = (wb <= wa) || (r4 < (double)wa / (double)wb);
+    if (ta)
+        for (int d = 0; d < 3; ++d) va[d] = na[d] * ra;
+    if (tb)
+        for (int d = 0; d < 3; ++d) vb[d] = nb[d] * rb;
     *acc_a = ta;
     *acc_b = tb;
     return d2;

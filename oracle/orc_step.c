@@ -6,7 +6,9 @@
  *      (Sec. II), densities, Zbar, z* and the continuum lowering dE[Z] of every
  *      charge state by Ecker-Kroll (Eq. 5) or Stewart-Pyatt (Eq. 6) (Sec. V).
  *   S1 electron-electron and S2 electron-ion binary collisions (Sec. IV), by
- *      Takizuka-Abe's scattering law or (ORC_NANBU) Nanbu's cumulative law.
+ *      Takizuka-Abe's scattering law or (ORC_NANBU) Nanbu's cumulative law,
+ *      non-relativistic or (ORC_REL) in the pair's centre-of-momentum frame
+ *      with relativistic kinematics.
  *   S3 collisional ionization against the average cell ion with the Lotz cross
  *      section (Eq. 4) and the energy debit of Sec. IV; with ORC_ION_Z every
  *      ion's probability uses the cross section of its own charge state.
@@ -324,7 +326,7 @@ typedef struct {
     uint32_t *keys;
     int64_t *cnt;
     double *led;
-    int32_t law;          /* scattering law of S1, S2: 0 Takizuka-Abe, 1 Nanbu */
+    int32_t law;          /* S1, S2: bit 0 Nanbu (else Takizuka-Abe), bit 1 relativistic */
     int32_t *nabs;        /* this cell's photons absorbed per bin */
 } cctx;
 
@@ -903,7 +905,7 @@ void orc_step(orc_sim *s, uint32_t step, uint32_t flags, int32_t nthreads)
         cctx x;
         x.s = s;
         x.step = step;
-        x.law = (flags & ORC_NANBU) ? 1 : 0;
+        x.law = ((flags & ORC_NANBU) ? 1 : 0) | ((flags & ORC_REL) ? 2 : 0);
         x.key[0] = (uint32_t)s->r.seed;
         x.key[1] = (uint32_t)(s->r.seed >> 32);
         x.scratch = malloc(sizeof(double) * (size_t)pad);

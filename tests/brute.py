@@ -12,6 +12,7 @@ import math
 
 QE = 1.602176634e-19
 ME = 9.1093837015e-31
+CLIGHT = 299792458.0
 EPS0 = 8.8541878128e-12
 HBAR = 1.054571817e-34
 CL = 299792458.0
@@ -88,6 +89,7 @@ class Brute:
         self.s = spec
         self.key = (spec.seed & M32, (spec.seed >> 32) & M32)
         self.law = 0   # scattering law: 0 Takizuka-Abe, 1 Nanbu
+        self.rel = False   # relativistic kinematics
         self.sig = [[self._sigma(q, h) for q in range(3)] for h in spec.photon_hv]
 
     def _sigma(self, q, hv):
@@ -147,7 +149,78 @@ class Brute:
     def ke(v):
         return 0.5 * ME * (v[2] ** 2 + v[3] ** 2 + v[4] ** 2) / QE
 
+    def collide_rel(self, step, cell, a, b, mb, wb, coef, nunit, idx, purpose, counts):
+        """Relativistic pair in its centre-of-momentum frame, written with
+        4-momenta and the Lorentz boost matrix (t = E/c component first)."""
+        c = CLIGHT
+        wa = a[5]
+        w = self.rng(step, cell, idx, purpose, 0)
+        r4 = u32(w[3])
+
+        def four(v, m):
+            g = 1.0 / math.sqrt(1.0 - (v[0] ** 2 + v[1] ** 2 + v[2] ** 2) / c ** 2)
+            return [g * m * c, g * m * v[0], g * m * v[1], g * m * v[2]], g
+
+        def boost(pv, beta):
+            b2 = beta[0] ** 2 + beta[1] ** 2 + beta[2] ** 2
+            if b2 == 0.0:
+                return list(pv)
+            g = 1.0 / math.sqrt(1.0 - b2)
+            bx = beta[0] * pv[1] + beta[1] * pv[2] + beta[2] * pv[3]
+            t = g * (pv[0] - bx)
+            k = (g - 1.0) * bx / b2 - g * pv[0]
+            return [t, pv[1] + k * beta[0], pv[2] + k * beta[1], pv[3] + k * beta[2]]
+
+        Pa, ga = four(a[2:5], ME)
+        Pb, gb = four(b[2:5], mb)
+        beta = [(Pa[q] + Pb[q]) / (Pa[0] + Pb[0]) for q in (1, 2, 3)]
+        gc = 1.0 / math.sqrt(1.0 - (beta[0] ** 2 + beta[1] ** 2 + beta[2] ** 2))
+        Sa, Sb = boost(Pa, beta), boost(Pb, beta)
+        ps = Sa[1:]
+        p = math.sqrt(ps[0] ** 2 + ps[1] ** 2 + ps[2] ** 2)
+        if p == 0.0:
+            return
+        gas, gbs = Sa[0] / (ME * c), Sb[0] / (mb * c)
+        mab = ME * mb / (ME + mb)
+        s = (2.0 * coef * max(wa, wb) * nunit * mab ** 2 / (ME * ga * mb * gb)
+             * gc * p / (ME * ga + mb * gb) * (ME * gas * mb * gbs * c * c / p ** 2 + 1.0) ** 2 / c ** 4)
+        d2 = 0.5 * s
+        if self.law == 1:
+            omc = nanbu_omc(s, u52(w[0], w[1]))
+            st = math.sqrt(omc * (2.0 - omc))
+        else:
+            g = math.sqrt(-2 * math.log(u32(w[0]))) * math.cos(2 * math.pi * ((w[1] << 20) + 0.5) / 2 ** 52)
+            d = math.sqrt(d2) * g
+            st, omc = 2 * d / (1 + d * d), 2 * d * d / (1 + d * d)
+        ct = 1.0 - omc
+        phi = 2 * math.pi * ((w[2] << 20) + 0.5) / 2 ** 52
+        ux, uy, uz = ps[0] / p, ps[1] / p, ps[2] / p
+        up = math.hypot(ux, uy)
+        if up > 0:
+            e1 = [ux * uz / up, uy * uz / up, -up]
+            e2 = [-uy / up, ux / up, 0.0]
+            n = [ct * [ux, uy, uz][q] + st * math.cos(phi) * e1[q] + st * math.sin(phi) * e2[q]
+                 for q in range(3)]
+        else:
+            n = [st * math.cos(phi), st * math.sin(phi), ct * uz]
+        qa = [Sa[0]] + [p * n[q] for q in range(3)]
+        qb = [Sb[0]] + [-p * n[q] for q in range(3)]
+        back = [-beta[0], -beta[1], -beta[2]]
+        La, Lb = boost(qa, back), boost(qb, back)
+
+        def vel(P, m):
+            e = math.sqrt((m * c) ** 2 + P[1] ** 2 + P[2] ** 2 + P[3] ** 2)
+            return [P[q] * c / e for q in (1, 2, 3)]
+
+        if wa <= wb or r4 < wb / wa:
+            a[2:5] = vel(La, ME)
+        if wb <= wa or r4 < wa / wb:
+            b[2:5] = vel(Lb, mb)
+        counts["pairs"] += 1
+
     def collide(self, step, cell, a, b, mb, wb, coef, nunit, idx, purpose, counts):
+        if self.rel:
+            return self.collide_rel(step, cell, a, b, mb, wb, coef, nunit, idx, purpose, counts)
         ua = [a[2] - b[2], a[3] - b[3], a[4] - b[4]]
         u2 = ua[0] ** 2 + ua[1] ** 2 + ua[2] ** 2
         if u2 == 0.0:
@@ -198,6 +271,7 @@ class Brute:
     def step(self, cell_id, c, step, flags):
         s, t = self.s, self.t
         self.law = 1 if flags & 0x100 else 0
+        self.rel = bool(flags & 0x200)
         mi = t.mass_ion
         counts = {"pairs": 0, "ion": 0, "rec": 0, "photo": 0, "decay": 0, "auger": 0}
         es, ions = c.e, c.i

@@ -20,9 +20,10 @@ def _cells_from_state(st):
     return cells
 
 
-@pytest.mark.parametrize("ipd,seed,nanbu", [(0, 41, False), (1, 42, False), (1, 43, False),
-                                            (1, 44, True)])
-def test_oracle_matches_brute_force(orc, tables, ipd, seed, nanbu):
+@pytest.mark.parametrize("ipd,seed,nanbu,rel", [(0, 41, False, False), (1, 42, False, False),
+                                                (1, 43, False, False), (1, 44, True, False),
+                                                (0, 45, False, True), (1, 46, True, True)])
+def test_oracle_matches_brute_force(orc, tables, ipd, seed, nanbu, rel):
     rng = np.random.default_rng(seed)
     ncell = 10
     ne = rng.integers(1, 7, ncell)
@@ -38,7 +39,7 @@ def test_oracle_matches_brute_force(orc, tables, ipd, seed, nanbu):
     bf = brute.Brute(tables, spec)
     totals = {"pairs": 0, "ion": 0, "rec": 0, "photo": 0, "decay": 0, "auger": 0}
     for step in range(5):
-        flags = orc.ALL | (orc.NANBU if nanbu else 0)
+        flags = orc.ALL | (orc.NANBU if nanbu else 0) | (orc.REL if rel else 0)
         for c, cell in enumerate(cells):
             cnt = bf.step(c, cell, step, flags)
             for k in totals:
