@@ -47,7 +47,7 @@ def cpu_threads():
 
 
 def cpu_baseline(spec, parts, budget_s=15.0, max_steps=40, therm=False, ion_z=False, nanbu=False,
-                 single=True):
+                 rel=False, single=True):
     """The oracle on a bounded sample of the same workload: every cell of the
     same initial state, stepped from step 0 until about budget_s of work on the
     host's threads; then (single) step 0 again on one thread."""
@@ -60,7 +60,8 @@ def cpu_baseline(spec, parts, budget_s=15.0, max_steps=40, therm=False, ion_z=Fa
     coll = 0
     steps = 0
     t0 = time.perf_counter()
-    flags = O.ALL | (O.THERM if therm else 0) | (O.ION_Z if ion_z else 0) | (O.NANBU if nanbu else 0)
+    flags = (O.ALL | (O.THERM if therm else 0) | (O.ION_Z if ion_z else 0) | (O.NANBU if nanbu else 0)
+             | (O.REL if rel else 0))
     while steps < max_steps:
         sim.step(steps, flags, threads)
         cnt, _ = sim.counters()
@@ -439,6 +440,8 @@ def main():
                     help="c2: collisional ionization per ion charge state (variant of Sec. IV)")
     ap.add_argument("--nanbu", action="store_true",
                     help="c2: Nanbu's cumulative scattering law in the e-e and e-i collisions")
+    ap.add_argument("--rel", action="store_true",
+                    help="c2: relativistic binary collisions (centre-of-momentum frame)")
     ap.add_argument("--transport", action="store_true",
                     help="c2: per-cell photon field rebuilt after every step by the reduced "
                          "radiation transport (transport_photons)")
@@ -502,7 +505,7 @@ def main():
         % (bat.e_slots, bat.e_cap_max, time.perf_counter() - t0))
     stream = torch.cuda.current_stream()
     flags = (B.XP_ALL | (B.XP_THERM if args.therm else 0) | (B.XP_ION_Z if args.ion_z else 0)
-             | (B.XP_NANBU if args.nanbu else 0))
+             | (B.XP_NANBU if args.nanbu else 0) | (B.XP_REL if args.rel else 0))
     for s in range(args.warmup):
         bat.step(s, flags, schedule=args.schedule)
         if args.transport:
@@ -563,6 +566,7 @@ def main():
                                   (", forced thermalization after S5" if args.therm else "")
                                   + (", ionization per ion charge state" if args.ion_z else "")
                                   + (", Nanbu scattering law" if args.nanbu else "")
+                                  + (", relativistic collisions" if args.rel else "")
                                   + (", reduced radiation transport after every step"
                                      if args.transport else "")),
                    "cells": spec.ncells, "electrons_start": parts.ne, "ions": ni,
@@ -575,7 +579,7 @@ def main():
     }
     valu = measured_valu()
     if (valu is not None and args.nx == 512 and args.ny == 512 and not args.therm and not args.ion_z
-            and not args.nanbu and not args.transport):
+            and not args.nanbu and not args.rel and not args.transport):
         # the step is bound by instruction issue, not by HBM: VALU instructions
         # of a launch (profiled) over the launch time measured here
         rate = valu / (avg_ms * 1e-3)
@@ -629,7 +633,7 @@ def main():
     if not args.no_cpu:
         log("timing the CPU oracle on a sample ...")
         out["cpu_baseline"] = cpu_baseline(spec, parts, therm=args.therm, ion_z=args.ion_z,
-                                           nanbu=args.nanbu)
+                                           nanbu=args.nanbu, rel=args.rel)
     print(json.dumps(out), flush=True)
 
 

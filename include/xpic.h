@@ -83,6 +83,17 @@ typedef int32_t xp_status;
  * to nu dt >> 1, where Takizuka-Abe's single small-angle step is out of its
  * range. */
 #define XP_NANBU   0x100u
+/* Variant, not part of XP_ALL: relativistic binary collisions in the e-e and
+ * e-i stages (Sec. IV cites relativistic weighted binary collisions for the
+ * code's collision model), after the centre-of-momentum-frame Monte-Carlo
+ * collision of Perez et al. (Phys. Plasmas 19, 083104 (2012)).  Velocities
+ * become momenta p = gamma m v, the pair is boosted to its centre-of-momentum
+ * frame, p_a* is turned by the angle drawn from the relativistic scattering
+ * parameter s (which tends to 2 <delta^2> of Takizuka-Abe for v << c) with
+ * Takizuka-Abe's law at <delta^2> = s / 2, or with XP_NANBU Nanbu's law at s,
+ * and both momenta are boosted back.  Pairing, draws and weighted acceptance
+ * are unchanged; the other stages keep their non-relativistic energies. */
+#define XP_REL     0x200u
 
 /* Device status bits (xp_batch.d_status, OR-ed by kernels). */
 #define XP_ST_CAPACITY  0x1u   /* a cell needed more electron slots than its capacity */
@@ -317,7 +328,7 @@ xp_status bin_particles(xp_ctx *ctx, const xp_particles *in, xp_batch *b,
 
 /* One Monte-Carlo step of every cell of every run in the batch (Sec. II-V):
  * moments and continuum lowering, e-e and e-i binary collisions (Takizuka-Abe,
- * or Nanbu's law with XP_NANBU), collisional
+ * or Nanbu's law with XP_NANBU, relativistic with XP_REL), collisional
  * ionization, three-body recombination, and -- when XP_PHOTO / XP_DECAY are in
  * p->flags -- the XFEL source terms of photo_auger_step, fused in the same
  * pass with dt_rad of the run table, then with XP_THERM the forced

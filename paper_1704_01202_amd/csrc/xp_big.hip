@@ -656,9 +656,10 @@ __global__ __launch_bounds__(BT) void k_big_unstage(BigArgs a, int species)
 
 // ---------------------------------------------------------------- S1, S2
 
-// NB: Nanbu's scattering law (XP_NANBU) instead of Takizuka-Abe's; the plain
-// instance carries none of its code.
-template <bool NB>
+// LAW: bit 0 Nanbu's scattering law (XP_NANBU) instead of Takizuka-Abe's,
+// bit 1 relativistic kinematics (XP_REL); the plain instance carries none of
+// their code.
+template <int LAW>
 __global__ __launch_bounds__(BT) void k_big_ee(BigArgs a)
 {
     __shared__ int cnt[XP_NCOUNT];
@@ -698,21 +699,20 @@ __global__ __launch_bounds__(BT) void k_big_ee(BigArgs a)
         const uint32_t st = step_of(s, r.run);
         const uint32_t lcell = (uint32_t)(r.cell - RR.cell_begin);
         const uint32_t k0 = (uint32_t)RR.seed, k1 = (uint32_t)(RR.seed >> 32);
-        constexpr bool nanbu = NB;
         if (k == 0 && start == 3 && tid == 0) {
             const int p0 = 0, p1 = 1, p2 = 2;
             collide_slots(vx, vy, vz, w, vx, vy, vz, p0, p1, w[p1], f_ee, f_ee, ahalf, nunit, st, lcell, 0u,
-                          RP_EE_TRI << 24, k0, k1, cnt, nanbu);
+                          RP_EE_TRI << 24, k0, k1, cnt, LAW, ME, ME);
             collide_slots(vx, vy, vz, w, vx, vy, vz, p1, p2, w[p2], f_ee, f_ee, ahalf, nunit, st, lcell, 1u,
-                          RP_EE_TRI << 24, k0, k1, cnt, nanbu);
+                          RP_EE_TRI << 24, k0, k1, cnt, LAW, ME, ME);
             collide_slots(vx, vy, vz, w, vx, vy, vz, p2, p0, w[p0], f_ee, f_ee, ahalf, nunit, st, lcell, 2u,
-                          RP_EE_TRI << 24, k0, k1, cnt, nanbu);
+                          RP_EE_TRI << 24, k0, k1, cnt, LAW, ME, ME);
             cnt[XP_C_TRIPLET] += 3;
         }
         for (int j = jlo + tid; j < jhi; j += BT) {
             const int e = start + 2 * j, f = start + 2 * j + 1;
             collide_slots(vx, vy, vz, w, vx, vy, vz, e, f, w[f], f_ee, f_ee, afull, nunit, st, lcell,
-                          (uint32_t)j, RP_EE << 24, k0, k1, cnt, nanbu);
+                          (uint32_t)j, RP_EE << 24, k0, k1, cnt, LAW, ME, ME);
         }
         __syncthreads();
         if (tid == 0 && k == 0) cnt[XP_C_EE] += npairs;
@@ -722,7 +722,7 @@ __global__ __launch_bounds__(BT) void k_big_ee(BigArgs a)
     }
 }
 
-template <bool NB>
+template <int LAW>
 __global__ __launch_bounds__(BT) void k_big_ei(BigArgs a)
 {
     __shared__ int cnt[XP_NCOUNT];
@@ -766,8 +766,7 @@ __global__ __launch_bounds__(BT) void k_big_ei(BigArgs a)
             const uint32_t st = step_of(s, r.run);
             const uint32_t lcell = (uint32_t)(r.cell - R.cell_begin);
             const uint32_t k0 = (uint32_t)R.seed, k1 = (uint32_t)(R.seed >> 32);
-            constexpr bool nanbu = NB;
-            for (int q = base + tid; q < base + n; q += BT) {
+                for (int q = base + tid; q < base + n; q += BT) {
                 for (int kk = q; kk < nmax; kk += nmin) {
                     int e, i;
                     if (ne >= ni) { e = kk; i = q; }
@@ -775,7 +774,7 @@ __global__ __launch_bounds__(BT) void k_big_ei(BigArgs a)
                     const int z = zz[i];
                     if (z == 0) continue;
                     collide_slots(vx, vy, vz, w, ix, iy, iz, e, i, 1u, fe_ei, fi_ei, a1 * (double)(z * z),
-                                  nunit, st, lcell, (uint32_t)kk, RP_EI << 24, k0, k1, cnt, nanbu);
+                                  nunit, st, lcell, (uint32_t)kk, RP_EI << 24, k0, k1, cnt, LAW, ME, mi);
                 }
             }
             __syncthreads();
@@ -2057,16 +2056,26 @@ hipError_t big_launch(BigArgs& a, bool all_cells, hipStream_t s)
         if ((e = big_sort(a, 0, BN_PERM_E, RP_PERM_E, a.key_a, a.val_a, a.key_b, a.val_b, gch, gcell, s)) != hipSuccess)
             return e;
         hipLaunchKernelGGL(k_big_gather, dim3(gch), dim3(BT), 0, s, a, 0, 0);
+        // scattering law: bit 0 Nanbu, bit 1 relativistic
+        const int law = ((flags & XP_NANBU) ? 1 : 0) | ((flags & XP_REL) ? 2 : 0);
         if (flags & XP_EE) {
-            if (flags & XP_NANBU) hipLaunchKernelGGL(k_big_ee<true>, dim3(gch), dim3(BT), 0, s, a);
-            else hipLaunchKernelGGL(k_big_ee<false>, dim3(gch), dim3(BT), 0, s, a);
+            switch (law) {
+            case 0: hipLaunchKernelGGL(k_big_ee<0>, dim3(gch), dim3(BT), 0, s, a); break;
+            case 1: hipLaunchKernelGGL(k_big_ee<1>, dim3(gch), dim3(BT), 0, s, a); break;
+            case 2: hipLaunchKernelGGL(k_big_ee<2>, dim3(gch), dim3(BT), 0, s, a); break;
+            default: hipLaunchKernelGGL(k_big_ee<3>, dim3(gch), dim3(BT), 0, s, a); break;
+            }
         }
         if (flags & XP_EI) {
             if ((e = big_sort(a, 1, BN_EI, RP_PERM_I, a.key_c, a.val_c, a.key_b, a.val_b, gch, gcell, s)) != hipSuccess)
                 return e;
             hipLaunchKernelGGL(k_big_gather, dim3(gch), dim3(BT), 0, s, a, 1, 0);
-            if (flags & XP_NANBU) hipLaunchKernelGGL(k_big_ei<true>, dim3(gch), dim3(BT), 0, s, a);
-            else hipLaunchKernelGGL(k_big_ei<false>, dim3(gch), dim3(BT), 0, s, a);
+            switch (law) {
+            case 0: hipLaunchKernelGGL(k_big_ei<0>, dim3(gch), dim3(BT), 0, s, a); break;
+            case 1: hipLaunchKernelGGL(k_big_ei<1>, dim3(gch), dim3(BT), 0, s, a); break;
+            case 2: hipLaunchKernelGGL(k_big_ei<2>, dim3(gch), dim3(BT), 0, s, a); break;
+            default: hipLaunchKernelGGL(k_big_ei<3>, dim3(gch), dim3(BT), 0, s, a); break;
+            }
             hipLaunchKernelGGL(k_big_gather, dim3(gch), dim3(BT), 0, s, a, 1, 1);
             hipLaunchKernelGGL(k_big_unstage, dim3(gch), dim3(BT), 0, s, a, 1);
         }

@@ -292,21 +292,134 @@ __device__ __forceinline__ Coll ta77(double& ax, double& ay, double& az, double&
     return out;
 }
 
+// Relativistic binary collision in the pair's centre-of-momentum frame (the
+// Monte-Carlo collision of Perez et al., Phys. Plasmas 19, 083104 (2012)):
+// momenta p = gamma m v boosted to the frame moving with v_C = (p_a + p_b)
+// c^2 / (E_a + E_b); there p_a* is turned by the angle drawn from the
+// scattering parameter
+//   s = 2 qq n m_ab^2 / (m_a g_a m_b g_b) * g_C |p*| / (m_a g_a + m_b g_b)
+//       * (m_a g_a* m_b g_b* c^2 / |p*|^2 + 1)^2 / c^4
+// (qq = coef, n = max(w) nunit; s -> 2 <delta^2> of Takizuka-Abe for v << c),
+// by Takizuka-Abe's law with <delta^2> = s / 2 or with nanbu by Nanbu's law;
+// p_b*' = -p_a*', both boosted back, v = p c / sqrt(m^2 c^2 + p^2).  Draws,
+// rotation and weighted acceptance as in ta77.  (gamma_C - 1) / v_C^2 is
+// written gamma_C^2 / ((gamma_C + 1) c^2).
+__device__ __noinline__ Coll ta77_rel(double& ax, double& ay, double& az, double& bx, double& by,
+                                      double& bz, double ma, double mb, uint32_t wa, uint32_t wb,
+                                      double coef, double nunit, const Words& d, bool nanbu)
+{
+    Coll out{-1.0, 0, 0};
+    const double c = CLIGHT, c2 = c * c;
+    const double va2 = (ax * ax + ay * ay) + az * az;
+    const double vb2 = (bx * bx + by * by) + bz * bz;
+    const double ga = 1.0 / sqrt(1.0 - va2 / c2);
+    const double gb = 1.0 / sqrt(1.0 - vb2 / c2);
+    const double pax = (ga * ma) * ax, pay = (ga * ma) * ay, paz = (ga * ma) * az;
+    const double pbx = (gb * mb) * bx, pby = (gb * mb) * by, pbz = (gb * mb) * bz;
+    const double ea = (ga * ma) * c2, eb = (gb * mb) * c2;
+    const double etot = ea + eb;
+    const double vcx = ((pax + pbx) * c2) / etot;
+    const double vcy = ((pay + pby) * c2) / etot;
+    const double vcz = ((paz + pbz) * c2) / etot;
+    const double vc2 = (vcx * vcx + vcy * vcy) + vcz * vcz;
+    const double gc = 1.0 / sqrt(1.0 - vc2 / c2);
+    const double g = (gc * gc) / ((gc + 1.0) * c2);
+    const double vpa = (vcx * pax + vcy * pay) + vcz * paz;
+    const double vpb = (vcx * pbx + vcy * pby) + vcz * pbz;
+    const double ka = g * vpa - (gc * ea) / c2;
+    const double psx = pax + ka * vcx, psy = pay + ka * vcy, psz = paz + ka * vcz;
+    const double eas = gc * (ea - vpa), ebs = gc * (eb - vpb);
+    const double p2 = (psx * psx + psy * psy) + psz * psz;
+    if (p2 == 0.0) return out;
+    const double p = sqrt(p2);
+    const double gas = eas / (ma * c2), gbs = ebs / (mb * c2);
+    const uint32_t wmax = wa > wb ? wa : wb;
+    const double mab = (ma * mb) / (ma + mb);
+    const double x = (((ma * gas) * (mb * gbs)) * c2) / p2 + 1.0;
+    const double s = ((((2.0 * coef) * ((double)wmax * nunit)) * (mab * mab)) / ((ma * ga) * (mb * gb))) *
+                     ((gc * p) / (ma * ga + mb * gb)) * ((x * x) / (c2 * c2));
+    const double d2 = 0.5 * s;
+    double st, omc;
+    if (nanbu) {
+        omc = nanbu_omc(s, u52(d.x0, d.x1));
+        st = sqrt(omc * (2.0 - omc));
+    } else {
+        double s2, cc2;
+        xsincos2pi((uint64_t)d.x1 << 20, s2, cc2);
+        const double gg = sqrt(-2.0 * xlog(u32(d.x0))) * cc2;
+        const double dl = sqrt(d2) * gg;
+        const double dd = dl * dl;
+        const double den = 1.0 + dd;
+        st = (2.0 * dl) / den;
+        omc = (2.0 * dd) / den;
+    }
+    double sp, cp;
+    xsincos2pi((uint64_t)d.x2 << 20, sp, cp);
+    const double a = st * cp;
+    const double bb = st * sp;
+    const double up = sqrt(psx * psx + psy * psy);
+    double dpx, dpy, dpz;
+    if (up > 0.0) {
+        dpx = ((psx / up) * psz) * a - ((psy / up) * p) * bb - psx * omc;
+        dpy = ((psy / up) * psz) * a + ((psx / up) * p) * bb - psy * omc;
+        dpz = -(up * a) - psz * omc;
+    } else {
+        const double apz = fabs(psz);
+        dpx = apz * a;
+        dpy = apz * bb;
+        dpz = -(psz * omc);
+    }
+    const double qax = psx + dpx, qay = psy + dpy, qaz = psz + dpz;
+    const double qbx = -qax, qby = -qay, qbz = -qaz;
+    const double vqa = (vcx * qax + vcy * qay) + vcz * qaz;
+    const double vqb = (vcx * qbx + vcy * qby) + vcz * qbz;
+    const double la = g * vqa + (gc * eas) / c2;
+    const double lb = g * vqb + (gc * ebs) / c2;
+    const double nax = qax + la * vcx, nay = qay + la * vcy, naz = qaz + la * vcz;
+    const double nbx = qbx + lb * vcx, nby = qby + lb * vcy, nbz = qbz + lb * vcz;
+    const double na2 = (nax * nax + nay * nay) + naz * naz;
+    const double nb2 = (nbx * nbx + nby * nby) + nbz * nbz;
+    const double ra = c / sqrt((ma * ma) * c2 + na2);
+    const double rb = c / sqrt((mb * mb) * c2 + nb2);
+    bool ta = true, tb = true;
+    if (wa != wb) {
+        const double r4 = u32(d.x3);
+        ta = (wa < wb) || (r4 < (double)wb / (double)wa);
+        tb = (wb < wa) || (r4 < (double)wa / (double)wb);
+    }
+    if (ta) {
+        ax = nax * ra;
+        ay = nay * ra;
+        az = naz * ra;
+    }
+    if (tb) {
+        bx = nbx * rb;
+        by = nby * rb;
+        bz = nbz * rb;
+    }
+    out.d2 = d2;
+    out.acc_a = ta;
+    out.acc_b = tb;
+    return out;
+}
+
 // One binary collision between slot e of (avx, avy, avz, aw) and slot b of
 // (bvx, bvy, bvz) with weight wb, on LDS arrays; draws from Philox counter
-// (c0, c1, idx, c3).  Counts go to cnt (XP_C_* indices).  nanbu selects
-// Nanbu's scattering law instead of Takizuka-Abe's.
+// (c0, c1, idx, c3).  Counts go to cnt (XP_C_* indices).  law: bit 0
+// Nanbu's scattering law instead of Takizuka-Abe's, bit 1 relativistic
+// kinematics (ta77_rel, with the masses ma and mb).
 __device__ __forceinline__ void collide_slots(double* avx, double* avy, double* avz, const uint32_t* aw,
                                            double* bvx, double* bvy, double* bvz, int e, int b,
                                            uint32_t wb, double fa, double fb, double coef,
                                            double nunit, uint32_t c0, uint32_t c1, uint32_t idx,
                                            uint32_t c3, uint32_t k0, uint32_t k1, int* cnt,
-                                           bool nanbu)
+                                           int law, double ma = 0.0, double mb = 0.0)
 {
     double ax = avx[e], ay = avy[e], az = avz[e];
     double bx = bvx[b], by = bvy[b], bz = bvz[b];
     const Words d = philox(c0, c1, idx, c3, k0, k1);
-    const Coll c = ta77(ax, ay, az, bx, by, bz, fa, fb, aw[e], wb, coef, nunit, d, nanbu);
+    const Coll c = (law & 2) ? ta77_rel(ax, ay, az, bx, by, bz, ma, mb, aw[e], wb, coef, nunit, d, (law & 1) != 0)
+                             : ta77(ax, ay, az, bx, by, bz, fa, fb, aw[e], wb, coef, nunit, d, (law & 1) != 0);
     if (c.d2 < 0.0) {
         atomicAdd(&cnt[XP_C_U0], 1);
         return;

@@ -628,8 +628,9 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
     // other items are adjacent pairs of the permutation.  Phase 1 is e-i:
     // round robin over the smaller population, round by round.
     const bool do_ee = (flags & XP_EE) && ne >= 2;
-    // scattering law: Takizuka-Abe, or (XP_NANBU, the Nanbu instances only) Nanbu
-    const bool nanbu = XV == 2 && (flags & XP_NANBU) != 0;
+    // scattering law bits: 1 Nanbu (else Takizuka-Abe), 2 relativistic (both
+    // only in the instances that carry the variants' code)
+    const int law = XV == 2 ? (((flags & XP_NANBU) ? 1 : 0) | ((flags & XP_REL) ? 2 : 0)) : 0;
     const bool do_ei = (flags & XP_EI) && ne >= 1 && ni >= 1;
     if ((flags & (XP_EE | XP_EI)) && ne >= 1 && (ne >= 2 || ni >= 1)) make_perm(RP_PERM_E, ne, L.perm_e);
     const double mee = (ME * ME) / (ME + ME);
@@ -691,7 +692,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
                         purpose = RP_EE;
                     }
                     collide_slots(L.evx, L.evy, L.evz, L.ew, bvx, bvy, bvz, e, bb, wb, fa, fb, coef, nunit,
-                                  step, lcell, idx, purpose << 24, key0, key1, S.cnt, nanbu);
+                                  step, lcell, idx, purpose << 24, key0, key1, S.cnt, law, ME, ion ? mi : ME);
                 }
             }
             T::sync();

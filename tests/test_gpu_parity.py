@@ -446,3 +446,33 @@ def test_recombination_selection_lds(ctx):
         assert rec == 46 + 78 + 34 + 24 + 11 + 1 + 8, rec
     # (C1 recombines a few times per cell and step from step 55 on, through
     # both paths: test_c1_parity)
+
+
+def test_relativistic_collisions(ctx):
+    # the relativistic variant of S1/S2 (XP_REL): C1 (1.35-1.5 keV source
+    # electrons), keV-hot cells under the wave, block and lane-group schedules
+    # with and without Nanbu's law, the global-memory path, a reduced C2
+    spec, parts = W.config_c1()
+    run_pair(ctx, spec, parts, 30, flags=O.ALL | O.REL, check_every=10, capacity=(3, 16),
+             label="C1/rel")
+    for sched in (1, 2, 5):
+        for law in (O.REL, O.REL | O.NANBU):
+            rng = np.random.default_rng(61)
+            ne = rng.integers(1, 14, 10)
+            ni = rng.integers(1, 7, 10)
+            spec, parts = cases.one_run(10, ne, ni, 8000.0, 5.0, seed=62, lnl=4.0, dt=0.05e-15)
+            parts.iz[:] = rng.integers(3, 12, parts.ni)
+            parts.ew[:] = rng.choice([1, 2, 3], parts.ne)
+            run_pair(ctx, spec, parts, 6, flags=O.ALL | law, check_every=2, capacity=(5, 4),
+                     schedule=sched, label="rel/%d/%d" % (sched, law))
+    run_pair(ctx, spec, parts, 6, flags=O.ALL | O.REL, check_every=3, capacity=(5, 16),
+             schedule=3, big="all", label="rel/global")
+    ne = np.array([60, 3000, 2600, 45, 0])
+    ni = np.array([50, 1500, 600, 40, 20])
+    spec, parts = cases.one_run(ne.size, ne, ni, 2000.0, 0.1, seed=98, e_weight=1, dt=0.05e-15,
+                                photon_hv=(1850.0,), photon_n=(4e29,))
+    bat, _ = run_pair(ctx, spec, parts, 4, check_every=2, label="oversized/rel",
+                      flags=O.ALL | O.REL | O.NANBU)
+    assert bat.stats()[2] == 2
+    spec, parts = W.config_c2(nx=6, ny=6)
+    run_pair(ctx, spec, parts, 10, flags=O.ALL | O.REL, check_every=5, label="C2r/rel")
