@@ -29,6 +29,7 @@ THERM = 0x40   # variant: forced thermalization after S5 (Sec. VI.C), not in ALL
 ION_Z = 0x80   # variant: S3 cross section per ion charge state (Sec. IV), not in ALL
 NANBU = 0x100  # variant: Nanbu's cumulative scattering law in S1, S2, not in ALL
 REL = 0x200    # variant: relativistic binary collisions in S1, S2, not in ALL
+REC_XS = 0x400  # variant: S4 per ion from the Lotz rate by detailed balance, not in ALL
 
 COUNTERS = ["EE", "EI", "TRIPLET", "ACCEPT", "U0", "DELTA2_GT1",
             "ION_FIRED", "ION_ACCEPTED", "ION_STARVED",
@@ -115,6 +116,8 @@ def lib():
         L.orc_collide.restype = d
         L.orc_collide.argtypes = [vp, vp, d, d, u32, u32, d, d, vp, i32, vp, vp]
         L.orc_nanbu_a.restype = d; L.orc_nanbu_a.argtypes = [d]
+        L.orc_e1x.restype = d; L.orc_e1x.argtypes = [d]
+        L.orc_rec_xs.restype = d; L.orc_rec_xs.argtypes = [vp, i32, d, d, vp, d]
         L.orc_nanbu_omc.restype = d; L.orc_nanbu_omc.argtypes = [d, d]
         L.orc_u32.restype = d; L.orc_u32.argtypes = [u32]
         L.orc_create.restype = vp; L.orc_create.argtypes = [vp, vp]
@@ -265,6 +268,10 @@ class Tables:
     def photo_sigma(self, s, hv):
         return lib().orc_photo_sigma(C.byref(self.s), int(s), float(hv))
 
+    def rec_xs(self, z, t_ev, n_e, dE, dt):
+        d = np.ascontiguousarray(dE, dtype=np.float64)
+        return lib().orc_rec_xs(C.byref(self.s), int(z), float(t_ev), float(n_e), _p(d), float(dt))
+
 
 def u32(x):
     return lib().orc_u32(int(x))
@@ -289,6 +296,11 @@ def collide(va, vb, ma, mb, wa, wb, coef, nunit, draws, law):
     d2 = lib().orc_collide(_p(va), _p(vb), float(ma), float(mb), int(wa), int(wb),
                            float(coef), float(nunit), _p(d), int(law), C.byref(aa), C.byref(ab))
     return va, vb, d2, aa.value, ab.value
+
+
+def e1x(x):
+    """exp(x) E1(x)."""
+    return lib().orc_e1x(float(x))
 
 
 def nanbu_a(s):

@@ -44,6 +44,7 @@ extern "C" {
 #define ORC_ION_Z   0x80u   /* variant: S3 cross section per ion charge state (Sec. IV) */
 #define ORC_NANBU   0x100u  /* variant: Nanbu's cumulative scattering law in S1, S2 */
 #define ORC_REL     0x200u  /* variant: relativistic binary collisions in S1, S2 */
+#define ORC_REC_XS  0x400u  /* variant: S4 per ion from the Lotz rate by detailed balance */
 
 /* Per-cell, per-step event counters. */
 enum {
@@ -133,6 +134,14 @@ double orc_collide(double va[3], double vb[3], double ma, double mb, uint32_t wa
 double orc_collide_rel(double va[3], double vb[3], double ma, double mb, uint32_t wa,
                        uint32_t wb, double qq_coef, double nunit, const uint32_t draws[4],
                        int32_t nanbu, int32_t *acc_a, int32_t *acc_b);
+/* exp(x) E1(x) for x > 0 (E1 the exponential integral). */
+double orc_e1x(double x);
+/* Probability per step dt (s) that an ion of charge z recombines to z - 1 by
+ * three-body recombination at electron temperature tev (eV) and density n_e
+ * (m^-3), the inverse of the Lotz ionization of z - 1 by detailed balance
+ * (not clamped). */
+double orc_rec_xs(const orc_tables *t, int32_t z, double tev, double n_e, const double dE[13],
+                  double dt);
 double orc_nanbu_a(double s);
 double orc_nanbu_omc(double s, double u);
 

@@ -111,6 +111,90 @@ double orc_lotz(const orc_tables *t, int32_t zc, const double dE[13], double e)
     return sig;
 }
 
+/*
+ * exp(x) E1(x), x > 0.  E1(x) = -gamma - ln x - sum_{k>=1} (-x)^k / (k k!) for
+ * x <= 1 (24 terms), and for x > 1 the continued fraction
+ * E1(x) = exp(-x) / (x + 1 - 1/(x + 3 - 4/(x + 5 - 9/(x + 7 - ...)))) evaluated
+ * backward from depth 80 (Abramowitz & Stegun 5.1.22 contracted).
+ * Pinned against scipy.special.exp1 by tests/test_oracle_recxs.py.
+ */
+double orc_e1x(double x)
+{
+    if (x <= 1.0) {
+        double sum = 0.0, term = 1.0;
+        for (int k = 1; k <= 24; ++k) {
+            term = (term * (-x)) / (double)k;
+            sum = sum + term / (double)k;
+        }
+        double e1 = (-0.57721566490153286 - orc_log(x)) - sum;
+        return orc_exp(x) * e1;
+    }
+    double t = x + 161.0;
+    for (int k = 80; k >= 1; --k) t = (x + (double)(2 * k - 1)) - (double)(k * k) / t;
+    return 1.0 / t;
+}
+
+/* Degeneracy of the ground configuration of charge state z: the product over
+ * subshells of C(capacity, occupancy). */
+static double ground_degeneracy(int32_t z)
+{
+    static const int cap[ORC_NSUB] = {2, 2, 6, 2, 6};
+    int occ[ORC_NSUB];
+    orc_occupancy(z, 0, occ);
+    double g = 1.0;
+    for (int s = 0; s < ORC_NSUB; ++s) {
+        double c = 1.0;
+        for (int j = 0; j < occ[s]; ++j) c = (c * (double)(cap[s] - j)) / (double)(j + 1);
+        g = g * c;
+    }
+    return g;
+}
+
+/*
+ * Three-body recombination z -> z-1 from cross sections (Sec. IV names it as
+ * the model's next step).  Detailed balance with the collisional ionization
+ * of z-1 (Lotz, Eq. 4):  the recombination rate per ion of charge z is
+ * S_{z-1}(T) n_e^2 / Phi_z(T), where
+ *   S_{z-1} = sum_s a_s N_s vbar / (P_s T) [E1(x_s) - b_s e^{c_s} x_s / (x_s + c_s) E1(x_s + c_s)],
+ *     x_s = P_s / T, over the occupied subshells of the ground configuration of
+ *     z - 1 with their lowered bindings P_s, vbar = sqrt(8 k T / (pi m_e)),
+ *   Phi_z = 2 (g_z / g_{z-1}) (m_e k T / (2 pi hbar^2))^{3/2} exp(-P_v / T),
+ *     the Saha factor with the lowered binding P_v of the valence subshell of
+ *     z - 1 and ground-configuration degeneracies g.
+ * The probability per step is that rate times dt.  Both exponentials are
+ * folded together: S e^{x_v} uses exp(x) E1(x) and e^{x_v - x_s} <= 1.
+ */
+double orc_rec_xs(const orc_tables *t, int32_t z, double tev, double n_e, const double dE[13],
+                  double dt)
+{
+    if (z < 1 || z > ORC_ZMAX || !(n_e > 0.0) || !(tev > 0.0)) return 0.0;
+    int zl = z - 1;
+    int occ[ORC_NSUB];
+    orc_occupancy(zl, 0, occ);
+    int v = orc_valence(zl, 0);
+    double pv = t->bind[zl][v] - dE[zl];
+    if (pv < 1.0) pv = 1.0;
+    double xv = pv / tev;
+    double vbar = sqrt((8.0 * (tev * ORC_QE)) / (ORC_PI * ORC_ME));
+    double sum = 0.0;
+    for (int s = 0; s < ORC_NSUB; ++s) {
+        if (occ[s] <= 0) continue;
+        double p = t->bind[zl][s] - dE[zl];
+        if (p < 1.0) p = 1.0;
+        double x = p / tev;
+        double br = orc_e1x(x);
+        if (t->lotz_b[s] != 0.0) {
+            double c = t->lotz_c[s];
+            br = br - (t->lotz_b[s] * (x / (x + c))) * orc_e1x(x + c);
+        }
+        double term = ((((t->lotz_a[s] * 1.0e-4) * (double)occ[s]) * vbar) / (p * tev)) * (br * orc_exp(xv - x));
+        sum = sum + term;
+    }
+    double q = (ORC_ME * (tev * ORC_QE)) / ((2.0 * ORC_PI) * (ORC_HBAR * ORC_HBAR));
+    double phi0 = (2.0 * (ground_degeneracy(z) / ground_degeneracy(zl))) * (q * sqrt(q));
+    return ((sum * (n_e * n_e)) * dt) / phi0;
+}
+
 /* Zbar_EOS(n_i, T): bilinear in (ln n_i, ln T) on the table grid, clamped. */
 double orc_eos(const orc_tables *t, double n_i, double tev)
 {

@@ -12,7 +12,9 @@
  *   S3 collisional ionization against the average cell ion with the Lotz cross
  *      section (Eq. 4) and the energy debit of Sec. IV; with ORC_ION_Z every
  *      ion's probability uses the cross section of its own charge state.
- *   S4 three-body recombination constrained by Zbar_EOS(n_i, T_e) (Sec. IV).
+ *   S4 three-body recombination constrained by Zbar_EOS(n_i, T_e) (Sec. IV),
+ *      or (ORC_REC_XS) per ion from the rate that detailed balance gives the
+ *      inverse of the Lotz ionization (orc_rec_xs).
  *   S5 K-vacancy decay with Auger / K-alpha branching and subshell
  *      photoionization (Eq. 3) (Sec. III).
  *   Optionally (ORC_THERM) the forced thermalization of Sec. VI.C right after
@@ -37,7 +39,7 @@
  * words decide collisional ionization and the photo events of 1s, 2s, 2p. */
 enum { P_PERM_E = 1, P_PERM_I = 2, P_REC_I = 3, P_REC_E = 4, P_EE = 5,
        P_EE_TRI = 6, P_EI = 7, P_ION = 8, P_DECAY = 9, P_DIR = 10, P_BIN = 11,
-       P_THERM = 12 };
+       P_THERM = 12, P_REC_XS = 13 };
 
 #define NMOM 32
 
@@ -708,24 +710,58 @@ static void step_cell(cctx *x, ocell *c, uint32_t flags)
             if (tp < 0.01) tp = 0.01;
         }
         m[15] = tp;
-        double n_i = ((double)ni * r->w0) / r->volume;
-        double zeos = orc_eos(t, n_i, tp);
-        double dd = (double)sz - (double)ni * zeos;
-        if (dd > 0.0) {
-            int64_t nrec = (int64_t)floor(dd + 0.5);
-            int nelig = 0;
-            for (int j = 0; j < ni; ++j) nelig += c->iz[j] > r->z_floor;
-            if (nrec > nelig) nrec = nelig;
-            if (nrec > ne) nrec = ne;
-            if (nrec > 0) {
-                make_perm(x, P_REC_I, ni, x->perm_i);
-                make_perm(x, P_REC_E, ne, x->perm_b);
-                int *sel_i = x->perm_a;          /* reuse: chosen ions in order */
-                int got = 0;
-                for (int q = 0; q < ni && got < nrec; ++q) {
-                    int i = x->perm_i[q];
-                    if (c->iz[i] > r->z_floor) sel_i[got++] = i;
+        int64_t nrec = 0;
+        int *sel_i = x->perm_a;          /* reuse: chosen ions in order */
+        if (flags & ORC_REC_XS) {
+            /* per ion from its own charge state's rate (orc_rec_xs) at the
+             * temperature and electron density after S3: every ion with
+             * Z > z_floor draws U32(word 0 of its REC_XS call) against its
+             * probability; the firing ions recombine in slot order, at most
+             * one per electron */
+            double n_e = ((double)we * r->w0) / r->volume;
+            double prec[ORC_ZMAX + 1];
+            int held[ORC_ZMAX + 1] = {0};
+            for (int j = 0; j < ni; ++j) held[c->iz[j]] = 1;
+            for (int z = 0; z <= ORC_ZMAX; ++z) {
+                prec[z] = 0.0;
+                if (!held[z] || z <= r->z_floor || z < 1) continue;
+                double pz = orc_rec_xs(t, z, tp, n_e, dE, r->dt);
+                if (pz > 1.0) {
+                    pz = 1.0;
+                    x->cnt[OC_P_CLAMPED]++;
                 }
+                prec[z] = pz;
+            }
+            for (int i = 0; i < ni && nrec < ne; ++i) {
+                int z = c->iz[i];
+                if (z <= r->z_floor || !(prec[z] > 0.0)) continue;
+                uint32_t d[4];
+                rng(x, (uint32_t)i, P_REC_XS, 0, d);
+                if (orc_u32(d[0]) < prec[z]) sel_i[nrec++] = i;
+            }
+        } else {
+            double n_i = ((double)ni * r->w0) / r->volume;
+            double zeos = orc_eos(t, n_i, tp);
+            double dd = (double)sz - (double)ni * zeos;
+            if (dd > 0.0) {
+                nrec = (int64_t)floor(dd + 0.5);
+                int nelig = 0;
+                for (int j = 0; j < ni; ++j) nelig += c->iz[j] > r->z_floor;
+                if (nrec > nelig) nrec = nelig;
+                if (nrec > ne) nrec = ne;
+                if (nrec > 0) {
+                    make_perm(x, P_REC_I, ni, x->perm_i);
+                    int got = 0;
+                    for (int q = 0; q < ni && got < nrec; ++q) {
+                        int i = x->perm_i[q];
+                        if (c->iz[i] > r->z_floor) sel_i[got++] = i;
+                    }
+                }
+            }
+        }
+        {
+            if (nrec > 0) {
+                make_perm(x, P_REC_E, ne, x->perm_b);
                 uint32_t *wp = malloc(sizeof(uint32_t) * (size_t)ne);
                 for (int j = 0; j < ne; ++j) wp[j] = c->ew[j];
                 for (int q = 0; q < nrec; ++q) wp[x->perm_b[q]] -= 1;
