@@ -94,6 +94,20 @@ typedef int32_t xp_status;
  * and both momenta are boosted back.  Pairing, draws and weighted acceptance
  * are unchanged; the other stages keep their non-relativistic energies. */
 #define XP_REL     0x200u
+/* Variant, not part of XP_ALL: three-body recombination (S4) from cross
+ * sections instead of the EOS constraint (Sec. IV names it as the model's
+ * next step).  The rate per ion of charge Z is the inverse of the Lotz
+ * ionization of Z-1 by detailed balance: S_{Z-1}(T) n_e^2 / Phi_Z(T), S the
+ * Maxwellian Lotz rate of the ground configuration of Z-1 with lowered
+ * bindings (Eq. 4 and its exponential-integral closed form), Phi_Z the Saha
+ * factor 2 (g_Z / g_{Z-1}) (m_e k T / (2 pi hbar^2))^{3/2} exp(-P_v / T) with
+ * ground-configuration degeneracies g and the lowered valence binding P_v of
+ * Z-1; T and n_e of the electrons after S3.  Each ion with Z > z_floor fires
+ * when U32(word 0 of its Philox call, purpose 13) is below that probability
+ * times dt (clamped at 1); the firing ions recombine in slot order with the
+ * electrons of the REC_E permutation, at most one per electron, with S4's
+ * energy bookkeeping and rescale. */
+#define XP_REC_XS  0x400u
 
 /* Device status bits (xp_batch.d_status, OR-ed by kernels). */
 #define XP_ST_CAPACITY  0x1u   /* a cell needed more electron slots than its capacity */

@@ -22,6 +22,7 @@ XP_THERM = 0x40   # variant: forced thermalization after S5 (Sec. VI.C), not in 
 XP_ION_Z = 0x80   # variant: S3 cross section per ion charge state (Sec. IV), not in XP_ALL
 XP_NANBU = 0x100  # variant: Nanbu's cumulative scattering law in e-e and e-i, not in XP_ALL
 XP_REL = 0x200    # variant: relativistic binary collisions in e-e and e-i, not in XP_ALL
+XP_REC_XS = 0x400  # variant: recombination from cross sections by detailed balance, not in XP_ALL
 XP_ST_CAPACITY, XP_ST_NONFINITE, XP_ST_BIN_SIZE, XP_ST_RUN_TABLE = 0x1, 0x2, 0x4, 0x8
 XP_NCOUNT, XP_NLEDGER, XP_NMOM, XP_MAX_BINS = 24, 8, 32, 16
 XP_NSTATS = 68

@@ -403,7 +403,8 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
         }
         // the variants, per-cell records and per-cell photon fields are
         // compiled into their own kernels
-        const bool xv = (flags & (XP_THERM | XP_ION_Z | XP_NANBU | XP_REL)) != 0 || b->d_cell_counters || b->d_cell_ledger ||
+        const bool xv = (flags & (XP_THERM | XP_ION_Z | XP_NANBU | XP_REL | XP_REC_XS)) != 0 || b->d_cell_counters ||
+                        b->d_cell_ledger ||
                         b->d_cell_moments || b->d_cell_nhv || b->d_cell_nabs;
         for (int tier = 0;; ++tier) {
             const bool last = ce >= ce_top || tier >= xpd::BIG_COUNT_SLOT - 1;
@@ -492,7 +493,7 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
 xp_status collide_ionize_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, void* stream)
 {
     if (!p) return fail(XP_ERR_INVALID_ARG, "null step parameters");
-    return launch_step(ctx, b, p, p->flags & (XP_ALL | XP_THERM | XP_ION_Z | XP_NANBU | XP_REL), stream);
+    return launch_step(ctx, b, p, p->flags & (XP_ALL | XP_THERM | XP_ION_Z | XP_NANBU | XP_REL | XP_REC_XS), stream);
 }
 
 xp_status collide_ionize_step_static(xp_ctx* ctx, const xp_batch* b, const xp_step_params* p, void* stream)
@@ -515,7 +516,7 @@ xp_status collide_ionize_step_static(xp_ctx* ctx, const xp_batch* b, const xp_st
     xp_batch v = *b;
     v.d_work = ptr;
     v.work_bytes = (size_t)XP_STATIC_SCRATCH_BYTES;
-    return launch_step(ctx, &v, p, p->flags & (XP_ALL | XP_THERM | XP_ION_Z | XP_NANBU | XP_REL), stream);
+    return launch_step(ctx, &v, p, p->flags & (XP_ALL | XP_THERM | XP_ION_Z | XP_NANBU | XP_REL | XP_REC_XS), stream);
 }
 
 xp_status photo_auger_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, void* stream)

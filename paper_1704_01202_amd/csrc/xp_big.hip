@@ -96,6 +96,7 @@ __global__ void k_big_init(BigArgs a)
         r.need = 0;
         r.zc = 0;
         r.zmask = r.zeval = 0;
+        r.zmask4 = 0;
         r.acc = 0;
         r.nrec = 0;
         r.epn = 0;
@@ -882,13 +883,13 @@ __global__ __launch_bounds__(BT) void k_big_fire(BigArgs a)
 
 // Per-cell exclusive scan of the ion-chunk counts in ccnt.  mode 0: fired
 // ions of S3; 1: recombination-eligible ranks of S4; 2: electrons appended by
-// S5 (with the capacity check).
+// S5 (with the capacity check); 3: ions firing in S4 (XP_REC_XS).
 __global__ __launch_bounds__(BT) void k_big_cscan(BigArgs a, int mode)
 {
     __shared__ int red[BT / 64];
     const int tid = threadIdx.x;
     const int nb = a.hdr->count;
-    const int needbit = mode == 0 ? BN_ION : (mode == 1 ? BN_REC : 0);
+    const int needbit = mode == 0 ? BN_ION : ((mode == 1 || mode == 3) ? BN_REC : 0);
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
         BigRec& r = a.rec[b];
         if (r.state || (needbit && !(r.need & needbit))) continue;
@@ -905,6 +906,11 @@ __global__ __launch_bounds__(BT) void k_big_cscan(BigArgs a, int mode)
             if (mode == 0) {
                 r.cnt[XP_C_ION_FIRED] += carry;
                 if (carry > 0) r.need |= BN_FIRED;
+            } else if (mode == 3) {
+                // XP_REC_XS: the firing ions recombine in slot order, at most
+                // one per electron
+                r.nrec = carry < r.ne ? carry : r.ne;
+                if (r.nrec == 0) r.need &= ~BN_REC;
             } else if (mode == 2) {
                 if ((long long)r.ne + carry > (long long)r.ecap) {
                     r.state = 1;
@@ -1208,13 +1214,16 @@ __global__ __launch_bounds__(BT) void k_big_s4part(BigArgs a)
         const int n = r.ni - base < BIG_CH ? r.ni - base : BIG_CH;
         const int64_t o = r.io + base;
         long long s1 = 0, el = 0;
+        uint32_t ml = 0;
         for (int j = tid; j < n; j += BT) {
             const int z = s.iz[o + j];
             s1 += z;
             el += z > zf ? 1 : 0;
+            ml |= 1u << z;
         }
         s1 = block_isum<BT>(s1, ired);
         el = block_isum<BT>(el, ired);
+        if (ml) atomicOr(&r.zmask4, ml);
         if (tid == 0) {
             atomicAdd(&r.sz4, (unsigned long long)s1);
             atomicAdd(&r.nelig, (unsigned long long)el);
@@ -1225,6 +1234,8 @@ __global__ __launch_bounds__(BT) void k_big_s4part(BigArgs a)
 __global__ __launch_bounds__(BT) void k_big_s4fin(BigArgs a)
 {
     __shared__ double red[2 * (BIG_MAX_CHUNKS / 64)];
+    __shared__ double tps;
+    __shared__ int any, clamped;
     const StepArgs& s = a.s;
     const int nb = a.hdr->count;
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
@@ -1242,21 +1253,56 @@ __global__ __launch_bounds__(BT) void k_big_s4fin(BigArgs a)
                 if (tp < 0.01) tp = 0.01;
             }
             r.mom[15] = tp;
-            const double n_i = ((double)ni * R.w0) / R.volume;
-            const double zeos = eos_zbar(s.tab, n_i, tp);
-            const double dd = (double)(long long)r.sz4 - (double)ni * zeos;
-            if (dd > 0.0) {
-                long long nrec = (long long)floor(dd + 0.5);
-                if (nrec > (long long)r.nelig) nrec = (long long)r.nelig;
-                if (nrec > ne) nrec = ne;
-                if (nrec > 0) {
-                    r.nrec = (int32_t)nrec;
-                    r.need |= BN_REC;
-                    r.ws = 0;
+            tps = tp;
+            any = 0;
+            clamped = 0;
+            if (!(s.flags & XP_REC_XS)) {
+                const double n_i = ((double)ni * R.w0) / R.volume;
+                const double zeos = eos_zbar(s.tab, n_i, tp);
+                const double dd = (double)(long long)r.sz4 - (double)ni * zeos;
+                if (dd > 0.0) {
+                    long long nrec = (long long)floor(dd + 0.5);
+                    if (nrec > (long long)r.nelig) nrec = (long long)r.nelig;
+                    if (nrec > ne) nrec = ne;
+                    if (nrec > 0) {
+                        r.nrec = (int32_t)nrec;
+                        r.need |= BN_REC;
+                        r.ws = 0;
+                    }
                 }
             }
         }
         __syncthreads();
+        if (s.flags & XP_REC_XS) {
+            // per charge state held by an ion: the recombination probability
+            // at the temperature and electron density after S3; the ions
+            // draw in k_big_recfire
+            const double tp = tps;
+            const double ne4 = ((double)(long long)r.we4 * R.w0) / R.volume;
+            const int zf = R.z_floor;
+            const int z = threadIdx.x;
+            if (z < 14) {
+                double pz = 0.0;
+                if ((r.zmask4 & (1u << z)) && z > zf && z >= 1) {
+                    pz = rec_xs_prob(s.tab, z, tp, ne4, r.mom + 16, R.dt);
+                    if (pz > 1.0) {
+                        pz = 1.0;
+                        atomicAdd(&clamped, 1);
+                    }
+                }
+                r.prz[z] = pz;
+                if (pz > 0.0) atomicOr(&any, 1);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                r.cnt[XP_C_P_CLAMPED] += clamped;
+                if (any) {
+                    r.need |= BN_REC;
+                    r.ws = 0;
+                }
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -1292,6 +1338,57 @@ __global__ __launch_bounds__(BT) void k_big_recsel(BigArgs a, int pass)
                 },
                 red);
         }
+    }
+}
+
+// XP_REC_XS: every ion with Z > z_floor draws U32(word 0 of its REC_XS call)
+// against the probability of its charge state; the firing ions per chunk go
+// to ccnt (scanned per cell by k_big_cscan mode 3).
+__global__ __launch_bounds__(BT) void k_big_recfire(BigArgs a)
+{
+    __shared__ long long ired[BT / 64];
+    const int tid = threadIdx.x;
+    const StepArgs& s = a.s;
+    const int nci = a.hdr->n_i_chunks;
+    for (int g = blockIdx.x; g < nci; g += gridDim.x) {
+        BigRec& r = a.rec[a.i_chunk_cell[g]];
+        if (!big_live(r, BN_REC)) continue;
+        const int zf = s.runs[r.run].z_floor;
+        const int base = (g - r.ci0) * BIG_CH;
+        const int n = r.ni - base < BIG_CH ? r.ni - base : BIG_CH;
+        long long c = 0;
+        for (int q = tid; q < n; q += BT) {
+            const int i = base + q;
+            const int z = s.iz[r.io + i];
+            bool f = false;
+            if (z > zf && r.prz[z] > 0.0) f = u32(draw(s, r, (uint32_t)i, RP_REC_XS, 0).x0) < r.prz[z];
+            a.iflag[r.ip0 + i] = f ? 1 : 0;
+            c += f ? 1 : 0;
+        }
+        c = block_isum<BT>(c, ired);
+        if (tid == 0) a.ccnt[g] = (int32_t)c;
+    }
+}
+
+// XP_REC_XS: the firing ions in slot order, sel[ip0 + rank] for ranks below
+// the cell's recombination count.
+__global__ __launch_bounds__(BT) void k_big_recfirelist(BigArgs a)
+{
+    __shared__ int red[BT / 64];
+    const int nci = a.hdr->n_i_chunks;
+    for (int g = blockIdx.x; g < nci; g += gridDim.x) {
+        const BigRec& r = a.rec[a.i_chunk_cell[g]];
+        if (!big_live(r, BN_REC)) continue;
+        const int cb = a.ccnt[g];
+        if (cb >= r.nrec) continue;
+        const int base = (g - r.ci0) * BIG_CH;
+        const int n = r.ni - base < BIG_CH ? r.ni - base : BIG_CH;
+        block_ordered_select<BT>(
+            n, [&](int q) { return a.iflag[r.ip0 + base + q] != 0; },
+            [&](int q, int pos) {
+                if (cb + pos < r.nrec) a.sel[r.ip0 + cb + pos] = base + q;
+            },
+            red);
     }
 }
 
@@ -2099,13 +2196,22 @@ hipError_t big_launch(BigArgs& a, bool all_cells, hipStream_t s)
         hipLaunchKernelGGL(k_big_plan, dim3(1), dim3(1024), 0, s, a, 0);
         hipLaunchKernelGGL(k_big_s4part, dim3(gch), dim3(BT), 0, s, a);
         hipLaunchKernelGGL(k_big_s4fin, dim3(gcell), dim3(BT), 0, s, a);
-        if ((e = big_sort(a, 1, BN_REC, RP_REC_I, a.key_c, a.val_c, a.key_b, a.val_b, gch, gcell, s)) != hipSuccess)
-            return e;
-        if ((e = big_sort(a, 0, BN_REC, RP_REC_E, a.key_a, a.val_a, a.key_b, a.val_b, gch, gcell, s)) != hipSuccess)
-            return e;
-        hipLaunchKernelGGL(k_big_recsel, dim3(gch), dim3(BT), 0, s, a, 0);
-        hipLaunchKernelGGL(k_big_cscan, dim3(gcell), dim3(BT), 0, s, a, 1);
-        hipLaunchKernelGGL(k_big_recsel, dim3(gch), dim3(BT), 0, s, a, 1);
+        if (flags & XP_REC_XS) {
+            // the ions by their own draws, in slot order
+            hipLaunchKernelGGL(k_big_recfire, dim3(gch), dim3(BT), 0, s, a);
+            hipLaunchKernelGGL(k_big_cscan, dim3(gcell), dim3(BT), 0, s, a, 3);
+            hipLaunchKernelGGL(k_big_recfirelist, dim3(gch), dim3(BT), 0, s, a);
+            if ((e = big_sort(a, 0, BN_REC, RP_REC_E, a.key_a, a.val_a, a.key_b, a.val_b, gch, gcell, s)) != hipSuccess)
+                return e;
+        } else {
+            if ((e = big_sort(a, 1, BN_REC, RP_REC_I, a.key_c, a.val_c, a.key_b, a.val_b, gch, gcell, s)) != hipSuccess)
+                return e;
+            if ((e = big_sort(a, 0, BN_REC, RP_REC_E, a.key_a, a.val_a, a.key_b, a.val_b, gch, gcell, s)) != hipSuccess)
+                return e;
+            hipLaunchKernelGGL(k_big_recsel, dim3(gch), dim3(BT), 0, s, a, 0);
+            hipLaunchKernelGGL(k_big_cscan, dim3(gcell), dim3(BT), 0, s, a, 1);
+            hipLaunchKernelGGL(k_big_recsel, dim3(gch), dim3(BT), 0, s, a, 1);
+        }
         hipLaunchKernelGGL(k_big_wp, dim3(gch), dim3(BT), 0, s, a);
         hipLaunchKernelGGL(k_big_wpdec, dim3(gch), dim3(BT), 0, s, a);
         hipLaunchKernelGGL(k_big_drift, dim3(gch), dim3(BT), 0, s, a, 1);

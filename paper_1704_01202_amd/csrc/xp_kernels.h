@@ -167,6 +167,8 @@ struct BigRec {
     double p, kth, debit, alpha;
     double u[3];
     uint32_t zmask, zeval;             // charge states held by ions (< 13); evaluated in S3
+    uint32_t zmask4, pad1;             // charge states held by ions before S4 (XP_REC_XS)
+    double prz[14];                    // S4 recombination probability per charge state (XP_REC_XS)
     double ppz[13][5], lnpz[13][5];    // S3 lowered bindings and their logarithms per state
     double pz[13];                     // S3 probability per evaluated state
     double mom[XP_NMOM];

@@ -138,6 +138,77 @@ __device__ __forceinline__ double lowered(const DevTables* tb, int z, int s, con
     return p < 1.0 ? 1.0 : p;
 }
 
+// exp(x) E1(x) for x > 0: the series -gamma - ln x - sum (-x)^k / (k k!) to
+// k = 24 for x <= 1, the contracted continued fraction
+// E1 = exp(-x) / (x + 1 - 1/(x + 3 - 4/(x + 5 - ...))) from depth 80 above.
+__device__ __noinline__ double e1x(double x)
+{
+    if (x <= 1.0) {
+        double sum = 0.0, term = 1.0;
+        for (int k = 1; k <= 24; ++k) {
+            term = (term * (-x)) / (double)k;
+            sum = sum + term / (double)k;
+        }
+        const double e1 = (-0.57721566490153286 - xlog(x)) - sum;
+        return xexp(x) * e1;
+    }
+    double t = x + 161.0;
+    for (int k = 80; k >= 1; --k) t = (x + (double)(2 * k - 1)) - (double)(k * k) / t;
+    return 1.0 / t;
+}
+
+// Degeneracy of the ground configuration of charge state z: the product over
+// subshells of C(capacity, occupancy).
+__device__ __forceinline__ double ground_degeneracy(int z)
+{
+    const Occ o = occupancy(z, 0);
+    const int cap[5] = {2, 2, 6, 2, 6};
+    double g = 1.0;
+    for (int s = 0; s < 5; ++s) {
+        double c = 1.0;
+        for (int j = 0; j < o.s[s]; ++j) c = (c * (double)(cap[s] - j)) / (double)(j + 1);
+        g = g * c;
+    }
+    return g;
+}
+
+// Three-body recombination z -> z-1 per step dt (XP_REC_XS): detailed balance
+// with the Lotz ionization of z-1 (Eq. 4), S_{z-1}(T) n_e^2 dt / Phi_z(T),
+// S the Maxwellian rate of the occupied subshells of the ground configuration
+// of z-1 with their lowered bindings, Phi_z = 2 (g_z / g_{z-1})
+// (m_e k T / (2 pi hbar^2))^{3/2} exp(-P_v / T) with the lowered binding P_v
+// of its valence subshell.  S e^{P_v/T} is formed from exp(x) E1(x) and
+// exp(x_v - x_s) <= 1, so nothing overflows.  Not clamped.
+__device__ __noinline__ double rec_xs_prob(const DevTables* tb, int z, double tev, double n_e,
+                                           const double* dE, double dt)
+{
+    if (z < 1 || z > 13 || !(n_e > 0.0) || !(tev > 0.0)) return 0.0;
+    const int zl = z - 1;
+    const Occ o = occupancy(zl, 0);
+    const int v = valence(zl, 0);
+    double pv = tb->bind[zl][v] - dE[zl];
+    if (pv < 1.0) pv = 1.0;
+    const double xv = pv / tev;
+    const double vbar = sqrt((8.0 * (tev * QE)) / (PI * ME));
+    double sum = 0.0;
+    for (int s = 0; s < 5; ++s) {
+        if (o.s[s] <= 0) continue;
+        double p = tb->bind[zl][s] - dE[zl];
+        if (p < 1.0) p = 1.0;
+        const double x = p / tev;
+        double br = e1x(x);
+        if (tb->lotz_b[s] != 0.0) {
+            const double c = tb->lotz_c[s];
+            br = br - (tb->lotz_b[s] * (x / (x + c))) * e1x(x + c);
+        }
+        const double term = ((((tb->lotz_a[s] * 1.0e-4) * (double)o.s[s]) * vbar) / (p * tev)) * (br * xexp(xv - x));
+        sum = sum + term;
+    }
+    const double q = (ME * (tev * QE)) / ((2.0 * PI) * (HBAR * HBAR));
+    const double phi0 = (2.0 * (ground_degeneracy(z) / ground_degeneracy(zl))) * (q * sqrt(q));
+    return ((sum * (n_e * n_e)) * dt) / phi0;
+}
+
 struct Coll {
     double d2;        // <delta^2>, or -1 when the relative velocity is zero
     int acc_a, acc_b;

@@ -37,6 +37,7 @@ struct CellSharedT {
     double sig[XP_MAX_BINS][3];
     double ssum[13][3];
     double pz[13];        // S3 probability per evaluated charge state
+    double prz[14];       // S4 (XP_REC_XS) recombination probability per charge state
     double lnp[5];        // S3 logarithms of the lowered bindings, one per subshell
     double dbl[8];
     int ints[8];
@@ -864,19 +865,71 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
         // Zbar_EOS: its two logarithms on two threads, shared through LDS
         if (tid < 2) S.dbl[2 + tid] = xlog(tid == 0 ? n_i : tp);
         T::sync();
-        const double zeos = eos_zbar_ln(tb, S.dbl[2], S.dbl[3]);
-        const double dd = (double)szr - (double)ni * zeos;
-        if (dd > 0.0) {
-            long long nrec = (long long)floor(dd + 0.5);
-            long long el = 0;
-            for (int j = tid; j < ni; j += B) el += L.iz[j] > R->z_floor ? 1 : 0;
-            const long long nelig = T::isum(el, S);
-            if (nrec > nelig) nrec = nelig;
-            if (nrec > ne) nrec = ne;
+        const int zf = R->z_floor;
+        long long nrec = 0;
+        bool ions_listed = false;
+        if (XV && (flags & XP_REC_XS)) {
+            // per ion from its own charge state's rate (detailed balance with
+            // the Lotz ionization) at the temperature and electron density
+            // after S3; the firing ions recombine in slot order, at most one
+            // per electron
+            long long wel = 0;
+            for (int j = tid; j < ne; j += B) wel += L.ew[j];
+            const long long we4 = T::isum(wel, S);
+            const double ne4 = ((double)we4 * w0) / vol;
+            uint32_t ml = 0;
+            for (int i = tid; i < ni; i += B) ml |= 1u << L.iz[i];
+            if (ml) atomicOr((unsigned*)&S.ints[3], ml);
+            T::sync();
+            const uint32_t held = (uint32_t)S.ints[3];
+            for (int z = tid; z < 14; z += B) {
+                double pz = 0.0;
+                if ((held & (1u << z)) && z > zf && z >= 1) {
+                    pz = rec_xs_prob(tb, z, tp, ne4, dE, dt);
+                    if (pz > 1.0) {
+                        pz = 1.0;
+                        atomicAdd(&S.cnt[XP_C_P_CLAMPED], 1);
+                    }
+                }
+                S.prz[z] = pz;
+            }
+            T::sync();
+            const int nf = T::select(
+                ni,
+                [&](int i) {
+                    const int z = L.iz[i];
+                    if (z <= zf || !(S.prz[z] > 0.0)) return false;
+                    return u32(rng((uint32_t)i, RP_REC_XS, 0).x0) < S.prz[z];
+                },
+                [&](int i, int pos) {
+                    if (pos < ne) L.list[pos] = i;
+                },
+                S);
+            nrec = nf < ne ? nf : ne;
+            ions_listed = true;
+        } else {
+            const double zeos = eos_zbar_ln(tb, S.dbl[2], S.dbl[3]);
+            const double dd = (double)szr - (double)ni * zeos;
+            if (dd > 0.0) {
+                nrec = (long long)floor(dd + 0.5);
+                long long el = 0;
+                for (int j = tid; j < ni; j += B) el += L.iz[j] > zf ? 1 : 0;
+                const long long nelig = T::isum(el, S);
+                if (nrec > nelig) nrec = nelig;
+                if (nrec > ne) nrec = ne;
+            }
+        }
+        {
             if (nrec > 0) {
                 const int nr = (int)nrec;
-                const int zf = R->z_floor;
-                if (nr <= REC_SELECT_MAX) {
+                if (ions_listed) {
+                    // the first nr electrons of the REC_E order
+                    if (nr <= REC_SELECT_MAX)
+                        smallest_fn<T>(ne, nr, step, lcell, RP_REC_E << 24, key0, key1, nullptr, 0, L.perm_e,
+                                       L.sbuf, S);
+                    else
+                        make_perm(RP_REC_E, ne, L.perm_e);
+                } else if (nr <= REC_SELECT_MAX) {
                     // the first nr eligible ions of the REC_I order and the
                     // first nr electrons of the REC_E order
                     smallest_fn<T>(ni, nr, step, lcell, RP_REC_I << 24, key0, key1, L.iz, zf, L.list, L.sbuf, S);

@@ -88,7 +88,8 @@ def test_flag_values_agree():
             for m in re.finditer(r"#define (XP_\w+)\s+0x([0-9A-Fa-f]+)u", text)}
     pairs = {"XP_EE": O.EE, "XP_EI": O.EI, "XP_ION": O.ION, "XP_REC": O.REC,
              "XP_PHOTO": O.PHOTO, "XP_DECAY": O.DECAY, "XP_ALL": O.ALL, "XP_THERM": O.THERM,
-             "XP_ION_Z": O.ION_Z, "XP_NANBU": O.NANBU, "XP_REL": O.REL}
+             "XP_ION_Z": O.ION_Z, "XP_NANBU": O.NANBU, "XP_REL": O.REL,
+             "XP_REC_XS": O.REC_XS}
     for name, oval in pairs.items():
         assert vals[name] == getattr(B, name) == oval, name
 

@@ -135,3 +135,25 @@ def test_big_path_nanbu(ctx):
     bat, sim = run_pair(ctx, spec, parts, 4, check_every=2, label="oversized/nanbu",
                         flags=O.ALL | O.NANBU)
     assert bat.stats()[2] == 2
+
+
+def test_big_path_recombination_cross_section(ctx):
+    # XP_REC_XS on the global-memory path: hundreds of firing ions per cell
+    # listed in slot order across chunks, fewer electrons than firing ions in
+    # one cell, clamped charge states; every cell through the path, then the
+    # same cells where only the large ones leave LDS
+    flags = (O.ALL & ~(O.PHOTO | O.DECAY)) | O.ION_Z | O.REC_XS
+    for big, sched in (("all", 3), ("auto", 0)):
+        spec, parts = cases.one_run(3, [1800, 700, 90], [600, 1200, 40], 1.0, 0.1, seed=91,
+                                    z0=8, e_weight=1, n_i=W.SOLID_NI * 4)
+        bat, _ = run_pair(ctx, spec, parts, 4, check_every=1, label="recxs/global/" + big,
+                          schedule=sched, big=big, flags=flags)
+        rc = bat.run_counters()[0]
+        assert rc[O.COUNTERS.index("REC")] > 0 and rc[O.COUNTERS.index("P_CLAMPED")] > 0
+    spec, parts = cases.one_run(3, [1800, 700, 90], [600, 1200, 40], 0.5, 0.1, seed=91,
+                                z0=10, e_weight=1, n_i=W.SOLID_NI * 20)
+    run_pair(ctx, spec, parts, 3, check_every=1, label="recxs/global/dense", schedule=3,
+             big="all", flags=flags)
+    spec, parts = W.config_c1()
+    run_pair(ctx, spec, parts, 6, flags=O.ALL | O.ION_Z | O.REC_XS, check_every=3,
+             capacity=(3, 16), label="C1/recxs/global", schedule=3, big="all")

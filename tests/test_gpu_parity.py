@@ -476,3 +476,30 @@ def test_relativistic_collisions(ctx):
     assert bat.stats()[2] == 2
     spec, parts = W.config_c2(nx=6, ny=6)
     run_pair(ctx, spec, parts, 10, flags=O.ALL | O.REL, check_every=5, label="C2r/rel")
+
+
+def test_recombination_cross_section(ctx):
+    # three-body recombination from the detailed-balance rate per charge
+    # state (XP_REC_XS, with the per-charge-state ionization of XP_ION_Z):
+    # cold dense cells where tens to hundreds of ions fire per step and some
+    # charge states clamp P at 1, under the wave, block, two-wave and
+    # lane-group schedules; C1 through the step where its electrons have
+    # cooled enough to recombine; a reduced C2
+    flags = (O.ALL & ~(O.PHOTO | O.DECAY)) | O.ION_Z | O.REC_XS
+    ne = [200, 120, 90, 60, 33, 140]
+    ni = [60, 100, 40, 30, 50, 12]
+    for sched in (0, 1, 2, 5):
+        spec, parts = cases.one_run(6, ne, ni, 1.0, 0.1, seed=96, z0=4, e_weight=1,
+                                    n_i=W.SOLID_NI * 4)
+        parts.iz[:] = np.random.default_rng(3).integers(3, 12, parts.ni)
+        bat, sim = run_pair(ctx, spec, parts, 3, check_every=1, schedule=sched, flags=flags,
+                            label="recxs/%d" % sched)
+        rc = bat.run_counters()[0]
+        assert rc[O.COUNTERS.index("REC")] > 0 and rc[O.COUNTERS.index("P_CLAMPED")] > 0
+    spec, parts = W.config_c1()
+    bat, _ = run_pair(ctx, spec, parts, 60, flags=O.ALL | O.ION_Z | O.REC_XS, check_every=20,
+                      capacity=(3, 16), label="C1/recxs")
+    assert bat.run_counters()[0][O.COUNTERS.index("REC")] > 0
+    spec, parts = W.config_c2(nx=6, ny=6)
+    run_pair(ctx, spec, parts, 10, flags=O.ALL | O.ION_Z | O.REC_XS, check_every=5,
+             label="C2r/recxs")
