@@ -30,14 +30,16 @@ ION_Z = 0x80   # variant: S3 cross section per ion charge state (Sec. IV), not i
 NANBU = 0x100  # variant: Nanbu's cumulative scattering law in S1, S2, not in ALL
 REL = 0x200    # variant: relativistic binary collisions in S1, S2, not in ALL
 REC_XS = 0x400  # variant: S4 per ion from the Lotz rate by detailed balance, not in ALL
+PHOTO_FRAC = 0x800  # variant: S5 photo events limited by the bin's photons in the cell
+KA_FIELD = 0x1000   # variant: K-alpha photons return to the photon field
 
 COUNTERS = ["EE", "EI", "TRIPLET", "ACCEPT", "U0", "DELTA2_GT1",
             "ION_FIRED", "ION_ACCEPTED", "ION_STARVED",
             "REC", "REC_SKIPPED", "E_REMOVED",
             "PHOTO_1S", "PHOTO_2S", "PHOTO_2P", "PHOTO_SKIPPED",
             "DECAY", "AUGER", "KALPHA", "P_CLAMPED", "IPD_CLAMPED", "E_NEW",
-            "THERM", "THERM_SKIPPED"]
-NCOUNT = 24
+            "THERM", "THERM_SKIPPED", "PHOTO_STARVED", "PHOTO_PARTIAL", "KA_FIELD"]
+NCOUNT = 27
 LEDGER = ["PHOTO_E", "AUGER_E", "ION_DEBIT", "REC_ADD", "REC_BIND", "KALPHA",
           "PHOTON_ABS"]
 NLEDGER = 8
@@ -134,6 +136,7 @@ def lib():
         L.orc_last_moments.restype = None; L.orc_last_moments.argtypes = [vp, vp]
         L.orc_diag.restype = None; L.orc_diag.argtypes = [vp, vp, vp, vp]
         L.orc_last_absorbed.restype = None; L.orc_last_absorbed.argtypes = [vp, vp]
+        L.orc_last_kalpha_field.restype = None; L.orc_last_kalpha_field.argtypes = [vp, vp]
         L.orc_get_cell_field.restype = None; L.orc_get_cell_field.argtypes = [vp, vp]
         L.orc_transport.restype = None; L.orc_transport.argtypes = [vp, vp]
         _lib = L
@@ -408,6 +411,13 @@ class Sim:
         a = np.zeros((self.ncells, MAX_BINS), dtype=np.int32)
         lib().orc_last_absorbed(self.h, _p(a))
         return a
+
+    def kalpha_field(self):
+        """K-alpha macro-photons returned per bin in the last step (KA_FIELD),
+        [ncells][MAX_BINS]."""
+        g = np.zeros((self.ncells, MAX_BINS), dtype=np.float64)
+        lib().orc_last_kalpha_field(self.h, _p(g))
+        return g
 
     def cell_field(self):
         """The photon field per cell, [ncells][n_bins]."""

@@ -45,6 +45,8 @@ extern "C" {
 #define ORC_NANBU   0x100u  /* variant: Nanbu's cumulative scattering law in S1, S2 */
 #define ORC_REL     0x200u  /* variant: relativistic binary collisions in S1, S2 */
 #define ORC_REC_XS  0x400u  /* variant: S4 per ion from the Lotz rate by detailed balance */
+#define ORC_PHOTO_FRAC 0x800u  /* variant: S5 photo events limited by the bin's photons in the cell */
+#define ORC_KA_FIELD   0x1000u /* variant: K-alpha photons return to the photon field */
 
 /* Per-cell, per-step event counters. */
 enum {
@@ -55,7 +57,8 @@ enum {
     OC_DECAY, OC_AUGER, OC_KALPHA,
     OC_P_CLAMPED, OC_IPD_CLAMPED, OC_E_NEW,
     OC_THERM, OC_THERM_SKIPPED,
-    OC_NCOUNT = 24
+    OC_PHOTO_STARVED, OC_PHOTO_PARTIAL, OC_KA_FIELD,
+    OC_NCOUNT = 27
 };
 
 /* Per-cell, per-step energy tallies (eV x weight units). */
@@ -173,6 +176,9 @@ void     orc_export(const orc_sim *s, int64_t *e_start, double *ex, double *ey,
 void     orc_last_counters(const orc_sim *s, int64_t *cnt, double *ledger);
 /* Photon events per bin of the last step, [ncells][ORC_MAX_BINS]. */
 void     orc_last_absorbed(const orc_sim *s, int32_t *nabs);
+/* K-alpha photons returned to the field in the last step (ORC_KA_FIELD), in
+ * macro-photons of each bin's energy, [ncells][ORC_MAX_BINS]. */
+void     orc_last_kalpha_field(const orc_sim *s, double *g);
 /* Current photon field per cell, [ncells][n_bins] (the uniform one if unset). */
 void     orc_get_cell_field(const orc_sim *s, double *nhv);
 /* Reduced radiation transport along x after a step (see orc_step.c):

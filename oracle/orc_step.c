@@ -16,7 +16,10 @@
  *      or (ORC_REC_XS) per ion from the rate that detailed balance gives the
  *      inverse of the Lotz ionization (orc_rec_xs).
  *   S5 K-vacancy decay with Auger / K-alpha branching and subshell
- *      photoionization (Eq. 3) (Sec. III).
+ *      photoionization (Eq. 3) (Sec. III).  With ORC_PHOTO_FRAC a bin can
+ *      give no more macro-photons than the cell holds; the event that finds
+ *      less than one left is a partial photoionization.  With ORC_KA_FIELD
+ *      the energy of every K-alpha photon goes back into the photon field.
  *   Optionally (ORC_THERM) the forced thermalization of Sec. VI.C right after
  *      S5: every free electron gets a new Maxwellian velocity at the cell
  *      temperature, corrected so that momentum and energy are unchanged.
@@ -39,7 +42,7 @@
  * words decide collisional ionization and the photo events of 1s, 2s, 2p. */
 enum { P_PERM_E = 1, P_PERM_I = 2, P_REC_I = 3, P_REC_E = 4, P_EE = 5,
        P_EE_TRI = 6, P_EI = 7, P_ION = 8, P_DECAY = 9, P_DIR = 10, P_BIN = 11,
-       P_THERM = 12, P_REC_XS = 13 };
+       P_THERM = 12, P_REC_XS = 13, P_PART = 14 };
 
 #define NMOM 32
 
@@ -62,6 +65,7 @@ struct orc_sim {
     double *mom;         /* [ncells][NMOM] */
     double *cell_nhv;    /* optional [ncells][n_bins] */
     int32_t *nabs;       /* [ncells][ORC_MAX_BINS] photons absorbed per bin, last step */
+    double *nka;         /* [ncells][ORC_MAX_BINS] K-alpha macro-photons returned, last step */
     double sigma[ORC_MAX_BINS][3];   /* photo cross section at each bin, m^2 */
 };
 
@@ -119,6 +123,7 @@ orc_sim *orc_create(const orc_tables *t, const orc_run *r)
     s->led = calloc((size_t)s->ncells * OL_NLEDGER, sizeof(double));
     s->mom = calloc((size_t)s->ncells * NMOM, sizeof(double));
     s->nabs = calloc((size_t)s->ncells * ORC_MAX_BINS, sizeof(int32_t));
+    s->nka = calloc((size_t)s->ncells * ORC_MAX_BINS, sizeof(double));
     for (int b = 0; b < r->n_bins; ++b)
         for (int q = 0; q < 3; ++q) s->sigma[b][q] = orc_photo_sigma(t, q, r->hv[b]);
     return s;
@@ -129,6 +134,7 @@ void orc_destroy(orc_sim *s)
     if (!s) return;
     for (int c = 0; c < s->ncells; ++c) cell_free(&s->cells[c]);
     free(s->cells); free(s->cnt); free(s->led); free(s->mom); free(s->cell_nhv); free(s->nabs);
+    free(s->nka);
     free(s);
 }
 
@@ -243,6 +249,11 @@ void orc_last_moments(const orc_sim *s, double *mom)
     memcpy(mom, s->mom, sizeof(double) * (size_t)s->ncells * NMOM);
 }
 
+void orc_last_kalpha_field(const orc_sim *s, double *g)
+{
+    memcpy(g, s->nka, sizeof(double) * (size_t)s->ncells * ORC_MAX_BINS);
+}
+
 void orc_last_absorbed(const orc_sim *s, int32_t *nabs)
 {
     memcpy(nabs, s->nabs, sizeof(int32_t) * (size_t)s->ncells * ORC_MAX_BINS);
@@ -270,8 +281,11 @@ void orc_get_cell_field(const orc_sim *s, double *nhv)
  * new density of cell i is the density entering it, the incident density
  * times the transmissions of the cells before it in the row (a quasi-static
  * Beer-Lambert profile: the crossing time of a row is taken as short against
- * the pulse).  trans[b] (if not NULL) is the mean over rows of the density
- * leaving the row divided by the incident density (0 for an empty bin).
+ * the pulse).  K-alpha photons that the step returned to bin b of a cell
+ * (ORC_KA_FIELD: g macro-photons of the bin's energy) join the beam leaving
+ * that cell: the density passed on is n_in tau + g w0 dx / (V c dt_rad).
+ * trans[b] (if not NULL) is the mean over rows of the density leaving the
+ * row divided by the incident density (0 for an empty bin).
  * The per-cell field is created from the uniform one if not set. */
 void orc_transport(orc_sim *s, double *trans)
 {
@@ -297,7 +311,7 @@ void orc_transport(orc_sim *s, double *trans)
                     double a = ((double)s->nabs[c * ORC_MAX_BINS + b] * r->w0) / (cross * n);
                     tau = a < 1.0 ? 1.0 - a : 0.0;
                 }
-                carry = carry * tau;
+                carry = carry * tau + (s->nka[c * ORC_MAX_BINS + b] * r->w0) / cross;
             }
             out_sum = out_sum + carry;
         }
@@ -330,6 +344,7 @@ typedef struct {
     double *led;
     int32_t law;          /* S1, S2: bit 0 Nanbu (else Takizuka-Abe), bit 1 relativistic */
     int32_t *nabs;        /* this cell's photons absorbed per bin */
+    double *nka;          /* this cell's K-alpha macro-photons returned per bin */
 } cctx;
 
 static void rng(const cctx *x, uint32_t idx, uint32_t purpose, uint32_t sub, uint32_t out[4])
@@ -826,6 +841,15 @@ static void step_cell(cctx *x, ocell *c, uint32_t flags)
         int photo = (flags & ORC_PHOTO) && nb > 0;
         const double *nhv = s->cell_nhv ? s->cell_nhv + (size_t)x->cell * nb : r->nhv;
         double ssum[13][3];
+        /* ORC_PHOTO_FRAC: macro-photons of each bin held by the cell, and
+         * those taken so far this step */
+        double budget[ORC_MAX_BINS], used[ORC_MAX_BINS];
+        for (int b = 0; b < nb; ++b) {
+            budget[b] = (nhv[b] * r->volume) / r->w0;
+            used[b] = 0.0;
+        }
+        /* ORC_KA_FIELD: K-alpha photons per charge state Z0 */
+        int64_t nka_z[ORC_ZMAX] = {0};
         if (photo) {
             for (int z = 0; z < 13; ++z)
                 for (int q = 0; q < 3; ++q) {
@@ -870,6 +894,7 @@ static void step_cell(cctx *x, ocell *c, uint32_t flags)
                         } else {
                             x->cnt[OC_KALPHA]++;
                             x->led[OL_KALPHA] += t->e_kalpha[z0];
+                            nka_z[z0]++;
                         }
                     }
                 }
@@ -901,6 +926,29 @@ static void step_cell(cctx *x, ocell *c, uint32_t flags)
                         if (cum > target) { sel = b; break; }
                     }
                     if (sel < 0) sel = lastpos;
+                    if (flags & ORC_PHOTO_FRAC) {
+                        /* one macro-photon per event while the bin has one;
+                         * with less than one left (f) the event is a partial
+                         * photoionization: a macro-photoelectron of weight f
+                         * units taking f of a unit of charge, which integer
+                         * weights carry as an event of probability f */
+                        double rem = budget[sel] - used[sel];
+                        if (rem >= 1.0) {
+                            used[sel] = used[sel] + 1.0;
+                        } else if (rem > 0.0) {
+                            used[sel] = budget[sel];
+                            uint32_t e[4];
+                            rng(x, (uint32_t)i, P_PART, (uint32_t)q, e);
+                            if (!(orc_u32(e[0]) < rem)) {
+                                x->cnt[OC_PHOTO_STARVED]++;
+                                continue;
+                            }
+                            x->cnt[OC_PHOTO_PARTIAL]++;
+                        } else {
+                            x->cnt[OC_PHOTO_STARVED]++;
+                            continue;
+                        }
+                    }
                     z = z + 1;
                     if (q == 0) kv = kv + 1;
                     double ep = r->hv[sel] - pp;
@@ -913,6 +961,22 @@ static void step_cell(cctx *x, ocell *c, uint32_t flags)
             }
             c->iz[i] = (uint8_t)z;
             c->ik[i] = (uint8_t)kv;
+        }
+        if (flags & ORC_KA_FIELD) {
+            /* each K-alpha photon's energy goes to the bin of the largest
+             * h nu not above it, as E_Ka / h nu photons of that bin (energy
+             * kept, never promoted above its own energy); with no such bin
+             * it leaves the plasma */
+            for (int z0 = 0; z0 < ORC_ZMAX; ++z0) {
+                if (nka_z[z0] == 0) continue;
+                double eka = t->e_kalpha[z0];
+                int kb = -1;
+                for (int b = 0; b < nb; ++b)
+                    if (r->hv[b] <= eka && (kb < 0 || r->hv[b] > r->hv[kb])) kb = b;
+                if (kb < 0) continue;
+                x->nka[kb] = x->nka[kb] + (double)nka_z[z0] * (eka / r->hv[kb]);
+                x->cnt[OC_KA_FIELD] += nka_z[z0];
+            }
         }
     }
     if (flags & ORC_THERM) thermalize(x, c);
@@ -931,6 +995,7 @@ void orc_step(orc_sim *s, uint32_t step, uint32_t flags, int32_t nthreads)
     memset(s->cnt, 0, sizeof(int64_t) * (size_t)s->ncells * OC_NCOUNT);
     memset(s->led, 0, sizeof(double) * (size_t)s->ncells * OL_NLEDGER);
     memset(s->nabs, 0, sizeof(int32_t) * (size_t)s->ncells * ORC_MAX_BINS);
+    memset(s->nka, 0, sizeof(double) * (size_t)s->ncells * ORC_MAX_BINS);
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #else
@@ -956,6 +1021,7 @@ void orc_step(orc_sim *s, uint32_t step, uint32_t flags, int32_t nthreads)
             x.cnt = s->cnt + (size_t)c * OC_NCOUNT;
             x.led = s->led + (size_t)c * OL_NLEDGER;
             x.nabs = s->nabs + (size_t)c * ORC_MAX_BINS;
+            x.nka = s->nka + (size_t)c * ORC_MAX_BINS;
             step_cell(&x, &s->cells[c], flags);
         }
         free(x.scratch); free(x.perm_e); free(x.perm_i); free(x.perm_a); free(x.perm_b); free(x.keys);
