@@ -35,8 +35,8 @@ extern "C" {
 #endif
 
 /* Layout version of the structs below; 2 added xp_batch.d_cell_nabs, 3 added
- * xp_batch.d_run_status. */
-#define XP_ABI_VERSION 3u
+ * xp_batch.d_run_status, 4 added three counters and xp_batch.d_cell_nka. */
+#define XP_ABI_VERSION 4u
 
 typedef int32_t xp_status;
 #define XP_OK                   0
@@ -109,6 +109,29 @@ typedef int32_t xp_status;
  * energy bookkeeping and rescale. */
 #define XP_REC_XS  0x400u
 
+/* Variant of S5 (Sec. III, photoionization): a bin of the photon field can
+ * give a cell no more photons than it holds, n_hv V real photons or
+ * n_hv V / w0 macro-photons.  The photo events of a cell take one each in ion
+ * order (1s, 2s, 2p within an ion) while one is left; the event that finds a
+ * fraction f in (0, 1) left is a partial photoionization: the paper's
+ * macro-photoelectron of weight f, with f of a unit of charge, which integer
+ * weight units carry as an event of probability f (32-bit draw, word 0 of
+ * the ion's call of purpose 14, sub = shell), after which the bin is spent;
+ * later events of the bin do not happen (XP_C_PHOTO_STARVED).  Without it
+ * every event takes its photon whatever the bin holds. */
+#define XP_PHOTO_FRAC 0x800u
+
+/* Variant of S5 (Sec. III, K-vacancy decay): the energy of a K-alpha photon
+ * goes back into the photon field, to the bin of the largest h nu not above
+ * E_Ka(Z0) (the lowest index among equal ones), as E_Ka / h nu photons of
+ * that bin, so that energy is kept and no photon is promoted above its own
+ * energy; with no such bin it leaves the plasma.  Per cell and bin the step
+ * writes g_b = sum over Z0 ascending of (number of K-alpha photons of ions of
+ * charge Z0 sent to b) * (E_Ka(Z0) / h nu_b), in macro-photons, to
+ * d_cell_nka; transport_photons adds them to the beam leaving the cell.
+ * The particle state is that of the step without it. */
+#define XP_KA_FIELD   0x1000u
+
 /* Device status bits (xp_batch.d_status, OR-ed by kernels). */
 #define XP_ST_CAPACITY  0x1u   /* a cell needed more electron slots than its capacity */
 #define XP_ST_NONFINITE 0x2u   /* a non-finite velocity was produced */
@@ -125,7 +148,10 @@ enum {
     XP_C_DECAY, XP_C_AUGER, XP_C_KALPHA,
     XP_C_P_CLAMPED, XP_C_IPD_CLAMPED, XP_C_E_NEW,
     XP_C_THERM, XP_C_THERM_SKIPPED,   /* cells thermalized / left as they were (XP_THERM) */
-    XP_NCOUNT = 24
+    XP_C_PHOTO_STARVED,   /* photo events whose bin was spent (XP_PHOTO_FRAC) */
+    XP_C_PHOTO_PARTIAL,   /* partial photoionizations that happened (XP_PHOTO_FRAC) */
+    XP_C_KA_FIELD,        /* K-alpha photons returned to the field (XP_KA_FIELD) */
+    XP_NCOUNT = 27
 };
 
 /* Per-cell energy tallies (eV x weight units). */
@@ -273,6 +299,9 @@ typedef struct {
                                        beside d_status by the step, the global-memory path and
                                        transport_photons (bin_particles sets d_status only);
                                        the caller clears a run's word */
+    double *d_cell_nka;             /* optional [n_cells][XP_MAX_BINS]: K-alpha macro-photons
+                                       returned per bin in the last step (XP_KA_FIELD; zeros
+                                       without it); read by transport_photons if set */
 } xp_batch;
 
 /* Unsorted input particles of a batch for bin_particles.  Particle p belongs
@@ -384,7 +413,8 @@ xp_status collide_ionize_step_static(xp_ctx *ctx, const xp_batch *b, const xp_st
  * state, then K-vacancy decay with KLL Auger / K-alpha branching and subshell
  * photoionization (Eq. 3) with the run's prescribed photon field, over
  * dt_rad, then with XP_THERM the forced thermalization of Sec. VI.C.
- * p->flags is masked to XP_PHOTO | XP_DECAY | XP_THERM. */
+ * p->flags is masked to XP_PHOTO | XP_DECAY | XP_THERM | XP_PHOTO_FRAC |
+ * XP_KA_FIELD. */
 xp_status photo_auger_step(xp_ctx *ctx, xp_batch *b, const xp_step_params *p,
                            void *stream);
 
@@ -396,8 +426,11 @@ xp_status photo_auger_step(xp_ctx *ctx, xp_batch *b, const xp_step_params *p,
  * by bin: the run's nhv[b] enters the row at its low-x face; cell i passes on
  * the fraction tau_i = 1 - nabs_i w0 dx / (V c dt_rad n_i) (0 if negative, 1
  * if n_i = 0) of the density n_i it had during the step, nabs_i being its
- * photon events of bin b in d_cell_nabs; its new density is the incident
- * density times tau_0 ... tau_{i-1} (multiplied left to right).  The profile
+ * photon events of bin b in d_cell_nabs; the density it passes on is
+ * n_in tau_i + g_i w0 dx / (V c dt_rad), g_i its K-alpha macro-photons of
+ * the bin in d_cell_nka (0 if d_cell_nka is NULL), so without K-alpha return
+ * the new density of cell i is the incident density times tau_0 ... tau_{i-1}
+ * (multiplied left to right).  The profile
  * is quasi-static: the light crossing time of a row is taken as short
  * against the pulse.  Call after collide_ionize_step / photo_auger_step
  * with d_cell_nabs set.  d_trans (optional, [n_runs][XP_MAX_BINS]) gets

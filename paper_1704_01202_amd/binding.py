@@ -23,8 +23,10 @@ XP_ION_Z = 0x80   # variant: S3 cross section per ion charge state (Sec. IV), no
 XP_NANBU = 0x100  # variant: Nanbu's cumulative scattering law in e-e and e-i, not in XP_ALL
 XP_REL = 0x200    # variant: relativistic binary collisions in e-e and e-i, not in XP_ALL
 XP_REC_XS = 0x400  # variant: recombination from cross sections by detailed balance, not in XP_ALL
+XP_PHOTO_FRAC = 0x800  # variant: photo events limited by the bin's photons in the cell, not in XP_ALL
+XP_KA_FIELD = 0x1000   # variant: K-alpha photons return to the photon field, not in XP_ALL
 XP_ST_CAPACITY, XP_ST_NONFINITE, XP_ST_BIN_SIZE, XP_ST_RUN_TABLE = 0x1, 0x2, 0x4, 0x8
-XP_NCOUNT, XP_NLEDGER, XP_NMOM, XP_MAX_BINS = 24, 8, 32, 16
+XP_NCOUNT, XP_NLEDGER, XP_NMOM, XP_MAX_BINS = 27, 8, 32, 16
 XP_NSTATS = 68
 XP_DIAG_RESET = 0x1
 
@@ -74,7 +76,8 @@ class XpBatch(C.Structure):
                 ("d_work", _vp), ("work_bytes", C.c_size_t),
                 ("e_cap_max", _i32), ("i_cap_max", _i32), ("d_stats", _vp),
                 ("big_cells_max", _i32), ("reserved0", _i32), ("big_e_slots", _i64),
-                ("big_i_slots", _i64), ("d_cell_nabs", _vp), ("d_run_status", _vp)]
+                ("big_i_slots", _i64), ("d_cell_nabs", _vp), ("d_run_status", _vp),
+                ("d_cell_nka", _vp)]
 
 
 class XpParticles(C.Structure):
@@ -102,7 +105,7 @@ class XpDiag(C.Structure):
 
 XP_STATIC_SCRATCH_BYTES = 64 << 20   # static workspace of collide_ionize_step_static
 
-ABI_VERSION = 3   # struct layouts mirrored below (XP_ABI_VERSION of include/xpic.h)
+ABI_VERSION = 4   # struct layouts mirrored below (XP_ABI_VERSION of include/xpic.h)
 
 EXPORTS = ["xp_abi_version", "xp_last_error", "xp_ctx_create", "xp_ctx_destroy",
            "xp_table_bytes", "init_species", "xp_work_bytes", "xp_step_work_bytes",

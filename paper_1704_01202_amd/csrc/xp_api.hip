@@ -314,6 +314,7 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
     a.cell_led = b->d_cell_ledger;
     a.cell_mom = b->d_cell_moments;
     a.cell_nabs = b->d_cell_nabs;
+    a.cell_nka = b->d_cell_nka;
     a.status = b->d_status;
     a.run_status = b->d_run_status;
     a.tab = ctx->d_tables;
@@ -403,9 +404,10 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
         }
         // the variants, per-cell records and per-cell photon fields are
         // compiled into their own kernels
-        const bool xv = (flags & (XP_THERM | XP_ION_Z | XP_NANBU | XP_REL | XP_REC_XS)) != 0 || b->d_cell_counters ||
-                        b->d_cell_ledger ||
-                        b->d_cell_moments || b->d_cell_nhv || b->d_cell_nabs;
+        const bool xv = (flags & (XP_THERM | XP_ION_Z | XP_NANBU | XP_REL | XP_REC_XS | XP_PHOTO_FRAC |
+                                  XP_KA_FIELD)) != 0 ||
+                        b->d_cell_counters || b->d_cell_ledger || b->d_cell_moments || b->d_cell_nhv ||
+                        b->d_cell_nabs || b->d_cell_nka;
         for (int tier = 0;; ++tier) {
             const bool last = ce >= ce_top || tier >= xpd::BIG_COUNT_SLOT - 1;
             a.lds_ce = ce;
@@ -493,7 +495,7 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
 xp_status collide_ionize_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, void* stream)
 {
     if (!p) return fail(XP_ERR_INVALID_ARG, "null step parameters");
-    return launch_step(ctx, b, p, p->flags & (XP_ALL | XP_THERM | XP_ION_Z | XP_NANBU | XP_REL | XP_REC_XS), stream);
+    return launch_step(ctx, b, p, p->flags & (XP_ALL | XP_THERM | XP_ION_Z | XP_NANBU | XP_REL | XP_REC_XS | XP_PHOTO_FRAC | XP_KA_FIELD), stream);
 }
 
 xp_status collide_ionize_step_static(xp_ctx* ctx, const xp_batch* b, const xp_step_params* p, void* stream)
@@ -516,13 +518,13 @@ xp_status collide_ionize_step_static(xp_ctx* ctx, const xp_batch* b, const xp_st
     xp_batch v = *b;
     v.d_work = ptr;
     v.work_bytes = (size_t)XP_STATIC_SCRATCH_BYTES;
-    return launch_step(ctx, &v, p, p->flags & (XP_ALL | XP_THERM | XP_ION_Z | XP_NANBU | XP_REL | XP_REC_XS), stream);
+    return launch_step(ctx, &v, p, p->flags & (XP_ALL | XP_THERM | XP_ION_Z | XP_NANBU | XP_REL | XP_REC_XS | XP_PHOTO_FRAC | XP_KA_FIELD), stream);
 }
 
 xp_status photo_auger_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, void* stream)
 {
     if (!p) return fail(XP_ERR_INVALID_ARG, "null step parameters");
-    return launch_step(ctx, b, p, p->flags & (XP_PHOTO | XP_DECAY | XP_THERM), stream);
+    return launch_step(ctx, b, p, p->flags & (XP_PHOTO | XP_DECAY | XP_THERM | XP_PHOTO_FRAC | XP_KA_FIELD), stream);
 }
 
 xp_status diagnostics(xp_ctx* ctx, const xp_batch* b, xp_diag* d_out, uint32_t what, void* stream)
@@ -570,6 +572,7 @@ xp_status transport_photons(xp_ctx* ctx, xp_batch* b, double* d_trans, void* str
     a.cell_run = b->d_cell_run;
     a.nhv = b->d_cell_nhv;
     a.nabs = b->d_cell_nabs;
+    a.nka = b->d_cell_nka;
     a.exit = (double*)b->d_work;
     a.trans = d_trans;
     a.status = b->d_status;

@@ -109,6 +109,8 @@ __global__ void k_big_init(BigArgs a)
         for (int q = 0; q < XP_NMOM; ++q) r.mom[q] = 0.0;
         for (int q = 0; q < XP_NCOUNT; ++q) r.cnt[q] = 0;
         for (int q = 0; q < XP_MAX_BINS; ++q) r.nabs[q] = 0;
+        for (int q = 0; q < 14; ++q) r.kz[q] = 0;
+        r.np5 = 0;
         for (int q = 0; q < XP_NLEDGER; ++q) r.led[q] = 0.0;
         const int64_t lim = (int64_t)BIG_MAX_CHUNKS * BIG_CH;
         if ((int64_t)r.ecap > lim || (int64_t)r.ni > lim) {
@@ -1673,6 +1675,7 @@ __global__ __launch_bounds__(64) void k_big_efin(BigArgs a)
 __global__ __launch_bounds__(BT) void k_big_s5a(BigArgs a)
 {
     __shared__ int cnt[XP_NCOUNT];
+    __shared__ int kz[14];
     __shared__ double led[XP_NLEDGER];
     __shared__ long long ired[BT / 64];
     const int tid = threadIdx.x;
@@ -1686,6 +1689,7 @@ __global__ __launch_bounds__(BT) void k_big_s5a(BigArgs a)
         const xp_run& R = s.runs[r.run];
         for (int q = tid; q < XP_NCOUNT; q += BT) cnt[q] = 0;
         for (int q = tid; q < XP_NLEDGER; q += BT) led[q] = 0.0;
+        for (int q = tid; q < 14; q += BT) kz[q] = 0;
         __syncthreads();
         const int nbins = R.n_bins;
         const bool photo = (flags & XP_PHOTO) && nbins > 0;
@@ -1694,12 +1698,12 @@ __global__ __launch_bounds__(BT) void k_big_s5a(BigArgs a)
         const double* dE = r.mom + 16;
         const int base = (g - r.ci0) * BIG_CH;
         const int n = r.ni - base < BIG_CH ? r.ni - base : BIG_CH;
-        long long newe = 0;
+        long long newe = 0, npf = 0;
         for (int q = tid; q < n; q += BT) {
             const int i = base + q;
             const int64_t pi = r.io + i;
             const int z0 = s.iz[pi], k0 = s.ik[pi];
-            uint32_t mask = 0, bins = 0;
+            uint32_t mask = 0, bins = 0, pf = 0, dec = 0;
             if (z0 < 13) {
                 const Occ o0 = occupancy(z0, k0);
                 const int nl0 = o0.s[1] + o0.s[2];
@@ -1716,6 +1720,7 @@ __global__ __launch_bounds__(BT) void k_big_s5a(BigArgs a)
                         }
                         if (u52(d.x0, d.x1) < pd) {
                             kv = k0 - 1;
+                            dec = 1;
                             atomicAdd(&cnt[XP_C_DECAY], 1);
                             if (nl0 >= 2 && u52(d.x2, d.x3) < ga / rate) {
                                 z = z0 + 1;
@@ -1724,6 +1729,7 @@ __global__ __launch_bounds__(BT) void k_big_s5a(BigArgs a)
                             } else {
                                 atomicAdd(&cnt[XP_C_KALPHA], 1);
                                 atomicAdd(&led[XP_L_KALPHA], tb->e_kalpha[z0]);
+                                if (flags & XP_KA_FIELD) atomicAdd(&kz[z0], 1);
                             }
                         }
                     }
@@ -1741,6 +1747,7 @@ __global__ __launch_bounds__(BT) void k_big_s5a(BigArgs a)
                             atomicAdd(&cnt[XP_C_P_CLAMPED], 1);
                         }
                         if (!(u32(fire[sh]) < p)) continue;
+                        pf |= 1u << sh;
                         const Occ on = occupancy(z, kv);
                         if (z >= 13 || on.s[sh] <= 0) {
                             atomicAdd(&cnt[XP_C_PHOTO_SKIPPED], 1);
@@ -1748,20 +1755,7 @@ __global__ __launch_bounds__(BT) void k_big_s5a(BigArgs a)
                         }
                         const double pp = lowered(tb, z0, sh, dE);
                         const Words d = draw(s, r, (uint32_t)i, RP_BIN, (uint32_t)sh);
-                        const double target = u52(d.x0, d.x1) * sum;
-                        double cum = 0.0;
-                        int sel = -1, lastpos = -1;
-                        for (int bq = 0; bq < nbins; ++bq) {
-                            if (!(R.hv[bq] >= pp)) continue;
-                            const double term = nhv[bq] * r.sig[bq][sh];
-                            cum = cum + term;
-                            if (term > 0.0) lastpos = bq;
-                            if (cum > target) {
-                                sel = bq;
-                                break;
-                            }
-                        }
-                        if (sel < 0) sel = lastpos;
+                        const int sel = photo_bin(R.hv, nhv, r.sig, nbins, sh, pp, u52(d.x0, d.x1) * sum);
                         z = z + 1;
                         if (sh == 0) kv = kv + 1;
                         mask |= 2u << sh;
@@ -1774,11 +1768,93 @@ __global__ __launch_bounds__(BT) void k_big_s5a(BigArgs a)
             }
             a.iaux[r.ip0 + i] = mask | (bins << 4) | ((uint32_t)z0 << 16) | ((uint32_t)k0 << 24);
             newe += __popc(mask);
+            if (flags & XP_PHOTO_FRAC) {
+                // the photo candidates and the decay, for k_big_s5fix
+                a.iflag[r.ip0 + i] = (uint8_t)(pf | (dec << 3));
+                npf += __popc(pf);
+            }
         }
         newe = block_isum<BT>(newe, ired);
         if (tid == 0) a.ccnt[g] = (int32_t)newe;
+        if (flags & XP_PHOTO_FRAC) {
+            npf = block_isum<BT>(npf, ired);
+            if (tid == 0 && npf) atomicAdd(&r.np5, (int32_t)npf);
+        }
+        if (flags & XP_KA_FIELD)
+            for (int q = tid; q < 13; q += BT)
+                if (kz[q]) atomicAdd(&r.kz[q], kz[q]);
         flush_counts(r, cnt, led);
         __syncthreads();
+    }
+}
+
+// XP_KA_FIELD: the K-alpha photons a cell returns to the field.  XP_PHOTO_FRAC:
+// when a cell's photo candidates outnumber the smallest whole budget of its
+// bins, one lane takes its ions again in slot order with the budget (as the
+// LDS step does), rewriting their Z, k, emission records and the electrons
+// per chunk, and corrects the photo counters.
+__global__ __launch_bounds__(64) void k_big_s5fix(BigArgs a)
+{
+    __shared__ double bud[XP_MAX_BINS], used[XP_MAX_BINS];
+    const StepArgs& s = a.s;
+    const DevTables* tb = s.tab;
+    const uint32_t flags = s.flags;
+    const int nb = a.hdr->count;
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+        BigRec& r = a.rec[b];
+        if (r.state || threadIdx.x != 0) continue;
+        const xp_run& R = s.runs[r.run];
+        const int nbins = R.n_bins;
+        if (flags & XP_KA_FIELD)
+            for (int z0 = 0; z0 < 13; ++z0)
+                if (r.kz[z0] && kalpha_bin(R.hv, nbins, tb->e_kalpha[z0]) >= 0) r.cnt[XP_C_KA_FIELD] += r.kz[z0];
+        if (!(flags & XP_PHOTO_FRAC) || !(flags & XP_PHOTO) || nbins <= 0) continue;
+        const double* nhv = (R.field_per_cell && s.cell_nhv) ? s.cell_nhv + (size_t)r.cell * XP_MAX_BINS : R.nhv;
+        double mmin = 1e300;
+        for (int bq = 0; bq < nbins; ++bq) {
+            const double m = (nhv[bq] * R.volume) / R.w0;
+            bud[bq] = m;
+            used[bq] = 0.0;
+            if (nhv[bq] > 0.0 && floor(m) < mmin) mmin = floor(m);
+        }
+        if (!((double)r.np5 > mmin)) continue;
+        const double* dE = r.mom + 16;
+        int dn[3] = {0, 0, 0}, dskip = 0, dst = 0, dpart = 0, chunk_new = 0;
+        for (int i = 0; i < r.ni; ++i) {
+            const uint32_t aux = a.iaux[r.ip0 + i];
+            const uint32_t fl = a.iflag[r.ip0 + i];
+            const uint32_t pfi = fl & 7u;
+            if (pfi) {
+                const int z0 = (aux >> 16) & 255u, k0 = (aux >> 24) & 255u;
+                int z = z0 + (int)(aux & 1u), kv = k0 - (int)((fl >> 3) & 1u);
+                const PhotoWalk w = photo_walk_ion(
+                    [&](uint32_t pu, uint32_t sub) { return draw(s, r, (uint32_t)i, pu, sub); }, tb, R.hv, nhv, r.sig,
+                    r.ssum, nbins, z0, pfi, dE, bud, used, z, kv);
+                int old = 0;
+                for (int q = 0; q < 3; ++q) {
+                    const int f = (int)((aux >> (1 + q)) & 1u);
+                    dn[q] += w.fired[q] - f;
+                    old += f;
+                }
+                dskip += w.skipped - (__popc(pfi) - old);
+                dst += w.starved;
+                dpart += w.partial;
+                a.iaux[r.ip0 + i] = (aux & 0xFFFF0001u) | w.mask | (w.bins << 4);
+                s.iz[r.io + i] = (uint8_t)z;
+                s.ik[r.io + i] = (uint8_t)kv;
+                chunk_new += __popc((aux & 1u) | w.mask);
+            } else {
+                chunk_new += (int)(aux & 1u);
+            }
+            if (((i + 1) & (BIG_CH - 1)) == 0 || i + 1 == r.ni) {
+                a.ccnt[r.ci0 + i / BIG_CH] = chunk_new;
+                chunk_new = 0;
+            }
+        }
+        for (int q = 0; q < 3; ++q) r.cnt[XP_C_PHOTO_1S + q] += dn[q];
+        r.cnt[XP_C_PHOTO_SKIPPED] += dskip;
+        r.cnt[XP_C_PHOTO_STARVED] += dst;
+        r.cnt[XP_C_PHOTO_PARTIAL] += dpart;
     }
 }
 
@@ -2058,6 +2134,12 @@ __global__ __launch_bounds__(64) void k_big_commit(BigArgs a)
         if (s.cell_nabs)
             for (int q = threadIdx.x; q < XP_MAX_BINS; q += 64)
                 s.cell_nabs[(size_t)cell * XP_MAX_BINS + q] = r.nabs[q];
+        if (s.cell_nka) {
+            const xp_run& R = s.runs[r.run];
+            for (int q = threadIdx.x; q < XP_MAX_BINS; q += 64)
+                s.cell_nka[(size_t)cell * XP_MAX_BINS + q] =
+                    (s.flags & XP_KA_FIELD) && q < R.n_bins ? kalpha_return(s.tab, R.hv, R.n_bins, r.kz, q) : 0.0;
+        }
         if (s.run_cnt)
             for (int q = threadIdx.x; q < XP_NCOUNT; q += 64)
                 if (r.cnt[q]) atomicAdd((unsigned long long*)&s.run_cnt[(size_t)r.run * XP_NCOUNT + q], (unsigned long long)r.cnt[q]);
@@ -2229,6 +2311,7 @@ hipError_t big_launch(BigArgs& a, bool all_cells, hipStream_t s)
     }
     if (flags & (XP_PHOTO | XP_DECAY)) {
         hipLaunchKernelGGL(k_big_s5a, dim3(gch), dim3(BT), 0, s, a);
+        if (flags & (XP_PHOTO_FRAC | XP_KA_FIELD)) hipLaunchKernelGGL(k_big_s5fix, dim3(gcell), dim3(64), 0, s, a);
         hipLaunchKernelGGL(k_big_cscan, dim3(gcell), dim3(BT), 0, s, a, 2);
         hipLaunchKernelGGL(k_big_s5b, dim3(gch), dim3(BT), 0, s, a);
     }

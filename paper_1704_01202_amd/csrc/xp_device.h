@@ -31,7 +31,7 @@ constexpr double PI = 3.141592653589793;
 enum : uint32_t {
     RP_PERM_E = 1, RP_PERM_I = 2, RP_REC_I = 3, RP_REC_E = 4, RP_EE = 5,
     RP_EE_TRI = 6, RP_EI = 7, RP_ION = 8, RP_DECAY = 9, RP_DIR = 10, RP_BIN = 11,
-    RP_THERM = 12, RP_REC_XS = 13
+    RP_THERM = 12, RP_REC_XS = 13, RP_PART = 14
 };
 
 __device__ __forceinline__ double bits_to_f64(uint64_t b) { return __longlong_as_double((long long)b); }

@@ -30,6 +30,7 @@ struct StepArgs {
     double* cell_led;
     double* cell_mom;
     int32_t* cell_nabs;         // optional [n_cells][XP_MAX_BINS] photon events per bin
+    double* cell_nka;           // optional [n_cells][XP_MAX_BINS] K-alpha macro-photons returned
     uint32_t* status;
     uint32_t* run_status;       // optional [n_runs]
     const DevTables* tab;
@@ -130,6 +131,7 @@ struct TransportArgs {
     const int32_t* cell_run;
     double* nhv;            // [n_cells][XP_MAX_BINS], rewritten
     const int32_t* nabs;    // [n_cells][XP_MAX_BINS], photon events of the last step
+    const double* nka;      // optional [n_cells][XP_MAX_BINS], K-alpha macro-photons returned
     double* exit;           // workspace [n_cells][XP_MAX_BINS]: exit density at each row start
     double* trans;          // optional [n_runs][XP_MAX_BINS]
     uint32_t* status;
@@ -177,6 +179,8 @@ struct BigRec {
     int32_t cnt[XP_NCOUNT];
     double led[XP_NLEDGER];
     int32_t nabs[XP_MAX_BINS];         // photon events per bin (S5)
+    int32_t kz[14];                    // K-alpha photons per charge state Z0 (XP_KA_FIELD)
+    int32_t np5, pad5;                 // S5 photo candidates (XP_PHOTO_FRAC)
     // forced thermalization (variant): weight units, lab-frame and drift-frame
     // kinetic energy, draw spread, draw mean, scale; keep: 0 resample, 1 keep
     // the velocities, 2 drift velocity only

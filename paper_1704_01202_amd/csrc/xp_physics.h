@@ -525,5 +525,108 @@ __device__ __forceinline__ double lotz_leaf(double x, double y, double z, uint32
     return ((double)w * sig) * sqrt(v2);
 }
 
+// ------------------------------------------- S5 photon field (Sec. III)
+
+// Bin of a photoionization of subshell s: the first bin, in bin order, at
+// which the running sum of n_hv sigma over the bins the lowered binding pp
+// allows passes target; the last bin with a positive term when rounding
+// leaves the sum short of it.
+__device__ __forceinline__ int photo_bin(const double* hv, const double* nhv, const double (*sig)[3],
+                                         int nb, int s, double pp, double target)
+{
+    double cum = 0.0;
+    int sel = -1, lastpos = -1;
+    for (int bq = 0; bq < nb; ++bq) {
+        if (!(hv[bq] >= pp)) continue;
+        const double term = nhv[bq] * sig[bq][s];
+        cum = cum + term;
+        if (term > 0.0) lastpos = bq;
+        if (cum > target) {
+            sel = bq;
+            break;
+        }
+    }
+    return sel < 0 ? lastpos : sel;
+}
+
+// XP_KA_FIELD: the bin of the largest h nu not above e, the lowest index
+// among equal ones; -1 if every bin lies above e.
+__device__ __forceinline__ int kalpha_bin(const double* hv, int nb, double e)
+{
+    int kb = -1;
+    for (int b = 0; b < nb; ++b)
+        if (hv[b] <= e && (kb < 0 || hv[b] > hv[kb])) kb = b;
+    return kb;
+}
+
+// XP_KA_FIELD: K-alpha macro-photons a cell returns to bin b, from its
+// K-alpha photons per charge state kz[Z0], summed over Z0 ascending.
+__device__ __forceinline__ double kalpha_return(const DevTables* tb, const double* hv, int nb, const int32_t* kz,
+                                                int b)
+{
+    double g = 0.0;
+    for (int z0 = 0; z0 < 13; ++z0) {
+        if (kz[z0] == 0) continue;
+        const double e = tb->e_kalpha[z0];
+        if (kalpha_bin(hv, nb, e) != b) continue;
+        g = g + (double)kz[z0] * (e / hv[b]);
+    }
+    return g;
+}
+
+// XP_PHOTO_FRAC, for a cell whose photo candidates may outnumber what a bin
+// holds: one ion's photo shells again, in order, from its state after decay
+// (z, kv in and out).  pf: the shells whose draw passed their probability
+// (candidates); each candidate that still has an electron takes one
+// macro-photon of its bin while one is left (bud[b] held, used[b] taken);
+// the one that finds a fraction f left happens with probability f (word 0 of
+// its call of purpose RP_PART), after which the bin is spent; later ones
+// starve.  draw(purpose, sub) gives the ion's Philox words.
+struct PhotoWalk {
+    uint32_t mask, bins;   // photo bits 1..3 and bins at 4 s, as the first pass records them
+    int fired[3], skipped, starved, partial;
+};
+
+template <class D>
+__device__ __noinline__ PhotoWalk photo_walk_ion(D draw, const DevTables* tb, const double* hv, const double* nhv,
+                                                 const double (*sig)[3], const double (*ssum)[3], int nb, int z0,
+                                                 uint32_t pf, const double* dE, double* bud, double* used, int& z,
+                                                 int& kv)
+{
+    PhotoWalk w = {0u, 0u, {0, 0, 0}, 0, 0, 0};
+    for (int s = 0; s < 3; ++s) {
+        if (!((pf >> s) & 1u)) continue;
+        const Occ on = occupancy(z, kv);
+        if (z >= 13 || on.s[s] <= 0) {
+            ++w.skipped;
+            continue;
+        }
+        const double pp = lowered(tb, z0, s, dE);
+        const Words d = draw(RP_BIN, (uint32_t)s);
+        const int sel = photo_bin(hv, nhv, sig, nb, s, pp, u52(d.x0, d.x1) * ssum[z0][s]);
+        const double rem = bud[sel] - used[sel];
+        if (rem >= 1.0) {
+            used[sel] = used[sel] + 1.0;
+        } else if (rem > 0.0) {
+            used[sel] = bud[sel];
+            const Words e = draw(RP_PART, (uint32_t)s);
+            if (!(u32(e.x0) < rem)) {
+                ++w.starved;
+                continue;
+            }
+            ++w.partial;
+        } else {
+            ++w.starved;
+            continue;
+        }
+        z = z + 1;
+        if (s == 0) kv = kv + 1;
+        w.mask |= 2u << s;
+        w.bins |= (uint32_t)sel << (4 * s);
+        ++w.fired[s];
+    }
+    return w;
+}
+
 }  // namespace xpd
 

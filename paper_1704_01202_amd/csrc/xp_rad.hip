@@ -8,9 +8,11 @@
 // each bin (the run's nhv) enters every row at its low-x face; cell i's new
 // density is the incident density times the transmissions of the cells before
 // it, a quasi-static Beer-Lambert profile (the crossing time of a row is taken
-// as short against the pulse).  Transmissions are multiplied left to right in
-// each row and rows are summed in order, so results do not depend on the
-// launch.
+// as short against the pulse).  K-alpha photons a cell returned to a bin
+// (g macro-photons, when nka is given) join the beam leaving it: the density
+// passed on is n_in tau + g w0 dx / (V c dt_rad).  Transmissions are applied
+// left to right in each row and rows are summed in order, so results do not
+// depend on the launch.
 #include <hip/hip_runtime.h>
 
 #include "xp_kernels.h"
@@ -38,6 +40,7 @@ constexpr int TS_SPAN = 64 * TS_CH;
 __global__ __launch_bounds__(TR_THREADS) void k_tr_rows(TransportArgs a)
 {
     __shared__ double tau[TR_SPAN];
+    __shared__ double gin[TR_SPAN];
     __shared__ double ent[TR_SPAN];
     __shared__ double carry_s;
     __shared__ unsigned long long starts[TR_THREADS / 64];
@@ -100,9 +103,22 @@ __global__ __launch_bounds__(TR_THREADS) void k_tr_rows(TransportArgs a)
                             t = ab < 1.0 ? 1.0 - ab : 0.0;
                         }
                         tau[q * TR_THREADS + lane] = t;
+                        if (a.nka) {
+                            const int i = i0 + q * TR_THREADS + lane;
+                            const double g = i < nx ? a.nka[(size_t)(rc + i) * XP_MAX_BINS + b] : 0.0;
+                            gin[q * TR_THREADS + lane] = (g * w0) / cross;
+                        }
                     }
                     __syncthreads();
-                    if (lane == 0) {
+                    if (lane == 0 && a.nka) {
+                        // with returned K-alpha photons: n tau + g per cell
+                        const int cnt = nx - i0 < TR_SPAN ? nx - i0 : TR_SPAN;
+                        for (int q = 0; q < cnt; ++q) {
+                            ent[q] = carry;
+                            carry = carry * tau[q] + gin[q];
+                        }
+                        carry_s = carry;
+                    } else if (lane == 0) {
                         // eight transmissions fetched ahead of their products; past
                         // the row's end tau = 1, which leaves the carry unchanged
                         const int cnt = nx - i0 < TR_SPAN ? nx - i0 : TR_SPAN;

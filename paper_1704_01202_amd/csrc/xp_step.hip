@@ -41,6 +41,9 @@ struct CellSharedT {
     double lnp[5];        // S3 logarithms of the lowered bindings, one per subshell
     double dbl[8];
     int ints[8];
+    int kz[14];                    // S5 K-alpha photons per charge state (XP_KA_FIELD)
+    double pbud[XP_MAX_BINS];      // S5 macro-photons per bin held by the cell (XP_PHOTO_FRAC)
+    double pused[XP_MAX_BINS];     // and taken so far
 };
 using CellShared = CellSharedT<256>;
 
@@ -546,8 +549,10 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
         L.fwok[j] = 0;
     }
     for (int q = tid; q < XP_NCOUNT; q += B) S.cnt[q] = 0;
-    if (XV)
+    if (XV) {
         for (int q = tid; q < XP_MAX_BINS; q += B) S.nabs[q] = 0;
+        for (int q = tid; q < 14; q += B) S.kz[q] = 0;
+    }
     for (int q = tid; q < XP_NLEDGER; q += B) S.led[q] = 0.0;
     for (int q = tid; q < XP_NMOM; q += B) S.mom[q] = 0.0;
     for (int q = tid; q < 8; q += B) S.ints[q] = 0;
@@ -1071,6 +1076,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
             L.k0[i] = (uint8_t)k0;
             uint8_t mask = 0;
             uint16_t bins = 0;
+            uint32_t pf = 0, dec = 0;
             if (z0 < 13) {
                 const Occ o0 = occupancy(z0, k0);
                 const int nl0 = o0.s[1] + o0.s[2];
@@ -1087,6 +1093,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
                         }
                         if (u52(d.x0, d.x1) < pd) {
                             kv = k0 - 1;
+                            dec = 1;
                             atomicAdd(&S.cnt[XP_C_DECAY], 1);
                             if (nl0 >= 2 && u52(d.x2, d.x3) < ga / rate) {
                                 z = z0 + 1;
@@ -1095,6 +1102,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
                             } else {
                                 atomicAdd(&S.cnt[XP_C_KALPHA], 1);
                                 atomicAdd(&S.led[XP_L_KALPHA], tb->e_kalpha[z0]);
+                                if (XV && (flags & XP_KA_FIELD)) atomicAdd(&S.kz[z0], 1);
                             }
                         }
                     }
@@ -1121,6 +1129,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
                             atomicAdd(&S.cnt[XP_C_P_CLAMPED], 1);
                         }
                         if (!(u32(fire[s]) < p)) continue;
+                        pf |= 1u << s;
                         const Occ on = occupancy(z, kv);
                         if (z >= 13 || on.s[s] <= 0) {
                             atomicAdd(&S.cnt[XP_C_PHOTO_SKIPPED], 1);
@@ -1128,20 +1137,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
                         }
                         const double pp = lowered(tb, z0, s, dE);
                         const Words d = rng((uint32_t)i, RP_BIN, (uint32_t)s);
-                        const double target = u52(d.x0, d.x1) * sum;
-                        double cum = 0.0;
-                        int sel = -1, lastpos = -1;
-                        for (int bq = 0; bq < nb; ++bq) {
-                            if (!(R->hv[bq] >= pp)) continue;
-                            const double term = nhv[bq] * S.sig[bq][s];
-                            cum = cum + term;
-                            if (term > 0.0) lastpos = bq;
-                            if (cum > target) {
-                                sel = bq;
-                                break;
-                            }
-                        }
-                        if (sel < 0) sel = lastpos;
+                        const int sel = photo_bin(R->hv, nhv, S.sig, nb, s, pp, u52(d.x0, d.x1) * sum);
                         z = z + 1;
                         if (s == 0) kv = kv + 1;
                         mask |= (uint8_t)(2u << s);
@@ -1152,15 +1148,69 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
                 L.iz[i] = (uint8_t)z;
                 L.ik[i] = (uint8_t)kv;
             }
+            // bits 0..3 the emissions; with XP_PHOTO_FRAC bits 4..6 the photo
+            // candidates and bit 7 a decay, for the budget walk below
+            if (XV && (flags & XP_PHOTO_FRAC)) {
+                mask |= (uint8_t)((pf << 4) | (dec << 7));
+                if (pf) atomicAdd(&S.ints[5], __popc(pf));
+            }
             L.emask[i] = mask;
             L.ebins[i] = bins;
         }
         T::sync();
+        if (XV && photo && (flags & XP_PHOTO_FRAC)) {
+            // a bin gives the cell no more macro-photons than it holds: when
+            // the candidates outnumber the smallest whole budget, one lane
+            // takes the ions again in slot order
+            if (tid == 0) {
+                double mmin = 1e300;
+                for (int bq = 0; bq < nb; ++bq) {
+                    const double m = (nhv[bq] * R->volume) / R->w0;
+                    S.pbud[bq] = m;
+                    S.pused[bq] = 0.0;
+                    if (nhv[bq] > 0.0 && floor(m) < mmin) mmin = floor(m);
+                }
+                if ((double)S.ints[5] > mmin) {
+                    int dn[3] = {0, 0, 0}, dskip = 0, dst = 0, dpart = 0;
+                    for (int i = 0; i < ni; ++i) {
+                        const uint32_t em = L.emask[i];
+                        const uint32_t pfi = (em >> 4) & 7u;
+                        if (!pfi) continue;
+                        const int z0 = L.z0[i], k0 = L.k0[i];
+                        int z = z0 + (int)(em & 1u), kv = k0 - (int)(em >> 7);
+                        const PhotoWalk w = photo_walk_ion(
+                            [&](uint32_t pu, uint32_t sub) { return rng((uint32_t)i, pu, sub); }, tb, R->hv, nhv,
+                            S.sig, S.ssum, nb, z0, pfi, dE, S.pbud, S.pused, z, kv);
+                        int old = 0;
+                        for (int q = 0; q < 3; ++q) {
+                            const int f = (int)((em >> (1 + q)) & 1u);
+                            dn[q] += w.fired[q] - f;
+                            old += f;
+                        }
+                        dskip += w.skipped - (__popc(pfi) - old);
+                        dst += w.starved;
+                        dpart += w.partial;
+                        L.emask[i] = (uint8_t)((em & 0xF1u) | w.mask);
+                        L.ebins[i] = (uint16_t)w.bins;
+                        L.iz[i] = (uint8_t)z;
+                        L.ik[i] = (uint8_t)kv;
+                    }
+                    for (int q = 0; q < 3; ++q) S.cnt[XP_C_PHOTO_1S + q] += dn[q];
+                    S.cnt[XP_C_PHOTO_SKIPPED] += dskip;
+                    S.cnt[XP_C_PHOTO_STARVED] += dst;
+                    S.cnt[XP_C_PHOTO_PARTIAL] += dpart;
+                }
+            }
+            T::sync();
+        }
+        if (XV && (flags & XP_KA_FIELD) && tid == 0)
+            for (int z0 = 0; z0 < 13; ++z0)
+                if (S.kz[z0] && kalpha_bin(R->hv, nb, tb->e_kalpha[z0]) >= 0) S.cnt[XP_C_KA_FIELD] += S.kz[z0];
         // pass 2: new electrons in ion-slot order (Auger, photo 1s, 2s, 2p)
         int base_pos = ne;
         for (int c0 = 0; c0 < ni; c0 += B) {
             const int i = c0 + tid;
-            const int cnt = i < ni ? __popc((unsigned)L.emask[i]) : 0;
+            const int cnt = i < ni ? __popc((unsigned)L.emask[i] & 15u) : 0;
             // exclusive prefix of cnt over the chunk (slot order)
             int tot;
             const int before = T::prefix(cnt, tot, S);
@@ -1168,7 +1218,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
             if (cnt > 0) {
                 const int z0 = L.z0[i], k0 = L.k0[i];
                 const Occ o0 = occupancy(z0, k0);
-                const uint8_t mask = L.emask[i];
+                const uint8_t mask = L.emask[i] & 15u;
                 for (int bit = 0; bit < 4; ++bit) {
                     if (!(mask & (1u << bit))) continue;
                     double en;
@@ -1326,6 +1376,10 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
         for (int q = tid; q < XP_NMOM; q += B) a.cell_mom[(size_t)cell * XP_NMOM + q] = S.mom[q];
     if (XV && a.cell_nabs)
         for (int q = tid; q < XP_MAX_BINS; q += B) a.cell_nabs[(size_t)cell * XP_MAX_BINS + q] = S.nabs[q];
+    if (XV && a.cell_nka)
+        for (int q = tid; q < XP_MAX_BINS; q += B)
+            a.cell_nka[(size_t)cell * XP_MAX_BINS + q] =
+                (flags & XP_KA_FIELD) && q < R->n_bins ? kalpha_return(tb, R->hv, R->n_bins, S.kz, q) : 0.0;
     return true;
 }
 

@@ -184,7 +184,7 @@ class Batch:
     """
 
     def __init__(self, ctx: Context, runs, capacity=(7, 16), cell_records=False,
-                 cell_nhv=None, big="auto"):
+                 cell_nhv=None, big="auto", kalpha_return=False):
         if big not in ("auto", "all"):
             raise ValueError("big must be 'auto' or 'all'")
         self.big = big
@@ -231,6 +231,12 @@ class Batch:
             self.d_cell_nabs = torch.zeros((max(self.n_cells, 1), B.XP_MAX_BINS), dtype=torch.int32,
                                            device=dev)
             self.d_trans = torch.zeros((self.n_runs, B.XP_MAX_BINS), dtype=torch.float64, device=dev)
+        # K-alpha photons returned to the field per cell and bin (steps with
+        # XP_KA_FIELD write them, transport_photons adds them to the beam)
+        self.d_cell_nka = None
+        if kalpha_return:
+            self.d_cell_nka = torch.zeros((max(self.n_cells, 1), B.XP_MAX_BINS), dtype=torch.float64,
+                                          device=dev)
         self.cell_records = cell_records
         if cell_records:
             self.d_cell_cnt = torch.zeros((nc, B.XP_NCOUNT), dtype=torch.int64, device=dev)
@@ -316,6 +322,7 @@ class Batch:
         b.big_e_slots, b.big_i_slots = self.big_e_slots, self.big_i_slots
         b.d_cell_nabs = _ptr(self.d_cell_nabs)
         b.d_run_status = _ptr(self.d_run_status)
+        b.d_cell_nka = _ptr(self.d_cell_nka)
         return b
 
     def _bin(self):
@@ -402,6 +409,12 @@ class Batch:
         nc = self.specs[run].nx * self.specs[run].ny
         return self.d_cell_nabs[c0:c0 + nc].cpu().numpy()
 
+    def kalpha_field(self, run=0):
+        """K-alpha macro-photons returned per bin by the last step, [cells][XP_MAX_BINS]."""
+        c0 = self.cell_begin[run]
+        nc = self.specs[run].nx * self.specs[run].ny
+        return self.d_cell_nka[c0:c0 + nc].cpu().numpy()
+
     def diagnostics(self, reset=False):
         out = torch.zeros(self.n_runs * C.sizeof(B.XpDiag), dtype=torch.uint8, device=self.device)
         B.diagnostics(self.ctx.h, self.struct(), out.data_ptr(),
@@ -424,18 +437,27 @@ class Batch:
         return self.d_stats.cpu().numpy().copy()
 
     # -- read-back for checks ---------------------------------------------------
-    def state(self, run=0) -> CompactState:
-        c0 = self.cell_begin[run]
-        nc = self.specs[run].nx * self.specs[run].ny
-        eo = self.d_e_off[c0:c0 + nc].cpu().numpy()
-        en = self.d_e_cnt[c0:c0 + nc].cpu().numpy().astype(np.int64)
-        io = self.d_i_off[c0:c0 + nc].cpu().numpy()
-        inn = self.d_i_cnt[c0:c0 + nc].cpu().numpy().astype(np.int64)
-        eidx = np.concatenate([np.arange(o, o + n) for o, n in zip(eo, en)]) if en.sum() else np.zeros(0, np.int64)
-        iidx = np.concatenate([np.arange(o, o + n) for o, n in zip(io, inn)]) if inn.sum() else np.zeros(0, np.int64)
-        g = lambda t, idx: t.cpu().numpy()[idx]
-        ey = g(self.ey, eidx) if self.two_d else np.zeros(eidx.size)
-        iy = g(self.iy, iidx) if self.two_d else np.zeros(iidx.size)
+    def _cells_state(self, c0, nc) -> CompactState:
+        """Live particles of cells [c0, c0 + nc) in slot order, gathered on the
+        device and copied once."""
+        dev = self.device
+
+        def live(off, cnt):
+            o = off[c0:c0 + nc]
+            n = cnt[c0:c0 + nc].to(torch.int64)
+            tot = int(n.sum().item())
+            if tot == 0:
+                return n, torch.zeros(0, dtype=torch.int64, device=dev)
+            first = torch.cumsum(n, 0) - n
+            rank = torch.arange(tot, dtype=torch.int64, device=dev) - torch.repeat_interleave(first, n)
+            return n, torch.repeat_interleave(o, n) + rank
+
+        en, eidx = live(self.d_e_off, self.d_e_cnt)
+        inn, iidx = live(self.d_i_off, self.d_i_cnt)
+        g = lambda t, idx: t.index_select(0, idx).cpu().numpy()
+        ey = g(self.ey, eidx) if self.two_d else np.zeros(eidx.numel())
+        iy = g(self.iy, iidx) if self.two_d else np.zeros(iidx.numel())
+        en, inn = en.cpu().numpy(), inn.cpu().numpy()
         return CompactState(
             e_start=np.concatenate([[0], np.cumsum(en)]), ex=g(self.ex, eidx), ey=ey,
             evx=g(self.evx, eidx), evy=g(self.evy, eidx), evz=g(self.evz, eidx),
@@ -443,6 +465,26 @@ class Batch:
             i_start=np.concatenate([[0], np.cumsum(inn)]), ix=g(self.ix, iidx), iy=iy,
             ivx=g(self.ivx, iidx), ivy=g(self.ivy, iidx), ivz=g(self.ivz, iidx),
             iz=g(self.iz, iidx), ik=g(self.ik, iidx))
+
+    def state(self, run=0) -> CompactState:
+        c0 = self.cell_begin[run]
+        return self._cells_state(c0, self.specs[run].nx * self.specs[run].ny)
+
+    def states(self):
+        """state(r) of every run, from one gather and one copy of the batch."""
+        whole = self._cells_state(0, self.n_cells)
+        out = []
+        for r, spec in enumerate(self.specs):
+            c0, nc = self.cell_begin[r], spec.nx * spec.ny
+            es, is_ = whole.e_start, whole.i_start
+            e0, e1, i0, i1 = es[c0], es[c0 + nc], is_[c0], is_[c0 + nc]
+            out.append(CompactState(
+                e_start=es[c0:c0 + nc + 1] - e0, ex=whole.ex[e0:e1], ey=whole.ey[e0:e1],
+                evx=whole.evx[e0:e1], evy=whole.evy[e0:e1], evz=whole.evz[e0:e1], ew=whole.ew[e0:e1],
+                i_start=is_[c0:c0 + nc + 1] - i0, ix=whole.ix[i0:i1], iy=whole.iy[i0:i1],
+                ivx=whole.ivx[i0:i1], ivy=whole.ivy[i0:i1], ivz=whole.ivz[i0:i1],
+                iz=whole.iz[i0:i1], ik=whole.ik[i0:i1]))
+        return out
 
     def cell_records_of(self, run=0):
         c0 = self.cell_begin[run]

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_function():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(B.EXPORTS)
-    assert lib.xp_abi_version() == B.ABI_VERSION == 3
+    assert lib.xp_abi_version() == B.ABI_VERSION == 4
     text = open(HEADER).read()
     assert re.search(r"#define XP_ABI_VERSION %du" % B.ABI_VERSION, text)
 
@@ -89,9 +89,22 @@ def test_flag_values_agree():
     pairs = {"XP_EE": O.EE, "XP_EI": O.EI, "XP_ION": O.ION, "XP_REC": O.REC,
              "XP_PHOTO": O.PHOTO, "XP_DECAY": O.DECAY, "XP_ALL": O.ALL, "XP_THERM": O.THERM,
              "XP_ION_Z": O.ION_Z, "XP_NANBU": O.NANBU, "XP_REL": O.REL,
-             "XP_REC_XS": O.REC_XS}
+             "XP_REC_XS": O.REC_XS, "XP_PHOTO_FRAC": O.PHOTO_FRAC, "XP_KA_FIELD": O.KA_FIELD}
     for name, oval in pairs.items():
         assert vals[name] == getattr(B, name) == oval, name
+
+
+def test_counter_names_agree():
+    # the header's counter enum, in order, is the oracle's counter list
+    from oracle import oracle as O
+    text = open(HEADER).read()
+    i = text.index("XP_C_EE = 0")
+    block = text[i:text.index("XP_NCOUNT", i)]
+    block = re.sub(r"/\*.*?\*/", "", block, flags=re.S)
+    names = re.findall(r"XP_C_(\w+)", block)
+    assert names == O.COUNTERS
+    n = int(re.search(r"XP_NCOUNT = (\d+)", text).group(1))
+    assert n == len(O.COUNTERS) == O.NCOUNT == B.XP_NCOUNT
 
 
 def test_entry_points_reject_null_arguments_without_a_device():

@@ -1,11 +1,15 @@
 """Parity at full size, in the launch configuration the benchmarks time.
 
 * The whole 512 x 512-cell target (33.5 M particles) stepped by the library
-  exactly as bench.py steps it (default schedule, LDS plans from the previous
-  step's statistics) against the oracle on every cell, for a few steps.
-* A sample of the 256-run batched scan at full size, including its largest
-  run (one cell with about 2 million particles on the global-memory path),
-  stepped together in one batch against each run's oracle.
+  exactly as bench.py steps it (default schedule, LDS plans from the
+  statistics the host has seen) against the oracle on every cell, over the
+  whole 200-step run: run counters after every step, the full particle state
+  at checkpoints.
+* The whole 1024 x 256 density ramp for 10 steps.
+* All 256 runs of the batched scan at full size in one batch (the largest is
+  one cell of about 2 million particles on the global-memory path) for 3
+  steps, and its 16 smallest runs for their whole 500 steps.
+* The 512 x 512 target with Nanbu's law and the reduced transport.
 """
 
 import os
@@ -29,51 +33,114 @@ def host_threads():
     return max(1, min(n, 16))
 
 
+def _c2_checkpoints(n):
+    return {0, 24, 49, 99, 149, n - 1}
+
+
 def test_c2_full_size_parity(ctx):
     spec, parts = W.config_c2()
-    say("C2 full: %d cells, %d electrons, %d ions" % (spec.ncells, parts.ne, parts.ni))
+    nsteps = spec.nsteps
+    say("C2 full: %d cells, %d electrons, %d ions, %d steps" % (spec.ncells, parts.ne, parts.ni, nsteps))
     sim = O.Sim(ctx.tables, spec)
     sim.bin(parts)
     bat = RT.Batch(ctx, [(spec, parts)], capacity=(7, 16))
     th = host_threads()
-    total = np.zeros(24, dtype=np.int64)
-    for s in range(3):
+    total = np.zeros(len(O.COUNTERS), dtype=np.int64)
+    for s in range(nsteps):
         bat.step(s)
         sim.step(s, O.ALL, th)
         torch.cuda.synchronize()
-        assert bat.status() == 0
-        w, nb = compare(bat.state(), sim.state(), "C2 full step %d" % s)
+        assert bat.status() == 0, s
         cnt, _ = sim.counters()
-        total += cnt[:, :24].sum(axis=0).astype(np.int64)
+        total += cnt.sum(axis=0).astype(np.int64)
         # the run's accumulated counters equal the oracle's per-step sums
-        assert np.array_equal(bat.run_counters()[0][:24].astype(np.int64), total), s
-        say("C2 full step %d ok (differing words %d)" % (s, nb))
+        assert np.array_equal(bat.run_counters()[0].astype(np.int64), total), s
+        if s in _c2_checkpoints(nsteps):
+            w, nb = compare(bat.state(), sim.state(), "C2 full step %d" % s)
+            say("C2 full step %d ok: %d electrons (differing words %d)" % (s, int(bat.d_e_cnt.sum()), nb))
+        elif s % 10 == 9:
+            say("C2 full step %d: counters ok" % s)
 
 
-def test_c4_full_size_sample_parity(ctx):
+def test_c3_full_grid_parity(ctx):
+    spec, parts = W.config_c3()
+    say("C3 full: %d cells, %d electrons, %d ions" % (spec.ncells, parts.ne, parts.ni))
+    sim = O.Sim(ctx.tables, spec)
+    sim.bin(parts)
+    bat = RT.Batch(ctx, [(spec, parts)], capacity=(7, 16))
+    th = host_threads()
+    total = np.zeros(len(O.COUNTERS), dtype=np.int64)
+    for s in range(10):
+        bat.step(s)
+        sim.step(s, O.ALL, th)
+        torch.cuda.synchronize()
+        assert bat.status() == 0, s
+        cnt, _ = sim.counters()
+        total += cnt.sum(axis=0).astype(np.int64)
+        assert np.array_equal(bat.run_counters()[0].astype(np.int64), total), s
+        if s in (0, 4, 9):
+            _, nb = compare(bat.state(), sim.state(), "C3 full step %d" % s)
+            say("C3 full step %d ok (differing words %d)" % (s, nb))
+
+
+def _step_all(sims, s, pool):
+    # single-cell runs: one oracle thread per run, the runs spread over a pool
+    list(pool.map(lambda sim: sim.step(s, O.ALL, 1), sims))
+
+
+def test_c4_all_runs_parity(ctx):
+    from concurrent.futures import ThreadPoolExecutor
     runs = W.config_c4_runs()
     sizes = np.array([p.ne + p.ni for _, p in runs])
-    order = np.argsort(sizes)
-    pick = sorted(set([int(order[-1]), int(order[0]), int(order[len(order) // 2]), 7, 100, 201]))
+    say("C4 all %d runs: %d particles, largest %d" % (len(runs), int(sizes.sum()), int(sizes.max())))
+    bat = RT.Batch(ctx, runs, capacity=(12, 16))
+    sims = []
+    for spec, parts in runs:
+        sim = O.Sim(ctx.tables, spec)
+        sim.bin(parts)
+        sims.append(sim)
+    with ThreadPoolExecutor(host_threads()) as pool:
+        for s in range(3):
+            bat.step(s)
+            _step_all(sims, s, pool)
+            torch.cuda.synchronize()
+            assert bat.status() == 0
+            gst = bat.states()
+            for k, sim in enumerate(sims):
+                compare(gst[k], sim.state(), "C4 run %d step %d" % (k, s))
+            say("C4 all runs step %d ok" % s)
+    assert bat.stats()[2] >= 1, "no run took the global-memory path"
+
+
+def test_c4_smallest_runs_full_length(ctx):
+    from concurrent.futures import ThreadPoolExecutor
+    runs = W.config_c4_runs()
+    sizes = np.array([p.ne + p.ni for _, p in runs])
+    pick = [int(r) for r in np.argsort(sizes)[:16]]
     sample = [runs[r] for r in pick]
-    say("C4 sample runs %s, particles %s" % (pick, [int(sizes[r]) for r in pick]))
-    bat = RT.Batch(ctx, sample, capacity=(10, 16))
+    nsteps = sample[0][0].nsteps
+    say("C4 smallest runs %s, %d steps" % (pick, nsteps))
+    bat = RT.Batch(ctx, sample, capacity=(12, 16))
     sims = []
     for spec, parts in sample:
         sim = O.Sim(ctx.tables, spec)
         sim.bin(parts)
         sims.append(sim)
-    th = host_threads()
-    for s in range(2):
-        bat.step(s)
-        for sim in sims:
-            sim.step(s, O.ALL, th)
-        torch.cuda.synchronize()
-        assert bat.status() == 0
-        for k, sim in enumerate(sims):
-            compare(bat.state(k), sim.state(), "C4 run %d step %d" % (pick[k], s))
-        say("C4 sample step %d ok" % s)
-    assert bat.stats()[2] >= 1, "no run took the global-memory path"
+    totals = np.zeros((len(sims), len(O.COUNTERS)), dtype=np.int64)
+    with ThreadPoolExecutor(host_threads()) as pool:
+        for s in range(nsteps):
+            bat.step(s)
+            _step_all(sims, s, pool)
+            for k, sim in enumerate(sims):
+                totals[k] += sim.counters()[0].sum(axis=0)
+            if s % 100 == 99 or s == nsteps - 1:
+                torch.cuda.synchronize()
+                assert bat.status() == 0
+                assert np.array_equal(bat.run_counters().astype(np.int64), totals), s
+                gst = bat.states()
+                for k, sim in enumerate(sims):
+                    compare(gst[k], sim.state(), "C4 run %d step %d" % (pick[k], s))
+                say("C4 smallest runs step %d ok" % s)
 
 
 def test_c2_full_size_variants_parity(ctx):
