@@ -343,9 +343,13 @@ __device__ __forceinline__ Coll ta77(double& ax, double& ay, double& az, double&
     }
     bool ta = true, tb = true;
     if (wa != wb) {
+        // only the heavier side draws, against w_light / w_heavy
         const double r4 = u32(d.x3);
-        ta = (wa < wb) || (r4 < (double)wb / (double)wa);
-        tb = (wb < wa) || (r4 < (double)wa / (double)wb);
+        const bool lighter_a = wa < wb;
+        const double ratio = lighter_a ? (double)wa / (double)wb : (double)wb / (double)wa;
+        const bool keep = r4 < ratio;
+        ta = lighter_a || keep;
+        tb = !lighter_a || keep;
     }
     if (ta) {
         ax = ax + fa * dux;
@@ -454,9 +458,13 @@ __device__ __noinline__ Coll ta77_rel(double& ax, double& ay, double& az, double
     const double rb = c / sqrt((mb * mb) * c2 + nb2);
     bool ta = true, tb = true;
     if (wa != wb) {
+        // only the heavier side draws, against w_light / w_heavy
         const double r4 = u32(d.x3);
-        ta = (wa < wb) || (r4 < (double)wb / (double)wa);
-        tb = (wb < wa) || (r4 < (double)wa / (double)wb);
+        const bool lighter_a = wa < wb;
+        const double ratio = lighter_a ? (double)wa / (double)wb : (double)wb / (double)wa;
+        const bool keep = r4 < ratio;
+        ta = lighter_a || keep;
+        tb = !lighter_a || keep;
     }
     if (ta) {
         ax = nax * ra;

@@ -53,7 +53,8 @@ using CellShared = CellSharedT<256>;
 template <int B>
 struct BlockTeam {
     static constexpr int N = B;
-    using Shared = CellShared;
+    // a wave's tree sums keep at most two row sums per 64 leaves in LDS
+    using Shared = CellSharedT<B == 64 ? 128 : 256>;
     __device__ static int rank() { return threadIdx.x; }
     __device__ static void sync() { __syncthreads(); }
     __device__ static long long isum(long long v, Shared& S) { return block_isum<B>(v, S.ired); }
@@ -232,7 +233,7 @@ template <int B, int XV>
 __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(3))) void k_step(StepArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ CellShared S;
+    __shared__ typename BlockTeam<B>::Shared S;
     __shared__ unsigned long long acc_cnt[XP_NCOUNT];
     __shared__ double acc_led[XP_NLEDGER];
     __shared__ int acc_run, acc_max;
@@ -370,30 +371,53 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 
 // Random permutation of slots 0..n-1: out[k] = slot of rank k when the slots
 // are sorted by (Philox word, slot); the word of slot i is word i % 4 of the
-// call (c0, c1, i / 4, c3).  A team of up to 64 lanes sorts in registers
-// (up to 2 keys per lane for a whole wave, 4 for a group); larger cells use an
-// LDS bitonic sort in sbuf (>= pow2(n) entries).  Out of line: the step calls
-// it four times.
+// call (c0, c1, i / 4, c3).  A team of up to 64 lanes sorts in registers,
+// up to 8 keys per lane for a whole wave and 4 for a group: with up to 2 keys
+// per lane every lane draws the Philox calls of its own keys; with more, each
+// call is drawn once and its four keys pass through sbuf.  Larger cells use
+// an LDS bitonic sort in sbuf (>= pow2(n) entries).  Out of line: the step
+// calls it four times.
 template <class T>
 __device__ __noinline__ void make_perm_fn(int n, uint32_t c0, uint32_t c1, uint32_t c3, uint32_t k0,
                                           uint32_t k1, int32_t* out, uint64_t* sbuf)
 {
     constexpr int W = T::N;
     const int tid = T::rank();
-    constexpr int KMAX = W == 64 ? 2 : 4;
+    constexpr int KMAX = W == 64 ? 8 : 4;
+    auto keys_to_lds = [&]() {
+        for (int g = tid; 4 * g < n; g += W) {
+            const Words w = philox(c0, c1, (uint32_t)g, c3, k0, k1);
+            const uint32_t k4[4] = {w.x0, w.x1, w.x2, w.x3};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = 4 * g + q;
+                if (i < n) sbuf[i] = ((uint64_t)k4[q] << 32) | (uint32_t)i;
+            }
+        }
+    };
     if (W <= 64 && n <= KMAX * W) {
         auto run_k = [&](auto kk) {
             constexpr int K = decltype(kk)::value;
             uint64_t key[K];
+            if constexpr (K <= 2) {
 #pragma unroll
-            for (int m = 0; m < K; ++m) {
-                const int i = tid + W * m;
-                key[m] = ~0ull;
-                if (i < n) {
-                    const Words w = philox(c0, c1, (uint32_t)(i >> 2), c3, k0, k1);
-                    const uint32_t q = i & 3;
-                    const uint32_t kw = q == 0 ? w.x0 : (q == 1 ? w.x1 : (q == 2 ? w.x2 : w.x3));
-                    key[m] = ((uint64_t)kw << 32) | (uint32_t)i;
+                for (int m = 0; m < K; ++m) {
+                    const int i = tid + W * m;
+                    key[m] = ~0ull;
+                    if (i < n) {
+                        const Words w = philox(c0, c1, (uint32_t)(i >> 2), c3, k0, k1);
+                        const uint32_t q = i & 3;
+                        const uint32_t kw = q == 0 ? w.x0 : (q == 1 ? w.x1 : (q == 2 ? w.x2 : w.x3));
+                        key[m] = ((uint64_t)kw << 32) | (uint32_t)i;
+                    }
+                }
+            } else {
+                keys_to_lds();
+                T::sync();
+#pragma unroll
+                for (int m = 0; m < K; ++m) {
+                    const int i = tid + W * m;
+                    key[m] = i < n ? sbuf[i] : ~0ull;
                 }
             }
             group_bitonic<W, K>(key);
@@ -404,21 +428,14 @@ __device__ __noinline__ void make_perm_fn(int n, uint32_t c0, uint32_t c1, uint3
             }
         };
         if (n <= W) run_k(std::integral_constant<int, 1>{});
-        else if (KMAX == 2 || n <= 2 * W) run_k(std::integral_constant<int, 2>{});
+        else if (n <= 2 * W) run_k(std::integral_constant<int, 2>{});
+        else if (n <= 4 * W) run_k(std::integral_constant<int, 4>{});
         else run_k(std::integral_constant<int, KMAX>{});
         T::sync();
         return;
     }
     const int p = pow2_at_least(n);
-    for (int g = tid; 4 * g < n; g += W) {
-        const Words w = philox(c0, c1, (uint32_t)g, c3, k0, k1);
-        const uint32_t k4[4] = {w.x0, w.x1, w.x2, w.x3};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int i = 4 * g + q;
-            if (i < n) sbuf[i] = ((uint64_t)k4[q] << 32) | (uint32_t)i;
-        }
-    }
+    keys_to_lds();
     for (int i = n + tid; i < p; i += W) sbuf[i] = ~0ull;
     T::sync();
     bitonic_sort<W>(sbuf, p);
