@@ -312,7 +312,8 @@ def bench_c3(args):
     sc = SC.Scan(ctx, [(spec, parts)], capacity=(3, 16))
     for _ in range(2):
         sc.eager_step()
-    cands = [{"schedule": s_, "quantile": q, "big_grid": 0} for s_ in (0, 1, 5) for q in (0.9, 0.99, 1.0)]
+    cands = [{"schedule": s_, "quantile": q, "big_grid": 0} for s_ in (0, 1, 5)
+             for q in (0.5, 0.75, 0.9, 0.99, 1.0)]
     best, best_ms = sc.autotune(cands, reps=2)
     log("autotune: " + ", ".join("%s/%.2f: %.3f ms" % (c["schedule"], c["quantile"], ms) for c, ms in sc.tuning))
     k = 5
@@ -392,11 +393,13 @@ def bench_c5(args):
     coll = sum(int(r["counters"][0] + r["counters"][1] + r["counters"][2]) for r in recs.values())
     del pool
     torch.cuda.empty_cache()
-    seq_recs = SV.sequential(ctx, trace, capacity=cap, on_done=lambda rec: log(
-        "sequential request %d (%d steps) done at %.1f s" % (rec["rid"], rec["steps"], rec["done"])))
-    seq = SV.latency_summary(seq_recs)
-    seq["status"] = max(r.get("status", 0) for r in seq_recs.values())
-    log("sequential: %s" % seq)
+    seq = None
+    if not args.no_seq:
+        seq_recs = SV.sequential(ctx, trace, capacity=cap, on_done=lambda rec: log(
+            "sequential request %d (%d steps) done at %.1f s" % (rec["rid"], rec["steps"], rec["done"])))
+        seq = SV.latency_summary(seq_recs)
+        seq["status"] = max(r.get("status", 0) for r in seq_recs.values())
+        log("sequential: %s" % seq)
     out = {
         "metric": "runs/hour (served stream)",
         "value": served["runs_per_hour"],
@@ -420,7 +423,7 @@ def bench_c5(args):
         "peak_resident_runs": peak,
         "longest_queue": waited,
         "sequential": seq,
-        "vs_sequential": served["runs_per_hour"] / seq["runs_per_hour"],
+        "vs_sequential": served["runs_per_hour"] / seq["runs_per_hour"] if seq else None,
     }
     print(json.dumps(out), flush=True)
 
@@ -461,7 +464,7 @@ def main():
     ap.add_argument("--serve-k", type=int, default=8, help="c5: steps between admission checks")
     ap.add_argument("--runs", type=int, default=256, help="c4: runs in the scan")
     ap.add_argument("--run-steps", type=int, default=500, help="c4: steps of every run")
-    ap.add_argument("--no-seq", action="store_true", help="c4: skip the sequential leg (profiling)")
+    ap.add_argument("--no-seq", action="store_true", help="c4, c5: skip the sequential leg")
     ap.add_argument("--no-scan", action="store_true",
                     help="c2: leave out the batched-scan measurement (C4 runs at full length)")
     ap.add_argument("--no-full-run", action="store_true",

@@ -54,7 +54,7 @@ class Scan:
         """Time `reps` real steps per candidate; keep the fastest."""
         if candidates is None:
             candidates = [{"schedule": s, "quantile": q, "big_grid": g}
-                          for s in (0, 1, 5) for q in (0.9, 0.99, 1.0) for g in (0, 1024, 8192)]
+                          for s in (0, 1, 5) for q in (0.75, 0.9, 0.99) for g in (0, 1024, 8192)]
         stream = torch.cuda.current_stream()
         best, best_ms = None, float("inf")
         self.tuning = []
