@@ -435,29 +435,30 @@ static xp_status launch_step(xp_ctx* ctx, xp_batch* b, const xp_step_params* p, 
                 if (m > 4 * w) sched = m > 128 ? 2 : 1;   // plan too large for the group
             }
             // kernel instance: plain, extended, or extended with Nanbu's law
-            const int level = (flags & (XP_NANBU | XP_REL)) ? 2 : (xv ? 1 : 0);
+            const int level = (flags & XP_REL) ? 3 : ((flags & XP_NANBU) ? 2 : (xv ? 1 : 0));
             auto pick = [level](void (*k0)(xpd::StepArgs), void (*k1)(xpd::StepArgs),
-                                void (*k2)(xpd::StepArgs)) {
-                return level == 2 ? (const void*)k2 : (level == 1 ? (const void*)k1 : (const void*)k0);
+                                void (*k2)(xpd::StepArgs), void (*k3)(xpd::StepArgs)) {
+                return level == 3 ? (const void*)k3
+                                  : (level == 2 ? (const void*)k2 : (level == 1 ? (const void*)k1 : (const void*)k0));
             };
             const void* fn;
             int threads = 64, per_cell_groups = 1;
             switch (sched) {
-            case 1: fn = pick(xpd::k_step<64, 0>, xpd::k_step<64, 1>, xpd::k_step<64, 2>); break;
+            case 1: fn = pick(xpd::k_step<64, 0>, xpd::k_step<64, 1>, xpd::k_step<64, 2>, xpd::k_step<64, 3>); break;
             case 2:
-                fn = pick(xpd::k_step<256, 0>, xpd::k_step<256, 1>, xpd::k_step<256, 2>);
+                fn = pick(xpd::k_step<256, 0>, xpd::k_step<256, 1>, xpd::k_step<256, 2>, xpd::k_step<256, 3>);
                 threads = 256;
                 break;
             case 4:
-                fn = pick(xpd::k_step_g<32, 0>, xpd::k_step_g<32, 1>, xpd::k_step_g<32, 2>);
+                fn = pick(xpd::k_step_g<32, 0>, xpd::k_step_g<32, 1>, xpd::k_step_g<32, 2>, xpd::k_step_g<32, 3>);
                 per_cell_groups = 2;
                 break;
             case 5:
-                fn = pick(xpd::k_step_g<16, 0>, xpd::k_step_g<16, 1>, xpd::k_step_g<16, 2>);
+                fn = pick(xpd::k_step_g<16, 0>, xpd::k_step_g<16, 1>, xpd::k_step_g<16, 2>, xpd::k_step_g<16, 3>);
                 per_cell_groups = 4;
                 break;
             default:
-                fn = pick(xpd::k_step_g<8, 0>, xpd::k_step_g<8, 1>, xpd::k_step_g<8, 2>);
+                fn = pick(xpd::k_step_g<8, 0>, xpd::k_step_g<8, 1>, xpd::k_step_g<8, 2>, xpd::k_step_g<8, 3>);
                 per_cell_groups = 8;
                 break;
             }

@@ -71,10 +71,11 @@ size_t step_lds_bytes(int ce, int ci);
 void lds_limits(size_t max_lds, int* e_lds, int* i_lds);
 size_t lds_budget(size_t max_lds);
 
-// XV: 0 the plain step; 1 compiled with the method's variants XP_THERM and
-// XP_ION_Z, the per-cell records and per-cell photon fields; 2 as 1 plus
-// Nanbu's scattering law (XP_NANBU).  Each level leaves out the code of the
-// next, which keeps its registers for the path it runs.
+// XV: 0 the plain step; 1 compiled with the method's variants (XP_THERM,
+// XP_ION_Z, XP_REC_XS, XP_PHOTO_FRAC, XP_KA_FIELD), the per-cell records and
+// per-cell photon fields; 2 as 1 plus Nanbu's scattering law (XP_NANBU); 3 as
+// 2 plus relativistic collisions (XP_REL).  Each level leaves out the code of
+// the next, which keeps its registers for the path it runs.
 template <int B, int XV>
 __global__ void k_step(StepArgs a);
 // 64 / W cells per wave, W lanes per cell (W = 32, 16, 8); plans with at most

@@ -596,7 +596,7 @@ struct PhotoWalk {
 };
 
 template <class D>
-__device__ __noinline__ PhotoWalk photo_walk_ion(D draw, const DevTables* tb, const double* hv, const double* nhv,
+__device__ __forceinline__ PhotoWalk photo_walk_ion(D draw, const DevTables* tb, const double* hv, const double* nhv,
                                                  const double (*sig)[3], const double (*ssum)[3], int nb, int z0,
                                                  uint32_t pf, const double* dE, double* bud, double* used, int& z,
                                                  int& kv)

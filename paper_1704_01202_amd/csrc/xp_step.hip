@@ -479,6 +479,23 @@ __device__ __noinline__ void smallest_fn(int n, int k, uint32_t c0, uint32_t c1,
     T::sync();
 }
 
+// XP_KA_FIELD, at the commit of a cell: the K-alpha photons that found a bin
+// (counter, lane 0) and the macro-photons returned per bin (d_cell_nka, zeros
+// without the variant).  Out of line: the step calls it only with the variant
+// or the array set.
+__device__ __noinline__ void kalpha_record(const StepArgs& a, int cell, const xp_run* R, const DevTables* tb,
+                                           const int* kz, int* cnt, int rank, int width)
+{
+    const bool on = (a.flags & XP_KA_FIELD) != 0;
+    if (on && rank == 0)
+        for (int z0 = 0; z0 < 13; ++z0)
+            if (kz[z0] && kalpha_bin(R->hv, R->n_bins, tb->e_kalpha[z0]) >= 0) cnt[XP_C_KA_FIELD] += kz[z0];
+    if (a.cell_nka)
+        for (int q = rank; q < XP_MAX_BINS; q += width)
+            a.cell_nka[(size_t)cell * XP_MAX_BINS + q] =
+                on && q < R->n_bins ? kalpha_return(tb, R->hv, R->n_bins, kz, q) : 0.0;
+}
+
 // Recombinations of a step at most this many select their ions and electrons
 // by extraction; more sort the whole permutation.
 constexpr int REC_SELECT_MAX = 12;
@@ -653,7 +670,8 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
     const bool do_ee = (flags & XP_EE) && ne >= 2;
     // scattering law bits: 1 Nanbu (else Takizuka-Abe), 2 relativistic (both
     // only in the instances that carry the variants' code)
-    const int law = XV == 2 ? (((flags & XP_NANBU) ? 1 : 0) | ((flags & XP_REL) ? 2 : 0)) : 0;
+    const int law = XV == 2 ? ((flags & XP_NANBU) ? 1 : 0)
+                  : (XV == 3 ? (((flags & XP_NANBU) ? 1 : 0) | 2) : 0);
     const bool do_ei = (flags & XP_EI) && ne >= 1 && ni >= 1;
     if ((flags & (XP_EE | XP_EI)) && ne >= 1 && (ne >= 2 || ni >= 1)) make_perm(RP_PERM_E, ne, L.perm_e);
     const double mee = (ME * ME) / (ME + ME);
@@ -1220,9 +1238,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
             }
             T::sync();
         }
-        if (XV && (flags & XP_KA_FIELD) && tid == 0)
-            for (int z0 = 0; z0 < 13; ++z0)
-                if (S.kz[z0] && kalpha_bin(R->hv, nb, tb->e_kalpha[z0]) >= 0) S.cnt[XP_C_KA_FIELD] += S.kz[z0];
+
         // pass 2: new electrons in ion-slot order (Auger, photo 1s, 2s, 2p)
         int base_pos = ne;
         for (int c0 = 0; c0 < ni; c0 += B) {
@@ -1385,6 +1401,10 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
         a.e_cnt[cell] = ne;
         S.ints[6] = ne;
     }
+    if (XV && (a.cell_nka || (flags & XP_KA_FIELD))) {
+        kalpha_record(a, cell, R, tb, S.kz, S.cnt, tid, B);
+        T::sync();
+    }
     if (XV && a.cell_cnt)
         for (int q = tid; q < XP_NCOUNT; q += B) a.cell_cnt[(size_t)cell * XP_NCOUNT + q] = S.cnt[q];
     if (XV && a.cell_led)
@@ -1393,10 +1413,6 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
         for (int q = tid; q < XP_NMOM; q += B) a.cell_mom[(size_t)cell * XP_NMOM + q] = S.mom[q];
     if (XV && a.cell_nabs)
         for (int q = tid; q < XP_MAX_BINS; q += B) a.cell_nabs[(size_t)cell * XP_MAX_BINS + q] = S.nabs[q];
-    if (XV && a.cell_nka)
-        for (int q = tid; q < XP_MAX_BINS; q += B)
-            a.cell_nka[(size_t)cell * XP_MAX_BINS + q] =
-                (flags & XP_KA_FIELD) && q < R->n_bins ? kalpha_return(tb, R->hv, R->n_bins, S.kz, q) : 0.0;
     return true;
 }
 
@@ -1415,6 +1431,11 @@ template __global__ void k_step<256, 2>(StepArgs);
 template __global__ void k_step_g<32, 2>(StepArgs);
 template __global__ void k_step_g<16, 2>(StepArgs);
 template __global__ void k_step_g<8, 2>(StepArgs);
+template __global__ void k_step<64, 3>(StepArgs);
+template __global__ void k_step<256, 3>(StepArgs);
+template __global__ void k_step_g<32, 3>(StepArgs);
+template __global__ void k_step_g<16, 3>(StepArgs);
+template __global__ void k_step_g<8, 3>(StepArgs);
 
 __global__ void k_step_prep(int32_t* counts, int32_t* stats)
 {
