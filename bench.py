@@ -47,7 +47,7 @@ def cpu_threads():
 
 
 def cpu_baseline(spec, parts, budget_s=15.0, max_steps=40, therm=False, ion_z=False, nanbu=False,
-                 rel=False, single=True):
+                 rel=False, rec_xs=False, photo_frac=False, single=True):
     """The oracle on a bounded sample of the same workload: every cell of the
     same initial state, stepped from step 0 until about budget_s of work on the
     host's threads; then (single) step 0 again on one thread."""
@@ -61,7 +61,7 @@ def cpu_baseline(spec, parts, budget_s=15.0, max_steps=40, therm=False, ion_z=Fa
     steps = 0
     t0 = time.perf_counter()
     flags = (O.ALL | (O.THERM if therm else 0) | (O.ION_Z if ion_z else 0) | (O.NANBU if nanbu else 0)
-             | (O.REL if rel else 0))
+             | (O.REL if rel else 0) | (O.REC_XS if rec_xs else 0) | (O.PHOTO_FRAC if photo_frac else 0))
     while steps < max_steps:
         sim.step(steps, flags, threads)
         cnt, _ = sim.counters()
@@ -445,6 +445,12 @@ def main():
                     help="c2: Nanbu's cumulative scattering law in the e-e and e-i collisions")
     ap.add_argument("--rel", action="store_true",
                     help="c2: relativistic binary collisions (centre-of-momentum frame)")
+    ap.add_argument("--rec-xs", action="store_true",
+                    help="c2: three-body recombination from cross sections by detailed balance")
+    ap.add_argument("--photo-frac", action="store_true",
+                    help="c2: photo events limited by the bin's photons in the cell (partial photoionization)")
+    ap.add_argument("--ka-field", action="store_true",
+                    help="c2: K-alpha photons returned to the per-cell photon field (with --transport)")
     ap.add_argument("--transport", action="store_true",
                     help="c2: per-cell photon field rebuilt after every step by the reduced "
                          "radiation transport (transport_photons)")
@@ -502,13 +508,16 @@ def main():
     if args.transport:
         import numpy as np
         field = np.tile(np.asarray(spec.photon_n, dtype=np.float64), (spec.ncells, 1))
-    bat = RT.Batch(ctx, [(spec, parts)], capacity=(7, 16), cell_nhv=field)
+    bat = RT.Batch(ctx, [(spec, parts)], capacity=(7, 16), cell_nhv=field,
+                   kalpha_return=args.ka_field and args.transport)
     torch.cuda.synchronize()
     log("binned into slabs: e_slots %d, max cap %d (%.1f s)"
         % (bat.e_slots, bat.e_cap_max, time.perf_counter() - t0))
     stream = torch.cuda.current_stream()
     flags = (B.XP_ALL | (B.XP_THERM if args.therm else 0) | (B.XP_ION_Z if args.ion_z else 0)
-             | (B.XP_NANBU if args.nanbu else 0) | (B.XP_REL if args.rel else 0))
+             | (B.XP_NANBU if args.nanbu else 0) | (B.XP_REL if args.rel else 0)
+             | (B.XP_REC_XS if args.rec_xs else 0) | (B.XP_PHOTO_FRAC if args.photo_frac else 0)
+             | (B.XP_KA_FIELD if args.ka_field else 0))
     for s in range(args.warmup):
         bat.step(s, flags, schedule=args.schedule)
         if args.transport:
@@ -570,6 +579,9 @@ def main():
                                   + (", ionization per ion charge state" if args.ion_z else "")
                                   + (", Nanbu scattering law" if args.nanbu else "")
                                   + (", relativistic collisions" if args.rel else "")
+                                  + (", recombination from cross sections" if args.rec_xs else "")
+                                  + (", photon budget with partial photoionization" if args.photo_frac else "")
+                                  + (", K-alpha return to the field" if args.ka_field else "")
                                   + (", reduced radiation transport after every step"
                                      if args.transport else "")),
                    "cells": spec.ncells, "electrons_start": parts.ne, "ions": ni,
@@ -581,8 +593,9 @@ def main():
         "collisions_total": coll,
     }
     valu = measured_valu()
-    if (valu is not None and args.nx == 512 and args.ny == 512 and not args.therm and not args.ion_z
-            and not args.nanbu and not args.rel and not args.transport):
+    plain = not (args.therm or args.ion_z or args.nanbu or args.rel or args.transport or args.rec_xs
+                 or args.photo_frac or args.ka_field)
+    if valu is not None and args.nx == 512 and args.ny == 512 and plain:
         # the step is bound by instruction issue, not by HBM: VALU instructions
         # of a launch (profiled) over the launch time measured here
         rate = valu / (avg_ms * 1e-3)
@@ -636,7 +649,8 @@ def main():
     if not args.no_cpu:
         log("timing the CPU oracle on a sample ...")
         out["cpu_baseline"] = cpu_baseline(spec, parts, therm=args.therm, ion_z=args.ion_z,
-                                           nanbu=args.nanbu, rel=args.rel)
+                                           nanbu=args.nanbu, rel=args.rel, rec_xs=args.rec_xs,
+                                           photo_frac=args.photo_frac)
     print(json.dumps(out), flush=True)
 
 
