@@ -392,8 +392,15 @@ __global__ __launch_bounds__(BT) void k_big_keys(BigArgs a, int species, int nee
 }
 
 // One wave per chunk: digit counts -> hist[256 * c0 + digit * nc + chunk].
+// sub: sort the first nsub slots of the cell's range (the REC_E candidates)
+// instead of all of them.
+__device__ __forceinline__ int big_count(const BigRec& r, int species, int sub)
+{
+    return sub ? r.nsub : (species == 0 ? r.epn : r.ni);
+}
+
 __global__ __launch_bounds__(64) void k_big_rhist(BigArgs a, int species, int needbit, int shift,
-                                                  const uint32_t* key)
+                                                  const uint32_t* key, int sub)
 {
     __shared__ uint32_t h[256];
     const int nch = species == 0 ? a.hdr->n_e_chunks : a.hdr->n_i_chunks;
@@ -403,7 +410,7 @@ __global__ __launch_bounds__(64) void k_big_rhist(BigArgs a, int species, int ne
         if (!big_live(r, needbit)) continue;
         const int c0 = species == 0 ? r.ce0 : r.ci0;
         const int nc = species == 0 ? r.nce : r.nci;
-        const int cnt = species == 0 ? r.epn : r.ni;
+        const int cnt = big_count(r, species, sub);
         const int64_t pop = species == 0 ? r.ep0 : r.ip0;
         const int k = g - c0;
         const int base = k * BIG_CH;
@@ -496,7 +503,7 @@ __global__ __launch_bounds__(1024) void k_big_rscan(BigArgs a, int species, int 
 // contiguously at the chunk's global offset for that digit.
 __global__ __launch_bounds__(256) void k_big_rscatter(BigArgs a, int species, int needbit, int shift,
                                                       const uint32_t* key, const uint32_t* val,
-                                                      uint32_t* key_out, uint32_t* val_out)
+                                                      uint32_t* key_out, uint32_t* val_out, int sub)
 {
     __shared__ uint32_t lstart[256];     // local start of each digit's run in the chunk
     __shared__ uint32_t gbase[256];      // global offset of each digit for this chunk
@@ -512,7 +519,7 @@ __global__ __launch_bounds__(256) void k_big_rscatter(BigArgs a, int species, in
         const BigRec& r = a.rec[map[g]];
         if (!big_live(r, needbit)) continue;
         const int c0 = species == 0 ? r.ce0 : r.ci0;
-        const int cnt = species == 0 ? r.epn : r.ni;
+        const int cnt = big_count(r, species, sub);
         const int64_t pop = species == 0 ? r.ep0 : r.ip0;
         const int base = (g - c0) * BIG_CH;
         const int n = cnt - base < BIG_CH ? cnt - base : BIG_CH;
@@ -568,6 +575,103 @@ __global__ __launch_bounds__(256) void k_big_rscatter(BigArgs a, int species, in
             val_out[dst] = sval[t];
         }
         __syncthreads();
+    }
+}
+
+// ---- S4 electrons: the first nrec ranks of the REC_E permutation without
+// sorting the whole population.  The top 8 bits of the Philox words are
+// counted per chunk (k_big_rhist, shift 24); the smallest digit D whose
+// cumulative count reaches nrec bounds the candidates: every slot whose word
+// has a top digit <= D (nsub of them, in slot order) is copied to key_b /
+// val_b, the radix passes sort those nsub slots by (word, slot), and the first
+// nrec ranks are copied to val_a.  Every slot left out has a larger word than
+// every candidate, so the ranks are those of the whole permutation.
+
+// Per cell: the bound D, the candidates nsub, and per chunk the offset of its
+// candidates (in hist[256 * chunk], after the chunk's counts are used).
+__global__ __launch_bounds__(256) void k_sel_find(BigArgs a)
+{
+    __shared__ uint32_t red[8];
+    __shared__ uint32_t tots[256];
+    __shared__ int dsel;
+    const int tid = threadIdx.x;
+    const int nb = a.hdr->count;
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+        BigRec& r = a.rec[b];
+        if (!big_live(r, BN_REC)) continue;
+        const int c0 = r.ce0, nc = r.nce;
+        uint32_t t = 0;
+        for (int k = 0; k < nc; ++k) t += a.hist[(size_t)256 * (c0 + k) + tid];
+        uint32_t tot;
+        const uint32_t incl = block_exclusive_sum<256, uint32_t>(t, red, tot) + t;
+        tots[tid] = incl;
+        if (tid == 0) dsel = 255;
+        __syncthreads();
+        // the smallest digit whose cumulative count reaches nrec
+        if (incl >= (uint32_t)r.nrec && (tid == 0 || tots[tid - 1] < (uint32_t)r.nrec)) dsel = tid;
+        __syncthreads();
+        const int d = dsel;
+        // candidates per chunk, then their exclusive scan over the chunks
+        for (int k = tid; k < nc; k += 256) {
+            uint32_t* h = a.hist + (size_t)256 * (c0 + k);
+            uint32_t c = 0;
+            for (int q = 0; q <= d; ++q) c += h[q];
+            h[0] = c;
+        }
+        __syncthreads();
+        uint32_t carry = 0;
+        for (int k0 = 0; k0 < nc; k0 += 256) {
+            const int k = k0 + tid;
+            uint32_t* h = a.hist + (size_t)256 * (c0 + k);
+            const uint32_t c = k < nc ? h[0] : 0u;
+            uint32_t ctot;
+            const uint32_t ex = block_exclusive_sum<256, uint32_t>(c, red, ctot);
+            if (k < nc) h[0] = carry + ex;
+            carry += ctot;
+        }
+        if (tid == 0) {
+            r.seld = d;
+            r.nsub = (int32_t)carry;
+        }
+        __syncthreads();
+    }
+}
+
+// The candidates of every chunk to key_b / val_b in slot order.
+__global__ __launch_bounds__(BT) void k_sel_compact(BigArgs a)
+{
+    __shared__ int red[BT / 64];
+    const int nce = a.hdr->n_e_chunks;
+    for (int g = blockIdx.x; g < nce; g += gridDim.x) {
+        const BigRec& r = a.rec[a.e_chunk_cell[g]];
+        if (!big_live(r, BN_REC)) continue;
+        const int base = (g - r.ce0) * BIG_CH;
+        const int n = r.epn - base < BIG_CH ? r.epn - base : BIG_CH;
+        if (n <= 0) continue;
+        const int64_t in = r.ep0 + base;
+        const int64_t out = r.ep0 + (int64_t)a.hist[(size_t)256 * g];
+        const uint32_t d = (uint32_t)r.seld;
+        block_ordered_select<BT>(
+            n, [&](int q) { return (a.key_a[in + q] >> 24) <= d; },
+            [&](int q, int pos) {
+                a.key_b[out + pos] = a.key_a[in + q];
+                a.val_b[out + pos] = a.val_a[in + q];
+            },
+            red);
+    }
+}
+
+// The first nrec sorted candidates (val_b) to val_a.
+__global__ __launch_bounds__(BT) void k_sel_copy(BigArgs a)
+{
+    const int nce = a.hdr->n_e_chunks;
+    for (int g = blockIdx.x; g < nce; g += gridDim.x) {
+        const BigRec& r = a.rec[a.e_chunk_cell[g]];
+        if (!big_live(r, BN_REC)) continue;
+        const int base = (g - r.ce0) * BIG_CH;
+        if (base >= r.nrec) continue;
+        const int n = r.nrec - base < BIG_CH ? r.nrec - base : BIG_CH;
+        for (int q = threadIdx.x; q < n; q += BT) a.val_a[r.ep0 + base + q] = a.val_b[r.ep0 + base + q];
     }
 }
 
@@ -2196,19 +2300,42 @@ BigPlan big_plan(int32_t big_max, int64_t e_pop, int64_t i_pop)
 
 namespace {
 
+// Four stable 8-bit radix passes over the words (key) with the slots (val);
+// an even number of passes, so the result ends in key / val.
+hipError_t big_radix(BigArgs& a, int species, int needbit, uint32_t* key, uint32_t* val, uint32_t* key2,
+                     uint32_t* val2, unsigned gch, unsigned gcell, hipStream_t s, int sub)
+{
+    for (int shift = 0; shift < 32; shift += 8) {
+        hipLaunchKernelGGL(k_big_rhist, dim3(gch), dim3(64), 0, s, a, species, needbit, shift, (const uint32_t*)key,
+                           sub);
+        hipLaunchKernelGGL(k_big_rscan, dim3(gcell), dim3(1024), 0, s, a, species, needbit);
+        hipLaunchKernelGGL(k_big_rscatter, dim3(gch), dim3(256), 0, s, a, species, needbit, shift,
+                           (const uint32_t*)key, (const uint32_t*)val, key2, val2, sub);
+        uint32_t* t = key; key = key2; key2 = t;
+        t = val; val = val2; val2 = t;
+    }
+    return hipGetLastError();
+}
+
 hipError_t big_sort(BigArgs& a, int species, int needbit, uint32_t purpose, uint32_t* key,
                     uint32_t* val, uint32_t* key2, uint32_t* val2, unsigned gch, unsigned gcell,
                     hipStream_t s)
 {
     hipLaunchKernelGGL(k_big_keys, dim3(gch), dim3(BT), 0, s, a, species, needbit, purpose, key, val);
-    for (int shift = 0; shift < 32; shift += 8) {
-        hipLaunchKernelGGL(k_big_rhist, dim3(gch), dim3(64), 0, s, a, species, needbit, shift, (const uint32_t*)key);
-        hipLaunchKernelGGL(k_big_rscan, dim3(gcell), dim3(1024), 0, s, a, species, needbit);
-        hipLaunchKernelGGL(k_big_rscatter, dim3(gch), dim3(256), 0, s, a, species, needbit, shift,
-                           (const uint32_t*)key, (const uint32_t*)val, key2, val2);
-        uint32_t* t = key; key = key2; key2 = t;
-        t = val; val = val2; val2 = t;
-    }
+    return big_radix(a, species, needbit, key, val, key2, val2, gch, gcell, s, 0);
+}
+
+// The REC_E ranks 0 .. nrec - 1 of every recombining cell in val_a (see
+// k_sel_find); key_a / val_a hold the keys, key_b / val_b the candidates.
+hipError_t big_select_rec_e(BigArgs& a, unsigned gch, unsigned gcell, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_big_keys, dim3(gch), dim3(BT), 0, s, a, 0, (int)BN_REC, (uint32_t)RP_REC_E, a.key_a, a.val_a);
+    hipLaunchKernelGGL(k_big_rhist, dim3(gch), dim3(64), 0, s, a, 0, (int)BN_REC, 24, (const uint32_t*)a.key_a, 0);
+    hipLaunchKernelGGL(k_sel_find, dim3(gcell), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_sel_compact, dim3(gch), dim3(BT), 0, s, a);
+    hipError_t e = big_radix(a, 0, BN_REC, a.key_b, a.val_b, a.key_a, a.val_a, gch, gcell, s, 1);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sel_copy, dim3(gch), dim3(BT), 0, s, a);
     return hipGetLastError();
 }
 
@@ -2283,13 +2410,11 @@ hipError_t big_launch(BigArgs& a, bool all_cells, hipStream_t s)
             hipLaunchKernelGGL(k_big_recfire, dim3(gch), dim3(BT), 0, s, a);
             hipLaunchKernelGGL(k_big_cscan, dim3(gcell), dim3(BT), 0, s, a, 3);
             hipLaunchKernelGGL(k_big_recfirelist, dim3(gch), dim3(BT), 0, s, a);
-            if ((e = big_sort(a, 0, BN_REC, RP_REC_E, a.key_a, a.val_a, a.key_b, a.val_b, gch, gcell, s)) != hipSuccess)
-                return e;
+            if ((e = big_select_rec_e(a, gch, gcell, s)) != hipSuccess) return e;
         } else {
             if ((e = big_sort(a, 1, BN_REC, RP_REC_I, a.key_c, a.val_c, a.key_b, a.val_b, gch, gcell, s)) != hipSuccess)
                 return e;
-            if ((e = big_sort(a, 0, BN_REC, RP_REC_E, a.key_a, a.val_a, a.key_b, a.val_b, gch, gcell, s)) != hipSuccess)
-                return e;
+            if ((e = big_select_rec_e(a, gch, gcell, s)) != hipSuccess) return e;
             hipLaunchKernelGGL(k_big_recsel, dim3(gch), dim3(BT), 0, s, a, 0);
             hipLaunchKernelGGL(k_big_cscan, dim3(gcell), dim3(BT), 0, s, a, 1);
             hipLaunchKernelGGL(k_big_recsel, dim3(gch), dim3(BT), 0, s, a, 1);
