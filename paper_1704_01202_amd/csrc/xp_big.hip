@@ -392,7 +392,7 @@ __global__ __launch_bounds__(BT) void k_big_keys(BigArgs a, int species, int nee
 }
 
 // One wave per chunk: digit counts -> hist[256 * c0 + digit * nc + chunk].
-// sub: sort the first nsub slots of the cell's range (the REC_E candidates)
+// sub: sort the first nsub slots of the cell's range (the S4 rank candidates)
 // instead of all of them.
 __device__ __forceinline__ int big_count(const BigRec& r, int species, int sub)
 {
@@ -578,18 +578,53 @@ __global__ __launch_bounds__(256) void k_big_rscatter(BigArgs a, int species, in
     }
 }
 
-// ---- S4 electrons: the first nrec ranks of the REC_E permutation without
-// sorting the whole population.  The top 8 bits of the Philox words are
-// counted per chunk (k_big_rhist, shift 24); the smallest digit D whose
-// cumulative count reaches nrec bounds the candidates: every slot whose word
-// has a top digit <= D (nsub of them, in slot order) is copied to key_b /
-// val_b, the radix passes sort those nsub slots by (word, slot), and the first
-// nrec ranks are copied to val_a.  Every slot left out has a larger word than
-// every candidate, so the ranks are those of the whole permutation.
+// ---- S4 ranks: the first nrec ranks of the REC_E permutation (electrons) and
+// the first nrec recombination-eligible ions (Z above the run's floor) of the
+// REC_I permutation, without sorting the whole population.  The top 8 bits of
+// the Philox words of the slots that take part (every electron; the eligible
+// ions) are counted per chunk (k_sel_hist); the smallest digit D whose
+// cumulative count reaches nrec bounds the candidates: every taking-part slot
+// whose word has a top digit <= D (nsub of them, in slot order) is copied to
+// key_b / val_b, the radix passes sort those nsub slots by (word, slot), and
+// the first nrec ranks are copied out (val_a for electrons, sel for ions).
+// Every slot left out has a larger word than every candidate, so the ranks
+// are those of the whole permutation, ineligible ions skipped.  species 0
+// reads the keys from key_a / val_a, species 1 from key_c / val_c.
+
+__device__ __forceinline__ bool sel_takes_part(const BigArgs& a, const BigRec& r, int species, int j)
+{
+    return species == 0 || (int)a.s.iz[r.io + j] > a.s.runs[r.run].z_floor;
+}
+
+// One wave per chunk: top-digit counts of the taking-part slots -> hist[256 * chunk].
+__global__ __launch_bounds__(64) void k_sel_hist(BigArgs a, int species)
+{
+    __shared__ uint32_t h[256];
+    const int nch = species == 0 ? a.hdr->n_e_chunks : a.hdr->n_i_chunks;
+    const int32_t* map = species == 0 ? a.e_chunk_cell : a.i_chunk_cell;
+    const uint32_t* key = species == 0 ? a.key_a : a.key_c;
+    for (int g = blockIdx.x; g < nch; g += gridDim.x) {
+        const BigRec& r = a.rec[map[g]];
+        if (!big_live(r, BN_REC)) continue;
+        const int c0 = species == 0 ? r.ce0 : r.ci0;
+        const int cnt = species == 0 ? r.epn : r.ni;
+        const int64_t pop = species == 0 ? r.ep0 : r.ip0;
+        const int base = (g - c0) * BIG_CH;
+        const int n = cnt - base < BIG_CH ? cnt - base : BIG_CH;
+        for (int q = threadIdx.x; q < 256; q += 64) h[q] = 0;
+        __syncthreads();
+        for (int q = threadIdx.x; q < n; q += 64)
+            if (sel_takes_part(a, r, species, base + q)) atomicAdd(&h[key[pop + base + q] >> 24], 1u);
+        __syncthreads();
+        uint32_t* hc = a.hist + (size_t)256 * g;
+        for (int q = threadIdx.x; q < 256; q += 64) hc[q] = h[q];
+        __syncthreads();
+    }
+}
 
 // Per cell: the bound D, the candidates nsub, and per chunk the offset of its
 // candidates (in hist[256 * chunk], after the chunk's counts are used).
-__global__ __launch_bounds__(256) void k_sel_find(BigArgs a)
+__global__ __launch_bounds__(256) void k_sel_find(BigArgs a, int species)
 {
     __shared__ uint32_t red[8];
     __shared__ uint32_t tots[256];
@@ -599,7 +634,8 @@ __global__ __launch_bounds__(256) void k_sel_find(BigArgs a)
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
         BigRec& r = a.rec[b];
         if (!big_live(r, BN_REC)) continue;
-        const int c0 = r.ce0, nc = r.nce;
+        const int c0 = species == 0 ? r.ce0 : r.ci0;
+        const int nc = species == 0 ? r.nce : r.nci;
         uint32_t t = 0;
         for (int k = 0; k < nc; ++k) t += a.hist[(size_t)256 * (c0 + k) + tid];
         uint32_t tot;
@@ -638,40 +674,51 @@ __global__ __launch_bounds__(256) void k_sel_find(BigArgs a)
 }
 
 // The candidates of every chunk to key_b / val_b in slot order.
-__global__ __launch_bounds__(BT) void k_sel_compact(BigArgs a)
+__global__ __launch_bounds__(BT) void k_sel_compact(BigArgs a, int species)
 {
     __shared__ int red[BT / 64];
-    const int nce = a.hdr->n_e_chunks;
-    for (int g = blockIdx.x; g < nce; g += gridDim.x) {
-        const BigRec& r = a.rec[a.e_chunk_cell[g]];
+    const int nch = species == 0 ? a.hdr->n_e_chunks : a.hdr->n_i_chunks;
+    const int32_t* map = species == 0 ? a.e_chunk_cell : a.i_chunk_cell;
+    const uint32_t* key = species == 0 ? a.key_a : a.key_c;
+    const uint32_t* val = species == 0 ? a.val_a : a.val_c;
+    for (int g = blockIdx.x; g < nch; g += gridDim.x) {
+        const BigRec& r = a.rec[map[g]];
         if (!big_live(r, BN_REC)) continue;
-        const int base = (g - r.ce0) * BIG_CH;
-        const int n = r.epn - base < BIG_CH ? r.epn - base : BIG_CH;
+        const int c0 = species == 0 ? r.ce0 : r.ci0;
+        const int cnt = species == 0 ? r.epn : r.ni;
+        const int64_t pop = species == 0 ? r.ep0 : r.ip0;
+        const int base = (g - c0) * BIG_CH;
+        const int n = cnt - base < BIG_CH ? cnt - base : BIG_CH;
         if (n <= 0) continue;
-        const int64_t in = r.ep0 + base;
-        const int64_t out = r.ep0 + (int64_t)a.hist[(size_t)256 * g];
+        const int64_t in = pop + base;
+        const int64_t out = pop + (int64_t)a.hist[(size_t)256 * g];
         const uint32_t d = (uint32_t)r.seld;
         block_ordered_select<BT>(
-            n, [&](int q) { return (a.key_a[in + q] >> 24) <= d; },
+            n, [&](int q) { return (key[in + q] >> 24) <= d && sel_takes_part(a, r, species, base + q); },
             [&](int q, int pos) {
-                a.key_b[out + pos] = a.key_a[in + q];
-                a.val_b[out + pos] = a.val_a[in + q];
+                a.key_b[out + pos] = key[in + q];
+                a.val_b[out + pos] = val[in + q];
             },
             red);
     }
 }
 
-// The first nrec sorted candidates (val_b) to val_a.
-__global__ __launch_bounds__(BT) void k_sel_copy(BigArgs a)
+// The first nrec sorted candidates (val_b): electrons to val_a, ions to sel.
+__global__ __launch_bounds__(BT) void k_sel_copy(BigArgs a, int species)
 {
-    const int nce = a.hdr->n_e_chunks;
-    for (int g = blockIdx.x; g < nce; g += gridDim.x) {
-        const BigRec& r = a.rec[a.e_chunk_cell[g]];
+    const int nch = species == 0 ? a.hdr->n_e_chunks : a.hdr->n_i_chunks;
+    const int32_t* map = species == 0 ? a.e_chunk_cell : a.i_chunk_cell;
+    for (int g = blockIdx.x; g < nch; g += gridDim.x) {
+        const BigRec& r = a.rec[map[g]];
         if (!big_live(r, BN_REC)) continue;
-        const int base = (g - r.ce0) * BIG_CH;
+        const int base = (g - (species == 0 ? r.ce0 : r.ci0)) * BIG_CH;
         if (base >= r.nrec) continue;
         const int n = r.nrec - base < BIG_CH ? r.nrec - base : BIG_CH;
-        for (int q = threadIdx.x; q < n; q += BT) a.val_a[r.ep0 + base + q] = a.val_b[r.ep0 + base + q];
+        const int64_t pop = species == 0 ? r.ep0 : r.ip0;
+        if (species == 0)
+            for (int q = threadIdx.x; q < n; q += BT) a.val_a[pop + base + q] = a.val_b[pop + base + q];
+        else
+            for (int q = threadIdx.x; q < n; q += BT) a.sel[pop + base + q] = (int32_t)a.val_b[pop + base + q];
     }
 }
 
@@ -988,14 +1035,14 @@ __global__ __launch_bounds__(BT) void k_big_fire(BigArgs a)
 }
 
 // Per-cell exclusive scan of the ion-chunk counts in ccnt.  mode 0: fired
-// ions of S3; 1: recombination-eligible ranks of S4; 2: electrons appended by
-// S5 (with the capacity check); 3: ions firing in S4 (XP_REC_XS).
+// ions of S3; 2: electrons appended by S5 (with the capacity check); 3: ions
+// firing in S4 (XP_REC_XS).
 __global__ __launch_bounds__(BT) void k_big_cscan(BigArgs a, int mode)
 {
     __shared__ int red[BT / 64];
     const int tid = threadIdx.x;
     const int nb = a.hdr->count;
-    const int needbit = mode == 0 ? BN_ION : ((mode == 1 || mode == 3) ? BN_REC : 0);
+    const int needbit = mode == 0 ? BN_ION : (mode == 3 ? BN_REC : 0);
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
         BigRec& r = a.rec[b];
         if (r.state || (needbit && !(r.need & needbit))) continue;
@@ -1244,34 +1291,25 @@ __global__ __launch_bounds__(BT) void k_big_apply3(BigArgs a)
     }
 }
 
-// Drift-frame rescale: mode 0 (S3) electrons 0 .. ne0-1 by sqrt(1 - debit/K_th);
-// mode 1 (S4) every electron with reduced weight > 0 by sqrt(1 + E_add/K_th),
-// and the reduced weights become the weights.
-__global__ __launch_bounds__(BT) void k_big_rescale(BigArgs a, int mode)
+// Drift-frame rescale of S3: electrons 0 .. ne0-1 by sqrt(1 - debit/K_th).
+// (S4's rescale by sqrt(1 + E_add/K_th) is applied by k_big_emove as it
+// stages the surviving electrons.)
+__global__ __launch_bounds__(BT) void k_big_rescale(BigArgs a)
 {
     const StepArgs& s = a.s;
-    const int needbit = mode == 0 ? BN_FIRED : BN_REC_APPLY;
     const int nce = a.hdr->n_e_chunks;
     for (int g = blockIdx.x; g < nce; g += gridDim.x) {
         const BigRec& r = a.rec[a.e_chunk_cell[g]];
-        if (!big_live(r, needbit)) continue;
-        if (mode == 0 && !(r.debit > 0.0)) continue;
+        if (!big_live(r, BN_FIRED)) continue;
+        if (!(r.debit > 0.0)) continue;
         const int base = (g - r.ce0) * BIG_CH;
         const int n = r.epn - base < BIG_CH ? r.epn - base : BIG_CH;
         const int64_t o = r.eo + base;
         const double ux = r.u[0], uy = r.u[1], uz = r.u[2], al = r.alpha;
         for (int j = threadIdx.x; j < n; j += BT) {
-            bool go = true;
-            if (mode == 1) {
-                const uint32_t w2 = a.wp[r.ep0 + base + j];
-                go = w2 > 0;
-                s.ew[o + j] = w2;
-            }
-            if (go) {
-                s.evx[o + j] = ux + al * (s.evx[o + j] - ux);
-                s.evy[o + j] = uy + al * (s.evy[o + j] - uy);
-                s.evz[o + j] = uz + al * (s.evz[o + j] - uz);
-            }
+            s.evx[o + j] = ux + al * (s.evx[o + j] - ux);
+            s.evy[o + j] = uy + al * (s.evy[o + j] - uy);
+            s.evz[o + j] = uz + al * (s.evz[o + j] - uz);
         }
     }
 }
@@ -1408,41 +1446,6 @@ __global__ __launch_bounds__(BT) void k_big_s4fin(BigArgs a)
                 }
             }
             __syncthreads();
-        }
-    }
-}
-
-// Recombination-eligible ions along the REC_I order: count per chunk (pass 0)
-// or write the first nrec into sel (pass 1, after the per-cell scan).
-__global__ __launch_bounds__(BT) void k_big_recsel(BigArgs a, int pass)
-{
-    __shared__ int red[BT / 64];
-    __shared__ long long ired[BT / 64];
-    const int tid = threadIdx.x;
-    const StepArgs& s = a.s;
-    const int nci = a.hdr->n_i_chunks;
-    for (int g = blockIdx.x; g < nci; g += gridDim.x) {
-        const BigRec& r = a.rec[a.i_chunk_cell[g]];
-        if (!big_live(r, BN_REC)) continue;
-        const int zf = s.runs[r.run].z_floor;
-        const int base = (g - r.ci0) * BIG_CH;
-        const int n = r.ni - base < BIG_CH ? r.ni - base : BIG_CH;
-        const uint32_t* perm = a.val_c + r.ip0;
-        auto elig = [&](int q) { return (int)s.iz[r.io + perm[base + q]] > zf; };
-        if (pass == 0) {
-            long long c = 0;
-            for (int q = tid; q < n; q += BT) c += elig(q) ? 1 : 0;
-            c = block_isum<BT>(c, ired);
-            if (tid == 0) a.ccnt[g] = (int32_t)c;
-        } else {
-            const int cb = a.ccnt[g];
-            if (cb >= r.nrec) continue;
-            block_ordered_select<BT>(
-                n, elig,
-                [&](int q, int pos) {
-                    if (cb + pos < r.nrec) a.sel[r.ip0 + cb + pos] = (int32_t)perm[base + q];
-                },
-                red);
         }
     }
 }
@@ -1613,13 +1616,15 @@ __global__ __launch_bounds__(64) void k_big_recfin(BigArgs a)
     }
 }
 
-// One wave per cell: the pairs' energies summed left to right in pair order
-// (512 at a time staged in LDS, lane 0 adds them eight loads ahead), then the
-// rescale factor of the remaining electrons.
+// One wave per cell: the pairs' energies summed left to right in pair order,
+// then the rescale factor of the remaining electrons.  The terms pass through
+// LDS 512 at a time; the wave's loads of the next 512 are in flight while
+// lane 0 adds the current ones, and lane 0 reads each group of eight terms
+// before adding the previous eight, so the sum waits on its additions only.
 __global__ __launch_bounds__(64) void k_big_recsum(BigArgs a)
 {
-    constexpr int SPAN = 512;
-    __shared__ double v[SPAN];
+    constexpr int SPAN = 512, PER = SPAN / 64;
+    __shared__ double v[SPAN + 8];
     const int lane = threadIdx.x;
     const int nb = a.hdr->count;
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
@@ -1628,18 +1633,39 @@ __global__ __launch_bounds__(64) void k_big_recsum(BigArgs a)
         const int nr = r.nrec;
         const double* term = a.fip + r.ip0;
         double eadd = 0.0;
+        double nxt[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int q = lane + 64 * u;
+            nxt[u] = q < nr ? term[q] : 0.0;
+        }
         for (int t0 = 0; t0 < nr; t0 += SPAN) {
             const int cnt = nr - t0 < SPAN ? nr - t0 : SPAN;
-            for (int q = lane; q < SPAN; q += 64) v[q] = q < cnt ? term[t0 + q] : 0.0;
+#pragma unroll
+            for (int u = 0; u < PER; ++u) v[lane + 64 * u] = nxt[u];
+            if (lane < 8) v[SPAN + lane] = 0.0;
             __syncthreads();
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int q = t0 + SPAN + lane + 64 * u;
+                nxt[u] = q < nr ? term[q] : 0.0;
+            }
             if (lane == 0) {
                 int q = 0;
-                for (; q + 8 <= cnt; q += 8) {
-                    double tt[8];
+                if (cnt >= 8) {
+                    double cur[8];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) tt[u] = v[q + u];
+                    for (int u = 0; u < 8; ++u) cur[u] = v[u];
+                    for (; q + 8 <= cnt; q += 8) {
+                        // v[q + 8 .. q + 15] lies within the padded buffer
+                        double nx[8];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) eadd = eadd + tt[u];
+                        for (int u = 0; u < 8; ++u) nx[u] = v[q + 8 + u];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) eadd = eadd + cur[u];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) cur[u] = nx[u];
+                    }
                 }
                 for (; q < cnt; ++q) eadd = eadd + v[q];
             }
@@ -1654,12 +1680,14 @@ __global__ __launch_bounds__(64) void k_big_recsum(BigArgs a)
     }
 }
 
-// Stable removal of the electrons whose weight reached zero, chunk-parallel
-// and out of place: k_big_ecount counts the survivors of each electron chunk
-// (into hist), k_big_escan turns the counts into per-cell offsets, k_big_emove
-// stages each survivor at its final rank (x, y in gev[0], gev[1]; vx, vy, vz,
-// w in ev4) and k_big_eback copies the staged survivors to the front of the
-// cell's slab.  Survivors keep their order.
+// Stable removal of the electrons whose reduced weight (wp) reached zero,
+// chunk-parallel and out of place: k_big_ecount counts the survivors of each
+// electron chunk (into hist), k_big_escan turns the counts into per-cell
+// offsets, k_big_emove stages each survivor at its final rank with its reduced
+// weight and its velocity rescaled in the drift frame by sqrt(1 + E_add/K_th)
+// (x, y in gev[0], gev[1]; vx, vy, vz, w in ev4) and k_big_eback copies the
+// staged survivors to the front of the cell's slab.  Survivors keep their
+// order.
 __global__ __launch_bounds__(BT) void k_big_ecount(BigArgs a)
 {
     __shared__ long long ired[BT / 64];
@@ -1672,7 +1700,7 @@ __global__ __launch_bounds__(BT) void k_big_ecount(BigArgs a)
         const int base = (g - r.ce0) * BIG_CH;
         const int n = r.epn - base < BIG_CH ? r.epn - base : BIG_CH;
         long long c = 0;
-        for (int j = threadIdx.x; j < n; j += BT) c += s.ew[r.eo + base + j] > 0 ? 1 : 0;
+        for (int j = threadIdx.x; j < n; j += BT) c += a.wp[r.ep0 + base + j] > 0 ? 1 : 0;
         c = block_isum<BT>(c, ired);
         if (threadIdx.x == 0) cnt[g] = (uint32_t)c;
     }
@@ -1716,10 +1744,13 @@ __global__ __launch_bounds__(BT) void k_big_emove(BigArgs a)
         const int base = (g - r.ce0) * BIG_CH;
         const int n = r.epn - base < BIG_CH ? r.epn - base : BIG_CH;
         const int64_t o = r.eo + base;
+        const uint32_t* wp = a.wp + r.ep0 + base;
+        const double ux = r.u[0], uy = r.u[1], uz = r.u[2], al = r.alpha;
         int out = (int)off[g];
         for (int c0 = 0; c0 < n; c0 += BT) {
             const int j = c0 + threadIdx.x;
-            const bool alive = j < n && s.ew[o + j] > 0;
+            const uint32_t w = j < n ? wp[j] : 0u;
+            const bool alive = w > 0;
             int tot;
             const int ex = block_exclusive_sum<BT, int>(alive ? 1 : 0, red, tot);
             if (alive) {
@@ -1727,8 +1758,11 @@ __global__ __launch_bounds__(BT) void k_big_emove(BigArgs a)
                 a.gev[0][d] = s.ex[o + j];
                 a.gev[1][d] = s.ey ? s.ey[o + j] : 0.0;
                 double* rec = a.ev4 + 4 * d;
-                *(double2*)rec = make_double2(s.evx[o + j], s.evy[o + j]);
-                *(double2*)(rec + 2) = make_double2(s.evz[o + j], (double)s.ew[o + j]);
+                const double vx = ux + al * (s.evx[o + j] - ux);
+                const double vy = uy + al * (s.evy[o + j] - uy);
+                const double vz = uz + al * (s.evz[o + j] - uz);
+                *(double2*)rec = make_double2(vx, vy);
+                *(double2*)(rec + 2) = make_double2(vz, (double)w);
             }
             out += tot;
         }
@@ -2325,17 +2359,22 @@ hipError_t big_sort(BigArgs& a, int species, int needbit, uint32_t purpose, uint
     return big_radix(a, species, needbit, key, val, key2, val2, gch, gcell, s, 0);
 }
 
-// The REC_E ranks 0 .. nrec - 1 of every recombining cell in val_a (see
-// k_sel_find); key_a / val_a hold the keys, key_b / val_b the candidates.
-hipError_t big_select_rec_e(BigArgs& a, unsigned gch, unsigned gcell, hipStream_t s)
+// S4 ranks of every recombining cell (see k_sel_find): species 0 the REC_E
+// ranks 0 .. nrec - 1 in val_a, species 1 the first nrec eligible ions of
+// the REC_I order in sel.  The keys go to key_a / val_a (key_c / val_c), the
+// candidates to key_b / val_b.
+hipError_t big_select_ranks(BigArgs& a, int species, unsigned gch, unsigned gcell, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_big_keys, dim3(gch), dim3(BT), 0, s, a, 0, (int)BN_REC, (uint32_t)RP_REC_E, a.key_a, a.val_a);
-    hipLaunchKernelGGL(k_big_rhist, dim3(gch), dim3(64), 0, s, a, 0, (int)BN_REC, 24, (const uint32_t*)a.key_a, 0);
-    hipLaunchKernelGGL(k_sel_find, dim3(gcell), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_sel_compact, dim3(gch), dim3(BT), 0, s, a);
-    hipError_t e = big_radix(a, 0, BN_REC, a.key_b, a.val_b, a.key_a, a.val_a, gch, gcell, s, 1);
+    uint32_t* key = species == 0 ? a.key_a : a.key_c;
+    uint32_t* val = species == 0 ? a.val_a : a.val_c;
+    hipLaunchKernelGGL(k_big_keys, dim3(gch), dim3(BT), 0, s, a, species, (int)BN_REC,
+                       (uint32_t)(species == 0 ? RP_REC_E : RP_REC_I), key, val);
+    hipLaunchKernelGGL(k_sel_hist, dim3(gch), dim3(64), 0, s, a, species);
+    hipLaunchKernelGGL(k_sel_find, dim3(gcell), dim3(256), 0, s, a, species);
+    hipLaunchKernelGGL(k_sel_compact, dim3(gch), dim3(BT), 0, s, a, species);
+    hipError_t e = big_radix(a, species, BN_REC, a.key_b, a.val_b, key, val, gch, gcell, s, 1);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sel_copy, dim3(gch), dim3(BT), 0, s, a);
+    hipLaunchKernelGGL(k_sel_copy, dim3(gch), dim3(BT), 0, s, a, species);
     return hipGetLastError();
 }
 
@@ -2399,7 +2438,7 @@ hipError_t big_launch(BigArgs& a, bool all_cells, hipStream_t s)
         hipLaunchKernelGGL(k_big_kth, dim3(gch), dim3(BT), 0, s, a, 0);
         hipLaunchKernelGGL(k_big_accept, dim3(gcell), dim3(64), 0, s, a);
         hipLaunchKernelGGL(k_big_apply3, dim3(gch), dim3(BT), 0, s, a);
-        hipLaunchKernelGGL(k_big_rescale, dim3(gch), dim3(BT), 0, s, a, 0);
+        hipLaunchKernelGGL(k_big_rescale, dim3(gch), dim3(BT), 0, s, a);
     }
     if (flags & XP_REC) {
         hipLaunchKernelGGL(k_big_plan, dim3(1), dim3(1024), 0, s, a, 0);
@@ -2410,14 +2449,10 @@ hipError_t big_launch(BigArgs& a, bool all_cells, hipStream_t s)
             hipLaunchKernelGGL(k_big_recfire, dim3(gch), dim3(BT), 0, s, a);
             hipLaunchKernelGGL(k_big_cscan, dim3(gcell), dim3(BT), 0, s, a, 3);
             hipLaunchKernelGGL(k_big_recfirelist, dim3(gch), dim3(BT), 0, s, a);
-            if ((e = big_select_rec_e(a, gch, gcell, s)) != hipSuccess) return e;
+            if ((e = big_select_ranks(a, 0, gch, gcell, s)) != hipSuccess) return e;
         } else {
-            if ((e = big_sort(a, 1, BN_REC, RP_REC_I, a.key_c, a.val_c, a.key_b, a.val_b, gch, gcell, s)) != hipSuccess)
-                return e;
-            if ((e = big_select_rec_e(a, gch, gcell, s)) != hipSuccess) return e;
-            hipLaunchKernelGGL(k_big_recsel, dim3(gch), dim3(BT), 0, s, a, 0);
-            hipLaunchKernelGGL(k_big_cscan, dim3(gcell), dim3(BT), 0, s, a, 1);
-            hipLaunchKernelGGL(k_big_recsel, dim3(gch), dim3(BT), 0, s, a, 1);
+            if ((e = big_select_ranks(a, 1, gch, gcell, s)) != hipSuccess) return e;
+            if ((e = big_select_ranks(a, 0, gch, gcell, s)) != hipSuccess) return e;
         }
         hipLaunchKernelGGL(k_big_wp, dim3(gch), dim3(BT), 0, s, a);
         hipLaunchKernelGGL(k_big_wpdec, dim3(gch), dim3(BT), 0, s, a);
@@ -2427,7 +2462,6 @@ hipError_t big_launch(BigArgs& a, bool all_cells, hipStream_t s)
         hipLaunchKernelGGL(k_big_recfin, dim3(gcell), dim3(64), 0, s, a);
         hipLaunchKernelGGL(k_big_recapply, dim3(gch), dim3(BT), 0, s, a);
         hipLaunchKernelGGL(k_big_recsum, dim3(gcell), dim3(64), 0, s, a);
-        hipLaunchKernelGGL(k_big_rescale, dim3(gch), dim3(BT), 0, s, a, 1);
         hipLaunchKernelGGL(k_big_ecount, dim3(gch), dim3(BT), 0, s, a);
         hipLaunchKernelGGL(k_big_escan, dim3(gcell), dim3(BT), 0, s, a);
         hipLaunchKernelGGL(k_big_emove, dim3(gch), dim3(BT), 0, s, a);

@@ -166,7 +166,7 @@ struct BigRec {
     int32_t need;                      // BN_* bits
     int32_t zc, acc, nrec, epn;        // epn: electrons covered by the current chunk plan
     int32_t nnew5, nkeep;              // electrons appended by the source terms; survivors of S4
-    int32_t seld, nsub;                // S4 REC_E: top-8-bit digit bound, electrons at or below it
+    int32_t seld, nsub;                // S4 ranks: top-8-bit digit bound, candidates at or below it
     unsigned long long we, wb, sz, sz2, ws, nelig, nfired, we4, wb4, sz4;
     double p, kth, debit, alpha;
     double u[3];
