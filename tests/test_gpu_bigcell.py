@@ -56,6 +56,19 @@ def test_big_path_recombination(ctx):
     assert bat.run_counters()[0][O.COUNTERS.index("REC")] > 0
 
 
+def test_big_path_recombination_many(ctx):
+    # thousands of recombinations per cell and step (5000, 8000 and 700 in the
+    # first step, up to every eligible ion; 3977 and 450 in the second): the
+    # REC_E and REC_I ranks taken from candidates across many chunks, the
+    # ordered sum of the pair energies over several 512-term spans with ragged
+    # tails, and the drift-frame rescale of the survivors as they are compacted
+    spec, parts = cases.one_run(3, [20000, 9000, 3300], [5000, 8000, 700], 2.0, 0.1, seed=93,
+                                z0=6, e_weight=1)
+    bat, _ = run_pair(ctx, spec, parts, 3, check_every=1, label="rec/global/many", schedule=3,
+                      big="all", flags=O.ALL & ~(O.PHOTO | O.DECAY))
+    assert bat.run_counters()[0][O.COUNTERS.index("REC")] >= 18000
+
+
 def test_oversized_cells_take_global_path(ctx):
     # cells beyond the LDS plans (1500 ions; 2600 electrons; 9000 electrons)
     # beside small cells that stay in LDS
