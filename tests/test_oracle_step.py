@@ -1,7 +1,8 @@
 """Whole-step pins of the oracle: statistics against closed forms and exact
 conservation laws.
 
-* e-i temperature relaxation against the Spitzer rate (ODE integrated here).
+* e-i temperature relaxation against the Spitzer rate (ODE integrated here),
+  and its extrapolation to dt -> 0 in (nu_ei dt)^(1/3).
 * collisional ionization: the cell-average probability equals n_e <sigma v> dt
   of the Lotz cross section for a Maxwellian (E1 closed form), and the number
   of fired ions is binomial with that probability (Sec. IV).
@@ -68,6 +69,25 @@ def test_spitzer_relaxation(orc, tables):
     assert r_large < r_small
     growth = (1 - r_large) / (1 - r_small)
     assert 1.4 < growth < 4.5, (r_small, r_large)
+
+
+def test_spitzer_rate_extrapolated(orc, tables):
+    """The step's relaxation rate extrapolated to dt -> 0 equals the Spitzer
+    rate to 5 %: at nu_ei dt = 2.5e-5 ... 1.6e-3 (the same total time, two
+    seeds each) the ratio falls linearly in (nu_ei dt)^(1/3), and the fitted
+    line meets dt = 0 at 1.  A rate off by a constant factor (a Coulomb
+    logarithm or a variance factor) moves the intercept, which the bounds of
+    test_spitzer_relaxation would let pass for up to 16 %."""
+    mi = 100.0 * ME
+    tab = cases.tables_with(tables, mass_ion=mi)
+    xs, rs = [], []
+    for fac, n in ((2.5e-5, 400), (1e-4, 100), (4e-4, 25), (1.6e-3, 7)):
+        for seed in (31, 32):
+            xs.append(fac ** (1.0 / 3.0))
+            rs.append(_relax_ratio(orc, tab, mi, fac, n, seed))
+    slope, r0 = np.polyfit(xs, rs, 1)
+    assert slope < 0.0, (slope, r0)
+    assert abs(r0 - 1.0) < 0.05, (r0, rs)
 
 
 def _lotz_rate(tables, zc, dE, tev):
