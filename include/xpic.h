@@ -19,7 +19,7 @@
  * step and skips its later stages.  Either way the batch needs re-binning with
  * more capacity before its results mean anything.  When the batch carries
  * d_run_status, each such bit is also OR-ed into the word of the run the cell
- * belongs to, so that runs sharing a batch can be judged one by one.
+ * belongs to, so that each run sharing a batch reports its own condition.
  *
  * Units: SI for positions, velocities, volumes and densities; energies and
  * temperatures in eV; table cross sections in cm^2.
