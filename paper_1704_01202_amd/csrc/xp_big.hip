@@ -623,50 +623,78 @@ __global__ __launch_bounds__(64) void k_sel_hist(BigArgs a, int species)
 }
 
 // Per cell: the bound D, the candidates nsub, and per chunk the offset of its
-// candidates (in hist[256 * chunk], after the chunk's counts are used).
-__global__ __launch_bounds__(256) void k_sel_find(BigArgs a, int species)
+// candidates (in hist[256 * chunk], after the chunk's counts are used).  1024
+// threads: thread (quarter, digit) adds a quarter of the digit's column with
+// eight loads in flight; each wave then counts the candidates of every 16th
+// chunk from a coalesced read of the chunk's row.
+__global__ __launch_bounds__(1024) void k_sel_find(BigArgs a, int species)
 {
-    __shared__ uint32_t red[8];
+    __shared__ uint32_t qsum[4][256];
+    __shared__ uint32_t red[16];
     __shared__ uint32_t tots[256];
     __shared__ int dsel;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, d0 = tid & 255, qt = tid >> 8;
+    const int lane = tid & 63, wid = tid >> 6;
     const int nb = a.hdr->count;
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
         BigRec& r = a.rec[b];
         if (!big_live(r, BN_REC)) continue;
         const int c0 = species == 0 ? r.ce0 : r.ci0;
         const int nc = species == 0 ? r.nce : r.nci;
-        uint32_t t = 0;
-        for (int k = 0; k < nc; ++k) t += a.hist[(size_t)256 * (c0 + k) + tid];
+        // the digit totals over the cell's chunks
+        const int per = (nc + 3) / 4;
+        const int k0 = qt * per, k1 = k0 + per < nc ? k0 + per : nc;
+        const uint32_t* col = a.hist + (size_t)256 * c0 + d0;
+        uint32_t part = 0;
+        int k = k0;
+        for (; k + 8 <= k1; k += 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = col[(size_t)256 * (k + u)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) part += v[u];
+        }
+        for (; k < k1; ++k) part += col[(size_t)256 * k];
+        qsum[qt][d0] = part;
+        __syncthreads();
+        const uint32_t t = tid < 256 ? qsum[0][tid] + qsum[1][tid] + qsum[2][tid] + qsum[3][tid] : 0u;
         uint32_t tot;
-        const uint32_t incl = block_exclusive_sum<256, uint32_t>(t, red, tot) + t;
-        tots[tid] = incl;
+        const uint32_t incl = block_exclusive_sum<1024, uint32_t>(t, red, tot) + t;
+        if (tid < 256) tots[tid] = incl;
         if (tid == 0) dsel = 255;
         __syncthreads();
         // the smallest digit whose cumulative count reaches nrec
-        if (incl >= (uint32_t)r.nrec && (tid == 0 || tots[tid - 1] < (uint32_t)r.nrec)) dsel = tid;
+        if (tid < 256 && incl >= (uint32_t)r.nrec && (tid == 0 || tots[tid - 1] < (uint32_t)r.nrec)) dsel = tid;
         __syncthreads();
-        const int d = dsel;
-        // candidates per chunk, then their exclusive scan over the chunks
-        for (int k = tid; k < nc; k += 256) {
-            uint32_t* h = a.hist + (size_t)256 * (c0 + k);
+        const uint32_t d = (uint32_t)dsel;
+        // candidates per chunk: a wave reads the chunk's 256 counts and adds
+        // those of digits <= d
+        for (int kc = wid; kc < nc; kc += 16) {
+            uint32_t* h = a.hist + (size_t)256 * (c0 + kc);
             uint32_t c = 0;
-            for (int q = 0; q <= d; ++q) c += h[q];
-            h[0] = c;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t q = (uint32_t)(lane + 64 * u);
+                c += q <= d ? h[q] : 0u;
+            }
+            c = (uint32_t)wave_isum64((long long)c);
+            __builtin_amdgcn_wave_barrier();
+            if (lane == 0) h[0] = c;
         }
         __syncthreads();
+        // their exclusive scan over the chunks
         uint32_t carry = 0;
-        for (int k0 = 0; k0 < nc; k0 += 256) {
-            const int k = k0 + tid;
-            uint32_t* h = a.hist + (size_t)256 * (c0 + k);
-            const uint32_t c = k < nc ? h[0] : 0u;
+        for (int kb = 0; kb < nc; kb += 1024) {
+            const int kc = kb + tid;
+            uint32_t* h = a.hist + (size_t)256 * (c0 + kc);
+            const uint32_t c = kc < nc ? h[0] : 0u;
             uint32_t ctot;
-            const uint32_t ex = block_exclusive_sum<256, uint32_t>(c, red, ctot);
-            if (k < nc) h[0] = carry + ex;
+            const uint32_t ex = block_exclusive_sum<1024, uint32_t>(c, red, ctot);
+            if (kc < nc) h[0] = carry + ex;
             carry += ctot;
         }
         if (tid == 0) {
-            r.seld = d;
+            r.seld = (int32_t)d;
             r.nsub = (int32_t)carry;
         }
         __syncthreads();
@@ -2370,7 +2398,7 @@ hipError_t big_select_ranks(BigArgs& a, int species, unsigned gch, unsigned gcel
     hipLaunchKernelGGL(k_big_keys, dim3(gch), dim3(BT), 0, s, a, species, (int)BN_REC,
                        (uint32_t)(species == 0 ? RP_REC_E : RP_REC_I), key, val);
     hipLaunchKernelGGL(k_sel_hist, dim3(gch), dim3(64), 0, s, a, species);
-    hipLaunchKernelGGL(k_sel_find, dim3(gcell), dim3(256), 0, s, a, species);
+    hipLaunchKernelGGL(k_sel_find, dim3(gcell), dim3(1024), 0, s, a, species);
     hipLaunchKernelGGL(k_sel_compact, dim3(gch), dim3(BT), 0, s, a, species);
     hipError_t e = big_radix(a, species, BN_REC, a.key_b, a.val_b, key, val, gch, gcell, s, 1);
     if (e != hipSuccess) return e;
