@@ -1110,7 +1110,7 @@ __global__ __launch_bounds__(BT) void k_big_cscan(BigArgs a, int mode)
 // reduced weights wp (mode 1, S4).
 __global__ __launch_bounds__(BT) void k_big_drift(BigArgs a, int mode)
 {
-    __shared__ double red[2 * (BIG_CH / 64)];
+    __shared__ double red3[6 * (BIG_CH / 64)];
     __shared__ long long ired[BT / 64];
     const int tid = threadIdx.x;
     const StepArgs& s = a.s;
@@ -1123,16 +1123,25 @@ __global__ __launch_bounds__(BT) void k_big_drift(BigArgs a, int mode)
         const int n = r.epn - base < BIG_CH ? r.epn - base : BIG_CH;
         const int64_t o = r.eo + base;
         const uint32_t* wsrc = mode == 0 ? s.ew + o : a.wp + r.ep0 + base;
+        // the weights summed in the same pass (every leaf j < n is visited once)
         long long wl = 0;
-        for (int j = tid; j < n; j += BT) wl += wsrc[j];
+        const double *vx = s.evx + o, *vy = s.evy + o, *vz = s.evz + o;
+        double tx, ty, tz;
+        block_tree_sum3<BT>(BIG_CH, [&](int j, double& x, double& y, double& z) {
+            if (j < n) {
+                const uint32_t wu = wsrc[j];
+                wl += wu;
+                const double w = (double)wu;
+                x = w * vx[j];
+                y = w * vy[j];
+                z = w * vz[j];
+            }
+        }, red3, tx, ty, tz);
         wl = block_isum<BT>(wl, ired);
-        const double* v3[3] = {s.evx + o, s.evy + o, s.evz + o};
-        for (int d = 0; d < 3; ++d) {
-            const double* v = v3[d];
-            const double t = block_tree_sum<BT>(BIG_CH, [&](int j) {
-                return j < n ? (double)wsrc[j] * v[j] : 0.0;
-            }, red);
-            if (tid == 0) a.part[1 + d][g] = t;
+        if (tid == 0) {
+            a.part[1][g] = tx;
+            a.part[2][g] = ty;
+            a.part[3][g] = tz;
         }
         if (tid == 0 && wl) atomicAdd(&r.ws, (unsigned long long)wl);
     }

@@ -314,6 +314,79 @@ __device__ double block_tree_sum(int n, F leaf, double* red)
     return r + 0.0;
 }
 
+// Three canonical pairwise sums at once, each with the tree of
+// block_tree_sum: leaf(j, x, y, z) gives the three leaves of index j (+0 for
+// j >= n is the caller's).  One pass over the leaves, one barrier per level
+// for the three trees.  red must hold 6 * max(1, P/64) doubles; the sums (+0.0)
+// are returned to every thread of a block of B threads.
+template <int B, class F>
+__device__ void block_tree_sum3(int n, F leaf, double* red, double& sx, double& sy, double& sz)
+{
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wid = tid >> 6;
+    int p = 64;
+    while (p < n) p <<= 1;
+    const int rows = p >> 6;
+    if (rows == 1) {
+        double x = 0.0, y = 0.0, z = 0.0;
+        if (wid == 0) {
+            if (lane < n) leaf(lane, x, y, z);
+            x = wave_tree_sum64(x);
+            y = wave_tree_sum64(y);
+            z = wave_tree_sum64(z);
+        }
+        if (B > 64) {
+            __syncthreads();
+            if (tid == 0) {
+                red[0] = x;
+                red[1] = y;
+                red[2] = z;
+            }
+            __syncthreads();
+            x = red[0];
+            y = red[1];
+            z = red[2];
+            __syncthreads();
+        }
+        sx = x + 0.0;
+        sy = y + 0.0;
+        sz = z + 0.0;
+        return;
+    }
+    // component c's rows in red[2 rows c ...], ping-ponged as in block_tree_sum
+    for (int r = wid; r < rows; r += B / 64) {
+        const int j = (r << 6) + lane;
+        double x = 0.0, y = 0.0, z = 0.0;
+        if (j < n) leaf(j, x, y, z);
+        x = wave_tree_sum64(x);
+        y = wave_tree_sum64(y);
+        z = wave_tree_sum64(z);
+        if (lane == 0) {
+            red[r] = x;
+            red[2 * rows + r] = y;
+            red[4 * rows + r] = z;
+        }
+    }
+    __syncthreads();
+    int so = 0, dof = rows;   // offsets of src and dst within a component's buffer
+    for (int len = rows; len > 1; len >>= 1) {
+        const int half = len >> 1;
+        for (int i = tid; i < 3 * half; i += B) {
+            const int c = i / half, ii = i - c * half;
+            double* cb = red + 2 * rows * c;
+            cb[dof + ii] = cb[so + 2 * ii] + cb[so + 2 * ii + 1];
+        }
+        __syncthreads();
+        const int t = so;
+        so = dof;
+        dof = t;
+    }
+    sx = red[so] + 0.0;
+    sy = red[2 * rows + so] + 0.0;
+    sz = red[4 * rows + so] + 0.0;
+    __syncthreads();
+}
+
 // Block-wide integer sum (any order).
 template <int B>
 __device__ long long block_isum(long long v, long long* red)
