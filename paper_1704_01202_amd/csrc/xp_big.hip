@@ -205,27 +205,27 @@ __global__ __launch_bounds__(BT) void k_big_s0(BigArgs a)
         // record per electron in slot order turns three random reads into one
         const bool stage = (s.flags & (XP_EE | XP_EI)) != 0;
         double* e4 = a.ev4 + 4 * (r.ep0 + base);
-        for (int j = tid; j < n; j += BT) {
+        // one pass: every leaf j < n is visited once, so the weight sums, the
+        // finiteness check and the staging ride on the bulk-energy tree
+        const double ke = block_tree_sum<BT>(BIG_CH, [&](int j) {
+            if (j >= n) return 0.0;
             const double x = s.evx[o + j], y = s.evy[o + j], z = s.evz[o + j];
             bad |= !(__builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z));
             const long long w = s.ew[o + j];
             wl += w;
-            if (HALF_ME_OVER_QE * ((x * x + y * y) + z * z) < ebulk) bl += w;
+            const double e = HALF_ME_OVER_QE * ((x * x + y * y) + z * z);
+            if (e < ebulk) bl += w;
             if (stage) {
                 e4[4 * j] = x;
                 e4[4 * j + 1] = y;
                 e4[4 * j + 2] = z;
                 e4[4 * j + 3] = (double)w;
             }
-        }
+            return e < ebulk ? (double)w * e : 0.0;
+        }, red);
         if (bad) flag_status(s, r.run, XP_ST_NONFINITE);
         const long long we = block_isum<BT>(wl, ired);
         const long long wb = block_isum<BT>(bl, ired);
-        const double ke = block_tree_sum<BT>(BIG_CH, [&](int j) {
-            if (j >= n) return 0.0;
-            const double e = kin_at(s, o + j);
-            return e < ebulk ? (double)s.ew[o + j] * e : 0.0;
-        }, red);
         if (tid == 0) {
             a.part[0][g] = ke;
             atomicAdd(&r.we, (unsigned long long)we);
@@ -1368,18 +1368,18 @@ __global__ __launch_bounds__(BT) void k_big_s4part(BigArgs a)
         const int n = r.epn - base < BIG_CH ? r.epn - base : BIG_CH;
         const int64_t o = r.eo + base;
         long long wl = 0, bl = 0;
-        for (int j = tid; j < n; j += BT) {
-            const long long w = s.ew[o + j];
-            wl += w;
-            if (kin_at(s, o + j) < ebulk) bl += w;
-        }
-        wl = block_isum<BT>(wl, ired);
-        bl = block_isum<BT>(bl, ired);
+        // one pass: the weight sums ride on the bulk-energy tree (every leaf
+        // j < n is visited once)
         const double ke = block_tree_sum<BT>(BIG_CH, [&](int j) {
             if (j >= n) return 0.0;
+            const long long w = s.ew[o + j];
+            wl += w;
             const double e = kin_at(s, o + j);
-            return e < ebulk ? (double)s.ew[o + j] * e : 0.0;
+            if (e < ebulk) bl += w;
+            return e < ebulk ? (double)w * e : 0.0;
         }, red);
+        wl = block_isum<BT>(wl, ired);
+        bl = block_isum<BT>(bl, ired);
         if (tid == 0) {
             a.part[0][g] = ke;
             atomicAdd(&r.we4, (unsigned long long)wl);
