@@ -430,7 +430,7 @@ __global__ __launch_bounds__(64) void k_big_rhist(BigArgs a, int species, int ne
 // quarter q of digit d's column (coalesced across d), the quarter totals are
 // scanned per digit, the digit totals across digits, and each thread adds
 // its offset to its quarter.
-__global__ __launch_bounds__(1024) void k_big_rscan(BigArgs a, int species, int needbit)
+__global__ __launch_bounds__(1024) void k_big_rscan(BigArgs a, int species, int needbit, int sub)
 {
     __shared__ uint32_t qsum[4][256];
     __shared__ uint32_t red[16];
@@ -440,7 +440,8 @@ __global__ __launch_bounds__(1024) void k_big_rscan(BigArgs a, int species, int 
         const BigRec& r = a.rec[b];
         if (!big_live(r, needbit)) continue;
         const int c0 = species == 0 ? r.ce0 : r.ci0;
-        const int nc = species == 0 ? r.nce : r.nci;
+        // with sub, only the chunks that hold the nsub candidates have counts
+        const int nc = sub ? (r.nsub + BIG_CH - 1) / BIG_CH : (species == 0 ? r.nce : r.nci);
         if (nc == 0) continue;
         const int per = (nc + 3) / 4;
         const int k0 = qt * per, k1 = k0 + per < nc ? k0 + per : nc;
@@ -2379,7 +2380,7 @@ hipError_t big_radix(BigArgs& a, int species, int needbit, uint32_t* key, uint32
     for (int shift = 0; shift < 32; shift += 8) {
         hipLaunchKernelGGL(k_big_rhist, dim3(gch), dim3(64), 0, s, a, species, needbit, shift, (const uint32_t*)key,
                            sub);
-        hipLaunchKernelGGL(k_big_rscan, dim3(gcell), dim3(1024), 0, s, a, species, needbit);
+        hipLaunchKernelGGL(k_big_rscan, dim3(gcell), dim3(1024), 0, s, a, species, needbit, sub);
         hipLaunchKernelGGL(k_big_rscatter, dim3(gch), dim3(256), 0, s, a, species, needbit, shift,
                            (const uint32_t*)key, (const uint32_t*)val, key2, val2, sub);
         uint32_t* t = key; key = key2; key2 = t;
