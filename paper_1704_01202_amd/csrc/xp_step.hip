@@ -53,6 +53,7 @@ using CellShared = CellSharedT<256>;
 template <int B>
 struct BlockTeam {
     static constexpr int N = B;
+    static constexpr bool REREAD = true;   // see step_args
     // a wave's tree sums keep at most two row sums per 64 leaves in LDS
     using Shared = CellSharedT<B == 64 ? 128 : 256>;
     __device__ static int rank() { return threadIdx.x; }
@@ -92,6 +93,7 @@ struct BlockTeam {
 template <int W>
 struct GroupTeam {
     static constexpr int N = W;
+    static constexpr bool REREAD = false;   // see step_args
     using Shared = CellSharedT<1>;
     __device__ static int rank() { return threadIdx.x & (W - 1); }
     // the groups of a workgroup share one wave: LDS accesses of a wave are
@@ -214,6 +216,25 @@ __host__ __device__ size_t step_lds_bytes_dev(int ce, int ci)
     size_t n = r(8ull * ps) + 3 * r(8ull * ce) + 3 * r(8ull * ci) + 3 * r(4ull * ce) +
                2 * r(4ull * ci) + r(2ull * ci) + r(12ull * ci) + r(ce) + 6 * r(ci);
     return n;
+}
+
+using KArgsPtr = const StepArgs __attribute__((address_space(4)))*;
+// The launch's step arguments as a stage of the step reads them.  For teams
+// with REREAD, a pointer to the kernarg segment (the kernel's only argument,
+// at its start) made opaque: loads through it are not hoisted above this
+// point, so a stage's argument values need not stay live through the stages
+// before it (fewer scalar registers spilled to vector lanes in the wave and
+// block kernels).  The lane-group kernels read the kernel's argument as it is.
+template <class T>
+__device__ __forceinline__ auto step_args(const StepArgs& a)
+{
+    if constexpr (T::REREAD) {
+        uint64_t v = (uint64_t)__builtin_amdgcn_kernarg_segment_ptr();
+        asm volatile("" : "+s"(v));
+        return (KArgsPtr)v;
+    } else {
+        return &a;
+    }
 }
 
 template <class T, int XV>
@@ -505,24 +526,25 @@ constexpr int REC_SELECT_MAX = 12;
 template <class T, int XV>
 __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, const Lds& L)
 {
+    auto ka = step_args<T>(a);
     constexpr int B = T::N;
     const int tid = T::rank();
-    if (cell < 0 || cell >= a.n_cells) return false;
-    const int run = a.cell_run[cell];
-    const xp_run* R = a.runs + run;
-    const DevTables* tb = a.tab;
+    if (cell < 0 || cell >= ka->n_cells) return false;
+    const int run = ka->cell_run[cell];
+    const xp_run* R = ka->runs + run;
+    const DevTables* tb = ka->tab;
     const uint32_t lcell = (uint32_t)(cell - R->cell_begin);
-    const uint32_t step = a.d_step ? a.d_step[run] : a.step;
+    const uint32_t step = ka->d_step ? ka->d_step[run] : ka->step;
     const uint32_t key0 = (uint32_t)R->seed, key1 = (uint32_t)(R->seed >> 32);
-    const uint32_t flags = a.flags;
+    const uint32_t flags = ka->flags;
     const double w0 = R->w0, vol = R->volume, dt = R->dt;
     const double mi = tb->mass_ion;
 
-    int ne = a.e_cnt[cell];
-    const int ecap = a.e_cap[cell];
-    const int ni = a.i_cnt[cell];
-    const int64_t eo = a.e_off[cell], io = a.i_off[cell];
-    const int ce = a.lds_ce, ci = a.lds_ci;
+    int ne = ka->e_cnt[cell];
+    const int ecap = ka->e_cap[cell];
+    const int ni = ka->i_cnt[cell];
+    const int64_t eo = ka->e_off[cell], io = ka->i_off[cell];
+    const int ce = ka->lds_ce, ci = ka->lds_ci;
     // the LDS plan of this launch bounds the cell; a cell beyond it is passed to
     // the next (larger) plan, a cell beyond its slab capacity is an error
     const int lim = ecap < ce ? ecap : ce;
@@ -530,9 +552,9 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
     // beyond every LDS plan: hand the cell to the global-memory path
     auto to_big = [&]() {
         if (tid == 0) {
-            if (a.big_out) {
-                const int k = atomicAdd(a.big_out_count, 1);
-                if (k < a.big_out_cap) a.big_out[k] = cell;
+            if (ka->big_out) {
+                const int k = atomicAdd(ka->big_out_count, 1);
+                if (k < ka->big_out_cap) ka->big_out[k] = cell;
                 else flag_status(a, run, XP_ST_CAPACITY);
             } else {
                 flag_status(a, run, XP_ST_CAPACITY);
@@ -540,14 +562,14 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
         }
     };
     auto defer = [&]() {
-        if (!a.defer_out) {
+        if (!ka->defer_out) {
             to_big();
             return;
         }
         if (tid == 0) {
-            const int k = atomicAdd(a.defer_out_count, 1);
-            a.defer_out[k] = cell;
-            if (a.stats) atomicAdd(&a.stats[1], 1);
+            const int k = atomicAdd(ka->defer_out_count, 1);
+            ka->defer_out[k] = cell;
+            if (ka->stats) atomicAdd(&ka->stats[1], 1);
         }
     };
     if (ni > ci) {
@@ -568,18 +590,18 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
     };
 
     for (int j = tid; j < ne; j += B) {
-        L.evx[j] = a.evx[eo + j];
-        L.evy[j] = a.evy[eo + j];
-        L.evz[j] = a.evz[eo + j];
-        L.ew[j] = a.ew[eo + j];
+        L.evx[j] = ka->evx[eo + j];
+        L.evy[j] = ka->evy[eo + j];
+        L.evz[j] = ka->evz[eo + j];
+        L.ew[j] = ka->ew[eo + j];
         L.eorg[j] = j;
     }
     for (int j = tid; j < ni; j += B) {
-        L.ivx[j] = a.ivx[io + j];
-        L.ivy[j] = a.ivy[io + j];
-        L.ivz[j] = a.ivz[io + j];
-        L.iz[j] = a.iz[io + j];
-        L.ik[j] = a.ik[io + j];
+        L.ivx[j] = ka->ivx[io + j];
+        L.ivy[j] = ka->ivy[io + j];
+        L.ivz[j] = ka->ivz[io + j];
+        L.iz[j] = ka->iz[io + j];
+        L.ik[j] = ka->ik[io + j];
         L.fwok[j] = 0;
     }
     for (int q = tid; q < XP_NCOUNT; q += B) S.cnt[q] = 0;
@@ -593,6 +615,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
     T::sync();
 
     // ---------------- S0: moments and continuum lowering -----------------
+    ka = step_args<T>(a);
     const double ebulk = R->e_bulk;
     auto kin = [&](int j) {
         const double x = L.evx[j], y = L.evy[j], z = L.evz[j];
@@ -662,6 +685,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
     const double qe4 = (QE * QE) * (QE * QE);
 
     // ---------------- S1, S2: binary collisions ----------------
+    ka = step_args<T>(a);
     // Every collision of the step goes through one call site (the scattering
     // is the largest code of the step).  Phase 0 is e-e: with an odd count
     // >= 3, item 0 is the triplet (three collisions in sequence at dt/2), the
@@ -751,6 +775,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
     bool overflow = false, deferred = false;
 
     // ---------------- S3: collisional ionization ----------------
+    ka = step_args<T>(a);
     if ((flags & XP_ION) && ne >= 1 && ni >= 1) {
         // charge states are unchanged since the moments: reuse their sum
         const int zc = (int)((2 * sz + wi) / (2 * wi));
@@ -890,6 +915,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
     }
 
     // ---------------- S4: three-body recombination ----------------
+    ka = step_args<T>(a);
     if (!overflow && !deferred && (flags & XP_REC) && ne >= 1 && ni >= 1) {
         // charge states changed only by S3 since the moments
         const long long szr = sz + s3_accepted;
@@ -1085,13 +1111,14 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
     }
 
     // ---------------- S5: K-vacancy decay and photoionization ----------------
+    ka = step_args<T>(a);
     if (!overflow && !deferred && (flags & (XP_PHOTO | XP_DECAY))) {
         const int nb = R->n_bins;
         const bool photo = (flags & XP_PHOTO) && nb > 0;
-        const double* nhv = (XV && R->field_per_cell && a.cell_nhv) ? a.cell_nhv + (size_t)cell * XP_MAX_BINS : R->nhv;
+        const double* nhv = (XV && R->field_per_cell && ka->cell_nhv) ? ka->cell_nhv + (size_t)cell * XP_MAX_BINS : R->nhv;
         const double dtr = R->dt_rad;
         if (photo) {
-            const double* rs = a.run_sig + (size_t)run * (XP_MAX_BINS * 3);
+            const double* rs = ka->run_sig + (size_t)run * (XP_MAX_BINS * 3);
             for (int q = tid; q < 3 * nb; q += B) S.sig[q / 3][q % 3] = rs[q];
             T::sync();
             for (int q = tid; q < 39; q += B) {
@@ -1352,6 +1379,7 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
     }
 
     // ---------------- commit ----------------
+    ka = step_args<T>(a);
     if (overflow) {
         if (tid == 0) flag_status(a, run, XP_ST_CAPACITY);
         return false;
@@ -1364,17 +1392,17 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
     for (int j = tid; j < ne; j += B) {
         const double x = L.evx[j], y = L.evy[j], z = L.evz[j];
         bad |= !(__builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z));
-        a.evx[eo + j] = x;
-        a.evy[eo + j] = y;
-        a.evz[eo + j] = z;
-        a.ew[eo + j] = L.ew[j];
+        ka->evx[eo + j] = x;
+        ka->evy[eo + j] = y;
+        ka->evz[eo + j] = z;
+        ka->ew[eo + j] = L.ew[j];
     }
     for (int j = tid; j < ni; j += B) {
-        a.ivx[io + j] = L.ivx[j];
-        a.ivy[io + j] = L.ivy[j];
-        a.ivz[io + j] = L.ivz[j];
-        a.iz[io + j] = L.iz[j];
-        a.ik[io + j] = L.ik[j];
+        ka->ivx[io + j] = L.ivx[j];
+        ka->ivy[io + j] = L.ivy[j];
+        ka->ivz[io + j] = L.ivz[j];
+        ka->iz[io + j] = L.iz[j];
+        ka->ik[io + j] = L.ik[j];
     }
     if (bad) flag_status(a, run, XP_ST_NONFINITE);
     T::sync();
@@ -1383,36 +1411,36 @@ __device__ bool step_cell(const StepArgs& a, int cell, typename T::Shared& S, co
         const int org = L.eorg[j];
         if (org == j) continue;
         if (org >= 0) {
-            L.evx[j] = a.ex[eo + org];
-            L.evy[j] = a.ey ? a.ey[eo + org] : 0.0;
+            L.evx[j] = ka->ex[eo + org];
+            L.evy[j] = ka->ey ? ka->ey[eo + org] : 0.0;
         } else {
             const int i = -1 - org;
-            L.evx[j] = a.ix[io + i];
-            L.evy[j] = a.iy ? a.iy[io + i] : 0.0;
+            L.evx[j] = ka->ix[io + i];
+            L.evy[j] = ka->iy ? ka->iy[io + i] : 0.0;
         }
     }
     T::sync();
     for (int j = tid; j < ne; j += B) {
         if (L.eorg[j] == j) continue;
-        a.ex[eo + j] = L.evx[j];
-        if (a.ey) a.ey[eo + j] = L.evy[j];
+        ka->ex[eo + j] = L.evx[j];
+        if (ka->ey) ka->ey[eo + j] = L.evy[j];
     }
     if (tid == 0) {
-        a.e_cnt[cell] = ne;
+        ka->e_cnt[cell] = ne;
         S.ints[6] = ne;
     }
-    if (XV && (a.cell_nka || (flags & XP_KA_FIELD))) {
+    if (XV && (ka->cell_nka || (flags & XP_KA_FIELD))) {
         kalpha_record(a, cell, R, tb, S.kz, S.cnt, tid, B);
         T::sync();
     }
-    if (XV && a.cell_cnt)
-        for (int q = tid; q < XP_NCOUNT; q += B) a.cell_cnt[(size_t)cell * XP_NCOUNT + q] = S.cnt[q];
-    if (XV && a.cell_led)
-        for (int q = tid; q < XP_NLEDGER; q += B) a.cell_led[(size_t)cell * XP_NLEDGER + q] = S.led[q];
-    if (XV && a.cell_mom)
-        for (int q = tid; q < XP_NMOM; q += B) a.cell_mom[(size_t)cell * XP_NMOM + q] = S.mom[q];
-    if (XV && a.cell_nabs)
-        for (int q = tid; q < XP_MAX_BINS; q += B) a.cell_nabs[(size_t)cell * XP_MAX_BINS + q] = S.nabs[q];
+    if (XV && ka->cell_cnt)
+        for (int q = tid; q < XP_NCOUNT; q += B) ka->cell_cnt[(size_t)cell * XP_NCOUNT + q] = S.cnt[q];
+    if (XV && ka->cell_led)
+        for (int q = tid; q < XP_NLEDGER; q += B) ka->cell_led[(size_t)cell * XP_NLEDGER + q] = S.led[q];
+    if (XV && ka->cell_mom)
+        for (int q = tid; q < XP_NMOM; q += B) ka->cell_mom[(size_t)cell * XP_NMOM + q] = S.mom[q];
+    if (XV && ka->cell_nabs)
+        for (int q = tid; q < XP_MAX_BINS; q += B) ka->cell_nabs[(size_t)cell * XP_MAX_BINS + q] = S.nabs[q];
     return true;
 }
 
